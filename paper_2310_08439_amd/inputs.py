@@ -1,0 +1,203 @@
+"""Seeded synthetic inputs shared by the FP64 oracle tests and the HIP path.
+
+This module holds no arithmetic of the potential itself: it only builds
+lattices, draws random displacements, species, velocities and MLP weights,
+and lays out the radial-basis parameters.  Both sides of every parity test
+read the arrays it returns; neither side imports the other.
+
+Workloads stand in for the paper's bulk-metal MD configurations (bcc W at
+a = 3.1887 A and 2.8 A, Sec. IV.C and IV.D): Gaussian-displaced perfect
+lattices replace thermal snapshots and randomly initialised MLPs replace the
+trained potentials (the DFT training set and weights are not available).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Fractional basis of the conventional cubic cells and of the orthorhombic
+# four-atom hcp cell (a, a*sqrt(3), c).
+_BASIS = {
+    "fcc": np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]]),
+    "bcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]),
+    "hcp": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 5.0 / 6.0, 0.5], [0.0, 1.0 / 3.0, 0.5]]),
+}
+
+ACT_TANH = 0
+ACT_SQUAREPLUS = 1
+
+
+def cell_lengths(kind: str, a: float, c_over_a: float = math.sqrt(8.0 / 3.0)) -> np.ndarray:
+    """Edge lengths of one conventional cell of the lattice."""
+    if kind in ("fcc", "bcc"):
+        return np.array([a, a, a], dtype=np.float64)
+    if kind == "hcp":
+        return np.array([a, a * math.sqrt(3.0), a * c_over_a], dtype=np.float64)
+    raise ValueError(f"unknown lattice {kind!r}")
+
+
+def lattice(kind: str, a: float, cells: Sequence[int]) -> Tuple[np.ndarray, np.ndarray]:
+    """Perfect periodic lattice: positions [N,3] (float64) and box [3].
+
+    Atoms are ordered cell by cell (x fastest), basis atom innermost.
+    """
+    cells = tuple(int(c) for c in cells)
+    basis = _BASIS[kind]
+    edge = cell_lengths(kind, a)
+    iz, iy, ix = np.meshgrid(np.arange(cells[2]), np.arange(cells[1]), np.arange(cells[0]), indexing="ij")
+    origins = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    frac = (origins[:, None, :] + basis[None, :, :]).reshape(-1, 3)
+    pos = frac * edge[None, :]
+    box = edge * np.array(cells, dtype=np.float64)
+    return pos, box
+
+
+@dataclasses.dataclass
+class System:
+    pos: np.ndarray        # [N,3] float64, wrapped into [0, L)
+    species: np.ndarray    # [N] int32
+    box: np.ndarray        # [3] float64, orthorhombic, periodic in x, y, z
+    masses: np.ndarray     # [S] float64, amu
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def make_system(kind: str, a: float, cells: Sequence[int], sigma: float, n_species: int = 1,
+                seed: int = 0, masses: Optional[Sequence[float]] = None) -> System:
+    """Gaussian-displaced lattice with species split exactly evenly at random.
+
+    Displacements are i.i.d. N(0, sigma^2) per Cartesian component; positions
+    are then wrapped into the box.  Species: N//S atoms of each species (the
+    remainder goes to the lowest species), assigned by a random permutation.
+    """
+    rng = np.random.default_rng(seed)
+    pos, box = lattice(kind, a, cells)
+    n = pos.shape[0]
+    if sigma > 0:
+        pos = pos + rng.normal(0.0, sigma, size=pos.shape)
+    pos = np.mod(pos, box[None, :])
+    pos[pos >= box[None, :]] = 0.0
+    base = n // n_species
+    counts = [base + (1 if s < n % n_species else 0) for s in range(n_species)]
+    species = np.repeat(np.arange(n_species, dtype=np.int32), counts)
+    species = rng.permutation(species).astype(np.int32)
+    if masses is None:
+        masses = [183.84] * n_species
+    return System(pos=np.ascontiguousarray(pos), species=np.ascontiguousarray(species),
+                  box=box.astype(np.float64), masses=np.asarray(masses, dtype=np.float64))
+
+
+@dataclasses.dataclass
+class ModelSpec:
+    n_species: int
+    n_radial: int              # K
+    max_moment: int            # M, 0..3
+    hidden: List[int]          # hidden widths, e.g. [64, 64]
+    rcut: float
+    mu: np.ndarray             # [K]
+    eta: np.ndarray            # [K]
+    params: np.ndarray         # float64, all species packed (see param_layout)
+    activation: int = ACT_TANH
+
+    @property
+    def n_features(self) -> int:
+        return self.n_species * self.n_radial * (self.max_moment + 1)
+
+
+def param_layout(n_features: int, hidden: Sequence[int]) -> List[Tuple[str, Tuple[int, ...]]]:
+    """Per-species parameter blocks, in storage order.
+
+    Layer l maps width w_{l-1} to w_l with W_l stored row-major [w_l][w_{l-1}]
+    followed by its bias b_l [w_l]; the last layer maps the last hidden width
+    to one output (the atomic energy).
+    """
+    widths = [n_features] + list(hidden) + [1]
+    out = []
+    for li in range(len(widths) - 1):
+        out.append((f"W{li + 1}", (widths[li + 1], widths[li])))
+        out.append((f"b{li + 1}", (widths[li + 1],)))
+    return out
+
+
+def params_per_species(n_features: int, hidden: Sequence[int]) -> int:
+    return sum(int(np.prod(s)) for _, s in param_layout(n_features, hidden))
+
+
+def radial_grid(n_radial: int, rcut: float, r_min: float = 2.0) -> Tuple[np.ndarray, np.ndarray]:
+    """Gaussian centres mu_k = r_min + k*delta and widths eta = 1/(2 delta^2)."""
+    delta = (rcut - r_min) / n_radial
+    mu = r_min + delta * np.arange(n_radial, dtype=np.float64)
+    eta = np.full(n_radial, 1.0 / (2.0 * delta * delta), dtype=np.float64)
+    return mu, eta
+
+
+def make_model(n_species: int, n_radial: int, max_moment: int, hidden: Sequence[int], rcut: float,
+               seed: int, activation: int = ACT_TANH, weight_scale: float = 1.0,
+               r_min: float = 2.0) -> ModelSpec:
+    """Random per-element MLPs: W ~ N(0, 1/fan_in) * weight_scale, biases 0.
+
+    Draw order: species 0 layer 1, 2, ..., then species 1, ... (PCG64 stream
+    of numpy.default_rng(seed)).
+    """
+    rng = np.random.default_rng(seed)
+    nf = n_species * n_radial * (max_moment + 1)
+    layout = param_layout(nf, hidden)
+    blocks = []
+    for _s in range(n_species):
+        for name, shape in layout:
+            if name.startswith("W"):
+                fan_in = shape[1]
+                blocks.append(rng.normal(0.0, 1.0 / math.sqrt(fan_in), size=shape).ravel() * weight_scale)
+            else:
+                blocks.append(np.zeros(shape, dtype=np.float64).ravel())
+    mu, eta = radial_grid(n_radial, rcut, r_min)
+    return ModelSpec(n_species=n_species, n_radial=n_radial, max_moment=max_moment, hidden=list(hidden),
+                     rcut=float(rcut), mu=mu, eta=eta, params=np.concatenate(blocks).astype(np.float64),
+                     activation=activation)
+
+
+def maxwell_boltzmann(masses_amu: np.ndarray, temperature_k: float, seed: int) -> np.ndarray:
+    """Velocities in A/fs with the centre-of-mass velocity removed (no rescale)."""
+    kb_ev = 8.617333262e-5
+    mvv2e = 103.6427  # amu*(A/fs)^2 -> eV
+    rng = np.random.default_rng(seed)
+    sd = np.sqrt(kb_ev * temperature_k / (mvv2e * masses_amu))[:, None]
+    v = rng.normal(0.0, 1.0, size=(masses_amu.shape[0], 3)) * sd
+    p = (masses_amu[:, None] * v).sum(0) / masses_amu.sum()
+    return v - p[None, :]
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (sizes of the paper-derived configurations)
+# ---------------------------------------------------------------------------
+
+def workload(name: str):
+    """(System, ModelSpec, skin) for a named workload.
+
+    oracle32   : 32-atom fcc (2x2x2, a=3.61), sigma 0.1, rc 5.0, K 8, M 3, MLP 64-64.
+    fcc32k     : 32,000-atom fcc (20^3, a=3.61), sigma 0.05, rc 6.0, K 8, M 3, MLP 64-64.
+    bcc1m      : 1,024,000-atom bcc alloy (80^3, a=3.16, 50/50), sigma 0.08, rc 6.0, K 12, M 3, 128-128.
+    bcc4k      : 4,096-atom sub-cell of the bcc alloy workload (16^3), own seed.
+    """
+    if name == "oracle32":
+        sysm = make_system("fcc", 3.61, (2, 2, 2), 0.1, 1, seed=0, masses=[63.546])
+        model = make_model(1, 8, 3, [64, 64], 5.0, seed=100)
+        return sysm, model, 0.0
+    if name == "fcc32k":
+        sysm = make_system("fcc", 3.61, (20, 20, 20), 0.05, 1, seed=1, masses=[63.546])
+        model = make_model(1, 8, 3, [64, 64], 6.0, seed=101)
+        return sysm, model, 0.0
+    if name == "bcc1m":
+        sysm = make_system("bcc", 3.16, (80, 80, 80), 0.08, 2, seed=2, masses=[183.84, 95.95])
+        model = make_model(2, 12, 3, [128, 128], 6.0, seed=102)
+        return sysm, model, 0.0
+    if name == "bcc4k":
+        sysm = make_system("bcc", 3.16, (16, 16, 16), 0.08, 2, seed=20, masses=[183.84, 95.95])
+        model = make_model(2, 12, 3, [128, 128], 6.0, seed=102)
+        return sysm, model, 0.0
+    raise KeyError(name)
