@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of one TensorMD energy+force step on one MI355X.
+
+A step is the whole hot path on one batch of synthetic input: on-device
+cell-list neighbour rebuild, descriptors, per-element MLP forward+backward,
+adjoint forces and virial, FP64 totals.  The workload is the 1,024,000-atom
+two-element bcc alloy (80^3 cells, a = 3.16 A, sigma = 0.08 A, rcut 6 A,
+K = 12, M = 3, MLP 96-128-128-1): value = ns/step/atom with the MLP in BF16
+on MFMA; the FP32 path is timed beside it.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ns/step/atom (E+F) at 1M atoms, BF16-MLP vs FP32; serving p50/p99 latency"
+PEAK_FP32_VECTOR_TFLOPS = 157.3     # published MI355X FP32 vector peak
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(spec, n_atoms: int, pairs: int) -> dict:
+    """Flops each kernel must perform by the method's definition (2 per FMA).
+
+    descriptor: P = sum_c h_k M_d          -> 2*K*D per pair
+    adjoint:    U = P' M and V = P' h       -> 4*K*D per pair
+    mlp:        forward 2*(F*H + (L-1)*H*H + H) + backward 2*((L-1)*H*H + H*F) per atom
+    """
+    K, M = spec.n_radial, spec.max_moment
+    D = (M + 1) * (M + 2) * (M + 3) // 6
+    F = spec.n_features
+    H = spec.hidden[0]
+    L = len(spec.hidden)
+    mlp = 2 * (F * H + (L - 1) * H * H + H) + 2 * ((L - 1) * H * H + H * F)
+    return {"descriptor": 2 * K * D * pairs, "adjoint": 4 * K * D * pairs, "mlp": mlp * n_atoms}
+
+
+def cpu_baseline(seconds: float) -> dict:
+    """The FP64 oracle (full E+F incl. its brute-force neighbour search) on the
+    4,096-atom sub-cell of the same alloy and model, repeated for ~`seconds`."""
+    import oracle
+    from paper_2310_08439_amd import inputs
+    s, spec, _ = inputs.workload("bcc4k")
+    oracle.lib()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.energy_forces(spec, s.pos, s.species, s.box)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": el / (reps * s.n) * 1e9, "unit": "ns/step/atom", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"full FP64 E+F (brute-force neighbours included) of the 4,096-atom bcc sub-cell with the "
+                      f"1M-atom workload's model, {reps} repetitions in {el:.1f} s"}
+
+
+def accuracy(tmd, ev, pos, sp, s, spec, n_sample: int, precision: int) -> dict:
+    """Sampled per-atom energy and force errors against the FP64 oracle."""
+    import numpy as np
+    import oracle
+    ev.model.set_precision(precision)
+    E, Ea, F, _ = ev.energy_forces(pos, sp, s.box)
+    sel = np.random.default_rng(1234).choice(s.n, n_sample, replace=False)
+    Ear, Fr = oracle.forces_subset(spec, s.pos, s.species, s.box, sel)
+    Ea = Ea.cpu().numpy().astype(np.float64)[sel]
+    Fg = F.cpu().numpy().astype(np.float64)[sel]
+    return {"sampled_atoms": int(n_sample), "max_abs_dE_atom_eV": float(np.abs(Ea - Ear).max()),
+            "force_rms_err_eV_per_A": float(math.sqrt(np.mean((Fg - Fr) ** 2))),
+            "force_rms_eV_per_A": float(math.sqrt(np.mean(Fr ** 2)))}
+
+
+def time_precision(tmd, torch, ev, pos, sp, box, precision, steps, warmup):
+    ev.model.set_precision(precision)
+    for _ in range(warmup):
+        ev.build(pos, sp, box)
+        ev.energy_forces(pos, sp, box, rebuild=False, atom_energy=False)
+    torch.cuda.synchronize()
+    ev.ctx.profile_reset()
+    ev.ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev.build(pos, sp, box)
+        E, _, F, W = ev.energy_forces(pos, sp, box, rebuild=False, atom_energy=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev.ctx.profile(False)
+    prof = ev.ctx.profile_read()
+    return (t1 - t0) / steps, prof, E
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bcc1m", choices=["bcc1m", "fcc32k", "bcc4k"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-samples", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the multi-GPU (spatial decomposition) path is a design, "
+              "not part of this build; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2310_08439_amd import inputs, tmd
+
+    s, spec, skin = inputs.workload(args.workload)
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    ev = tmd.Evaluator(spec, s.n, s.box, skin=skin, precision=tmd.BF16_MLP)
+    ev.build(pos, sp, s.box)
+    pairs, max_row = tmd.nlist_stats(ev.ctx, ev.nl)
+
+    res = {}
+    for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
+        sec, prof, E = time_precision(tmd, torch, ev, pos, sp, s.box, prec, args.steps, args.warmup)
+        res[name] = {"sec": sec, "prof": prof, "E": E}
+
+    flops = algorithmic_flops(spec, s.n, pairs)
+    prof = res["bf16"]["prof"]
+    avg_ms = {k: v[0] / v[1] for k, v in prof.items()}
+    dom = max(avg_ms, key=avg_ms.get)
+    if dom in flops:
+        if dom == "mlp":
+            bound, peak = "mfma", PEAK_BF16_MFMA_TFLOPS
+        else:
+            bound, peak = "alu", PEAK_FP32_VECTOR_TFLOPS
+        achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "algorithmic_flops_per_launch": int(flops[dom])}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None}
+
+    acc = {}
+    if args.accuracy_samples > 0:
+        for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
+            acc[name] = accuracy(tmd, ev, pos, sp, s, spec, args.accuracy_samples, prec)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    ns_bf16 = res["bf16"]["sec"] / s.n * 1e9
+    ns_fp32 = res["fp32"]["sec"] / s.n * 1e9
+    kernels = {}
+    for name in ("bf16", "fp32"):
+        kernels[name] = {k: round(v[0] / v[1], 4) for k, v in sorted(res[name]["prof"].items())}
+    line = {
+        "metric": METRIC,
+        "value": round(ns_bf16, 4),
+        "unit": "ns/step/atom",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["bf16"]["sec"] * 1e3, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mlp/fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {s.n} atoms, box {s.box[0]:.2f} A, rcut {spec.rcut}, "
+                               f"K {spec.n_radial}, M {spec.max_moment}, S {spec.n_species}, "
+                               f"MLP {spec.n_features}-{'-'.join(map(str, spec.hidden))}-1, neighbour rebuild each step",
+                   "atoms": s.n, "pairs": pairs, "max_row": max_row, "parallelism": "single GPU"},
+        "fp32": {"ns_per_step_atom": round(ns_fp32, 4), "ms_per_step": round(res["fp32"]["sec"] * 1e3, 4)},
+        "bf16_speedup_vs_fp32": round(ns_fp32 / ns_bf16, 4),
+        "energy_per_atom": {"bf16": res["bf16"]["E"] / s.n, "fp32": res["fp32"]["E"] / s.n},
+        "kernels_avg_ms": kernels,
+        "accuracy_vs_oracle": acc,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

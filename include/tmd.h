@@ -1,0 +1,191 @@
+/*
+ * tmd.h -- C ABI of libtmd.so: TensorMD energy, force and virial evaluation
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The computation follows the TensorMD paper (arXiv 2310.08439):
+ *   neighbour table of typed neighbours (Sec. III.A, the R_abc / D_abcx tensors)
+ *   -> radial functions H_abck times moment tensors M_abcd of the neighbour unit
+ *      vectors, contracted to G_abkm = sigma(T_dm (H_abck M_abcd)^2)
+ *      (Sec. III.A, eqns T_dm, tensor_formalism, sigma_function)
+ *   -> per-element MLP atomic energies E_a, E = sum_a E_a (Sec. III.A)
+ *   -> forces by the adjoint chain P', U, V, F1, F2 and ScatterSum
+ *      (Sec. III.A, eqns dP_abkd, U_abck, F1_abcx, F2_abcx), plus the virial.
+ *
+ * Conventions
+ *   Units: Angstrom, eV, amu, fs.
+ *   Boxes are orthorhombic and periodic in x, y and z.
+ *   Pair vector D = x_j + n*L - x_i (neighbour minus centre, n the periodic image).
+ *   Radial functions h_k(R) = exp(-eta_k (R - mu_k)^2) * f_c(R) with the cosine
+ *   cutoff f_c(R) = (cos(pi R / rcut) + 1)/2 for R < rcut and 0 beyond.
+ *   Descriptor feature index ((b*K + k)*(M+1) + m), b = species of the neighbour.
+ *   Virial W_ab = -sum over pairs of D_a dE/dD_b, reported as (xx, yy, zz, xy, xz, yz).
+ *
+ * Ownership
+ *   The caller owns every pointer argument; pointers marked "device" are HIP
+ *   device allocations (for instance torch tensors), pointers marked "host" are
+ *   host memory.  The library owns only the opaque handles and frees them in
+ *   the matching *_destroy.  No call keeps a caller pointer after it returns.
+ *   All device work is enqueued on the context's stream.  Calls that write a
+ *   host output synchronise that stream before returning.
+ *
+ * Errors
+ *   Every call returns a tmd_status; nothing throws across the ABI.
+ *   tmd_last_error(ctx) returns a message for the last failure on ctx.
+ *
+ * Threads
+ *   A context is used by one host thread at a time.
+ */
+#ifndef TMD_H
+#define TMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TMD_OK = 0,
+    TMD_ERR_INVALID_ARGUMENT = 1,  /* null pointer, bad size, species out of range, bad model shape */
+    TMD_ERR_CAPACITY = 2,          /* a neighbour list row would exceed the list capacity */
+    TMD_ERR_OUT_OF_MEMORY = 3,     /* device allocation failed */
+    TMD_ERR_DEVICE = 4,            /* a HIP runtime call failed */
+    TMD_ERR_NUMERICAL = 5,         /* non-finite position or two atoms at distance 0 */
+    TMD_ERR_NOT_READY = 6,         /* asynchronous result not available yet */
+    TMD_ERR_REJECTED = 7           /* request can never be admitted (larger than the budget) */
+} tmd_status;
+
+/* Arithmetic of the MLP stage.  Descriptors and the adjoint always run in
+ * FP32 and totals in FP64 (compensated). */
+typedef enum {
+    TMD_FP32 = 0,      /* MLP GEMMs on FP32 MFMA, FP32 accumulation */
+    TMD_BF16_MLP = 1   /* MLP GEMM operands rounded to BF16 (nearest-even), FP32 accumulation */
+} tmd_precision;
+
+typedef enum { TMD_ACT_TANH = 0, TMD_ACT_SQUAREPLUS = 1 } tmd_activation;
+
+typedef struct tmd_context tmd_context;
+typedef struct tmd_model tmd_model;
+typedef struct tmd_nlist tmd_nlist;
+
+/* One periodic system.  pos: device, [n_atoms][3] FP64; species: device,
+ * [n_atoms] int32 in [0, n_species). */
+typedef struct {
+    int64_t n_atoms;
+    const double* pos;
+    const int32_t* species;
+    double box[3];
+} tmd_system_view;
+
+#define TMD_MAX_HIDDEN 4
+
+/* Shape of a model (Sec. III.A and the tensor ranges of Table I).
+ *   n_species   S, 1..8 (the neighbour-species index b and the MLP selector)
+ *   n_radial    K, 4..128; K must be 4, 6 or 8 times a power of two
+ *   max_moment  M, 0..3 (D = 1, 4, 10, 20 moment components)
+ *   n_hidden    1..4 hidden layers, all of the same width hidden[0] in {32, 64, 128}
+ *   activation  tmd_activation of the hidden layers; the output layer is linear
+ *   rcut        cutoff radius (A), > 0
+ *   mu, eta     host, [K] FP64: Gaussian centres and widths of h_k. */
+typedef struct {
+    int32_t n_species;
+    int32_t n_radial;
+    int32_t max_moment;
+    int32_t n_hidden;
+    int32_t hidden[TMD_MAX_HIDDEN];
+    int32_t activation;
+    int32_t reserved;
+    double rcut;
+    const double* mu;
+    const double* eta;
+} tmd_model_spec;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL for the legacy default stream). */
+tmd_status tmd_context_create(int device, void* hip_stream, tmd_context** out);
+void tmd_context_destroy(tmd_context* ctx);
+/* Re-target the context at another stream of the same device. */
+tmd_status tmd_context_set_stream(tmd_context* ctx, void* hip_stream);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char* tmd_last_error(const tmd_context* ctx);
+
+/* Per-kernel timing.  While enabled, every kernel the context launches is
+ * bracketed by two HIP events on the context's stream.  tmd_profile_read
+ * synchronises, writes up to max_kernels entries (name[i] is a 32-byte
+ * NUL-terminated field of the host array names, total_ms[i] the summed
+ * duration, count[i] the number of launches) and returns the number of
+ * distinct kernels.  tmd_profile_reset clears the totals. */
+tmd_status tmd_profile_enable(tmd_context* ctx, int on);
+tmd_status tmd_profile_reset(tmd_context* ctx);
+int32_t tmd_profile_read(tmd_context* ctx, int32_t max_kernels, char* names, double* total_ms, int64_t* count);
+
+/* ---------------------------------------------------------------- model */
+
+/* Upload a model.  params: host FP32, per species in species order, each block
+ * laid out layer by layer as W_l row-major [out][in] followed by b_l [out],
+ * ending with the output layer w [1][hidden] and its bias [1].  Block length:
+ * sum_l (w_l * w_{l-1} + w_l) + hidden + 1 with w_0 = S*K*(M+1). */
+tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const float* params, tmd_model** out);
+/* Replace the weights of an existing model (same layout as tmd_model_create). */
+tmd_status tmd_model_set_params(tmd_model* model, const float* params);
+tmd_status tmd_model_set_precision(tmd_model* model, tmd_precision precision);
+/* Number of floats per species block of params. */
+int64_t tmd_model_params_per_species(const tmd_model* model);
+int32_t tmd_model_n_features(const tmd_model* model);
+void tmd_model_destroy(tmd_model* model);
+
+/* ---------------------------------------------------------------- neighbour list */
+
+/* A neighbour list for up to n_atoms atoms with room for `capacity`
+ * neighbours of each species per atom. */
+tmd_status tmd_nlist_create(tmd_context* ctx, int64_t n_atoms, int32_t n_species, int32_t capacity,
+                            tmd_nlist** out);
+void tmd_nlist_destroy(tmd_nlist* nl);
+
+/* Cell-list neighbour search under periodic boundaries (the binning search of
+ * Sec. IV.D).  Lists every (j, n) != (i, 0) with |x_j + n*L - x_i| < rcut + skin,
+ * evaluated in FP64 on positions wrapped into [0, L); periodic self-images are
+ * included.  On TMD_ERR_CAPACITY *required_capacity (host, may be NULL) is the
+ * smallest capacity that would fit; the list is then unusable.  Synchronises. */
+tmd_status tmd_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, double rcut, double skin,
+                               tmd_nlist* nl, int32_t* required_capacity);
+
+/* Copy the list out, in original atom numbering.  Device outputs:
+ * nbr [n][S][capacity] int32 (-1 padding), img [n][S][capacity][3] int32
+ * periodic image, cnt [n][S] int32 entries per neighbour species.
+ * Order within a row is unspecified. */
+tmd_status tmd_nlist_export(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt);
+int32_t tmd_nlist_capacity(const tmd_nlist* nl);
+
+/* Totals of the last build: *total_pairs (host) = number of list entries,
+ * *max_row (host) = longest per-species row.  Synchronises. */
+tmd_status tmd_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row);
+
+/* ---------------------------------------------------------------- evaluation */
+
+/* Descriptors G (device, [n][S*K*(M+1)] FP32, original atom order) for the
+ * positions in sys, using a list built by tmd_build_neighbors for the same
+ * atoms (positions may have moved by less than skin/2 since). */
+tmd_status tmd_descriptors(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
+                           const tmd_nlist* nl, float* G);
+
+/* Energy, forces and virial (Sec. III.A).  energy: host FP64 total (Neumaier-
+ * compensated sum of atomic energies); atom_energy: device [n] FP32 or NULL;
+ * forces: device [n][3] FP32 (F = -dE/dx); virial6: host FP64 [6] or NULL.
+ * Synchronises the stream. */
+tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
+                             const tmd_nlist* nl, double* energy, float* atom_energy, float* forces,
+                             double* virial6);
+
+/* Same as tmd_energy_forces but leaves the totals on the device and does not
+ * synchronise: totals7 is device FP64 [7] = (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz). */
+tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
+                                   const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMD_H */

@@ -1,0 +1,495 @@
+// C ABI of libtmd.so (declared in include/tmd.h): handle management, argument
+// validation and the order of the kernels on the context's stream.
+#include "tmd_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace tmd {
+
+void* Workspace::get(const std::string& key, size_t bytes, hipError_t* err) {
+    if (*err != hipSuccess) return nullptr;
+    bytes = std::max<size_t>(bytes, 256);
+    auto it = bufs.find(key);
+    if (it != bufs.end() && it->second.second >= bytes) return it->second.first;
+    if (it != bufs.end()) {
+        // the old buffer may still be read by queued work
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) { *err = e; return nullptr; }
+        (void)hipFree(it->second.first);
+        bufs.erase(it);
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    bufs[key] = {p, bytes};
+    return p;
+}
+
+void Workspace::release() {
+    for (auto& kv : bufs) (void)hipFree(kv.second.first);
+    bufs.clear();
+}
+
+hipEvent_t Profiler::get_event() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void Profiler::collect() {
+    for (auto& r : pending) {
+        float ms = 0.0f;
+        (void)hipEventSynchronize(r.stop);
+        (void)hipEventElapsedTime(&ms, r.start, r.stop);
+        size_t q = 0;
+        while (q < names.size() && names[q] != r.name) ++q;
+        if (q == names.size()) {
+            names.push_back(r.name);
+            total_ms.push_back(0.0);
+            count.push_back(0);
+        }
+        total_ms[q] += ms;
+        count[q] += 1;
+        pool.push_back(r.start);
+        pool.push_back(r.stop);
+    }
+    pending.clear();
+}
+
+void Profiler::release() {
+    collect();
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+tmd_status fail(tmd_context* ctx, tmd_status st, const std::string& msg) {
+    if (ctx) ctx->last_error = msg;
+    return st;
+}
+
+tmd_status hip_fail(tmd_context* ctx, hipError_t e, const char* what) {
+    const tmd_status st = (e == hipErrorOutOfMemory) ? TMD_ERR_OUT_OF_MEMORY : TMD_ERR_DEVICE;
+    return fail(ctx, st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+uint16_t float_to_bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40);  // NaN
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int choose_kc(int K) {
+    for (int kc : {8, 6, 4})
+        if (K % kc == 0 && is_pow2(K / kc) && K / kc <= 64) return kc;
+    return 0;
+}
+
+tmd_status upload_params(tmd_model* m, const float* params) {
+    tmd_context* ctx = m->ctx;
+    const int S = m->S, L = m->L, H = m->H, F = m->F, Fpad = m->Fpad;
+    std::vector<float> w32((size_t)S * m->w_species_stride, 0.0f);
+    std::vector<float> bias((size_t)S * L * H, 0.0f), wout((size_t)S * H, 0.0f), bout(S, 0.0f);
+    for (int s = 0; s < S; ++s) {
+        const float* p = params + (size_t)s * m->per_species;
+        float* ws = w32.data() + (size_t)s * m->w_species_stride;
+        int in = F;
+        for (int l = 0; l < L; ++l) {
+            const int in_pad = (l == 0) ? Fpad : H;
+            for (int o = 0; o < H; ++o)
+                for (int q = 0; q < in; ++q) {
+                    const float v = p[(size_t)o * in + q];
+                    ws[m->w_off[l] + (size_t)o * in_pad + q] = v;
+                    ws[m->wt_off[l] + (size_t)q * H + o] = v;
+                }
+            p += (size_t)H * in;
+            for (int o = 0; o < H; ++o) bias[((size_t)s * L + l) * H + o] = p[o];
+            p += H;
+            in = H;
+        }
+        for (int o = 0; o < H; ++o) wout[(size_t)s * H + o] = p[o];
+        bout[s] = p[H];
+    }
+    std::vector<uint16_t> wbf(w32.size());
+    for (size_t q = 0; q < w32.size(); ++q) wbf[q] = float_to_bf16_rne(w32[q]);
+    TMD_HIP(ctx, hipMemcpy(m->w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice));
+    TMD_HIP(ctx, hipMemcpy(m->wbf, wbf.data(), wbf.size() * 2, hipMemcpyHostToDevice));
+    TMD_HIP(ctx, hipMemcpy(m->bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
+    TMD_HIP(ctx, hipMemcpy(m->wout, wout.data(), wout.size() * 4, hipMemcpyHostToDevice));
+    TMD_HIP(ctx, hipMemcpy(m->bout, bout.data(), bout.size() * 4, hipMemcpyHostToDevice));
+    return TMD_OK;
+}
+
+tmd_status check_system(tmd_context* ctx, const tmd_system_view* sys) {
+    if (!sys || !sys->pos || !sys->species) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null system pointer");
+    if (sys->n_atoms <= 0) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_atoms must be positive");
+    if (sys->n_atoms >= (int64_t)1 << 31) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "more than 2^31-1 atoms");
+    for (int a = 0; a < 3; ++a)
+        if (!(sys->box[a] > 0.0) || !std::isfinite(sys->box[a]))
+            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "box edges must be positive and finite");
+    return TMD_OK;
+}
+
+tmd_status check_eval(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl) {
+    if (!m || !nl) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null model or neighbour list");
+    tmd_status st = check_system(ctx, sys);
+    if (st != TMD_OK) return st;
+    if (!nl->built) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "neighbour list has not been built");
+    if (nl->n != sys->n_atoms) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "neighbour list built for another atom count");
+    if (nl->S != m->S) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "neighbour list and model species counts differ");
+    for (int a = 0; a < 3; ++a)
+        if (nl->box[a] != sys->box[a])
+            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "box changed since the neighbour list was built");
+    if (nl->rlist < m->rcut) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "neighbour list cutoff below the model cutoff");
+    return TMD_OK;
+}
+
+struct EvalBuffers {
+    float *G, *dG, *Ei, *Fown, *Fin;
+    double *vir, *totals;
+};
+
+tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, EvalBuffers* b) {
+    const int64_t n = nl->n;
+    hipError_t e = hipSuccess;
+    b->G = (float*)ctx->ws.get("ev.G", sizeof(float) * n * m->F, &e);
+    b->dG = (float*)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
+    b->Ei = (float*)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
+    b->Fown = (float*)ctx->ws.get("ev.Fown", sizeof(float) * 3 * n, &e);
+    b->Fin = (float*)ctx->ws.get("ev.Fin", sizeof(float) * 3 * n, &e);
+    b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * 6 * (size_t)adjoint_blocks(m, nl), &e);
+    b->totals = (double*)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "evaluation workspace allocation");
+    return TMD_OK;
+}
+
+tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
+                             double* totals7_dev, float* atom_energy, float* forces) {
+    EvalBuffers b;
+    tmd_status st = eval_buffers(ctx, m, nl, &b);
+    if (st != TMD_OK) return st;
+    if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
+    if ((st = launch_descriptors(ctx, m, nl, b.G)) != TMD_OK) return st;
+    if ((st = launch_mlp(ctx, m, nl, b.G, b.Ei, b.dG)) != TMD_OK) return st;
+    TMD_HIP(ctx, hipMemsetAsync(b.Fin, 0, sizeof(float) * 3 * nl->n, ctx->stream));
+    int nvir = 0;
+    if ((st = launch_adjoint(ctx, m, nl, b.dG, b.Fown, b.Fin, b.vir, &nvir)) != TMD_OK) return st;
+    return launch_finalize(ctx, nl, b.Ei, b.Fown, b.Fin, b.vir, nvir, atom_energy, forces,
+                           totals7_dev ? totals7_dev : b.totals);
+}
+
+}  // namespace
+}  // namespace tmd
+
+using namespace tmd;
+
+extern "C" {
+
+tmd_status tmd_context_create(int device, void* hip_stream, tmd_context** out) {
+    if (!out) return TMD_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TMD_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return TMD_ERR_DEVICE;
+    tmd_context* ctx = new (std::nothrow) tmd_context();
+    if (!ctx) return TMD_ERR_OUT_OF_MEMORY;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipHostMalloc((void**)&ctx->h_totals, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_flags, sizeof(int32_t) * 64, hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return TMD_ERR_OUT_OF_MEMORY;
+    }
+    *out = ctx;
+    return TMD_OK;
+}
+
+void tmd_context_destroy(tmd_context* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->ws.release();
+    ctx->prof.release();
+    if (ctx->h_totals) (void)hipHostFree(ctx->h_totals);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    delete ctx;
+}
+
+tmd_status tmd_context_set_stream(tmd_context* ctx, void* hip_stream) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    ctx->stream = (hipStream_t)hip_stream;
+    return TMD_OK;
+}
+
+const char* tmd_last_error(const tmd_context* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+tmd_status tmd_profile_enable(tmd_context* ctx, int on) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    ctx->prof.on = on != 0;
+    return TMD_OK;
+}
+
+tmd_status tmd_profile_reset(tmd_context* ctx) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    ctx->prof.collect();
+    ctx->prof.names.clear();
+    ctx->prof.total_ms.clear();
+    ctx->prof.count.clear();
+    return TMD_OK;
+}
+
+int32_t tmd_profile_read(tmd_context* ctx, int32_t max_kernels, char* names, double* total_ms, int64_t* count) {
+    if (!ctx) return 0;
+    ctx->prof.collect();
+    const int32_t n = (int32_t)ctx->prof.names.size();
+    for (int32_t q = 0; q < n && q < max_kernels; ++q) {
+        if (names) {
+            std::memset(names + 32 * q, 0, 32);
+            std::strncpy(names + 32 * q, ctx->prof.names[q].c_str(), 31);
+        }
+        if (total_ms) total_ms[q] = ctx->prof.total_ms[q];
+        if (count) count[q] = ctx->prof.count[q];
+    }
+    return n;
+}
+
+tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const float* params, tmd_model** out) {
+    if (!ctx || !spec || !params || !out) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null argument");
+    *out = nullptr;
+    const int S = spec->n_species, K = spec->n_radial, M = spec->max_moment, L = spec->n_hidden;
+    if (S < 1 || S > kMaxSpecies) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_species must be in 1..8");
+    if (K < 4 || K > 128) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_radial must be in 4..128");
+    const int kc = choose_kc(K);
+    if (!kc) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_radial must be 4, 6 or 8 times a power of two");
+    if (M < 0 || M > 3) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "max_moment must be in 0..3");
+    if (L < 1 || L > TMD_MAX_HIDDEN) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_hidden must be in 1..4");
+    const int H = spec->hidden[0];
+    if (H != 32 && H != 64 && H != 128) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "hidden width must be 32, 64 or 128");
+    for (int l = 1; l < L; ++l)
+        if (spec->hidden[l] != H) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "all hidden layers must have one width");
+    if (spec->activation != TMD_ACT_TANH && spec->activation != TMD_ACT_SQUAREPLUS)
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "unknown activation");
+    if (!(spec->rcut > 0.0) || !std::isfinite(spec->rcut)) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "rcut must be positive");
+    if (!spec->mu || !spec->eta) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null mu or eta");
+    for (int k = 0; k < K; ++k)
+        if (!std::isfinite(spec->mu[k]) || !(spec->eta[k] >= 0.0))
+            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "mu must be finite and eta non-negative");
+    tmd_model* m = new (std::nothrow) tmd_model();
+    if (!m) return fail(ctx, TMD_ERR_OUT_OF_MEMORY, "host allocation");
+    m->ctx = ctx;
+    m->S = S;
+    m->K = K;
+    m->M = M;
+    m->D = (M + 1) * (M + 2) * (M + 3) / 6;
+    m->F = S * K * (M + 1);
+    m->Fpad = (m->F + 31) / 32 * 32;
+    m->L = L;
+    m->H = H;
+    m->act = spec->activation;
+    m->kc = kc;
+    m->rcut = spec->rcut;
+    int64_t per = 0;
+    int in = m->F;
+    for (int l = 0; l < L; ++l) {
+        per += (int64_t)H * in + H;
+        in = H;
+    }
+    m->per_species = per + H + 1;
+    int64_t off = 0;
+    m->w_off.resize(L);
+    m->wt_off.resize(L);
+    for (int l = 0; l < L; ++l) {
+        const int in_pad = (l == 0) ? m->Fpad : H;
+        m->w_off[l] = off;
+        off += (int64_t)H * in_pad;
+        m->wt_off[l] = off;
+        off += (int64_t)H * in_pad;
+    }
+    m->w_species_stride = off;
+    std::vector<float> mu(K), eta(K);
+    for (int k = 0; k < K; ++k) {
+        mu[k] = (float)spec->mu[k];
+        eta[k] = (float)spec->eta[k];
+    }
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    };
+    alloc((void**)&m->mu, 4 * K);
+    alloc((void**)&m->eta, 4 * K);
+    alloc((void**)&m->w32, 4 * (size_t)S * off);
+    alloc((void**)&m->wbf, 2 * (size_t)S * off);
+    alloc((void**)&m->bias, 4 * (size_t)S * L * H);
+    alloc((void**)&m->wout, 4 * (size_t)S * H);
+    alloc((void**)&m->bout, 4 * (size_t)S);
+    if (e == hipSuccess) e = hipMemcpy(m->mu, mu.data(), 4 * K, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->eta, eta.data(), 4 * K, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        tmd_model_destroy(m);
+        return hip_fail(ctx, e, "model allocation");
+    }
+    tmd_status st = upload_params(m, params);
+    if (st != TMD_OK) {
+        tmd_model_destroy(m);
+        return st;
+    }
+    *out = m;
+    return TMD_OK;
+}
+
+tmd_status tmd_model_set_params(tmd_model* m, const float* params) {
+    if (!m || !params) return TMD_ERR_INVALID_ARGUMENT;
+    TMD_HIP(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    return upload_params(m, params);
+}
+
+tmd_status tmd_model_set_precision(tmd_model* m, tmd_precision precision) {
+    if (!m) return TMD_ERR_INVALID_ARGUMENT;
+    if (precision != TMD_FP32 && precision != TMD_BF16_MLP)
+        return fail(m->ctx, TMD_ERR_INVALID_ARGUMENT, "unknown precision");
+    m->prec = precision;
+    return TMD_OK;
+}
+
+int64_t tmd_model_params_per_species(const tmd_model* m) { return m ? m->per_species : 0; }
+int32_t tmd_model_n_features(const tmd_model* m) { return m ? m->F : 0; }
+
+void tmd_model_destroy(tmd_model* m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : {(void*)m->mu, (void*)m->eta, (void*)m->w32, (void*)m->wbf, (void*)m->bias, (void*)m->wout,
+                    (void*)m->bout})
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+tmd_status tmd_nlist_create(tmd_context* ctx, int64_t n_atoms, int32_t n_species, int32_t capacity,
+                            tmd_nlist** out) {
+    if (!ctx || !out) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null argument");
+    *out = nullptr;
+    if (n_atoms <= 0 || n_atoms >= ((int64_t)1 << 31)) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "bad n_atoms");
+    if (n_species < 1 || n_species > kMaxSpecies) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_species must be in 1..8");
+    if (capacity < 1 || capacity > 4096) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "capacity must be in 1..4096");
+    tmd_nlist* nl = new (std::nothrow) tmd_nlist();
+    if (!nl) return fail(ctx, TMD_ERR_OUT_OF_MEMORY, "host allocation");
+    nl->ctx = ctx;
+    nl->nmax = n_atoms;
+    nl->S = n_species;
+    nl->cap = capacity;
+    const size_t n = (size_t)n_atoms, lst = (size_t)n_species * capacity * n;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    };
+    alloc((void**)&nl->perm, 4 * n);
+    alloc((void**)&nl->shift, 12 * n);
+    alloc((void**)&nl->xs, 32 * n);
+    alloc((void**)&nl->sp, 4 * n);
+    alloc((void**)&nl->nbr, 4 * lst);
+    alloc((void**)&nl->img, 4 * lst);
+    alloc((void**)&nl->cnt, 4 * (size_t)n_species * n);
+    alloc((void**)&nl->sp_idx, 4 * n);
+    if (e != hipSuccess) {
+        tmd_nlist_destroy(nl);
+        return hip_fail(ctx, e, "neighbour list allocation");
+    }
+    *out = nl;
+    return TMD_OK;
+}
+
+void tmd_nlist_destroy(tmd_nlist* nl) {
+    if (!nl) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : {(void*)nl->perm, (void*)nl->shift, (void*)nl->xs, (void*)nl->sp, (void*)nl->nbr, (void*)nl->img,
+                    (void*)nl->cnt, (void*)nl->sp_idx})
+        if (p) (void)hipFree(p);
+    delete nl;
+}
+
+int32_t tmd_nlist_capacity(const tmd_nlist* nl) { return nl ? nl->cap : 0; }
+
+tmd_status tmd_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    if (!nl || !nl->built) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "neighbour list has not been built");
+    return launch_nlist_stats(ctx, nl, total_pairs, max_row);
+}
+
+tmd_status tmd_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, double rcut, double skin, tmd_nlist* nl,
+                               int32_t* required_capacity) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    if (!nl) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null neighbour list");
+    tmd_status st = check_system(ctx, sys);
+    if (st != TMD_OK) return st;
+    if (sys->n_atoms > nl->nmax) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "more atoms than the list was created for");
+    if (!(rcut > 0.0) || !std::isfinite(rcut)) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "rcut must be positive");
+    if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "skin must be non-negative");
+    nl->built = false;
+    return launch_build_neighbors(ctx, sys, rcut + skin, nl, required_capacity);
+}
+
+tmd_status tmd_nlist_export(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    if (!nl || !nbr || !img || !cnt) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null argument");
+    if (!nl->built) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "neighbour list has not been built");
+    return launch_export_nlist(ctx, nl, nbr, img, cnt);
+}
+
+tmd_status tmd_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
+                           float* G) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    tmd_status st = check_eval(ctx, m, sys, nl);
+    if (st != TMD_OK) return st;
+    if (!G) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null G");
+    hipError_t e = hipSuccess;
+    float* Gs = (float*)ctx->ws.get("ev.G", sizeof(float) * nl->n * m->F, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "descriptor workspace");
+    if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
+    if ((st = launch_descriptors(ctx, m, nl, Gs)) != TMD_OK) return st;
+    return launch_permute_rows(ctx, nl, Gs, m->F, G);
+}
+
+tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
+                             double* energy, float* atom_energy, float* forces, double* virial6) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    tmd_status st = check_eval(ctx, m, sys, nl);
+    if (st != TMD_OK) return st;
+    if (!energy || !forces) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null energy or forces");
+    hipError_t e = hipSuccess;
+    double* tot = (double*)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "totals workspace");
+    if ((st = run_energy_forces(ctx, m, sys, nl, tot, atom_energy, forces)) != TMD_OK) return st;
+    TMD_HIP(ctx, hipMemcpyAsync(ctx->h_totals, tot, sizeof(double) * 7, hipMemcpyDeviceToHost, ctx->stream));
+    TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *energy = ctx->h_totals[0];
+    if (virial6)
+        for (int j = 0; j < 6; ++j) virial6[j] = ctx->h_totals[1 + j];
+    return TMD_OK;
+}
+
+tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys,
+                                   const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    tmd_status st = check_eval(ctx, m, sys, nl);
+    if (st != TMD_OK) return st;
+    if (!totals7 || !forces) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null totals or forces");
+    return run_energy_forces(ctx, m, sys, nl, totals7, atom_energy, forces);
+}
+
+}  // extern "C"

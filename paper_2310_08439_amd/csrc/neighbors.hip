@@ -1,0 +1,486 @@
+// Cell-list neighbour search under periodic boundary conditions.
+//
+// The paper updates its neighbour table with a binning method (Sec. IV.D) and
+// stores it as the padded, per-pair-type tensor R_abc with a mask (Sec. III.A).
+// Here the table is kept per neighbour species b as a column-major padded list
+// nbr[b][c][atom] (atom fastest, so a wave of consecutive atoms reads one
+// contiguous segment per neighbour slot) with a count per (b, atom) in place of
+// the mask.  Atoms are renumbered in cell-major order so that the atoms a wave
+// visits are spatially close and their neighbours share cache lines.
+//
+// Inclusion predicate (evaluated in FP64, every operation separately rounded):
+//   w = x - L*floor(x/L) (then folded into [0, L)),
+//   d = (w_j - w_i) + n*L per component, d2 = dx*dx + dy*dy + dz*dz,
+//   keep (j, n) != (i, 0) when d2 < rlist*rlist.
+#include "tmd_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace tmd {
+namespace {
+
+constexpr int kErrNonFinite = 1;
+constexpr int kErrSpecies = 2;
+constexpr int kErrCoincident = 4;
+
+__device__ inline double wrap_exact(double x, double L) {
+    double w = __dsub_rn(x, __dmul_rn(L, floor(__ddiv_rn(x, L))));
+    if (w < 0.0) w = __dadd_rn(w, L);
+    if (w >= L) w = __dsub_rn(w, L);
+    return w;
+}
+
+__device__ inline int cell_coord(double w, double inv_cw, int nc) {
+    int c = (int)(w * inv_cw);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+struct GridArgs {
+    double L[3];
+    double inv_cw[3];
+    int nc[3];
+    int reach[3];
+};
+
+__global__ void k_bin(int64_t n, const double* __restrict__ pos, const int32_t* __restrict__ species, int S,
+                      GridArgs g, double* __restrict__ wpos, int32_t* __restrict__ cell_of,
+                      int32_t* __restrict__ cellcount, int32_t* __restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c[3];
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * i + a];
+        if (!isfinite(x)) { bad = true; x = 0.0; }
+        double w = wrap_exact(x, g.L[a]);
+        wpos[3 * i + a] = w;
+        c[a] = cell_coord(w, g.inv_cw[a], g.nc[a]);
+    }
+    if (bad) atomicOr(&flags[0], kErrNonFinite);
+    int s = species[i];
+    if (s < 0 || s >= S) atomicOr(&flags[0], kErrSpecies);
+    int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+    cell_of[i] = cell;
+    atomicAdd(&cellcount[cell], 1);
+}
+
+// Exclusive scan of the cell counts by one block (cells are few: about N/14).
+__global__ void __launch_bounds__(1024) k_scan_cells(int64_t ncells, const int32_t* __restrict__ count,
+                                                     int32_t* __restrict__ start) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (ncells + 1023) / 1024;
+    const int64_t lo = t * per, hi = min<int64_t>(ncells, lo + per);
+    int32_t s = 0;
+    for (int64_t q = lo; q < hi; ++q) s += count[q];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - s;
+    for (int64_t q = lo; q < hi; ++q) {
+        start[q] = run;
+        run += count[q];
+    }
+    if (t == 1023) start[ncells] = part[1023];
+}
+
+__global__ void k_place(int64_t n, const int32_t* __restrict__ cell_of, const int32_t* __restrict__ start,
+                        int32_t* __restrict__ fill, int32_t* __restrict__ order) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cell = cell_of[i];
+    int slot = start[cell] + atomicAdd(&fill[cell], 1);
+    order[slot] = (int32_t)i;
+}
+
+// Insertion sort of each cell's atoms by original index: a deterministic order
+// independent of the atomic placement above.
+__global__ void k_sort_cells(int64_t ncells, const int32_t* __restrict__ start, int32_t* __restrict__ order) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int lo = start[c], hi = start[c + 1];
+    for (int a = lo + 1; a < hi; ++a) {
+        int32_t v = order[a];
+        int b = a - 1;
+        while (b >= lo && order[b] > v) {
+            order[b + 1] = order[b];
+            --b;
+        }
+        order[b + 1] = v;
+    }
+}
+
+__global__ void k_gather_sorted(int64_t n, const int32_t* __restrict__ order, const double* __restrict__ wpos,
+                                const double* __restrict__ pos, const int32_t* __restrict__ species, GridArgs g,
+                                int32_t* __restrict__ perm, int32_t* __restrict__ shift, double4* __restrict__ xs,
+                                int32_t* __restrict__ sp, int32_t* __restrict__ cell_sorted,
+                                const int32_t* __restrict__ cell_of, int32_t* __restrict__ spcount) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < n;
+    int s = -1;
+    if (valid) {
+        const int32_t i = order[p];
+        perm[p] = i;
+        double w[3];
+        for (int a = 0; a < 3; ++a) {
+            w[a] = wpos[3 * i + a];
+            double x = pos[3 * i + a];
+            double k = isfinite(x) ? rint((w[a] - x) / g.L[a]) : 0.0;
+            shift[3 * p + a] = (int32_t)k;
+        }
+        xs[p] = make_double4(w[0], w[1], w[2], 0.0);
+        s = species[i];
+        sp[p] = s;
+        cell_sorted[p] = cell_of[i];
+    }
+    // per-species counts: one atomic per wave and species (invalid species
+    // fail the build on the host and are not counted)
+    const int lane = threadIdx.x & 63;
+    for (int b = 0; b < kMaxSpecies; ++b) {
+        const unsigned long long m = __ballot(s == b);
+        if (m && lane == 0) atomicAdd(&spcount[b], (int)__popcll(m));
+    }
+}
+
+struct FillArgs {
+    GridArgs g;
+    int64_t n;
+    int S, cap;
+    double rl2;
+    const double4* xs;
+    const int32_t* sp;
+    const int32_t* cell_sorted;
+    const int32_t* cellstart;
+    int32_t* nbr;
+    int32_t* img;
+    int32_t* cnt;
+    int32_t* flags;
+};
+
+__device__ inline int floor_div(int a, int b) {
+    int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// One thread per atom (cell-major order): scan the stencil of cells within
+// `reach` (periodic images folded in), append accepted neighbours to the
+// list of their species.
+__global__ void __launch_bounds__(256) k_fill(FillArgs a) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const GridArgs& g = a.g;
+    const double4 xi = a.xs[p];
+    const int cell = a.cell_sorted[p];
+    const int cx = cell % g.nc[0];
+    const int cy = (cell / g.nc[0]) % g.nc[1];
+    const int cz = cell / (g.nc[0] * g.nc[1]);
+    int cnt[kMaxSpecies];
+#pragma unroll
+    for (int b = 0; b < kMaxSpecies; ++b) cnt[b] = 0;
+    bool coincident = false;
+    for (int oz = -g.reach[2]; oz <= g.reach[2]; ++oz) {
+        const int zz = cz + oz;
+        const int nz = floor_div(zz, g.nc[2]);
+        const int wz = zz - nz * g.nc[2];
+        const double sz = __dmul_rn((double)nz, g.L[2]);
+        for (int oy = -g.reach[1]; oy <= g.reach[1]; ++oy) {
+            const int yy = cy + oy;
+            const int ny = floor_div(yy, g.nc[1]);
+            const int wy = yy - ny * g.nc[1];
+            const double sy = __dmul_rn((double)ny, g.L[1]);
+            for (int ox = -g.reach[0]; ox <= g.reach[0]; ++ox) {
+                const int xx = cx + ox;
+                const int nx = floor_div(xx, g.nc[0]);
+                const int wx = xx - nx * g.nc[0];
+                const double sx = __dmul_rn((double)nx, g.L[0]);
+                const int c2 = (wz * g.nc[1] + wy) * g.nc[0] + wx;
+                const int lo = a.cellstart[c2], hi = a.cellstart[c2 + 1];
+                const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
+                for (int q = lo; q < hi; ++q) {
+                    if (zero_img && q == p) continue;
+                    const double4 xj = a.xs[q];
+                    const double dx = __dadd_rn(__dsub_rn(xj.x, xi.x), sx);
+                    const double dy = __dadd_rn(__dsub_rn(xj.y, xi.y), sy);
+                    const double dz = __dadd_rn(__dsub_rn(xj.z, xi.z), sz);
+                    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+                    if (!(d2 < a.rl2)) continue;
+                    if (d2 == 0.0) coincident = true;
+                    const int b = a.sp[q];
+                    if (b < 0 || b >= a.S) continue;  // reported by k_bin; never index with it
+                    int k = 0;
+#pragma unroll
+                    for (int bb = 0; bb < kMaxSpecies; ++bb)
+                        if (bb == b) { k = cnt[bb]; cnt[bb] = k + 1; }
+                    if (k < a.cap) {
+                        const int64_t off = ((int64_t)b * a.cap + k) * a.n + p;
+                        a.nbr[off] = q;
+                        a.img[off] = pack_img(nx, ny, nz);
+                    }
+                }
+            }
+        }
+    }
+    int mx = 0;
+#pragma unroll
+    for (int b = 0; b < kMaxSpecies; ++b) {
+        if (b < a.S) a.cnt[(int64_t)b * a.n + p] = min(cnt[b], a.cap);
+        mx = max(mx, cnt[b]);
+    }
+    if (mx > a.cap) atomicMax(&a.flags[1], mx);
+    if (coincident) atomicOr(&a.flags[0], kErrCoincident);
+}
+
+__global__ void k_species_place(int64_t n, const int32_t* __restrict__ sp, const int64_t* __restrict__ sp_off,
+                                int32_t* __restrict__ sp_fill, int32_t* __restrict__ sp_idx) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = p < n ? sp[p] : -1;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // one atomic per wave and species reserves the slots; lanes take them in lane order
+    for (int b = 0; b < kMaxSpecies; ++b) {
+        const unsigned long long m = __ballot(s == b);
+        if (!m) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&sp_fill[b], (int)__popcll(m));
+        base = __shfl(base, 0);
+        if (s == b) sp_idx[sp_off[b] + base + (int)__popcll(m & below)] = (int32_t)p;
+    }
+}
+
+__global__ void k_export(int64_t n, int S, int cap, const int32_t* __restrict__ perm, const int32_t* __restrict__ nbr,
+                         const int32_t* __restrict__ img, const int32_t* __restrict__ cnt, int32_t* __restrict__ onbr,
+                         int32_t* __restrict__ oimg, int32_t* __restrict__ ocnt) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = perm[p];
+    for (int b = 0; b < S; ++b) {
+        const int c = cnt[(int64_t)b * n + p];
+        ocnt[i * S + b] = c;
+        for (int k = 0; k < cap; ++k) {
+            const int64_t src = ((int64_t)b * cap + k) * n + p;
+            const int64_t dst = (i * S + b) * cap + k;
+            if (k < c) {
+                onbr[dst] = perm[nbr[src]];
+                int nx, ny, nz;
+                unpack_img(img[src], nx, ny, nz);
+                oimg[3 * dst] = nx;
+                oimg[3 * dst + 1] = ny;
+                oimg[3 * dst + 2] = nz;
+            } else {
+                onbr[dst] = -1;
+                oimg[3 * dst] = oimg[3 * dst + 1] = oimg[3 * dst + 2] = 0;
+            }
+        }
+    }
+}
+
+__global__ void k_refresh(int64_t n, const double* __restrict__ pos, const int32_t* __restrict__ perm,
+                          const int32_t* __restrict__ shift, double L0, double L1, double L2,
+                          double4* __restrict__ xs) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = perm[p];
+    const double x = pos[3 * i] + (double)shift[3 * p] * L0;
+    const double y = pos[3 * i + 1] + (double)shift[3 * p + 1] * L1;
+    const double z = pos[3 * i + 2] + (double)shift[3 * p + 2] * L2;
+    xs[p] = make_double4(x, y, z, 0.0);
+}
+
+__global__ void k_count_stats(int64_t total, const int32_t* __restrict__ cnt, unsigned long long* __restrict__ sum,
+                              int32_t* __restrict__ mx) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = q < total ? cnt[q] : 0;
+    int s = v, m = v;
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        m = max(m, __shfl_xor(m, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(sum, (unsigned long long)s);
+        atomicMax(mx, m);
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, double rlist, tmd_nlist* nl,
+                                  int32_t* required_capacity) {
+    const int64_t n = sys->n_atoms;
+    GridArgs g;
+    int64_t ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double L = sys->box[a];
+        int nc = (int)std::floor(L / (rlist * (1.0 + 1e-9)));
+        nc = std::max(1, std::min(nc, 1 << 20));
+        g.L[a] = L;
+        g.nc[a] = nc;
+        ncells *= nc;
+    }
+    // Keep the cell count proportional to the atom count (sparse boxes).
+    const int64_t max_cells = std::max<int64_t>(64, 4 * n);
+    while (ncells > max_cells) {
+        int a = 0;
+        for (int b = 1; b < 3; ++b)
+            if (g.nc[b] > g.nc[a]) a = b;
+        ncells /= g.nc[a];
+        g.nc[a] = std::max(1, g.nc[a] / 2);
+        ncells *= g.nc[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        g.inv_cw[a] = (double)g.nc[a] / g.L[a];
+        g.reach[a] = g.nc[a] == 1 ? (int)std::ceil(rlist / g.L[a]) : 1;
+        if (g.reach[a] > 100)
+            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "box edge far smaller than the cutoff");
+    }
+    hipError_t e = hipSuccess;
+    double* wpos = (double*)ctx->ws.get("nb.wpos", sizeof(double) * 3 * n, &e);
+    int32_t* cell_of = (int32_t*)ctx->ws.get("nb.cell_of", sizeof(int32_t) * n, &e);
+    int32_t* cell_sorted = (int32_t*)ctx->ws.get("nb.cell_sorted", sizeof(int32_t) * n, &e);
+    int32_t* order = (int32_t*)ctx->ws.get("nb.order", sizeof(int32_t) * n, &e);
+    int32_t* cellcount = (int32_t*)ctx->ws.get("nb.cellcount", sizeof(int32_t) * (ncells + 1), &e);
+    int32_t* cellfill = (int32_t*)ctx->ws.get("nb.cellfill", sizeof(int32_t) * (ncells + 1), &e);
+    int32_t* cellstart = (int32_t*)ctx->ws.get("nb.cellstart", sizeof(int32_t) * (ncells + 1), &e);
+    int32_t* flags = (int32_t*)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
+    int64_t* sp_off_d = (int64_t*)ctx->ws.get("nb.sp_off", sizeof(int64_t) * (kMaxSpecies + 1), &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "neighbour workspace allocation");
+    hipStream_t st = ctx->stream;
+    int32_t* spcount = flags + 8;
+    int32_t* spfill = flags + 24;
+    TMD_HIP(ctx, hipMemsetAsync(cellcount, 0, sizeof(int32_t) * (ncells + 1), st));
+    TMD_HIP(ctx, hipMemsetAsync(cellfill, 0, sizeof(int32_t) * (ncells + 1), st));
+    TMD_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 64, st));
+
+    {
+        ProfScope ps_(ctx, "nb_bin");
+        k_bin<<<grid_for(n), kBlock, 0, st>>>(n, sys->pos, sys->species, nl->S, g, wpos, cell_of, cellcount, flags);
+    }
+    {
+        ProfScope ps_(ctx, "nb_scan");
+        k_scan_cells<<<1, 1024, 0, st>>>(ncells, cellcount, cellstart);
+    }
+    {
+        ProfScope ps_(ctx, "nb_place");
+        k_place<<<grid_for(n), kBlock, 0, st>>>(n, cell_of, cellstart, cellfill, order);
+    }
+    {
+        ProfScope ps_(ctx, "nb_sort");
+        k_sort_cells<<<grid_for(ncells), kBlock, 0, st>>>(ncells, cellstart, order);
+    }
+    {
+        ProfScope ps_(ctx, "nb_gather");
+        k_gather_sorted<<<grid_for(n), kBlock, 0, st>>>(n, order, wpos, sys->pos, sys->species, g, nl->perm, nl->shift,
+                                                         nl->xs, nl->sp, cell_sorted, cell_of, spcount);
+    }
+    FillArgs fa;
+    fa.g = g;
+    fa.n = n;
+    fa.S = nl->S;
+    fa.cap = nl->cap;
+    fa.rl2 = rlist * rlist;
+    fa.xs = nl->xs;
+    fa.sp = nl->sp;
+    fa.cell_sorted = cell_sorted;
+    fa.cellstart = cellstart;
+    fa.nbr = nl->nbr;
+    fa.img = nl->img;
+    fa.cnt = nl->cnt;
+    fa.flags = flags;
+    {
+        ProfScope ps_(ctx, "nb_fill");
+        k_fill<<<grid_for(n), kBlock, 0, st>>>(fa);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, flags, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, st));
+    TMD_HIP(ctx, hipStreamSynchronize(st));
+    const int32_t errs = ctx->h_flags[0];
+    if (errs & kErrSpecies) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "species index outside [0, n_species)");
+    if (errs & kErrNonFinite) return fail(ctx, TMD_ERR_NUMERICAL, "non-finite atomic position");
+    if (errs & kErrCoincident) return fail(ctx, TMD_ERR_NUMERICAL, "two atoms at distance zero");
+    const int32_t need = ctx->h_flags[1];
+    if (need > nl->cap) {
+        if (required_capacity) *required_capacity = need;
+        nl->built = false;
+        return fail(ctx, TMD_ERR_CAPACITY, "neighbour list capacity " + std::to_string(nl->cap) +
+                                               " too small; need " + std::to_string(need));
+    }
+    if (required_capacity) *required_capacity = need;
+    int64_t off = 0;
+    for (int s = 0; s < nl->S; ++s) {
+        nl->sp_count[s] = ctx->h_flags[8 + s];
+        nl->sp_off[s] = off;
+        off += nl->sp_count[s];
+    }
+    nl->sp_off[nl->S] = off;
+    TMD_HIP(ctx, hipMemcpyAsync(sp_off_d, nl->sp_off, sizeof(int64_t) * (kMaxSpecies + 1), hipMemcpyHostToDevice, st));
+    {
+        ProfScope ps_(ctx, "nb_species");
+        k_species_place<<<grid_for(n), kBlock, 0, st>>>(n, nl->sp, sp_off_d, spfill, nl->sp_idx);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    // sp_off_d is read by the kernel above before any later host write to it
+    TMD_HIP(ctx, hipStreamSynchronize(st));
+    nl->n = n;
+    nl->rlist = rlist;
+    for (int a = 0; a < 3; ++a) {
+        nl->box[a] = sys->box[a];
+        nl->nc[a] = g.nc[a];
+        nl->reach[a] = g.reach[a];
+    }
+    nl->built = true;
+    return TMD_OK;
+}
+
+tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl) {
+    const int64_t n = nl->n;
+    {
+        ProfScope ps_(ctx, "refresh");
+        k_refresh<<<grid_for(n), kBlock, 0, ctx->stream>>>(n, sys->pos, nl->perm, nl->shift, sys->box[0], sys->box[1],
+                                                            sys->box[2], nl->xs);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
+}
+
+tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row) {
+    hipError_t e = hipSuccess;
+    void* buf = ctx->ws.get("nb.stats", 64, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stats workspace");
+    unsigned long long* sum = (unsigned long long*)buf;
+    int32_t* mx = (int32_t*)((char*)buf + 8);
+    const int64_t total = (int64_t)nl->S * nl->n;
+    TMD_HIP(ctx, hipMemsetAsync(buf, 0, 16, ctx->stream));
+    {
+        ProfScope ps_(ctx, "nb_stats");
+        k_count_stats<<<grid_for(total), kBlock, 0, ctx->stream>>>(total, nl->cnt, sum, mx);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, buf, 16, hipMemcpyDeviceToHost, ctx->stream));
+    TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long s;
+    std::memcpy(&s, ctx->h_flags, 8);
+    if (total_pairs) *total_pairs = (int64_t)s;
+    if (max_row) *max_row = ctx->h_flags[2];
+    return TMD_OK;
+}
+
+tmd_status launch_export_nlist(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt) {
+    const int64_t n = nl->n;
+    {
+        ProfScope ps_(ctx, "nb_export");
+        k_export<<<grid_for(n), kBlock, 0, ctx->stream>>>(n, nl->S, nl->cap, nl->perm, nl->nbr, nl->img, nl->cnt, nbr,
+                                                           img, cnt);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
+}
+
+}  // namespace tmd

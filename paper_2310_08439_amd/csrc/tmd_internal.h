@@ -1,0 +1,165 @@
+// Internal declarations of libtmd.so: handle layouts, kernel launch entry
+// points and small device helpers.  Not part of the public ABI (include/tmd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tmd.h"
+
+namespace tmd {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kBlock = 256;
+
+// Grow-only device buffers owned by a context, keyed by purpose.
+struct Workspace {
+    std::unordered_map<std::string, std::pair<void*, size_t>> bufs;
+    void* get(const std::string& key, size_t bytes, hipError_t* err);
+    void release();
+};
+
+}  // namespace tmd
+
+namespace tmd {
+// Optional per-kernel timing with HIP events recorded on the context's stream.
+struct ProfRec {
+    const char* name;
+    hipEvent_t start, stop;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::string> names;
+    std::vector<double> total_ms;
+    std::vector<int64_t> count;
+    hipEvent_t get_event();
+    void collect();  // synchronises on the pending events
+    void release();
+};
+}  // namespace tmd
+
+struct tmd_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    tmd::Workspace ws;
+    tmd::Profiler prof;
+    double* h_totals = nullptr;  // pinned host [8]
+    int32_t* h_flags = nullptr;  // pinned host [64]
+};
+
+namespace tmd {
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+    tmd_context* ctx;
+    ProfRec rec{};
+    ProfScope(tmd_context* c, const char* name) : ctx(c) {
+        if (!ctx->prof.on) return;
+        rec.name = name;
+        rec.start = ctx->prof.get_event();
+        rec.stop = ctx->prof.get_event();
+        (void)hipEventRecord(rec.start, ctx->stream);
+    }
+    ~ProfScope() {
+        if (!ctx->prof.on || !rec.name) return;
+        (void)hipEventRecord(rec.stop, ctx->stream);
+        ctx->prof.pending.push_back(rec);
+    }
+};
+}  // namespace tmd
+
+struct tmd_model {
+    tmd_context* ctx = nullptr;
+    int S = 0, K = 0, M = 0, D = 0, F = 0, Fpad = 0, L = 0, H = 0, act = 0;
+    int kc = 8;  // radial functions per thread in the descriptor / adjoint kernels
+    double rcut = 0.0;
+    tmd_precision prec = TMD_FP32;
+    int64_t per_species = 0;  // floats per species in the ABI parameter layout
+    // device parameters
+    float* mu = nullptr;   // [K]
+    float* eta = nullptr;  // [K]
+    // Per species, per layer l = 0..L-1: forward W_l [H][in_pad] and transposed
+    // W_l^T [in_pad][H] (in_pad = Fpad for l = 0, H otherwise), FP32 and BF16 copies.
+    float* w32 = nullptr;
+    __hip_bfloat16* wbf = nullptr;
+    int64_t w_species_stride = 0;         // elements per species in w32 / wbf
+    std::vector<int64_t> w_off, wt_off;   // per layer offsets inside a species block
+    float* bias = nullptr;   // [S][L][H]
+    float* wout = nullptr;   // [S][H]
+    float* bout = nullptr;   // [S]
+};
+
+struct tmd_nlist {
+    tmd_context* ctx = nullptr;
+    int64_t nmax = 0;
+    int S = 1;
+    int cap = 0;
+    // state of the last successful build
+    int64_t n = 0;
+    bool built = false;
+    double box[3] = {0, 0, 0};
+    double rlist = 0.0;
+    int nc[3] = {1, 1, 1};
+    int reach[3] = {1, 1, 1};
+    int64_t sp_count[tmd::kMaxSpecies] = {0};
+    int64_t sp_off[tmd::kMaxSpecies + 1] = {0};
+    // device arrays, sorted (cell-major) atom order
+    int32_t* perm = nullptr;     // [n]   sorted -> original index
+    int32_t* shift = nullptr;    // [n][3] wrap shift: x_wrapped = x + shift * L
+    double4* xs = nullptr;       // [n]   positions used by the kernels
+    int32_t* sp = nullptr;       // [n]   species
+    int32_t* nbr = nullptr;      // [S][cap][n] neighbour (sorted index)
+    int32_t* img = nullptr;      // [S][cap][n] periodic image, int8 x 3 packed
+    int32_t* cnt = nullptr;      // [S][n]
+    int32_t* sp_idx = nullptr;   // [n] sorted indices grouped by species
+};
+
+namespace tmd {
+
+// Status helpers ------------------------------------------------------------
+tmd_status fail(tmd_context* ctx, tmd_status st, const std::string& msg);
+tmd_status hip_fail(tmd_context* ctx, hipError_t e, const char* what);
+
+#define TMD_HIP(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return tmd::hip_fail((ctx), e_, #call); \
+    } while (0)
+
+// Image code: three signed 8-bit components.
+__host__ __device__ inline int32_t pack_img(int nx, int ny, int nz) {
+    return (int32_t)((uint32_t)(nx & 0xff) | ((uint32_t)(ny & 0xff) << 8) | ((uint32_t)(nz & 0xff) << 16));
+}
+__host__ __device__ inline void unpack_img(int32_t c, int& nx, int& ny, int& nz) {
+    nx = (int)(int8_t)(c & 0xff);
+    ny = (int)(int8_t)((c >> 8) & 0xff);
+    nz = (int)(int8_t)((c >> 16) & 0xff);
+}
+
+// Launchers (each enqueues on ctx->stream) ---------------------------------
+tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, double rlist, tmd_nlist* nl,
+                                  int32_t* required_capacity);
+tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl);
+tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G);
+tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* G, float* Ei,
+                      float* dG);
+tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG,
+                          float* Fown, float* Fin, double* vir_partials, int* nblocks_out);
+tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fown,
+                           const float* Fin, const double* vir_partials, int nvir, float* atom_energy,
+                           float* forces, double* totals7);
+tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, int width, float* out);
+tmd_status launch_export_nlist(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt);
+tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row);
+
+// Block size of the adjoint kernel, for sizing the virial partials.
+int adjoint_blocks(const tmd_model* m, const tmd_nlist* nl);
+
+}  // namespace tmd

@@ -1,0 +1,367 @@
+"""ctypes binding of libtmd.so (include/tmd.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the computation runs in the library's HIP kernels.
+The library must have been built (paper_2310_08439_amd/build.py); importing
+this module on a machine without it raises instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtmd.so")
+
+TMD_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "CAPACITY", 3: "OUT_OF_MEMORY", 4: "DEVICE",
+                5: "NUMERICAL", 6: "NOT_READY", 7: "REJECTED"}
+TMD_ERR_CAPACITY = 2
+FP32 = 0
+BF16_MLP = 1
+MAX_HIDDEN = 4
+
+# Every exported symbol of include/tmd.h, checked by the CPU test-suite.
+EXPORTS = (
+    "tmd_context_create", "tmd_context_destroy", "tmd_context_set_stream", "tmd_last_error",
+    "tmd_model_create", "tmd_model_set_params", "tmd_model_set_precision", "tmd_model_params_per_species",
+    "tmd_model_n_features", "tmd_model_destroy",
+    "tmd_nlist_create", "tmd_nlist_destroy", "tmd_build_neighbors", "tmd_nlist_export", "tmd_nlist_capacity",
+    "tmd_nlist_stats",
+    "tmd_descriptors", "tmd_energy_forces", "tmd_energy_forces_async",
+    "tmd_profile_enable", "tmd_profile_reset", "tmd_profile_read",
+)
+
+
+class TMDError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"tmd status {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class SystemView(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int64), ("pos", ctypes.c_void_p), ("species", ctypes.c_void_p),
+                ("box", ctypes.c_double * 3)]
+
+
+class ModelSpecC(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_radial", ctypes.c_int32), ("max_moment", ctypes.c_int32),
+                ("n_hidden", ctypes.c_int32), ("hidden", ctypes.c_int32 * MAX_HIDDEN),
+                ("activation", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rcut", ctypes.c_double),
+                ("mu", ctypes.c_void_p), ("eta", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtmd.so; raises FileNotFoundError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: run paper_2310_08439_amd/build.py (hipcc, gfx950)")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.tmd_context_create.argtypes = [ctypes.c_int, vp, P(vp)]
+    L.tmd_context_destroy.argtypes = [vp]
+    L.tmd_context_destroy.restype = None
+    L.tmd_context_set_stream.argtypes = [vp, vp]
+    L.tmd_last_error.argtypes = [vp]
+    L.tmd_last_error.restype = ctypes.c_char_p
+    L.tmd_model_create.argtypes = [vp, P(ModelSpecC), vp, P(vp)]
+    L.tmd_model_set_params.argtypes = [vp, vp]
+    L.tmd_model_set_precision.argtypes = [vp, ctypes.c_int]
+    L.tmd_model_params_per_species.argtypes = [vp]
+    L.tmd_model_params_per_species.restype = i64
+    L.tmd_model_n_features.argtypes = [vp]
+    L.tmd_model_n_features.restype = i32
+    L.tmd_model_destroy.argtypes = [vp]
+    L.tmd_model_destroy.restype = None
+    L.tmd_nlist_create.argtypes = [vp, i64, i32, i32, P(vp)]
+    L.tmd_nlist_destroy.argtypes = [vp]
+    L.tmd_nlist_destroy.restype = None
+    L.tmd_build_neighbors.argtypes = [vp, P(SystemView), dbl, dbl, vp, P(i32)]
+    L.tmd_nlist_export.argtypes = [vp, vp, vp, vp, vp]
+    L.tmd_nlist_capacity.argtypes = [vp]
+    L.tmd_nlist_capacity.restype = i32
+    L.tmd_nlist_stats.argtypes = [vp, vp, P(i64), P(i32)]
+    L.tmd_descriptors.argtypes = [vp, vp, P(SystemView), vp, vp]
+    L.tmd_energy_forces.argtypes = [vp, vp, P(SystemView), vp, P(dbl), vp, vp, vp]
+    L.tmd_energy_forces_async.argtypes = [vp, vp, P(SystemView), vp, vp, vp, vp]
+    L.tmd_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.tmd_profile_reset.argtypes = [vp]
+    L.tmd_profile_read.argtypes = [vp, i32, vp, vp, vp]
+    L.tmd_profile_read.restype = i32
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and the current torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self.device = device
+        torch.cuda.set_device(device)
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = ctypes.c_void_p()
+        st = self.lib.tmd_context_create(device, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
+        if st != TMD_OK:
+            raise TMDError(st, "tmd_context_create failed")
+        self.h = h
+
+    def check(self, st: int, what: str = ""):
+        if st != TMD_OK:
+            msg = self.lib.tmd_last_error(self.h).decode()
+            raise TMDError(st, f"{what}: {msg}" if what else msg)
+
+    def profile(self, on: bool):
+        self.check(self.lib.tmd_profile_enable(self.h, 1 if on else 0), "tmd_profile_enable")
+
+    def profile_reset(self):
+        self.check(self.lib.tmd_profile_reset(self.h), "tmd_profile_reset")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} of the launches timed since the last reset."""
+        maxk = 64
+        names = ctypes.create_string_buffer(32 * maxk)
+        tot = (ctypes.c_double * maxk)()
+        cnt = (ctypes.c_int64 * maxk)()
+        k = self.lib.tmd_profile_read(self.h, maxk, names, tot, cnt)
+        out = {}
+        for q in range(min(k, maxk)):
+            nm = names.raw[32 * q:32 * (q + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (float(tot[q]), int(cnt[q]))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tmd_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def system_view(pos, species, box) -> SystemView:
+    torch = _torch()
+    if pos.dtype != torch.float64 or not pos.is_cuda or not pos.is_contiguous() or pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be a contiguous [n,3] float64 device tensor")
+    if species.dtype != torch.int32 or not species.is_cuda or not species.is_contiguous():
+        raise ValueError("species must be a contiguous int32 device tensor")
+    v = SystemView()
+    v.n_atoms = pos.shape[0]
+    v.pos = _ptr(pos)
+    v.species = _ptr(species)
+    for a in range(3):
+        v.box[a] = float(box[a])
+    return v
+
+
+class Model:
+    """Device copy of a model (ModelSpec from paper_2310_08439_amd.inputs)."""
+
+    def __init__(self, ctx: Context, spec, precision: int = FP32):
+        self.ctx = ctx
+        self.spec = spec
+        c = ModelSpecC()
+        c.n_species = spec.n_species
+        c.n_radial = spec.n_radial
+        c.max_moment = spec.max_moment
+        c.n_hidden = len(spec.hidden)
+        for q, h in enumerate(spec.hidden):
+            c.hidden[q] = h
+        c.activation = spec.activation
+        c.rcut = spec.rcut
+        self._mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
+        self._eta = np.ascontiguousarray(spec.eta, dtype=np.float64)
+        c.mu = self._mu.ctypes.data
+        c.eta = self._eta.ctypes.data
+        params = np.ascontiguousarray(spec.params, dtype=np.float32)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.tmd_model_create(ctx.h, ctypes.byref(c), params.ctypes.data, ctypes.byref(h)),
+                  "tmd_model_create")
+        self.h = h
+        self.set_precision(precision)
+
+    @property
+    def n_features(self) -> int:
+        return int(self.ctx.lib.tmd_model_n_features(self.h))
+
+    def set_precision(self, precision: int):
+        self.ctx.check(self.ctx.lib.tmd_model_set_precision(self.h, int(precision)), "tmd_model_set_precision")
+        self.precision = precision
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.ctx.check(self.ctx.lib.tmd_model_set_params(self.h, p.ctypes.data), "tmd_model_set_params")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tmd_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_capacity(n_atoms: int, box, rlist: float, n_species: int) -> int:
+    vol = float(box[0]) * float(box[1]) * float(box[2])
+    mean = n_atoms / vol * 4.0 / 3.0 * math.pi * rlist ** 3
+    cap = int(mean * (1.0 / n_species + 0.3)) + 16
+    return max(16, (cap + 7) // 8 * 8)
+
+
+class NeighborList:
+    def __init__(self, ctx: Context, n_atoms: int, n_species: int, capacity: int):
+        self.ctx = ctx
+        self.n_atoms = n_atoms
+        self.n_species = n_species
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.tmd_nlist_create(ctx.h, n_atoms, n_species, capacity, ctypes.byref(h)), "tmd_nlist_create")
+        self.h = h
+        self.capacity = capacity
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tmd_nlist_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_neighbors(ctx: Context, pos, species, box, rcut: float, skin: float, nl: NeighborList) -> int:
+    """Returns the largest per-species row length; raises TMDError (status CAPACITY) on overflow."""
+    v = system_view(pos, species, box)
+    need = ctypes.c_int32(0)
+    st = ctx.lib.tmd_build_neighbors(ctx.h, ctypes.byref(v), float(rcut), float(skin), nl.h, ctypes.byref(need))
+    if st == TMD_ERR_CAPACITY:
+        err = TMDError(st, ctx.lib.tmd_last_error(ctx.h).decode())
+        err.required = int(need.value)
+        raise err
+    ctx.check(st, "tmd_build_neighbors")
+    return int(need.value)
+
+
+def export_neighbors(ctx: Context, nl: NeighborList):
+    """(nbr [n,S,cap], img [n,S,cap,3], cnt [n,S]) as device int32 tensors, original numbering."""
+    torch = _torch()
+    n, S, cap = nl.n_atoms, nl.n_species, nl.capacity
+    dev = torch.device("cuda", ctx.device)
+    nbr = torch.empty((n, S, cap), dtype=torch.int32, device=dev)
+    img = torch.empty((n, S, cap, 3), dtype=torch.int32, device=dev)
+    cnt = torch.empty((n, S), dtype=torch.int32, device=dev)
+    ctx.check(ctx.lib.tmd_nlist_export(ctx.h, nl.h, _ptr(nbr), _ptr(img), _ptr(cnt)), "tmd_nlist_export")
+    return nbr, img, cnt
+
+
+def nlist_stats(ctx: Context, nl: NeighborList) -> Tuple[int, int]:
+    """(total list entries, longest per-species row) of the last build."""
+    tot = ctypes.c_int64(0)
+    mx = ctypes.c_int32(0)
+    ctx.check(ctx.lib.tmd_nlist_stats(ctx.h, nl.h, ctypes.byref(tot), ctypes.byref(mx)), "tmd_nlist_stats")
+    return int(tot.value), int(mx.value)
+
+
+def descriptors(ctx: Context, model: Model, pos, species, box, nl: NeighborList):
+    torch = _torch()
+    v = system_view(pos, species, box)
+    G = torch.empty((pos.shape[0], model.n_features), dtype=torch.float32, device=pos.device)
+    ctx.check(ctx.lib.tmd_descriptors(ctx.h, model.h, ctypes.byref(v), nl.h, _ptr(G)), "tmd_descriptors")
+    return G
+
+
+def energy_forces(ctx: Context, model: Model, pos, species, box, nl: NeighborList, atom_energy: bool = True,
+                  out_forces=None, out_atom_energy=None) -> Tuple[float, object, object, np.ndarray]:
+    """(E, E_atoms or None, F [n,3] float32, virial (xx,yy,zz,xy,xz,yz))."""
+    torch = _torch()
+    v = system_view(pos, species, box)
+    n = pos.shape[0]
+    F = out_forces if out_forces is not None else torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+    Ea = None
+    if atom_energy:
+        Ea = out_atom_energy if out_atom_energy is not None else torch.empty(n, dtype=torch.float32, device=pos.device)
+    E = ctypes.c_double(0.0)
+    W = (ctypes.c_double * 6)()
+    ctx.check(ctx.lib.tmd_energy_forces(ctx.h, model.h, ctypes.byref(v), nl.h, ctypes.byref(E), _ptr(Ea), _ptr(F),
+                                        W), "tmd_energy_forces")
+    return float(E.value), Ea, F, np.array(list(W), dtype=np.float64)
+
+
+def energy_forces_async(ctx: Context, model: Model, pos, species, box, nl: NeighborList, totals7, forces,
+                        atom_energy=None):
+    v = system_view(pos, species, box)
+    ctx.check(ctx.lib.tmd_energy_forces_async(ctx.h, model.h, ctypes.byref(v), nl.h, _ptr(totals7), _ptr(atom_energy),
+                                              _ptr(forces)), "tmd_energy_forces_async")
+
+
+def virial_matrix(w6) -> np.ndarray:
+    xx, yy, zz, xy, xz, yz = w6
+    return np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+
+
+class Evaluator:
+    """Context + model + neighbour list for one system, regrowing the list on overflow."""
+
+    def __init__(self, spec, n_atoms: int, box, skin: float = 0.0, precision: int = FP32, device: int = 0,
+                 capacity: Optional[int] = None, ctx: Optional[Context] = None):
+        self.ctx = ctx if ctx is not None else Context(device)
+        self.model = Model(self.ctx, spec, precision)
+        self.spec = spec
+        self.skin = skin
+        cap = capacity or default_capacity(n_atoms, box, spec.rcut + skin, spec.n_species)
+        self.nl = NeighborList(self.ctx, n_atoms, spec.n_species, cap)
+
+    def build(self, pos, species, box) -> int:
+        try:
+            return build_neighbors(self.ctx, pos, species, box, self.spec.rcut, self.skin, self.nl)
+        except TMDError as e:
+            if e.status != TMD_ERR_CAPACITY:
+                raise
+            need = (e.required + 8 + 7) // 8 * 8
+            self.nl.close()
+            self.nl = NeighborList(self.ctx, self.nl.n_atoms, self.spec.n_species, need)
+            return build_neighbors(self.ctx, pos, species, box, self.spec.rcut, self.skin, self.nl)
+
+    def energy_forces(self, pos, species, box, rebuild: bool = True, atom_energy: bool = True):
+        if rebuild:
+            self.build(pos, species, box)
+        return energy_forces(self.ctx, self.model, pos, species, box, self.nl, atom_energy=atom_energy)
+
+    def descriptors(self, pos, species, box, rebuild: bool = True):
+        if rebuild:
+            self.build(pos, species, box)
+        return descriptors(self.ctx, self.model, pos, species, box, self.nl)

@@ -1,0 +1,336 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: neighbour lists bit-exact (as sets, counts equal); FP32 path
+|E - E_ref|/N <= 1e-5 eV and force RMS error <= 1e-4 eV/A; BF16-MLP path
+<= 1e-3 eV and <= 5e-3 eV/A; virial |dW_ab|/N <= rcut * (force bar);
+descriptors |dG| <= 2e-5 (|G_ref| + 1).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_08439_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+E_TOL_FP32, F_TOL_FP32 = 1e-5, 1e-4
+E_TOL_BF16, F_TOL_BF16 = 1e-3, 5e-3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def tmd(torch):
+    from paper_2310_08439_amd import tmd as _tmd
+    _tmd.load_library()
+    return _tmd
+
+
+@pytest.fixture(scope="module")
+def ctx(tmd):
+    c = tmd.Context(0)
+    yield c
+    c.close()
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _dev(torch, s):
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    return pos, sp
+
+
+def _gpu_eval(tmd, ctx, spec, s, prec, skin=0.0, capacity=None):
+    import torch
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, skin=skin, precision=prec, ctx=ctx, capacity=capacity)
+    E, Ea, F, W = ev.energy_forces(pos, sp, s.box)
+    return E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, ev
+
+
+def _check_ef(E, Ea, F, W, s, spec, etol, ftol, sel=None):
+    if sel is None:
+        Er, Ear, Fr, Wr = oracle.energy_forces(spec, s.pos, s.species, s.box)
+        dE = abs(E - Er) / s.n
+        frms = math.sqrt(np.mean((F - Fr) ** 2))
+        print(f"  |dE|/N={dE:.3e}  F rms err={frms:.3e}  (F rms={math.sqrt(np.mean(Fr ** 2)):.3e})", flush=True)
+        assert dE <= etol
+        assert frms <= ftol
+        np.testing.assert_allclose(Ea, Ear, atol=20 * etol)
+        Wm = np.array([[W[0], W[3], W[4]], [W[3], W[1], W[5]], [W[4], W[5], W[2]]])
+        # virial bar derived from the force bar: per atom |dW| <= rcut * F_tol
+        dW = np.abs(Wm - Wr).max() / s.n
+        print(f"  |dW|/N={dW:.3e}", flush=True)
+        assert dW <= spec.rcut * ftol
+    else:
+        Ear, Fr = oracle.forces_subset(spec, s.pos, s.species, s.box, sel)
+        frms = math.sqrt(np.mean((F[sel] - Fr) ** 2))
+        dEi = np.abs(Ea[sel] - Ear).max()
+        print(f"  sampled {len(sel)}: max|dE_i|={dEi:.3e}  F rms err={frms:.3e}", flush=True)
+        assert frms <= ftol
+        assert dEi <= 20 * etol
+
+
+# ------------------------------------------------------------------ neighbour lists
+
+def _gpu_pairs(tmd, ctx, nl, species):
+    nbr, img, cnt = tmd.export_neighbors(ctx, nl)
+    nbr, img, cnt = nbr.cpu().numpy(), img.cpu().numpy(), cnt.cpu().numpy()
+    rows = []
+    n, S, cap = nbr.shape
+    for b in range(S):
+        for c in range(cap):
+            m = cnt[:, b] > c
+            i = np.nonzero(m)[0]
+            j = nbr[m, b, c]
+            assert np.all(species[j] == b)
+            rows.append(np.stack([i, j, img[m, b, c, 0], img[m, b, c, 1], img[m, b, c, 2]], 1))
+    keys = np.concatenate(rows) if rows else np.zeros((0, 5), np.int64)
+    order = np.lexsort(keys.T[::-1])
+    return keys[order], cnt
+
+
+def _oracle_pairs(s, rlist):
+    nbr, img, cnt = oracle.neighbors(s.pos, s.species, s.box, rlist)
+    rows = []
+    for i in range(s.n):
+        c = cnt[i]
+        rows.append(np.concatenate([np.full((c, 1), i), nbr[i, :c, None], img[i, :c]], 1))
+    keys = np.concatenate(rows)
+    order = np.lexsort(keys.T[::-1])
+    per = np.zeros((s.n, int(s.species.max()) + 1), np.int64)
+    np.add.at(per, (keys[:, 0], s.species[keys[:, 1]]), 1)
+    return keys[order], per
+
+
+NB_CASES = {
+    "fcc32_rc5": lambda: (inputs.workload("oracle32")[0], 5.0, 0.0),
+    "bcc4k_rc6": lambda: (inputs.workload("bcc4k")[0], 6.0, 0.0),
+    "bcc4k_rc6_skin1": lambda: (inputs.workload("bcc4k")[0], 6.0, 1.0),
+    "fcc4_tiny_box_rc6": lambda: (inputs.make_system("fcc", 3.61, (1, 1, 1), 0.05, 1, seed=31), 6.0, 0.0),
+    "hcp_ortho_rc5": lambda: (inputs.make_system("hcp", 2.553, (3, 2, 2), 0.1, 3, seed=32), 5.0, 0.5),
+    "fcc32k_rc6": lambda: (inputs.workload("fcc32k")[0], 6.0, 0.0),
+}
+
+
+@pytest.mark.parametrize("case", list(NB_CASES))
+def test_neighbors_bitexact(tmd, ctx, torch, case):
+    s, rc, skin = NB_CASES[case]()
+    _note(f"neighbors {case} n={s.n} rc={rc} skin={skin}")
+    pos, sp = _dev(torch, s)
+    S = int(s.species.max()) + 1
+    cap = tmd.default_capacity(s.n, s.box, rc + skin, S)
+    nl = tmd.NeighborList(ctx, s.n, S, cap)
+    try:
+        tmd.build_neighbors(ctx, pos, sp, s.box, rc, skin, nl)
+    except tmd.TMDError as e:
+        nl = tmd.NeighborList(ctx, s.n, S, e.required)
+        tmd.build_neighbors(ctx, pos, sp, s.box, rc, skin, nl)
+    got, gcnt = _gpu_pairs(tmd, ctx, nl, s.species)
+    want, wcnt = _oracle_pairs(s, rc + skin)
+    assert np.array_equal(gcnt, wcnt)
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_capacity_overflow_reports_requirement(tmd, ctx, torch):
+    s = inputs.workload("oracle32")[0]
+    _note("capacity overflow n=32")
+    pos, sp = _dev(torch, s)
+    nl = tmd.NeighborList(ctx, s.n, 1, 8)
+    with pytest.raises(tmd.TMDError) as ei:
+        tmd.build_neighbors(ctx, pos, sp, s.box, 5.0, 0.0, nl)
+    assert ei.value.status == tmd.TMD_ERR_CAPACITY
+    _, _, cnt = oracle.neighbors(s.pos, s.species, s.box, 5.0)
+    assert ei.value.required == cnt.max()
+
+
+@pytest.mark.parametrize("kind", ["nan", "coincident", "species"])
+def test_input_errors(tmd, ctx, torch, kind):
+    s = inputs.workload("oracle32")[0]
+    _note(f"input error {kind}")
+    p = s.pos.copy()
+    spc = s.species.copy()
+    if kind == "nan":
+        p[3, 1] = np.nan
+    elif kind == "coincident":
+        p[5] = p[4]
+    else:
+        spc[7] = 3
+    pos = torch.tensor(p, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(spc, dtype=torch.int32, device="cuda")
+    nl = tmd.NeighborList(ctx, s.n, 1, 64)
+    with pytest.raises(tmd.TMDError) as ei:
+        tmd.build_neighbors(ctx, pos, sp, s.box, 5.0, 0.0, nl)
+    assert ei.value.status == {"nan": 5, "coincident": 5, "species": 1}[kind]
+
+
+# ------------------------------------------------------------------ descriptors
+
+@pytest.mark.parametrize("name", ["oracle32", "bcc4k"])
+def test_descriptors_parity(tmd, ctx, torch, name):
+    s, spec, _ = inputs.workload(name)
+    _note(f"descriptors {name} n={s.n}")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx)
+    G = ev.descriptors(pos, sp, s.box).cpu().numpy().astype(np.float64)
+    Gr = oracle.descriptors(spec, s.pos, s.species, s.box)
+    err = np.abs(G - Gr) / (np.abs(Gr) + 1.0)
+    print(f"  max scaled G err {err.max():.3e}", flush=True)
+    assert err.max() <= 2e-5
+
+
+@pytest.mark.parametrize("K,M,S", [(4, 0, 1), (8, 1, 2), (12, 2, 3), (16, 3, 1), (24, 3, 2), (32, 3, 1)])
+def test_descriptor_shapes(tmd, ctx, torch, K, M, S):
+    s = inputs.make_system("bcc", 3.16, (3, 3, 3), 0.12, S, seed=40 + K)
+    spec = inputs.make_model(S, K, M, [32], 5.5, seed=41)
+    _note(f"descriptor shape K={K} M={M} S={S} n={s.n}")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx)
+    G = ev.descriptors(pos, sp, s.box).cpu().numpy().astype(np.float64)
+    Gr = oracle.descriptors(spec, s.pos, s.species, s.box)
+    assert (np.abs(G - Gr) / (np.abs(Gr) + 1.0)).max() <= 2e-5
+
+
+# ------------------------------------------------------------------ energy / forces / virial
+
+@pytest.mark.parametrize("name", ["oracle32", "bcc4k", "fcc32k"])
+def test_energy_forces_fp32(tmd, ctx, torch, name):
+    s, spec, _ = inputs.workload(name)
+    _note(f"energy_forces fp32 {name} n={s.n}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
+    _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+
+
+@pytest.mark.parametrize("name", ["oracle32", "bcc4k"])
+def test_energy_forces_bf16(tmd, ctx, torch, name):
+    s, spec, _ = inputs.workload(name)
+    _note(f"energy_forces bf16 {name} n={s.n}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.BF16_MLP)
+    _check_ef(E, Ea, F, W, s, spec, E_TOL_BF16, F_TOL_BF16)
+
+
+@pytest.mark.parametrize("hidden,act,K,M", [([32], 0, 8, 3), ([64, 64, 64], 1, 8, 2), ([128, 128, 128, 128], 0, 4, 3),
+                                            ([64], 1, 16, 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_energy_forces_model_shapes(tmd, ctx, torch, hidden, act, K, M, prec):
+    s = inputs.make_system("bcc", 3.16, (3, 3, 3), 0.12, 2, seed=50)
+    spec = inputs.make_model(2, K, M, hidden, 5.5, seed=51, activation=act)
+    _note(f"energy_forces shapes hidden={hidden} act={act} K={K} M={M} prec={prec}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, prec)
+    etol, ftol = (E_TOL_FP32, F_TOL_FP32) if prec == 0 else (E_TOL_BF16, F_TOL_BF16)
+    _check_ef(E, Ea, F, W, s, spec, etol, ftol)
+
+
+def test_ragged_and_absent_species(tmd, ctx, torch):
+    """61 atoms (ragged MLP tiles), species 1 of 2 absent, one isolated atom."""
+    rng = np.random.default_rng(60)
+    pos = rng.uniform(0, 11.0, size=(60, 3))
+    pos = np.concatenate([pos, [[30.0, 30.0, 30.0]]])
+    box = np.array([40.0, 40.0, 40.0])
+    pos[:60] *= 1.0
+    # spread the 60 atoms so no two are closer than 1.8 A
+    keep = [0]
+    for q in range(1, 60):
+        if np.min(np.linalg.norm(pos[keep] - pos[q], axis=1)) > 1.8:
+            keep.append(q)
+    pos = np.concatenate([pos[keep], pos[60:]])
+    s = inputs.System(pos=pos, species=np.zeros(len(pos), np.int32), box=box, masses=np.array([63.5, 58.7]))
+    spec = inputs.make_model(2, 8, 3, [64, 64], 5.0, seed=61)
+    _note(f"ragged n={s.n}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
+    _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+    assert np.all(F[-1] == 0.0)
+
+
+def test_skin_entries_contribute_nothing(tmd, ctx, torch):
+    s, spec, _ = inputs.workload("oracle32")
+    _note("skin 1.5")
+    E0, _, F0, W0, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32, skin=0.0)
+    E1, _, F1, W1, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32, skin=1.5)
+    assert abs(E0 - E1) <= 1e-9 * abs(E0)
+    assert np.abs(F0 - F1).max() <= 1e-5
+
+
+def test_list_reuse_after_small_moves(tmd, ctx, torch):
+    """A list built with a skin stays valid for moves < skin/2 (positions refreshed each call)."""
+    s, spec, _ = inputs.workload("oracle32")
+    _note("list reuse")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, skin=1.0, ctx=ctx)
+    ev.build(pos, sp, s.box)
+    moved = s.pos + np.random.default_rng(70).uniform(-0.3, 0.3, s.pos.shape)
+    pm = torch.tensor(moved, dtype=torch.float64, device="cuda")
+    E, Ea, F, W = ev.energy_forces(pm, sp, s.box, rebuild=False)
+    s2 = inputs.System(pos=moved, species=s.species, box=s.box, masses=s.masses)
+    _check_ef(E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, s2, spec,
+              E_TOL_FP32, F_TOL_FP32)
+
+
+def test_forces_match_gpu_energy_differences(tmd, ctx, torch):
+    s, spec, _ = inputs.workload("oracle32")
+    _note("finite differences of the GPU energy")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx)
+    E, _, F, _ = ev.energy_forces(pos, sp, s.box)
+    F = F.cpu().numpy()
+    h = 2e-3
+    for i, x in ((0, 0), (11, 1), (27, 2)):
+        vals = []
+        for sgn in (1, -1):
+            p = s.pos.copy()
+            p[i, x] += sgn * h
+            pt = torch.tensor(p, dtype=torch.float64, device="cuda")
+            vals.append(ev.energy_forces(pt, sp, s.box)[0])
+        fd = -(vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - F[i, x]) <= 2e-3 * max(1.0, abs(F[i, x])) + 1e-3
+
+
+def test_repeat_runs(tmd, ctx, torch):
+    s, spec, _ = inputs.workload("bcc4k")
+    _note("repeat runs bcc4k")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx, precision=tmd.BF16_MLP)
+    E1, Ea1, F1, _ = ev.energy_forces(pos, sp, s.box)
+    E2, Ea2, F2, _ = ev.energy_forces(pos, sp, s.box)
+    assert E1 == E2
+    assert torch.equal(Ea1, Ea2)
+    assert (F1 - F2).abs().max().item() <= 1e-5
+
+
+# ------------------------------------------------------------------ full size (1,024,000 atoms)
+
+def test_bcc1m_sampled_parity(tmd, ctx, torch):
+    s, spec, _ = inputs.workload("bcc1m")
+    _note(f"bcc1m n={s.n} fp32 + bf16, sampled atoms vs oracle")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx, precision=tmd.FP32)
+    E32, Ea32, F32, W32 = ev.energy_forces(pos, sp, s.box)
+    Ea32 = Ea32.cpu().numpy().astype(np.float64)
+    F32 = F32.cpu().numpy().astype(np.float64)
+    ev.model.set_precision(tmd.BF16_MLP)
+    E16, Ea16, F16, W16 = ev.energy_forces(pos, sp, s.box, rebuild=False)
+    Ea16 = Ea16.cpu().numpy().astype(np.float64)
+    F16 = F16.cpu().numpy().astype(np.float64)
+    sel = np.random.default_rng(80).choice(s.n, 24, replace=False)
+    _check_ef(E32, Ea32, F32, W32, s, spec, E_TOL_FP32, F_TOL_FP32, sel=sel)
+    _check_ef(E16, Ea16, F16, W16, s, spec, E_TOL_BF16, F_TOL_BF16, sel=sel)
+    # properties at full size
+    assert abs(E32 - oracle.neumaier_sum(Ea32)) <= 1e-9 * abs(E32) + 1e-6
+    assert np.abs(F32.sum(0)).max() <= 1e-3
+    assert abs(E16 - E32) / s.n <= E_TOL_BF16
+    assert math.sqrt(np.mean((F16 - F32) ** 2)) <= F_TOL_BF16
+    print(f"  E/N fp32={E32 / s.n:.6f} bf16={E16 / s.n:.6f}", flush=True)
