@@ -138,8 +138,9 @@ void tmd_model_destroy(tmd_model* model);
 
 /* ---------------------------------------------------------------- neighbour list */
 
-/* A neighbour list for up to n_atoms atoms with room for `capacity`
- * neighbours of each species per atom. */
+/* A neighbour list for up to n_atoms atoms with room for at least `capacity`
+ * neighbours of each species per atom (rounded up to a multiple of 4;
+ * tmd_nlist_capacity reports the value used). */
 tmd_status tmd_nlist_create(tmd_context* ctx, int64_t n_atoms, int32_t n_species, int32_t capacity,
                             tmd_nlist** out);
 void tmd_nlist_destroy(tmd_nlist* nl);

@@ -162,7 +162,7 @@ tmd_status check_eval(tmd_context* ctx, const tmd_model* m, const tmd_system_vie
 }
 
 struct EvalBuffers {
-    float *G, *dG, *Ei, *Fown, *Fin;
+    float *G, *dG, *Ei, *Fs, *P;
     double *vir, *totals;
 };
 
@@ -172,9 +172,9 @@ tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* n
     b->G = (float*)ctx->ws.get("ev.G", sizeof(float) * n * m->F, &e);
     b->dG = (float*)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
     b->Ei = (float*)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
-    b->Fown = (float*)ctx->ws.get("ev.Fown", sizeof(float) * 3 * n, &e);
-    b->Fin = (float*)ctx->ws.get("ev.Fin", sizeof(float) * 3 * n, &e);
-    b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * 6 * (size_t)adjoint_blocks(m, nl), &e);
+    b->Fs = (float*)ctx->ws.get("ev.Fs", sizeof(float) * 3 * n, &e);
+    b->P = (float*)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->D, &e);
+    b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * 6 * (size_t)adjoint_max_partials(m, nl), &e);
     b->totals = (double*)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "evaluation workspace allocation");
     return TMD_OK;
@@ -186,13 +186,11 @@ tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_sys
     tmd_status st = eval_buffers(ctx, m, nl, &b);
     if (st != TMD_OK) return st;
     if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
-    if ((st = launch_descriptors(ctx, m, nl, b.G)) != TMD_OK) return st;
+    if ((st = launch_descriptors(ctx, m, nl, b.G, b.P)) != TMD_OK) return st;
     if ((st = launch_mlp(ctx, m, nl, b.G, b.Ei, b.dG)) != TMD_OK) return st;
-    TMD_HIP(ctx, hipMemsetAsync(b.Fin, 0, sizeof(float) * 3 * nl->n, ctx->stream));
     int nvir = 0;
-    if ((st = launch_adjoint(ctx, m, nl, b.dG, b.Fown, b.Fin, b.vir, &nvir)) != TMD_OK) return st;
-    return launch_finalize(ctx, nl, b.Ei, b.Fown, b.Fin, b.vir, nvir, atom_energy, forces,
-                           totals7_dev ? totals7_dev : b.totals);
+    if ((st = launch_adjoint(ctx, m, nl, b.dG, b.P, b.Fs, b.vir, &nvir)) != TMD_OK) return st;
+    return launch_finalize(ctx, nl, b.Ei, b.Fs, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals);
 }
 
 }  // namespace
@@ -392,8 +390,8 @@ tmd_status tmd_nlist_create(tmd_context* ctx, int64_t n_atoms, int32_t n_species
     nl->ctx = ctx;
     nl->nmax = n_atoms;
     nl->S = n_species;
-    nl->cap = capacity;
-    const size_t n = (size_t)n_atoms, lst = (size_t)n_species * capacity * n;
+    nl->cap = (capacity + 3) / 4 * 4;  // rows start 16-byte aligned
+    const size_t n = (size_t)n_atoms, lst = (size_t)n_species * nl->cap * n;
     hipError_t e = hipSuccess;
     auto alloc = [&](void** p, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 256));
@@ -418,7 +416,7 @@ void tmd_nlist_destroy(tmd_nlist* nl) {
     if (!nl) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)nl->perm, (void*)nl->shift, (void*)nl->xs, (void*)nl->sp, (void*)nl->nbr, (void*)nl->img,
-                    (void*)nl->cnt, (void*)nl->sp_idx})
+                    (void*)nl->cnt, (void*)nl->sp_idx, (void*)nl->cellstart})
         if (p) (void)hipFree(p);
     delete nl;
 }
@@ -461,7 +459,7 @@ tmd_status tmd_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_syste
     float* Gs = (float*)ctx->ws.get("ev.G", sizeof(float) * nl->n * m->F, &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor workspace");
     if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
-    if ((st = launch_descriptors(ctx, m, nl, Gs)) != TMD_OK) return st;
+    if ((st = launch_descriptors(ctx, m, nl, Gs, nullptr)) != TMD_OK) return st;
     return launch_permute_rows(ctx, nl, Gs, m->F, G);
 }
 

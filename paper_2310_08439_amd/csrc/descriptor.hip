@@ -21,6 +21,8 @@
 // Per-pair force partials of the chunks are summed with lane shuffles.
 #include "tmd_internal.h"
 
+#include <algorithm>
+
 namespace tmd {
 namespace {
 
@@ -113,31 +115,48 @@ struct PathArgs {
     // forward output / backward input
     float* G;
     const float* dG;
-    // backward outputs
-    float* Fown;
-    float* Fin;
+    // P [S][K][D][n] written by the forward pass (if non-null) and read back by the adjoint
+    float* Pbuf;
+    // backward output: virial block partials
     double* vir;
 };
 
 struct Pair {
     float dx, dy, dz, r2;
-    int q;  // neighbour (sorted index)
+    int q;     // neighbour (sorted index)
+    int code;  // stencil cell offset code of the entry (0..26) or 255
 };
 
-// NB consecutive list entries c0 .. c0+NB-1 of a row of nb (>= 1) entries:
-// all index loads are issued before all position loads so that they overlap.
-// Entries past the row end repeat the last valid entry (never a stale slot)
-// and are marked with r2 = +inf so that every consumer skips them.
 template <int NB>
-__device__ __forceinline__ void load_pairs(const PathArgs& a, const double4& xi, int64_t base, int c0, int nb,
+struct IntVec;
+template <>
+struct IntVec<2> {
+    using T = int2;
+    __device__ static void split(const int2& v, int* o) { o[0] = v.x, o[1] = v.y; }
+};
+template <>
+struct IntVec<4> {
+    using T = int4;
+    __device__ static void split(const int4& v, int* o) { o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w; }
+};
+
+// NB consecutive entries c0 .. c0+NB-1 (c0 a multiple of NB) of a list row of
+// nb (>= 1) entries starting at `row` (16-byte aligned): one vector load each
+// for indices and image words, then all position loads, so the loads overlap.
+// Entries past the row end are replaced by the last valid entry (never a
+// stale slot) and marked with r2 = +inf so that every consumer skips them.
+template <int NB>
+__device__ __forceinline__ void load_pairs(const PathArgs& a, const double4& xi, int64_t row, int c0, int nb,
                                            Pair (&pr)[NB]) {
     int q[NB], im[NB];
+    IntVec<NB>::split(*reinterpret_cast<const typename IntVec<NB>::T*>(a.nbr + row + c0), q);
+    IntVec<NB>::split(*reinterpret_cast<const typename IntVec<NB>::T*>(a.img + row + c0), im);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int64_t slot = base + (int64_t)min(c0 + j, nb - 1) * a.n;
-        q[j] = a.nbr[slot];
-        im[j] = a.img[slot];
-    }
+    for (int j = 1; j < NB; ++j)
+        if (c0 + j >= nb) {  // entry c0 < nb is always valid
+            q[j] = q[0];
+            im[j] = im[0];
+        }
     double4 xj[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) xj[j] = a.xs[q[j]];
@@ -151,11 +170,28 @@ __device__ __forceinline__ void load_pairs(const PathArgs& a, const double4& xi,
         pr[j].r2 = (c0 + j < nb) ? pr[j].dx * pr[j].dx + pr[j].dy * pr[j].dy + pr[j].dz * pr[j].dz
                                  : __builtin_inff();
         pr[j].q = q[j];
+        pr[j].code = img_ocode(im[j]);
     }
 }
 
 constexpr int kBatchFwd = 4;
 constexpr int kBatchAdj = 2;
+
+// A thread's KC x D tile of P in the element-major buffer [S][K][D][n]: element
+// (k, d) of atom p lives at ((b*K + k)*D + d)*n + p, so for a fixed element
+// the lanes of a wave (consecutive atoms, two chunks) write and read whole
+// contiguous cache lines.
+template <int KC, int D>
+__device__ __forceinline__ void store_tile(float* dst, int64_t n, const float (&P)[KC][D]) {
+#pragma unroll
+    for (int q = 0; q < KC * D; ++q) dst[(int64_t)q * n] = P[q / D][q % D];
+}
+
+template <int KC, int D>
+__device__ __forceinline__ void load_tile(const float* src, int64_t n, float (&P)[KC][D]) {
+#pragma unroll
+    for (int q = 0; q < KC * D; ++q) P[q / D][q % D] = src[(int64_t)q * n];
+}
 
 // P tile of one species for this thread's radial chunk.
 template <int KC, int M>
@@ -167,7 +203,7 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& x
 #pragma unroll
         for (int d = 0; d < D; ++d) P[kk][d] = 0.0f;
     const int nb = a.cnt[(int64_t)b * a.n + p];
-    const int64_t base = (int64_t)b * a.cap * a.n + p;
+    const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
     for (int c0 = 0; c0 < nb; c0 += kBatchFwd) {
       Pair prs[kBatchFwd];
       load_pairs<kBatchFwd>(a, xi, base, c0, nb, prs);
@@ -209,6 +245,7 @@ __global__ void __launch_bounds__(256) k_descriptor(PathArgs a) {
     for (int b = 0; b < a.S; ++b) {
         float P[KC][D];
         accumulate_P<KC, M>(a, xi, p, b, mu, nef, P);
+        if (a.Pbuf) store_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + p, a.n, P);
         float* Gp = a.G + p * a.F + (b * a.K + ch * KC) * (M + 1);
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
@@ -223,57 +260,54 @@ __global__ void __launch_bounds__(256) k_descriptor(PathArgs a) {
     }
 }
 
-template <int KC, int M>
-__global__ void __launch_bounds__(256) k_adjoint(PathArgs a) {
+// Per-atom adjoint for one (atom, radial chunk) thread: P' from dE/dG, then for
+// every pair U, V and g = dE/dD (summed over the atom's chunk lanes).  The
+// chunk-0 lane hands each pair's g to sink(q, slot, gx, gy, gz), accumulates the
+// atom's own force sum in Fo and the virial in W6.
+template <int KC, int M, class Sink>
+__device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int ch, int nch, float (&W6)[6],
+                                             float (&Fo)[3], Sink&& sink) {
     constexpr int D = Moments<M>::D;
-    __shared__ double red[6][kBlock / 64];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = t >> a.nch_log2;
-    const int nch = 1 << a.nch_log2;
-    const int ch = (int)(t & (nch - 1));
-    float W6[6] = {0, 0, 0, 0, 0, 0};
-    if (p < a.n) {
-        float mu[KC], nef[KC], m2eta[KC];
+    float mu[KC], nef[KC], m2eta[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        mu[kk] = a.mu[ch * KC + kk];
+        nef[kk] = -a.eta[ch * KC + kk] * kLog2e;
+        m2eta[kk] = -2.0f * a.eta[ch * KC + kk];
+    }
+    const double4 xi = a.xs[p];
+    for (int b = 0; b < a.S; ++b) {
+        float P[KC][D];
+        load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + p, a.n, P);
+        // P' = 2 T sigma' P in place (sigma' = dE/dS from dE/dG).
+        const float* dGp = a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1);
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
-            mu[kk] = a.mu[ch * KC + kk];
-            nef[kk] = -a.eta[ch * KC + kk] * kLog2e;
-            m2eta[kk] = -2.0f * a.eta[ch * KC + kk];
-        }
-        const double4 xi = a.xs[p];
-        float Fo[3] = {0.0f, 0.0f, 0.0f};
-        for (int b = 0; b < a.S; ++b) {
-            float P[KC][D];
-            accumulate_P<KC, M>(a, xi, p, b, mu, nef, P);
-            // P' = 2 T sigma' P in place (sigma' = dE/dS from dE/dG).
-            const float* dGp = a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1);
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk) {
+            for (int m = 0; m <= M; ++m) {
+                const float gbar = dGp[kk * (M + 1) + m];
+                float sbar;
+                if (m == 0) {
+                    float s = 0.0f;
 #pragma unroll
-                for (int m = 0; m <= M; ++m) {
-                    const float gbar = dGp[kk * (M + 1) + m];
-                    float sbar;
-                    if (m == 0) {
-                        float s = 0.0f;
-#pragma unroll
-                        for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
-                        sbar = s > 0.0f ? 0.5f * gbar * __builtin_amdgcn_rsqf(s) : 0.0f;
-                    } else {
-                        sbar = gbar;
-                    }
-#pragma unroll
-                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * sbar;
+                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
+                    sbar = s > 0.0f ? 0.5f * gbar * __builtin_amdgcn_rsqf(s) : 0.0f;
+                } else {
+                    sbar = gbar;
                 }
-            }
-            const int nb = a.cnt[(int64_t)b * a.n + p];
-            const int64_t base = (int64_t)b * a.cap * a.n + p;
-            for (int c0 = 0; c0 < nb; c0 += kBatchAdj) {
-              Pair prs[kBatchAdj];
-              load_pairs<kBatchAdj>(a, xi, base, c0, nb, prs);
 #pragma unroll
-              for (int j = 0; j < kBatchAdj; ++j) {
+                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * sbar;
+            }
+        }
+        const int nb = a.cnt[(int64_t)b * a.n + p];
+        const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
+        for (int c0 = 0; c0 < nb; c0 += kBatchAdj) {
+            Pair prs[kBatchAdj];
+            load_pairs<kBatchAdj>(a, xi, base, c0, nb, prs);
+#pragma unroll
+            for (int j = 0; j < kBatchAdj; ++j) {
                 const Pair& pr = prs[j];
-                if (pr.r2 >= a.rc2) continue;
+                if (pr.r2 >= a.rc2) continue;  // skin entries and padding carry no force
                 const float rinv = __builtin_amdgcn_rsqf(pr.r2);
                 const float R = pr.r2 * rinv;
                 const float ux = pr.dx * rinv, uy = pr.dy * rinv, uz = pr.dz * rinv;
@@ -314,10 +348,7 @@ __global__ void __launch_bounds__(256) k_adjoint(PathArgs a) {
                     Fo[0] += gx;
                     Fo[1] += gy;
                     Fo[2] += gz;
-                    const int q = pr.q;
-                    unsafeAtomicAdd(&a.Fin[3 * (int64_t)q + 0], -gx);
-                    unsafeAtomicAdd(&a.Fin[3 * (int64_t)q + 1], -gy);
-                    unsafeAtomicAdd(&a.Fin[3 * (int64_t)q + 2], -gz);
+                    sink(pr.q, pr.code, gx, gy, gz);
                     W6[0] -= pr.dx * gx;
                     W6[1] -= pr.dy * gy;
                     W6[2] -= pr.dz * gz;
@@ -325,16 +356,13 @@ __global__ void __launch_bounds__(256) k_adjoint(PathArgs a) {
                     W6[4] -= 0.5f * (pr.dx * gz + pr.dz * gx);
                     W6[5] -= 0.5f * (pr.dy * gz + pr.dz * gy);
                 }
-              }
             }
         }
-        if (ch == 0) {
-            a.Fown[3 * p + 0] = Fo[0];
-            a.Fown[3 * p + 1] = Fo[1];
-            a.Fown[3 * p + 2] = Fo[2];
-        }
     }
-    // Block reduction of the virial partials in FP64.
+}
+
+// Block reduction of the virial partials in FP64 (256 threads) into out[0..5].
+__device__ __forceinline__ void block_virial(const float (&W6)[6], double (*red)[kBlock / 64], double* out) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -346,15 +374,161 @@ __global__ void __launch_bounds__(256) k_adjoint(PathArgs a) {
     if (threadIdx.x < 6) {
         double s = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) s += red[threadIdx.x][w];
-        a.vir[(int64_t)blockIdx.x * 6 + threadIdx.x] = s;
+        out[threadIdx.x] = s;
     }
 }
 
-template <int KC>
-using KernelFn = void (*)(PathArgs);
+// Adjoint with the force scatter done by device-scope atomics: used only when
+// the stencil is wider than 3x3x3 (a box edge shorter than two list cutoffs).
+template <int KC, int M>
+__global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, float* F) {
+    __shared__ double red[6][kBlock / 64];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = t >> a.nch_log2;
+    const int nch = 1 << a.nch_log2;
+    const int ch = (int)(t & (nch - 1));
+    float W6[6] = {0, 0, 0, 0, 0, 0};
+    if (p < a.n) {
+        float Fo[3] = {0.0f, 0.0f, 0.0f};
+        adjoint_atom<KC, M>(a, p, ch, nch, W6, Fo, [&](int q, int, float gx, float gy, float gz) {
+            unsafeAtomicAdd(&F[3 * (int64_t)q + 0], -gx);
+            unsafeAtomicAdd(&F[3 * (int64_t)q + 1], -gy);
+            unsafeAtomicAdd(&F[3 * (int64_t)q + 2], -gz);
+        });
+        if (ch == 0) {
+            unsafeAtomicAdd(&F[3 * p + 0], Fo[0]);
+            unsafeAtomicAdd(&F[3 * p + 1], Fo[1]);
+            unsafeAtomicAdd(&F[3 * p + 2], Fo[2]);
+        }
+    }
+    block_virial(W6, red, a.vir + (int64_t)blockIdx.x * 6);
+}
+
+struct BlockGeom {
+    int nc[3];   // cells per dimension
+    int B[3];    // cells per block and dimension
+    int nb[3];   // blocks per dimension
+    int hmax;    // capacity of the LDS force accumulators (atoms)
+    const int32_t* cellstart;
+    float* F;
+};
+
+constexpr int kMaxHaloCells = 216;    // (4 + 2)^3
+constexpr int kMaxBlockCells = 64;    // 4^3
+
+__device__ __forceinline__ int wrap_cell(int c, int nc) {
+    c %= nc;
+    return c < 0 ? c + nc : c;
+}
+
+// Exclusive prefix sum of one value per thread over the 256 threads of a block.
+__device__ __forceinline__ void scan256(int v, int32_t* out, int32_t* wtmp) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wtmp[wv] = x;
+    __syncthreads();
+    int pre = 0;
+    for (int w = 0; w < wv; ++w) pre += wtmp[w];
+    out[t] = pre + x - v;
+    if (t == 255) out[256] = pre + x;
+    __syncthreads();
+}
+
+// Adjoint over one block of B0 x B1 x B2 cells (ScatterSum, Sec. III.A, done
+// in two levels like the paper's partial-then-global reduction): the forces on
+// the block's atoms and on its one-cell halo accumulate in LDS with LDS
+// atomics, located through the stencil offset each list entry recorded; the
+// block then adds its accumulators to F with coalesced device atomics, one
+// range per halo cell.
+template <int KC, int M>
+__global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom bg) {
+    extern __shared__ float sF[];  // [3][hmax]
+    __shared__ int32_t h_base[257], h_first[kMaxHaloCells];
+    __shared__ int32_t i_base[257], i_first[kMaxBlockCells];
+    __shared__ int32_t wtmp[kBlock / 64];
+    __shared__ double red[6][kBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int blk = blockIdx.x;
+    const int bx = blk % bg.nb[0], by = (blk / bg.nb[0]) % bg.nb[1], bz = blk / (bg.nb[0] * bg.nb[1]);
+    const int x0 = bx * bg.B[0], y0 = by * bg.B[1], z0 = bz * bg.B[2];
+    const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
+    const int nh = HX * HY * HZ, nI = bg.B[0] * bg.B[1] * bg.B[2];
+    int hcount = 0, icount = 0;
+    if (t < nh) {
+        const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
+        const int gc = (wrap_cell(z0 - 1 + hz, bg.nc[2]) * bg.nc[1] + wrap_cell(y0 - 1 + hy, bg.nc[1])) * bg.nc[0] +
+                       wrap_cell(x0 - 1 + hx, bg.nc[0]);
+        h_first[t] = bg.cellstart[gc];
+        hcount = bg.cellstart[gc + 1] - h_first[t];
+    }
+    if (t < nI) {
+        const int cx = x0 + t % bg.B[0], cy = y0 + (t / bg.B[0]) % bg.B[1], cz = z0 + t / (bg.B[0] * bg.B[1]);
+        i_first[t] = 0;
+        if (cx < bg.nc[0] && cy < bg.nc[1] && cz < bg.nc[2]) {
+            const int gc = (cz * bg.nc[1] + cy) * bg.nc[0] + cx;
+            i_first[t] = bg.cellstart[gc];
+            icount = bg.cellstart[gc + 1] - i_first[t];
+        }
+    }
+    scan256(hcount, h_base, wtmp);
+    scan256(icount, i_base, wtmp);
+    const int htot = h_base[nh];
+    for (int i = t; i < htot; i += kBlock) {
+        sF[i] = 0.0f;
+        sF[bg.hmax + i] = 0.0f;
+        sF[2 * bg.hmax + i] = 0.0f;
+    }
+    __syncthreads();
+    const int nch = 1 << a.nch_log2;
+    const int items = i_base[nI] << a.nch_log2;
+    float W6[6] = {0, 0, 0, 0, 0, 0};
+    for (int item = t; item < ((items + kBlock - 1) / kBlock) * kBlock; item += kBlock) {
+        if (item >= items) continue;
+        const int la = item >> a.nch_log2, ch = item & (nch - 1);
+        int ic = 0;
+        while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
+        const int64_t p = i_first[ic] + (la - i_base[ic]);
+        const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
+        float Fo[3] = {0.0f, 0.0f, 0.0f};
+        adjoint_atom<KC, M>(a, p, ch, nch, W6, Fo, [&](int q, int o, float gx, float gy, float gz) {
+            const int hq = ((iz + o / 9 - 1) * HY + (iy + (o / 3) % 3 - 1)) * HX + (ix + o % 3 - 1);
+            const int idx = h_base[hq] + (q - h_first[hq]);
+            atomicAdd(&sF[idx], -gx);
+            atomicAdd(&sF[bg.hmax + idx], -gy);
+            atomicAdd(&sF[2 * bg.hmax + idx], -gz);
+        });
+        if (ch == 0) {
+            const int hp = (iz * HY + iy) * HX + ix;
+            const int idx = h_base[hp] + (int)(p - h_first[hp]);
+            atomicAdd(&sF[idx], Fo[0]);
+            atomicAdd(&sF[bg.hmax + idx], Fo[1]);
+            atomicAdd(&sF[2 * bg.hmax + idx], Fo[2]);
+        }
+    }
+    __syncthreads();
+    for (int hc = wv; hc < nh; hc += kBlock / 64) {
+        const int lo = h_base[hc], cnt = h_base[hc + 1] - lo;
+        for (int k = lane; k < cnt; k += 64) {
+            const int64_t q = h_first[hc] + k;
+            const float fx = sF[lo + k], fy = sF[bg.hmax + lo + k], fz = sF[2 * bg.hmax + lo + k];
+            if (fx != 0.0f) unsafeAtomicAdd(&bg.F[3 * q + 0], fx);
+            if (fy != 0.0f) unsafeAtomicAdd(&bg.F[3 * q + 1], fy);
+            if (fz != 0.0f) unsafeAtomicAdd(&bg.F[3 * q + 2], fz);
+        }
+    }
+    block_virial(W6, red, a.vir + (int64_t)blockIdx.x * 6);
+}
+
+using PathFn = void (*)(PathArgs);
+using AtomicFn = void (*)(PathArgs, float*);
+using BlockedFn = void (*)(PathArgs, BlockGeom);
 
 template <int KC>
-KernelFn<KC> pick_desc(int M) {
+PathFn pick_desc(int M) {
     switch (M) {
         case 0: return k_descriptor<KC, 0>;
         case 1: return k_descriptor<KC, 1>;
@@ -363,20 +537,43 @@ KernelFn<KC> pick_desc(int M) {
     }
 }
 template <int KC>
-KernelFn<KC> pick_adj(int M) {
+AtomicFn pick_atomic(int M) {
     switch (M) {
-        case 0: return k_adjoint<KC, 0>;
-        case 1: return k_adjoint<KC, 1>;
-        case 2: return k_adjoint<KC, 2>;
-        default: return k_adjoint<KC, 3>;
+        case 0: return k_adjoint_atomic<KC, 0>;
+        case 1: return k_adjoint_atomic<KC, 1>;
+        case 2: return k_adjoint_atomic<KC, 2>;
+        default: return k_adjoint_atomic<KC, 3>;
+    }
+}
+template <int KC>
+BlockedFn pick_blocked(int M) {
+    switch (M) {
+        case 0: return k_adjoint_blocked<KC, 0>;
+        case 1: return k_adjoint_blocked<KC, 1>;
+        case 2: return k_adjoint_blocked<KC, 2>;
+        default: return k_adjoint_blocked<KC, 3>;
     }
 }
 
-void (*select_kernel(int kc, int M, bool adjoint))(PathArgs) {
+PathFn select_desc(int kc, int M) {
     switch (kc) {
-        case 4: return adjoint ? pick_adj<4>(M) : pick_desc<4>(M);
-        case 6: return adjoint ? pick_adj<6>(M) : pick_desc<6>(M);
-        default: return adjoint ? pick_adj<8>(M) : pick_desc<8>(M);
+        case 4: return pick_desc<4>(M);
+        case 6: return pick_desc<6>(M);
+        default: return pick_desc<8>(M);
+    }
+}
+AtomicFn select_atomic(int kc, int M) {
+    switch (kc) {
+        case 4: return pick_atomic<4>(M);
+        case 6: return pick_atomic<6>(M);
+        default: return pick_atomic<8>(M);
+    }
+}
+BlockedFn select_blocked(int kc, int M) {
+    switch (kc) {
+        case 4: return pick_blocked<4>(M);
+        case 6: return pick_blocked<6>(M);
+        default: return pick_blocked<8>(M);
     }
 }
 
@@ -409,14 +606,41 @@ unsigned path_grid(const tmd_model* m, const tmd_nlist* nl) {
     return (unsigned)((threads + kBlock - 1) / kBlock);
 }
 
+constexpr size_t kMaxDynLds = 56 * 1024;
+
+// Largest block shape whose halo accumulators fit in LDS for the densest cell.
+bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
+    static const int shapes[][3] = {{4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+    for (const auto& sh : shapes) {
+        int B[3], H = 1;
+        for (int d = 0; d < 3; ++d) {
+            B[d] = std::min(sh[d], nl->nc[d]);
+            H *= B[d] + 2;
+        }
+        const int64_t hmax = (int64_t)H * std::max(1, nl->max_occ);
+        if (hmax * 3 * (int64_t)sizeof(float) > (int64_t)kMaxDynLds) continue;
+        for (int d = 0; d < 3; ++d) {
+            bg->nc[d] = nl->nc[d];
+            bg->B[d] = B[d];
+            bg->nb[d] = (nl->nc[d] + B[d] - 1) / B[d];
+        }
+        bg->hmax = (int)hmax;
+        return true;
+    }
+    return false;
+}
+
 }  // namespace
 
-int adjoint_blocks(const tmd_model* m, const tmd_nlist* nl) { return (int)path_grid(m, nl); }
+int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl) {
+    return std::max<int64_t>((int64_t)path_grid(m, nl), nl->ncells);
+}
 
-tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G) {
+tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf) {
     PathArgs a = make_args(m, nl);
     a.G = G;
-    auto fn = select_kernel(m->kc, m->M, false);
+    a.Pbuf = Pbuf;
+    auto fn = select_desc(m->kc, m->M);
     {
         ProfScope ps_(ctx, "descriptor");
         fn<<<path_grid(m, nl), kBlock, 0, ctx->stream>>>(a);
@@ -425,21 +649,34 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     return TMD_OK;
 }
 
-tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Fown,
-                          float* Fin, double* vir_partials, int* nblocks_out) {
+tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Pbuf,
+                          float* Fsorted, double* vir_partials, int* nvir_out) {
     PathArgs a = make_args(m, nl);
     a.dG = dG;
-    a.Fown = Fown;
-    a.Fin = Fin;
+    a.Pbuf = Pbuf;
     a.vir = vir_partials;
-    const unsigned grid = path_grid(m, nl);
-    auto fn = select_kernel(m->kc, m->M, true);
-    {
-        ProfScope ps_(ctx, "adjoint");
-        fn<<<grid, kBlock, 0, ctx->stream>>>(a);
+    TMD_HIP(ctx, hipMemsetAsync(Fsorted, 0, sizeof(float) * 3 * nl->n, ctx->stream));
+    BlockGeom bg{};
+    if (nl->narrow && choose_blocks(nl, &bg)) {
+        bg.cellstart = nl->cellstart;
+        bg.F = Fsorted;
+        const unsigned grid = (unsigned)bg.nb[0] * bg.nb[1] * bg.nb[2];
+        auto fn = select_blocked(m->kc, m->M);
+        {
+            ProfScope ps_(ctx, "adjoint");
+            fn<<<grid, kBlock, sizeof(float) * 3 * (size_t)bg.hmax, ctx->stream>>>(a, bg);
+        }
+        *nvir_out = (int)grid;
+    } else {
+        const unsigned grid = path_grid(m, nl);
+        auto fn = select_atomic(m->kc, m->M);
+        {
+            ProfScope ps_(ctx, "adjoint");
+            fn<<<grid, kBlock, 0, ctx->stream>>>(a, Fsorted);
+        }
+        *nvir_out = (int)grid;
     }
     TMD_HIP(ctx, hipGetLastError());
-    *nblocks_out = (int)grid;
     return TMD_OK;
 }
 

@@ -24,14 +24,15 @@ __device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
     return a;
 }
 
+// Forces and atomic energies back to the caller's atom order.
 __global__ void k_scatter_out(int64_t n, const int32_t* __restrict__ perm, const float* __restrict__ Ei,
-                              const float* __restrict__ Fown, const float* __restrict__ Fin,
-                              float* __restrict__ atom_energy, float* __restrict__ forces) {
+                              const float* __restrict__ Fs, float* __restrict__ atom_energy, float* __restrict__ forces) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t i = perm[p];
-#pragma unroll
-    for (int x = 0; x < 3; ++x) forces[3 * i + x] = Fown[3 * p + x] + Fin[3 * p + x];
+    forces[3 * i + 0] = Fs[3 * p + 0];
+    forces[3 * i + 1] = Fs[3 * p + 1];
+    forces[3 * i + 2] = Fs[3 * p + 2];
     if (atom_energy) atom_energy[i] = Ei[p];
 }
 
@@ -107,13 +108,12 @@ __global__ void k_permute_rows(int64_t n, int width, const int32_t* __restrict__
 
 }  // namespace
 
-tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fown,
-                           const float* Fin, const double* vir_partials, int nvir, float* atom_energy,
-                           float* forces, double* totals7) {
+tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fs,
+                           const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7) {
     const int64_t n = nl->n;
     {
         ProfScope ps_(ctx, "scatter_out");
-        k_scatter_out<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, nl->perm, Ei, Fown, Fin,
+        k_scatter_out<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, nl->perm, Ei, Fs,
                                                                                          atom_energy, forces);
     }
     hipError_t e = hipSuccess;

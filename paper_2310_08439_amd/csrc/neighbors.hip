@@ -66,29 +66,57 @@ __global__ void k_bin(int64_t n, const double* __restrict__ pos, const int32_t* 
     atomicAdd(&cellcount[cell], 1);
 }
 
-// Exclusive scan of the cell counts by one block (cells are few: about N/14).
+// Exclusive scan by one block of 1024 threads over tiles of 1024 consecutive
+// elements in[q * stride] (coalesced for stride 1); out[n] receives the total.
+__device__ void block_exclusive_scan(int64_t n, const int32_t* __restrict__ in, int stride,
+                                     int32_t* __restrict__ out, int out_stride) {
+    __shared__ int32_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int32_t carry = 0;
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int64_t q = base + t;
+        const int32_t v = q < n ? in[q * stride] : 0;
+        int32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const int32_t s = wsum[w];
+            pre += (w < wv) ? s : 0;
+            tot += s;
+        }
+        if (q < n) out[q * out_stride] = carry + pre + x - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) out[n * out_stride] = carry;
+}
+
+// Exclusive scan of the cell counts (cells are few: about N/14).
 __global__ void __launch_bounds__(1024) k_scan_cells(int64_t ncells, const int32_t* __restrict__ count,
-                                                     int32_t* __restrict__ start) {
-    __shared__ int32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (ncells + 1023) / 1024;
-    const int64_t lo = t * per, hi = min<int64_t>(ncells, lo + per);
-    int32_t s = 0;
-    for (int64_t q = lo; q < hi; ++q) s += count[q];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = t >= off ? part[t - off] : 0;
+                                                     int32_t* __restrict__ start, int32_t* __restrict__ max_occ) {
+    block_exclusive_scan(ncells, count, 1, start, 1);
+    int32_t m = 0;
+    for (int64_t q = threadIdx.x; q < ncells; q += 1024) m = max(m, count[q]);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_occ, m);
+}
+
+// Per-species exclusive scans over the per-block species counts; the totals
+// go to spcount[s] for the host.
+__global__ void __launch_bounds__(1024) k_species_scan(int64_t nblk, int S, const int32_t* __restrict__ blkcnt,
+                                                       int32_t* __restrict__ blkoff, int32_t* __restrict__ spcount) {
+    for (int s = 0; s < S; ++s) {
+        block_exclusive_scan(nblk, blkcnt + s, kMaxSpecies, blkoff + s, kMaxSpecies);
         __syncthreads();
-        part[t] += v;
+        if (threadIdx.x == 0) spcount[s] = blkoff[nblk * kMaxSpecies + s];
         __syncthreads();
     }
-    int32_t run = part[t] - s;
-    for (int64_t q = lo; q < hi; ++q) {
-        start[q] = run;
-        run += count[q];
-    }
-    if (t == 1023) start[ncells] = part[1023];
 }
 
 __global__ void k_place(int64_t n, const int32_t* __restrict__ cell_of, const int32_t* __restrict__ start,
@@ -121,7 +149,7 @@ __global__ void k_gather_sorted(int64_t n, const int32_t* __restrict__ order, co
                                 const double* __restrict__ pos, const int32_t* __restrict__ species, GridArgs g,
                                 int32_t* __restrict__ perm, int32_t* __restrict__ shift, double4* __restrict__ xs,
                                 int32_t* __restrict__ sp, int32_t* __restrict__ cell_sorted,
-                                const int32_t* __restrict__ cell_of, int32_t* __restrict__ spcount) {
+                                const int32_t* __restrict__ cell_of, int32_t* __restrict__ blkcnt) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < n;
     int s = -1;
@@ -140,12 +168,19 @@ __global__ void k_gather_sorted(int64_t n, const int32_t* __restrict__ order, co
         sp[p] = s;
         cell_sorted[p] = cell_of[i];
     }
-    // per-species counts: one atomic per wave and species (invalid species
-    // fail the build on the host and are not counted)
-    const int lane = threadIdx.x & 63;
+    // per-block species counts (invalid species fail the build on the host and
+    // are not counted); scanned over blocks by k_species_scan
+    __shared__ int32_t wc[kBlock / 64][kMaxSpecies];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int b = 0; b < kMaxSpecies; ++b) {
         const unsigned long long m = __ballot(s == b);
-        if (m && lane == 0) atomicAdd(&spcount[b], (int)__popcll(m));
+        if (lane == 0) wc[wv][b] = (int32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxSpecies) {
+        int32_t tot = 0;
+        for (int w = 0; w < kBlock / 64; ++w) tot += wc[w][threadIdx.x];
+        blkcnt[(int64_t)blockIdx.x * kMaxSpecies + threadIdx.x] = tot;
     }
 }
 
@@ -162,6 +197,7 @@ struct FillArgs {
     int32_t* img;
     int32_t* cnt;
     int32_t* flags;
+    bool narrow;       // 3x3x3 stencil: entries record their stencil offset code
 };
 
 __device__ inline int floor_div(int a, int b) {
@@ -185,6 +221,7 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
 #pragma unroll
     for (int b = 0; b < kMaxSpecies; ++b) cnt[b] = 0;
     bool coincident = false;
+    int o = 0;  // stencil offset index in traversal order
     for (int oz = -g.reach[2]; oz <= g.reach[2]; ++oz) {
         const int zz = cz + oz;
         const int nz = floor_div(zz, g.nc[2]);
@@ -203,25 +240,37 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
                 const int c2 = (wz * g.nc[1] + wy) * g.nc[0] + wx;
                 const int lo = a.cellstart[c2], hi = a.cellstart[c2 + 1];
                 const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
-                for (int q = lo; q < hi; ++q) {
-                    if (zero_img && q == p) continue;
-                    const double4 xj = a.xs[q];
-                    const double dx = __dadd_rn(__dsub_rn(xj.x, xi.x), sx);
-                    const double dy = __dadd_rn(__dsub_rn(xj.y, xi.y), sy);
-                    const double dz = __dadd_rn(__dsub_rn(xj.z, xi.z), sz);
-                    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-                    if (!(d2 < a.rl2)) continue;
-                    if (d2 == 0.0) coincident = true;
-                    const int b = a.sp[q];
-                    if (b < 0 || b >= a.S) continue;  // reported by k_bin; never index with it
-                    int k = 0;
+                // stencil offset code of this cell (0..26), stored with each entry when the stencil is 3x3x3
+                const int ocode = a.narrow ? o : 255;
+                ++o;
+                // candidates in batches of 4: all position loads issued first
+                for (int q0 = lo; q0 < hi; q0 += 4) {
+                    double4 xj[4];
 #pragma unroll
-                    for (int bb = 0; bb < kMaxSpecies; ++bb)
-                        if (bb == b) { k = cnt[bb]; cnt[bb] = k + 1; }
-                    if (k < a.cap) {
-                        const int64_t off = ((int64_t)b * a.cap + k) * a.n + p;
-                        a.nbr[off] = q;
-                        a.img[off] = pack_img(nx, ny, nz);
+                    for (int j = 0; j < 4; ++j) xj[j] = a.xs[min(q0 + j, hi - 1)];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int q = q0 + j;
+                        if (q >= hi || (zero_img && q == p)) continue;
+                        const double dx = __dadd_rn(__dsub_rn(xj[j].x, xi.x), sx);
+                        const double dy = __dadd_rn(__dsub_rn(xj[j].y, xi.y), sy);
+                        const double dz = __dadd_rn(__dsub_rn(xj[j].z, xi.z), sz);
+                        const double d2 =
+                            __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+                        if (!(d2 < a.rl2)) continue;
+                        if (d2 == 0.0) coincident = true;
+                        const int b = a.sp[q];
+                        if (b < 0 || b >= a.S) continue;  // reported by k_bin; never index with it
+                        int k = 0;
+#pragma unroll
+                        for (int bb = 0; bb < kMaxSpecies; ++bb)
+                            if (bb == b) { k = cnt[bb]; cnt[bb] = k + 1; }
+                        if (k < a.cap) {
+                            // row-major: this thread's entries are consecutive addresses
+                            const int64_t off = (p * a.S + b) * a.cap + k;
+                            a.nbr[off] = q;
+                            a.img[off] = pack_img(nx, ny, nz, ocode);
+                        }
                     }
                 }
             }
@@ -237,20 +286,131 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
     if (coincident) atomicOr(&a.flags[0], kErrCoincident);
 }
 
+constexpr int kMaxCellAtoms = 64;
+
+// One wave per cell (stencils of at most 64 cells, cells of at most 64 atoms).
+// Each round the wave holds 64 candidates of the cell's stencil, in the same
+// order as k_fill visits them (stencil cell, then atom), and tests them with
+// the same FP64 predicate against every atom of the cell in turn.  An atom's
+// accepted candidates are compacted with a ballot and written to its row as
+// one contiguous run per species, so the list is identical to k_fill's while
+// every load and store of the wave is coalesced.
+__global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) {
+    __shared__ int32_t cnt_lds[kBlock / 64][kMaxCellAtoms][kMaxSpecies];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t cell = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+    if (cell >= ncells) return;  // whole wave
+    const GridArgs& g = a.g;
+    const int cx = (int)(cell % g.nc[0]), cy = (int)((cell / g.nc[0]) % g.nc[1]),
+              cz = (int)(cell / ((int64_t)g.nc[0] * g.nc[1]));
+    const int a0 = a.cellstart[cell], natoms = a.cellstart[cell + 1] - a0;
+    if (natoms == 0) return;  // nothing to list (and a0 may equal n)
+    if (natoms > kMaxCellAtoms) {  // the host reruns the build with k_fill
+        if (lane == 0) atomicOr(&a.flags[2], 1);
+        return;
+    }
+    const int wx = 2 * g.reach[0] + 1, wy = 2 * g.reach[1] + 1, wz = 2 * g.reach[2] + 1;
+    const int ns = wx * wy * wz;
+    // stencil cell of this lane (traversal order: z outer, x inner)
+    int first = 0, count = 0;
+    if (lane < ns) {
+        const int ox = lane % wx - g.reach[0], oy = (lane / wx) % wy - g.reach[1], oz = lane / (wx * wy) - g.reach[2];
+        const int xx = cx + ox, yy = cy + oy, zz = cz + oz;
+        const int nx = floor_div(xx, g.nc[0]), ny = floor_div(yy, g.nc[1]), nz = floor_div(zz, g.nc[2]);
+        const int c2 = ((zz - nz * g.nc[2]) * g.nc[1] + (yy - ny * g.nc[1])) * g.nc[0] + (xx - nx * g.nc[0]);
+        first = a.cellstart[c2];
+        count = a.cellstart[c2 + 1] - first;
+    }
+    int pre = count;  // inclusive scan over the stencil cells
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(pre, off);
+        if (lane >= off) pre += y;
+    }
+    const int total = __shfl(pre, 63);
+    pre -= count;  // exclusive
+    for (int i = lane; i < natoms * kMaxSpecies; i += 64) cnt_lds[wv][i / kMaxSpecies][i % kMaxSpecies] = 0;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool coincident = false;
+    for (int k0 = 0; k0 < total; k0 += 64) {
+        const int k = k0 + lane;
+        const bool valid = k < total;
+        // stencil cell holding candidate k: the last cell whose start is <= k
+        int sk = 0;
+        for (int s = 1; s < ns; ++s)
+            if (__builtin_amdgcn_readlane(pre, s) <= k) sk = s;
+        const int ox = sk % wx - g.reach[0], oy = (sk / wx) % wy - g.reach[1], oz = sk / (wx * wy) - g.reach[2];
+        const int nx = floor_div(cx + ox, g.nc[0]), ny = floor_div(cy + oy, g.nc[1]), nz = floor_div(cz + oz, g.nc[2]);
+        const double sx = __dmul_rn((double)nx, g.L[0]);
+        const double sy = __dmul_rn((double)ny, g.L[1]);
+        const double sz = __dmul_rn((double)nz, g.L[2]);
+        // every lane takes part in both shuffles (a shuffle from a lane that
+        // is inactive in a branch yields undefined data); select afterwards
+        const int first_sk = __shfl(first, sk);
+        const int pre_sk = __shfl(pre, sk);
+        const int q = valid ? first_sk + (k - pre_sk) : a0;
+        const double4 xj = a.xs[q];
+        const int bq = valid ? a.sp[q] : -1;
+        const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
+        const int32_t word = pack_img(nx, ny, nz, a.narrow ? sk : 255);
+        for (int i = 0; i < natoms; ++i) {
+            const int p = a0 + i;
+            const double4 xi = a.xs[p];
+            const double dx = __dadd_rn(__dsub_rn(xj.x, xi.x), sx);
+            const double dy = __dadd_rn(__dsub_rn(xj.y, xi.y), sy);
+            const double dz = __dadd_rn(__dsub_rn(xj.z, xi.z), sz);
+            const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            const bool acc = valid && !(zero_img && q == p) && d2 < a.rl2 && bq >= 0 && bq < a.S;
+            if (acc && d2 == 0.0) coincident = true;
+            for (int b = 0; b < a.S; ++b) {
+                const unsigned long long m = __ballot(acc && bq == b);
+                if (!m) continue;
+                const int base = cnt_lds[wv][i][b];
+                if (acc && bq == b) {
+                    const int c = base + (int)__popcll(m & below);
+                    if (c < a.cap) {
+                        const int64_t off = ((int64_t)p * a.S + b) * a.cap + c;
+                        a.nbr[off] = q;
+                        a.img[off] = word;
+                    }
+                }
+                if (lane == 0) cnt_lds[wv][i][b] = base + (int)__popcll(m);
+            }
+        }
+    }
+    int mx = 0;
+    if (lane < natoms) {
+        const int p = a0 + lane;
+        for (int b = 0; b < a.S; ++b) {
+            const int c = cnt_lds[wv][lane][b];
+            a.cnt[(int64_t)b * a.n + p] = min(c, a.cap);
+            mx = max(mx, c);
+        }
+    }
+    if (mx > a.cap) atomicMax(&a.flags[1], mx);
+    if (coincident) atomicOr(&a.flags[0], kErrCoincident);
+}
+
+// Atoms grouped by species in sorted order, without atomics: block offsets
+// from k_species_scan, wave offsets from the block's ballots, lane rank.
 __global__ void k_species_place(int64_t n, const int32_t* __restrict__ sp, const int64_t* __restrict__ sp_off,
-                                int32_t* __restrict__ sp_fill, int32_t* __restrict__ sp_idx) {
+                                const int32_t* __restrict__ blkoff, int32_t* __restrict__ sp_idx) {
+    __shared__ int32_t wc[kBlock / 64][kMaxSpecies];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = p < n ? sp[p] : -1;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // one atomic per wave and species reserves the slots; lanes take them in lane order
+    unsigned long long mine = 0;
     for (int b = 0; b < kMaxSpecies; ++b) {
         const unsigned long long m = __ballot(s == b);
-        if (!m) continue;
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&sp_fill[b], (int)__popcll(m));
-        base = __shfl(base, 0);
-        if (s == b) sp_idx[sp_off[b] + base + (int)__popcll(m & below)] = (int32_t)p;
+        if (lane == 0) wc[wv][b] = (int32_t)__popcll(m);
+        if (s == b) mine = m;
+    }
+    __syncthreads();
+    if (s >= 0 && s < kMaxSpecies) {
+        int32_t woff = 0;
+        for (int w = 0; w < wv; ++w) woff += wc[w][s];
+        sp_idx[sp_off[s] + blkoff[(int64_t)blockIdx.x * kMaxSpecies + s] + woff + (int)__popcll(mine & below)] =
+            (int32_t)p;
     }
 }
 
@@ -264,7 +424,7 @@ __global__ void k_export(int64_t n, int S, int cap, const int32_t* __restrict__ 
         const int c = cnt[(int64_t)b * n + p];
         ocnt[i * S + b] = c;
         for (int k = 0; k < cap; ++k) {
-            const int64_t src = ((int64_t)b * cap + k) * n + p;
+            const int64_t src = (p * S + b) * cap + k;
             const int64_t dst = (i * S + b) * cap + k;
             if (k < c) {
                 onbr[dst] = perm[nbr[src]];
@@ -342,19 +502,29 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
             return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "box edge far smaller than the cutoff");
     }
     hipError_t e = hipSuccess;
+    const int64_t nblk = (n + kBlock - 1) / kBlock;
+    const bool narrow = g.reach[0] == 1 && g.reach[1] == 1 && g.reach[2] == 1;
+    if (nl->cellstart_cap < ncells + 1) {
+        if (nl->cellstart) (void)hipFree(nl->cellstart);
+        nl->cellstart = nullptr;
+        nl->cellstart_cap = 0;
+        TMD_HIP(ctx, hipMalloc((void**)&nl->cellstart, sizeof(int32_t) * (ncells + 1)));
+        nl->cellstart_cap = ncells + 1;
+    }
+    int32_t* cellstart = nl->cellstart;
     double* wpos = (double*)ctx->ws.get("nb.wpos", sizeof(double) * 3 * n, &e);
     int32_t* cell_of = (int32_t*)ctx->ws.get("nb.cell_of", sizeof(int32_t) * n, &e);
     int32_t* cell_sorted = (int32_t*)ctx->ws.get("nb.cell_sorted", sizeof(int32_t) * n, &e);
     int32_t* order = (int32_t*)ctx->ws.get("nb.order", sizeof(int32_t) * n, &e);
     int32_t* cellcount = (int32_t*)ctx->ws.get("nb.cellcount", sizeof(int32_t) * (ncells + 1), &e);
     int32_t* cellfill = (int32_t*)ctx->ws.get("nb.cellfill", sizeof(int32_t) * (ncells + 1), &e);
-    int32_t* cellstart = (int32_t*)ctx->ws.get("nb.cellstart", sizeof(int32_t) * (ncells + 1), &e);
+    int32_t* blkcnt = (int32_t*)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
+    int32_t* blkoff = (int32_t*)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
     int32_t* flags = (int32_t*)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
     int64_t* sp_off_d = (int64_t*)ctx->ws.get("nb.sp_off", sizeof(int64_t) * (kMaxSpecies + 1), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "neighbour workspace allocation");
     hipStream_t st = ctx->stream;
     int32_t* spcount = flags + 8;
-    int32_t* spfill = flags + 24;
     TMD_HIP(ctx, hipMemsetAsync(cellcount, 0, sizeof(int32_t) * (ncells + 1), st));
     TMD_HIP(ctx, hipMemsetAsync(cellfill, 0, sizeof(int32_t) * (ncells + 1), st));
     TMD_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 64, st));
@@ -365,7 +535,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     }
     {
         ProfScope ps_(ctx, "nb_scan");
-        k_scan_cells<<<1, 1024, 0, st>>>(ncells, cellcount, cellstart);
+        k_scan_cells<<<1, 1024, 0, st>>>(ncells, cellcount, cellstart, flags + 4);
     }
     {
         ProfScope ps_(ctx, "nb_place");
@@ -378,7 +548,11 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     {
         ProfScope ps_(ctx, "nb_gather");
         k_gather_sorted<<<grid_for(n), kBlock, 0, st>>>(n, order, wpos, sys->pos, sys->species, g, nl->perm, nl->shift,
-                                                         nl->xs, nl->sp, cell_sorted, cell_of, spcount);
+                                                         nl->xs, nl->sp, cell_sorted, cell_of, blkcnt);
+    }
+    {
+        ProfScope ps_(ctx, "nb_species_scan");
+        k_species_scan<<<1, 1024, 0, st>>>(nblk, nl->S, blkcnt, blkoff, spcount);
     }
     FillArgs fa;
     fa.g = g;
@@ -394,13 +568,29 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     fa.img = nl->img;
     fa.cnt = nl->cnt;
     fa.flags = flags;
-    {
+    fa.narrow = narrow;
+    const int stencil_cells = (2 * g.reach[0] + 1) * (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
+    const bool by_cell = stencil_cells <= 64;
+    if (by_cell) {
+        ProfScope ps_(ctx, "nb_fill");
+        k_fill_cells<<<(unsigned)((ncells + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(fa, ncells);
+    } else {
         ProfScope ps_(ctx, "nb_fill");
         k_fill<<<grid_for(n), kBlock, 0, st>>>(fa);
     }
     TMD_HIP(ctx, hipGetLastError());
     TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, flags, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, st));
     TMD_HIP(ctx, hipStreamSynchronize(st));
+    if (by_cell && (ctx->h_flags[2] & 1)) {
+        // a cell holds more atoms than one wave can track: per-atom fill instead
+        {
+            ProfScope ps_(ctx, "nb_fill");
+            k_fill<<<grid_for(n), kBlock, 0, st>>>(fa);
+        }
+        TMD_HIP(ctx, hipGetLastError());
+        TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, flags, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, st));
+        TMD_HIP(ctx, hipStreamSynchronize(st));
+    }
     const int32_t errs = ctx->h_flags[0];
     if (errs & kErrSpecies) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "species index outside [0, n_species)");
     if (errs & kErrNonFinite) return fail(ctx, TMD_ERR_NUMERICAL, "non-finite atomic position");
@@ -423,13 +613,15 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     TMD_HIP(ctx, hipMemcpyAsync(sp_off_d, nl->sp_off, sizeof(int64_t) * (kMaxSpecies + 1), hipMemcpyHostToDevice, st));
     {
         ProfScope ps_(ctx, "nb_species");
-        k_species_place<<<grid_for(n), kBlock, 0, st>>>(n, nl->sp, sp_off_d, spfill, nl->sp_idx);
+        k_species_place<<<grid_for(n), kBlock, 0, st>>>(n, nl->sp, sp_off_d, blkoff, nl->sp_idx);
     }
     TMD_HIP(ctx, hipGetLastError());
-    // sp_off_d is read by the kernel above before any later host write to it
     TMD_HIP(ctx, hipStreamSynchronize(st));
     nl->n = n;
     nl->rlist = rlist;
+    nl->ncells = ncells;
+    nl->max_occ = ctx->h_flags[4];
+    nl->narrow = narrow;
     for (int a = 0; a < 3; ++a) {
         nl->box[a] = sys->box[a];
         nl->nc[a] = g.nc[a];

@@ -115,10 +115,16 @@ struct tmd_nlist {
     int32_t* shift = nullptr;    // [n][3] wrap shift: x_wrapped = x + shift * L
     double4* xs = nullptr;       // [n]   positions used by the kernels
     int32_t* sp = nullptr;       // [n]   species
-    int32_t* nbr = nullptr;      // [S][cap][n] neighbour (sorted index)
-    int32_t* img = nullptr;      // [S][cap][n] periodic image, int8 x 3 packed
+    int32_t* nbr = nullptr;      // [n][S][cap] neighbour (sorted index), row-major per atom
+    int32_t* img = nullptr;      // [n][S][cap] image word (pack_img)
     int32_t* cnt = nullptr;      // [S][n]
     int32_t* sp_idx = nullptr;   // [n] sorted indices grouped by species
+    // cell structure of the last build (sorted atoms are cell-major)
+    int32_t* cellstart = nullptr;  // [ncells + 1]
+    int64_t cellstart_cap = 0;
+    int64_t ncells = 0;
+    int max_occ = 0;               // most atoms in one cell
+    bool narrow = false;           // 3x3x3 stencil (every reach is 1)
 };
 
 namespace tmd {
@@ -133,10 +139,13 @@ tmd_status hip_fail(tmd_context* ctx, hipError_t e, const char* what);
         if (e_ != hipSuccess) return tmd::hip_fail((ctx), e_, #call); \
     } while (0)
 
-// Image code: three signed 8-bit components.
-__host__ __device__ inline int32_t pack_img(int nx, int ny, int nz) {
-    return (int32_t)((uint32_t)(nx & 0xff) | ((uint32_t)(ny & 0xff) << 8) | ((uint32_t)(nz & 0xff) << 16));
+// Image word of a list entry: three signed 8-bit image components and, in the
+// top byte, the entry's stencil cell offset code (0..26, or 255 when unused).
+__host__ __device__ inline int32_t pack_img(int nx, int ny, int nz, int ocode = 255) {
+    return (int32_t)((uint32_t)(nx & 0xff) | ((uint32_t)(ny & 0xff) << 8) | ((uint32_t)(nz & 0xff) << 16) |
+                     ((uint32_t)(ocode & 0xff) << 24));
 }
+__host__ __device__ inline int img_ocode(int32_t c) { return (int)(((uint32_t)c >> 24) & 0xff); }
 __host__ __device__ inline void unpack_img(int32_t c, int& nx, int& ny, int& nz) {
     nx = (int)(int8_t)(c & 0xff);
     ny = (int)(int8_t)((c >> 8) & 0xff);
@@ -147,19 +156,22 @@ __host__ __device__ inline void unpack_img(int32_t c, int& nx, int& ny, int& nz)
 tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, double rlist, tmd_nlist* nl,
                                   int32_t* required_capacity);
 tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl);
-tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G);
+// Descriptors G [n][F] (sorted order); when Pbuf is non-null the per-atom P
+// tensors [n][S][K][D] are kept there for the adjoint.
+tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf);
 tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* G, float* Ei,
                       float* dG);
-tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG,
-                          float* Fown, float* Fin, double* vir_partials, int* nblocks_out);
-tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fown,
-                           const float* Fin, const double* vir_partials, int nvir, float* atom_energy,
-                           float* forces, double* totals7);
+// Adjoint: forces accumulated into Fsorted [n][3] (zeroed by the launcher),
+// virial block partials into vir_partials (count returned in *nvir_out).
+tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Pbuf,
+                          float* Fsorted, double* vir_partials, int* nvir_out);
+tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fsorted,
+                           const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7);
 tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, int width, float* out);
 tmd_status launch_export_nlist(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt);
 tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row);
 
-// Block size of the adjoint kernel, for sizing the virial partials.
-int adjoint_blocks(const tmd_model* m, const tmd_nlist* nl);
+// Upper bound on the virial partials the adjoint writes.
+int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl);
 
 }  // namespace tmd

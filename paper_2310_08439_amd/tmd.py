@@ -249,7 +249,7 @@ class NeighborList:
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.tmd_nlist_create(ctx.h, n_atoms, n_species, capacity, ctypes.byref(h)), "tmd_nlist_create")
         self.h = h
-        self.capacity = capacity
+        self.capacity = int(ctx.lib.tmd_nlist_capacity(h))
 
     def close(self):
         if getattr(self, "h", None):

@@ -256,6 +256,25 @@ def test_ragged_and_absent_species(tmd, ctx, torch):
     assert np.all(F[-1] == 0.0)
 
 
+@pytest.mark.parametrize("case", ["tiny_box_wide_stencil", "two_cells_per_edge", "three_cells_per_edge"])
+def test_energy_forces_cell_geometries(tmd, ctx, torch, case):
+    """Box shapes that exercise the force-scatter variants: an edge shorter than
+    the cutoff (stencil wider than 3x3x3, device atomics), and 2 or 3 cells per
+    edge (halo cells that are periodic copies of interior cells)."""
+    if case == "tiny_box_wide_stencil":
+        s = inputs.make_system("fcc", 3.61, (1, 1, 2), 0.08, 1, seed=90)
+        spec = inputs.make_model(1, 8, 3, [32], 5.0, seed=91)
+    elif case == "two_cells_per_edge":
+        s = inputs.make_system("fcc", 3.61, (4, 4, 4), 0.08, 2, seed=92)
+        spec = inputs.make_model(2, 8, 3, [64, 64], 6.0, seed=93)
+    else:
+        s = inputs.make_system("bcc", 3.16, (6, 6, 6), 0.08, 2, seed=94)
+        spec = inputs.make_model(2, 12, 3, [64, 64], 5.5, seed=95)
+    _note(f"cell geometry {case} n={s.n} box={s.box}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
+    _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+
+
 def test_skin_entries_contribute_nothing(tmd, ctx, torch):
     s, spec, _ = inputs.workload("oracle32")
     _note("skin 1.5")
