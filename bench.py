@@ -45,6 +45,40 @@ def algorithmic_flops(spec, n_atoms: int, pairs: int) -> dict:
     return {"descriptor": 2 * K * D * pairs, "adjoint": 4 * K * D * pairs, "mlp": mlp * n_atoms}
 
 
+# Profiler scope name -> (rocprofv3 kernel-name prefix, source file of that kernel)
+KERNEL_OF_SCOPE = {
+    "adjoint": ("k_adjoint", "paper_2310_08439_amd/csrc/descriptor.hip"),
+    "descriptor": ("k_descriptor", "paper_2310_08439_amd/csrc/descriptor.hip"),
+    "mlp": ("k_mlp<true", "paper_2310_08439_amd/csrc/mlp.hip"),
+    "nb_fill": ("k_fill", "paper_2310_08439_amd/csrc/neighbors.hip"),
+}
+
+
+def measured_traffic(workload: str, scope: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, each counter scaled by its copy-kernel calibration factor.
+    None when there is no summary or the kernel's source changed since it was taken."""
+    import hashlib
+    import re
+    if scope not in KERNEL_OF_SCOPE:
+        return None
+    prefix, src = KERNEL_OF_SCOPE[scope]
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"`" + re.escape(src) + r"`: `([0-9a-f]{64})`", text)
+    cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    if not m or m.group(1) != cur:
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) == 6 and f[0] == "traffic" and f[1].startswith(prefix.replace(" ", "")):
+            fetch_kib, write_kib, ff, wf = map(float, f[2:])
+            return int(fetch_kib * 1024 * ff + write_kib * 1024 * wf)
+    return None
+
+
 def cpu_baseline(seconds: float) -> dict:
     """The FP64 oracle (full E+F incl. its brute-force neighbour search) on the
     4,096-atom sub-cell of the same alloy and model, repeated for ~`seconds`."""
@@ -109,6 +143,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-samples", type=int, default=8)
+    ap.add_argument("--mode", default="step", choices=["step", "copy"],
+                    help="copy: 3 device copies of 1 GiB, to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the multi-GPU (spatial decomposition) path is a design, "
@@ -118,6 +154,16 @@ def main():
     import numpy as np
     import torch
     from paper_2310_08439_amd import inputs, tmd
+
+    if args.mode == "copy":
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_copy": src.numel() * 4,
+                          "bytes_written_per_copy": dst.numel() * 4}), flush=True)
+        return
 
     s, spec, skin = inputs.workload(args.workload)
     pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
@@ -142,8 +188,8 @@ def main():
             bound, peak = "alu", PEAK_FP32_VECTOR_TFLOPS
         achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
         roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "algorithmic_flops_per_launch": int(flops[dom])}
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, dom),
+                "algorithmic_flops_per_launch": int(flops[dom]), "avg_launch_ms": round(avg_ms[dom], 4)}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
                 "traffic": None}

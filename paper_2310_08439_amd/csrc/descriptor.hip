@@ -15,9 +15,10 @@
 // Thread mapping: one thread per (centre atom, chunk of KC radial functions);
 // the K/KC chunk threads of an atom are adjacent lanes.  Each thread keeps its
 // P (or P') tile of KC x D values in registers and streams the atom's
-// neighbours from the column-major list, recomputing the pair geometry.  No
-// intermediate per-pair tensor is stored: the only HBM traffic is the list,
-// the positions (gathered, cache-resident), G / dG and the outputs.
+// neighbours from its row of the row-major list, recomputing the pair
+// geometry.  The only per-pair data in HBM is the list itself; the descriptor
+// pass also stores P (K x D floats per atom and element) so that the adjoint
+// pass can form P' without a second neighbour sweep.
 // Per-pair force partials of the chunks are summed with lane shuffles.
 #include "tmd_internal.h"
 
@@ -262,7 +263,8 @@ __global__ void __launch_bounds__(256) k_descriptor(PathArgs a) {
 
 // Per-atom adjoint for one (atom, radial chunk) thread: P' from dE/dG, then for
 // every pair U, V and g = dE/dD (summed over the atom's chunk lanes).  The
-// chunk-0 lane hands each pair's g to sink(q, slot, gx, gy, gz), accumulates the
+// chunk-0 lane hands each pair's g to sink(q, code, gx, gy, gz) (code = the
+// pair's stencil-offset code), accumulates the
 // atom's own force sum in Fo and the virial in W6.
 template <int KC, int M, class Sink>
 __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int ch, int nch, float (&W6)[6],

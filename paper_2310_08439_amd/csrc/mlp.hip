@@ -2,7 +2,7 @@
 // dE_a/dG_a by back-propagation (Sec. III.A; the paper fuses forward and
 // backward of the dense network into one kernel and keeps both W and W^T,
 // which is also done here: the backward GEMMs read stored transposes so that
-// every MFMA operand load is contiguous).
+// every operand row is contiguous).
 //
 // All GEMMs run on MFMA in the transposed orientation Z^T = W A^T: hidden
 // units are the MFMA rows and 16 atoms form the MFMA columns.  With that
@@ -16,8 +16,10 @@
 //         group g the 8 operand slots hold units {4g..4g+3, 16+4g..16+4g+3}.
 //   FP32: v_mfma_f32_16x16x4_f32.  One K-step covers 4 units, lane group g
 //         holding unit 16*blk + 4g + r in step (blk, r).
-// Atoms of one species are processed together through the species index
-// list built with the neighbour list.
+// A workgroup of 4 waves takes 64 or 128 atoms of one species; each
+// layer's weights (forward or transposed) are staged once per workgroup into
+// LDS in column chunks with padded rows, and all four waves read their MFMA
+// A operands from there.
 #include "tmd_internal.h"
 
 namespace tmd {
@@ -26,6 +28,8 @@ namespace {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int kWaves = 4;
 
 struct MlpArgs {
     int S, F, Fpad, act;
@@ -46,6 +50,27 @@ struct MlpArgs {
     int L;
 };
 
+template <bool BF16>
+struct WT;
+template <>
+struct WT<true> {
+    using T = __hip_bfloat16;
+    static constexpr int kPad = 8;     // elements of row padding in LDS
+    static constexpr int kChunk = 128;  // columns staged at a time
+};
+template <>
+struct WT<false> {
+    using T = float;
+    static constexpr int kPad = 4;
+    static constexpr int kChunk = 64;
+};
+
+// LDS capacity in elements: 128 rows x (chunk + pad).
+template <bool BF16>
+constexpr int lds_elems() {
+    return 128 * (WT<BF16>::kChunk + WT<BF16>::kPad);
+}
+
 __device__ __forceinline__ float act_f(int act, float z) {
     if (act == TMD_ACT_SQUAREPLUS) return 0.5f * (z + __builtin_sqrtf(z * z + 4.0f));
     // tanh(z) = 1 - 2/(exp(2z)+1); saturates cleanly to +-1
@@ -57,9 +82,6 @@ __device__ __forceinline__ float act_df(int act, float z, float a) {
     return 1.0f - a * a;
 }
 
-__device__ __forceinline__ bf16x4 load_bf4(const __hip_bfloat16* p) {
-    return *reinterpret_cast<const bf16x4*>(p);
-}
 __device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
@@ -72,18 +94,112 @@ __device__ __forceinline__ bf16x4 to_bf4(f32x4 v) {
     return r;
 }
 
-// One wave: CB column blocks of 16 atoms of species s.
+// Stage rows [0, nrows) x columns [c0, c0 + nc) of a row-major matrix with
+// `ld` elements per row into LDS rows of stride nc + pad.  All threads of the
+// workgroup take part; callers synchronise around it.
+template <bool BF16>
+__device__ __forceinline__ void stage(const typename WT<BF16>::T* W, int ld, int nrows, int c0, int nc,
+                                      typename WT<BF16>::T* lds) {
+    using T = typename WT<BF16>::T;
+    constexpr int V = 16 / sizeof(T);
+    const int per_row = nc / V, stride = nc + WT<BF16>::kPad;
+    for (int c = threadIdx.x; c < nrows * per_row; c += blockDim.x) {
+        const int r = c / per_row, k = (c - r * per_row) * V;
+        *reinterpret_cast<uint4*>(lds + r * stride + k) =
+            *reinterpret_cast<const uint4*>(W + (int64_t)r * ld + c0 + k);
+    }
+}
+
+// B operand of the first layer: four consecutive features of one atom's
+// descriptor row, zero past the row's end.
+__device__ __forceinline__ f32x4 load_g4(const float* G, int64_t atom, int F, int g0, bool valid) {
+    f32x4 v = {0, 0, 0, 0};
+    if (!valid || g0 >= F) return v;
+    const float* row = G + atom * F;
+    if ((F & 3) == 0) return *reinterpret_cast<const f32x4*>(row + g0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (g0 + r < F) v[r] = row[g0 + r];
+    return v;
+}
+
+__device__ __forceinline__ void store_dg4(float* dG, int64_t atom, int F, int f0, bool valid, f32x4 v) {
+    if (!valid || f0 >= F) return;
+    float* row = dG + atom * F;
+    if ((F & 3) == 0) {
+        *reinterpret_cast<f32x4*>(row + f0) = v;
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (f0 + r < F) row[f0 + r] = v[r];
+}
+
+// Hidden layer (H x H): acc[ob][cb] += W x, x held in the accumulator layout
+// of the previous layer.  W is row-major [H][H] in global memory, staged
+// through LDS in CH-column chunks; all indices are compile-time.
+template <bool BF16, int H, int CB>
+__device__ __forceinline__ void dense_hidden(const typename WT<BF16>::T* W, typename WT<BF16>::T* lds,
+                                             const f32x4 (&x)[H / 16][CB], f32x4 (&acc)[H / 16][CB]) {
+    using T = typename WT<BF16>::T;
+    constexpr int NB = H / 16;
+    constexpr int CH = WT<BF16>::kChunk < H ? WT<BF16>::kChunk : H;
+    constexpr int stride = CH + WT<BF16>::kPad;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int c0 = 0; c0 < H; c0 += CH) {
+        __syncthreads();
+        stage<BF16>(W, H, H, c0, CH, lds);
+        __syncthreads();
+        if constexpr (BF16) {
+#pragma unroll
+            for (int k0 = 0; k0 < CH; k0 += 32) {
+                const int blk = (c0 + k0) / 16;
+                bf16x8 bop[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) bop[cb] = cat8(to_bf4(x[blk][cb]), to_bf4(x[blk + 1][cb]));
+#pragma unroll
+                for (int ob = 0; ob < NB; ++ob) {
+                    const T* wr = lds + (16 * ob + col) * stride + k0 + 4 * grp;
+                    const bf16x8 av =
+                        cat8(*reinterpret_cast<const bf16x4*>(wr), *reinterpret_cast<const bf16x4*>(wr + 16));
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[cb], acc[ob][cb], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k0 = 0; k0 < CH; k0 += 16) {
+                const int blk = (c0 + k0) / 16;
+#pragma unroll
+                for (int ob = 0; ob < NB; ++ob) {
+                    const f32x4 wv = *reinterpret_cast<const f32x4*>(lds + (16 * ob + col) * stride + k0 + 4 * grp);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[r], x[blk][cb][r], acc[ob][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
 template <bool BF16, int H, int L, int CB>
 __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
     constexpr int NB = H / 16;
+    constexpr int kTile = kWaves * 16 * CB;
+    using T = typename WT<BF16>::T;
+    constexpr int PAD = WT<BF16>::kPad, CHUNK = WT<BF16>::kChunk;
+    __shared__ __attribute__((aligned(16))) T lds[lds_elems<BF16>()];
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, grp = lane >> 4;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    int s = -1;
+    const int64_t tile = blockIdx.x;
+    int s = 0;
     for (int q = 0; q < a.S; ++q)
-        if (wave >= a.tile_off[q] && wave < a.tile_off[q + 1]) s = q;
-    if (s < 0) return;
-    const int64_t first = a.sp_off[s] + (wave - a.tile_off[s]) * (16 * CB);
+        if (tile >= a.tile_off[q] && tile < a.tile_off[q + 1]) s = q;
+    const int64_t first = a.sp_off[s] + (tile - a.tile_off[s]) * kTile + (threadIdx.x >> 6) * (16 * CB);
     const int64_t end = a.sp_off[s + 1];
     int64_t atom[CB];
     bool valid[CB];
@@ -93,131 +209,25 @@ __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
         valid[cb] = r < end;
         atom[cb] = valid[cb] ? (int64_t)a.sp_idx[r] : 0;
     }
-    const float* w32 = a.w32 + s * a.wstride;
-    const __hip_bfloat16* wbf = a.wbf + s * a.wstride;
+    const T* wsp;
+    if constexpr (BF16) wsp = a.wbf + s * a.wstride;
+    else wsp = a.w32 + s * a.wstride;
     const float* bias = a.bias + (int64_t)s * L * H;
 
     f32x4 acc[NB][CB];
+    f32x4 x[NB][CB];
     f32x4 dact[L][NB][CB];
 
-    // ---- layer 1: Z1^T = W1 G^T + b1
+    auto set_bias = [&](const float* bl) {
 #pragma unroll
-    for (int ob = 0; ob < NB; ++ob) {
-        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * ob + 4 * grp);
+        for (int ob = 0; ob < NB; ++ob) {
+            f32x4 init = {0, 0, 0, 0};
+            if (bl) init = *reinterpret_cast<const f32x4*>(bl + 16 * ob + 4 * grp);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = bv;
-    }
-    if constexpr (BF16) {
-        for (int k0 = 0; k0 < a.Fpad; k0 += 32) {
-            bf16x8 bop[CB];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                f32x4 lo = {0, 0, 0, 0}, hi = {0, 0, 0, 0};
-                const int c0 = k0 + 4 * grp, c1 = k0 + 16 + 4 * grp;
-                if (valid[cb] && c0 < a.F) lo = *reinterpret_cast<const f32x4*>(a.G + atom[cb] * a.F + c0);
-                if (valid[cb] && c1 < a.F) hi = *reinterpret_cast<const f32x4*>(a.G + atom[cb] * a.F + c1);
-                bop[cb] = cat8(to_bf4(lo), to_bf4(hi));
-            }
-#pragma unroll
-            for (int ob = 0; ob < NB; ++ob) {
-                const __hip_bfloat16* wr = wbf + a.w_off[0] + (int64_t)(16 * ob + col) * a.Fpad + k0 + 4 * grp;
-                const bf16x8 av = cat8(load_bf4(wr), load_bf4(wr + 16));
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                    acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[cb], acc[ob][cb], 0, 0, 0);
-            }
-        }
-    } else {
-        for (int k0 = 0; k0 < a.Fpad; k0 += 16) {
-            f32x4 bv[CB];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                bv[cb] = f32x4{0, 0, 0, 0};
-                const int c0 = k0 + 4 * grp;
-                if (valid[cb] && c0 < a.F) bv[cb] = *reinterpret_cast<const f32x4*>(a.G + atom[cb] * a.F + c0);
-            }
-#pragma unroll
-            for (int ob = 0; ob < NB; ++ob) {
-                const f32x4 wv =
-                    *reinterpret_cast<const f32x4*>(w32 + a.w_off[0] + (int64_t)(16 * ob + col) * a.Fpad + k0 + 4 * grp);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-                        acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[r], bv[cb][r], acc[ob][cb], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int ob = 0; ob < NB; ++ob)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float z = acc[ob][cb][r];
-                const float y = act_f(a.act, z);
-                dact[0][ob][cb][r] = act_df(a.act, z, y);
-                acc[ob][cb][r] = y;
-            }
-
-    // ---- hidden layers 2..L: Z_l^T = W_l A_{l-1}^T + b_l
-    auto layer = [&](const float* w32l, const __hip_bfloat16* wbfl, const float* bl, bool add_bias) {
-        // snapshot the previous activations as B operands
-        if constexpr (BF16) {
-            bf16x8 bop[NB / 2][CB];
-#pragma unroll
-            for (int s2 = 0; s2 < NB / 2; ++s2)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) bop[s2][cb] = cat8(to_bf4(acc[2 * s2][cb]), to_bf4(acc[2 * s2 + 1][cb]));
-#pragma unroll
-            for (int ob = 0; ob < NB; ++ob) {
-                f32x4 init = {0, 0, 0, 0};
-                if (add_bias) init = *reinterpret_cast<const f32x4*>(bl + 16 * ob + 4 * grp);
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = init;
-            }
-#pragma unroll
-            for (int s2 = 0; s2 < NB / 2; ++s2)
-#pragma unroll
-                for (int ob = 0; ob < NB; ++ob) {
-                    const __hip_bfloat16* wr = wbfl + (int64_t)(16 * ob + col) * H + 32 * s2 + 4 * grp;
-                    const bf16x8 av = cat8(load_bf4(wr), load_bf4(wr + 16));
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-                        acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[s2][cb], acc[ob][cb], 0, 0, 0);
-                }
-        } else {
-            f32x4 xin[NB][CB];
-#pragma unroll
-            for (int ob = 0; ob < NB; ++ob)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) xin[ob][cb] = acc[ob][cb];
-#pragma unroll
-            for (int ob = 0; ob < NB; ++ob) {
-                f32x4 init = {0, 0, 0, 0};
-                if (add_bias) init = *reinterpret_cast<const f32x4*>(bl + 16 * ob + 4 * grp);
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = init;
-            }
-#pragma unroll
-            for (int blk = 0; blk < NB; ++blk)
-#pragma unroll
-                for (int ob = 0; ob < NB; ++ob) {
-                    const f32x4 wv =
-                        *reinterpret_cast<const f32x4*>(w32l + (int64_t)(16 * ob + col) * H + 16 * blk + 4 * grp);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb)
-                            acc[ob][cb] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(wv[r], xin[blk][cb][r], acc[ob][cb], 0, 0, 0);
-                }
+            for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = init;
         }
     };
-
-#pragma unroll
-    for (int l = 1; l < L; ++l) {
-        layer(w32 + a.w_off[l], wbf + a.w_off[l], bias + l * H, true);
+    auto activate = [&](int l) {
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
@@ -229,6 +239,70 @@ __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
                     dact[l][ob][cb][r] = act_df(a.act, z, y);
                     acc[ob][cb][r] = y;
                 }
+    };
+    auto keep = [&]() {
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) x[ob][cb] = acc[ob][cb];
+    };
+
+    // ---- layer 1: W_1 [H][Fpad] times G^T, weights staged in column chunks
+    set_bias(bias);
+    {
+        const T* W = wsp + a.w_off[0];
+        for (int c0 = 0; c0 < a.Fpad; c0 += CHUNK) {
+            const int nc = min(CHUNK, a.Fpad - c0);
+            const int stride = nc + PAD;
+            __syncthreads();
+            stage<BF16>(W, a.Fpad, H, c0, nc, lds);
+            __syncthreads();
+            if constexpr (BF16) {
+                for (int k0 = 0; k0 < nc; k0 += 32) {
+                    bf16x8 bop[CB];
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const int g0 = c0 + k0 + 4 * grp;
+                        bop[cb] = cat8(to_bf4(load_g4(a.G, atom[cb], a.F, g0, valid[cb])),
+                                       to_bf4(load_g4(a.G, atom[cb], a.F, g0 + 16, valid[cb])));
+                    }
+#pragma unroll
+                    for (int ob = 0; ob < NB; ++ob) {
+                        const T* wr = lds + (16 * ob + col) * stride + k0 + 4 * grp;
+                        const bf16x8 av =
+                            cat8(*reinterpret_cast<const bf16x4*>(wr), *reinterpret_cast<const bf16x4*>(wr + 16));
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[cb], acc[ob][cb], 0, 0, 0);
+                    }
+                }
+            } else {
+                for (int k0 = 0; k0 < nc; k0 += 16) {
+                    f32x4 bv[CB];
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) bv[cb] = load_g4(a.G, atom[cb], a.F, c0 + k0 + 4 * grp, valid[cb]);
+#pragma unroll
+                    for (int ob = 0; ob < NB; ++ob) {
+                        const f32x4 wv =
+                            *reinterpret_cast<const f32x4*>(lds + (16 * ob + col) * stride + k0 + 4 * grp);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[ob][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[r], bv[cb][r], acc[ob][cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    activate(0);
+    // ---- hidden layers 2..L
+#pragma unroll
+    for (int l = 1; l < L; ++l) {
+        keep();
+        set_bias(bias + l * H);
+        dense_hidden<BF16, H, CB>(wsp + a.w_off[l], lds, x, acc);
+        activate(l);
     }
 
     // ---- output layer: E = w_out . a_L + b_out; delta_L = w_out * act'(z_L)
@@ -259,7 +333,9 @@ __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
     // ---- backward through hidden layers: delta_{l-1} = (W_l^T delta_l) * act'(z_{l-1})
 #pragma unroll
     for (int l = L - 1; l >= 1; --l) {
-        layer(w32 + a.wt_off[l], wbf + a.wt_off[l], nullptr, false);
+        keep();
+        set_bias(nullptr);
+        dense_hidden<BF16, H, CB>(wsp + a.wt_off[l], lds, x, acc);
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
@@ -268,62 +344,69 @@ __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
                 for (int r = 0; r < 4; ++r) acc[ob][cb][r] *= dact[l - 1][ob][cb][r];
     }
 
-    // ---- dE/dG^T = W_1^T delta_1 : F output rows in blocks of 16
+    // ---- dE/dG^T = W_1^T delta_1: Fpad output rows; W_1^T [Fpad][H] is
+    // staged in panels of PR full rows.
+    constexpr int NS = NB / 2 > 0 ? NB / 2 : 1;
+    bf16x8 bop[NS][CB];
     if constexpr (BF16) {
-        bf16x8 bop[NB / 2][CB];
 #pragma unroll
         for (int s2 = 0; s2 < NB / 2; ++s2)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) bop[s2][cb] = cat8(to_bf4(acc[2 * s2][cb]), to_bf4(acc[2 * s2 + 1][cb]));
-        for (int fb = 0; fb < a.Fpad / 16; ++fb) {
+    }
+    const T* w1t = wsp + a.wt_off[0];
+    constexpr int PR = lds_elems<BF16>() / (H + PAD) / 16 * 16;
+    for (int r0 = 0; r0 < a.Fpad; r0 += PR) {
+        const int nr = min(PR, a.Fpad - r0);
+        __syncthreads();
+        stage<BF16>(w1t + (int64_t)r0 * H, H, nr, 0, H, lds);
+        __syncthreads();
+        for (int fb = 0; fb < nr / 16; ++fb) {
             f32x4 out[CB];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) out[cb] = f32x4{0, 0, 0, 0};
+            if constexpr (BF16) {
 #pragma unroll
-            for (int s2 = 0; s2 < NB / 2; ++s2) {
-                const __hip_bfloat16* wr = wbf + a.wt_off[0] + (int64_t)(16 * fb + col) * H + 32 * s2 + 4 * grp;
-                const bf16x8 av = cat8(load_bf4(wr), load_bf4(wr + 16));
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                    out[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[s2][cb], out[cb], 0, 0, 0);
-            }
-            const int f0 = 16 * fb + 4 * grp;
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-                if (valid[cb] && f0 < a.F) *reinterpret_cast<f32x4*>(a.dG + atom[cb] * a.F + f0) = out[cb];
-        }
-    } else {
-        for (int fb = 0; fb < a.Fpad / 16; ++fb) {
-            f32x4 out[CB];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) out[cb] = f32x4{0, 0, 0, 0};
-#pragma unroll
-            for (int blk = 0; blk < NB; ++blk) {
-                const f32x4 wv =
-                    *reinterpret_cast<const f32x4*>(w32 + a.wt_off[0] + (int64_t)(16 * fb + col) * H + 16 * blk + 4 * grp);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int s2 = 0; s2 < NB / 2; ++s2) {
+                    const T* wr = lds + (16 * fb + col) * (H + PAD) + 32 * s2 + 4 * grp;
+                    const bf16x8 av =
+                        cat8(*reinterpret_cast<const bf16x4*>(wr), *reinterpret_cast<const bf16x4*>(wr + 16));
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb)
-                        out[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[r], acc[blk][cb][r], out[cb], 0, 0, 0);
-            }
-            const int f0 = 16 * fb + 4 * grp;
+                        out[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[s2][cb], out[cb], 0, 0, 0);
+                }
+            } else {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-                if (valid[cb] && f0 < a.F) *reinterpret_cast<f32x4*>(a.dG + atom[cb] * a.F + f0) = out[cb];
+                for (int blk = 0; blk < NB; ++blk) {
+                    const f32x4 wv =
+                        *reinterpret_cast<const f32x4*>(lds + (16 * fb + col) * (H + PAD) + 16 * blk + 4 * grp);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            out[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[r], acc[blk][cb][r], out[cb], 0, 0, 0);
+                }
+            }
+            const int f0 = r0 + 16 * fb + 4 * grp;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) store_dg4(a.dG, atom[cb], a.F, f0, valid[cb], out[cb]);
         }
     }
 }
 
 using MlpFn = void (*)(MlpArgs);
 
+// Column blocks per wave: two (32 atoms) unless the H = 128 network is deep
+// enough that two blocks' activation derivatives would not fit in registers.
 template <bool BF16, int H>
 MlpFn pick_L(int L, int* cb) {
+    constexpr int C = (H == 128) ? 1 : 2;
+    *cb = (L <= 2) ? 2 : C;
     switch (L) {
-        case 1: *cb = 2; return k_mlp<BF16, H, 1, 2>;
-        case 2: *cb = 2; return k_mlp<BF16, H, 2, 2>;
-        case 3: *cb = 1; return k_mlp<BF16, H, 3, 1>;
-        default: *cb = 1; return k_mlp<BF16, H, 4, 1>;
+        case 1: return k_mlp<BF16, H, 1, 2>;
+        case 2: return k_mlp<BF16, H, 2, 2>;
+        case 3: return k_mlp<BF16, H, 3, C>;
+        default: return k_mlp<BF16, H, 4, C>;
     }
 }
 
@@ -346,14 +429,14 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl,
     a.Fpad = m->Fpad;
     a.act = m->act;
     a.L = m->L;
-    int cb = 1;
+    int cb = 2;
     MlpFn fn = (m->prec == TMD_BF16_MLP) ? pick_H<true>(m->H, m->L, &cb) : pick_H<false>(m->H, m->L, &cb);
-    const int apw = 16 * cb;
+    const int kTileAtoms = kWaves * 16 * cb;
     int64_t tiles = 0;
     for (int s = 0; s < m->S; ++s) {
         a.sp_off[s] = nl->sp_off[s];
         a.tile_off[s] = tiles;
-        tiles += (nl->sp_count[s] + apw - 1) / apw;
+        tiles += (nl->sp_count[s] + kTileAtoms - 1) / kTileAtoms;
     }
     a.sp_off[m->S] = nl->sp_off[m->S];
     a.tile_off[m->S] = tiles;
@@ -372,10 +455,9 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl,
     a.wout = m->wout;
     a.bout = m->bout;
     if (tiles == 0) return TMD_OK;
-    const unsigned grid = (unsigned)((tiles + 3) / 4);
     {
         ProfScope ps_(ctx, "mlp");
-        fn<<<grid, 256, 0, ctx->stream>>>(a);
+        fn<<<(unsigned)tiles, kWaves * 64, 0, ctx->stream>>>(a);
     }
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;

@@ -235,6 +235,18 @@ def test_energy_forces_model_shapes(tmd, ctx, torch, hidden, act, K, M, prec):
     _check_ef(E, Ea, F, W, s, spec, etol, ftol)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_energy_forces_feature_count_not_multiple_of_4(tmd, ctx, torch, prec):
+    """F = 3 species x K 6 x (M+1) 3 = 54: descriptor rows are not 16-byte multiples."""
+    s = inputs.make_system("bcc", 3.16, (3, 3, 3), 0.12, 3, seed=52)
+    spec = inputs.make_model(3, 6, 2, [64, 64], 5.5, seed=53)
+    assert spec.n_features % 4 != 0
+    _note(f"energy_forces F={spec.n_features} prec={prec}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, prec)
+    etol, ftol = (E_TOL_FP32, F_TOL_FP32) if prec == 0 else (E_TOL_BF16, F_TOL_BF16)
+    _check_ef(E, Ea, F, W, s, spec, etol, ftol)
+
+
 def test_ragged_and_absent_species(tmd, ctx, torch):
     """61 atoms (ragged MLP tiles), species 1 of 2 absent, one isolated atom."""
     rng = np.random.default_rng(60)
