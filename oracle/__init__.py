@@ -59,6 +59,16 @@ def lib():
         L.orc_wrap_positions.restype = None
         L.orc_neumaier_sum.argtypes = [i64, vp]
         L.orc_neumaier_sum.restype = dbl
+        L.orc_descriptor_jvp.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.orc_descriptor_jvp.restype = i32
+        L.orc_mlp_second.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_mlp_second.restype = i32
+        L.orc_train_loss_grad.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.orc_train_loss_grad.restype = i32
+        L.orc_nve.argtypes = [vp, i64, vp, vp, vp, vp, vp, dbl, i32, vp, vp]
+        L.orc_nve.restype = i32
+        L.orc_params_per_species.argtypes = [vp]
+        L.orc_params_per_species.restype = i32
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         _lib = L
@@ -202,3 +212,68 @@ def neumaier_sum(x) -> float:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def descriptor_jvp(spec, pos, species, box, r) -> np.ndarray:
+    """Descriptor tangents w [n,F] = d/de G(x + e r) along the field r [n,3]."""
+    pos, species, box = _sys_arrays(pos, species, box)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    mref = _ModelRef(spec)
+    w = np.empty((pos.shape[0], spec.n_features), dtype=np.float64)
+    rc = lib().orc_descriptor_jvp(mref.ref, pos.shape[0], _p(pos), _p(species), _p(box), _p(r), _p(w))
+    if rc != 0:
+        raise ValueError(f"oracle descriptor_jvp failed ({rc})")
+    return w
+
+
+def mlp_second(spec, species, G, w, e):
+    """(E [n], q [n], grad [S*P]) with q = grad_G E . w and grad = d/dtheta sum(e E - q)."""
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    mref = _ModelRef(spec)
+    n = G.shape[0]
+    E = np.empty(n, dtype=np.float64)
+    q = np.empty(n, dtype=np.float64)
+    grad = np.empty(spec.params.shape[0], dtype=np.float64)
+    rc = lib().orc_mlp_second(mref.ref, n, _p(species), _p(G), _p(w), _p(e), _p(E), _p(q), _p(grad))
+    if rc != 0:
+        raise ValueError(f"oracle mlp_second failed ({rc})")
+    return E, q, grad
+
+
+def train_loss_grad(spec, sys_off, pos, species, boxes, E_label, F_label, lam: float):
+    """(loss, loss_E, loss_F, grad [S*P]) of the force-matching loss over a batch."""
+    sys_off = np.ascontiguousarray(sys_off, dtype=np.int64)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    boxes = np.ascontiguousarray(boxes, dtype=np.float64)
+    E_label = np.ascontiguousarray(E_label, dtype=np.float64)
+    F_label = np.ascontiguousarray(F_label, dtype=np.float64)
+    mref = _ModelRef(spec)
+    out = np.zeros(3, dtype=np.float64)
+    grad = np.empty(spec.params.shape[0], dtype=np.float64)
+    rc = lib().orc_train_loss_grad(mref.ref, len(sys_off) - 1, _p(sys_off), _p(pos), _p(species), _p(boxes),
+                                   _p(E_label), _p(F_label), float(lam), _p(out[0:]), _p(out[1:]), _p(out[2:]),
+                                   _p(grad))
+    if rc != 0:
+        raise ValueError(f"oracle train_loss_grad failed ({rc})")
+    return float(out[0]), float(out[1]), float(out[2]), grad
+
+
+def nve(spec, pos, vel, species, masses, box, dt: float, n_steps: int):
+    """Velocity-Verlet NVE: (pos, vel, epot [n_steps+1], ekin [n_steps+1])."""
+    pos = np.array(pos, dtype=np.float64, copy=True)
+    vel = np.array(vel, dtype=np.float64, copy=True)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    masses = np.ascontiguousarray(masses, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    mref = _ModelRef(spec)
+    epot = np.empty(n_steps + 1, dtype=np.float64)
+    ekin = np.empty(n_steps + 1, dtype=np.float64)
+    rc = lib().orc_nve(mref.ref, pos.shape[0], _p(pos), _p(vel), _p(species), _p(masses), _p(box), float(dt),
+                       int(n_steps), _p(epot), _p(ekin))
+    if rc != 0:
+        raise ValueError(f"oracle nve failed ({rc})")
+    return pos, vel, epot, ekin

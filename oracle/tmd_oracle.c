@@ -17,7 +17,11 @@
  *   - atomic energies from a per-element MLP, E = sum_a E_a (Sec. III.A);
  *   - forces through the adjoint chain P' = 2 T sigma' P, U = P' M,
  *     V = P' H, F1 = U H' R', F2 = V M' and the scattered sum over pairs
- *     (Sec. III.A, eqns dP_abkd, U_abck, F1_abcx, F2_abcx).
+ *     (Sec. III.A, eqns dP_abkd, U_abck, F1_abcx, F2_abcx);
+ *   - beyond the paper (its potentials were trained elsewhere): the
+ *     force-matching loss and its parameter gradient, with the descriptor
+ *     tangent and a second-order network pass written from their definitions,
+ *     and a velocity-Verlet NVE integrator for the MD protocol (Sec. IV.D).
  *
  * Readings of points the paper leaves open (all listed in the design notes):
  * Gaussian radial functions exp(-eta_k (R - mu_k)^2); cosine cutoff
@@ -570,4 +574,285 @@ int orc_num_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Force matching (training): descriptor tangent, second-order MLP,     */
+/* loss and parameter gradient.  Not part of the paper's method (its    */
+/* potentials were trained elsewhere); these are plain definitions.     */
+/* ------------------------------------------------------------------ */
+
+/* Tangent of one atom's descriptors along a displacement field r:
+ * Gt = d/de G_i(x + e r) at e = 0.  For each pair c the tangent of
+ * D_c = x_j + n L - x_i is t = r_j - r_i, and through the definition
+ *   R_t = u . t,   u_t = (t - u (u . t)) / R,
+ *   Pt_bkd = sum_c [ h_k'(R) R_t M_d(u) + h_k(R) (grad_u M_d) . u_t ],
+ *   St_bkm = sum_{d of order m} 2 T_d P_bkd Pt_bkd,
+ *   Gt = St / (2 sqrt S) for m = 0 (0 where S = 0), St otherwise. */
+static void atom_G_tangent(const orc_model* m, int64_t i, const orc_pair* pr, int cnt, const double* r, double* Gt) {
+    const dims_t dm = dims_of(m);
+    double* P = (double*)malloc(sizeof(double) * dm.S * dm.K * dm.D);
+    double* Pt = (double*)calloc((size_t)dm.S * dm.K * dm.D, sizeof(double));
+    double* S = (double*)malloc(sizeof(double) * dm.F);
+    double* G = (double*)malloc(sizeof(double) * dm.F);
+    atom_P(m, pr, cnt, P);
+    atom_G(m, P, S, G);
+    for (int c = 0; c < cnt; ++c) {
+        const double* D = pr[c].d;
+        const double R = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+        if (!(R < m->rcut)) continue;
+        const double u[3] = {D[0] / R, D[1] / R, D[2] / R};
+        const int64_t j = pr[c].j;
+        const double t[3] = {r[3 * j] - r[3 * i], r[3 * j + 1] - r[3 * i + 1], r[3 * j + 2] - r[3 * i + 2]};
+        const double Rt = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+        const double ut[3] = {(t[0] - u[0] * Rt) / R, (t[1] - u[1] * Rt) / R, (t[2] - u[2] * Rt) / R};
+        const double fc = cutoff_fc(R, m->rcut), dfc = cutoff_dfc(R, m->rcut);
+        const int b = pr[c].sj;
+        for (int k = 0; k < dm.K; ++k) {
+            const double tk = R - m->mu[k];
+            const double f = exp(-m->eta[k] * tk * tk);
+            const double h = f * fc;
+            const double dh = (-2.0 * m->eta[k] * tk) * f * fc + f * dfc;
+            for (int d = 0; d < dm.D; ++d) {
+                double Mt = 0.0;
+                for (int a = 0; a < 3; ++a) Mt += dmoment_du(d, a, u) * ut[a];
+                Pt[(b * dm.K + k) * dm.D + d] += dh * Rt * moment(d, u) + h * Mt;
+            }
+        }
+    }
+    for (int b = 0; b < dm.S; ++b)
+        for (int k = 0; k < dm.K; ++k)
+            for (int mm = 0; mm <= dm.M; ++mm) {
+                double st = 0.0;
+                for (int d = 0; d < dm.D; ++d)
+                    if (order_of(d) == mm)
+                        st += 2.0 * TDM[d] * P[(b * dm.K + k) * dm.D + d] * Pt[(b * dm.K + k) * dm.D + d];
+                const int f = (b * dm.K + k) * (dm.M + 1) + mm;
+                Gt[f] = (mm == 0) ? (S[f] > 0.0 ? st / (2.0 * sqrt(S[f])) : 0.0) : st;
+            }
+    free(P); free(Pt); free(S); free(G);
+}
+
+/* Descriptor tangents w [n][F] of every atom along the field r [n][3]. */
+int orc_descriptor_jvp(const orc_model* m, int64_t n, const double* pos, const int32_t* sp, const double* box,
+                       const double* r, double* w) {
+    if (check_model(m)) return ORC_ERR_ARG;
+    const dims_t dm = dims_of(m);
+    double* wp = (double*)malloc(sizeof(double) * 3 * n);
+    orc_wrap_positions(n, pos, box, wp);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        int c;
+        orc_pair* pr = atom_pairs(i, n, wp, sp, box, m->rcut, &c);
+        atom_G_tangent(m, i, pr, c, r, w + (size_t)i * dm.F);
+        free(pr);
+    }
+    free(wp);
+    return ORC_OK;
+}
+
+static double act_d2f(int act, double z) {
+    if (act == 1) return 2.0 / pow(z * z + 4.0, 1.5);
+    double t = tanh(z);
+    return -2.0 * t * (1.0 - t * t);
+}
+
+/* One atom of the second-order network pass.  Primal z_l = W_l a_{l-1} + b_l,
+ * a_l = act(z_l), E = w_out . a_L + b_out; tangent along the input direction
+ * w: zt_l = W_l at_{l-1}, at_l = act'(z_l) zt_l, q = w_out . at_L (so q is
+ * grad_G E . w).  Reverse mode of J = e E - q through both graphs, adding
+ * dJ/dtheta into g (this species' parameter block). */
+static void mlp_second_atom(const orc_model* m, int species, const double* G, const double* w, double e,
+                            double* E_out, double* q_out, double* g) {
+    const int F = orc_n_features(m);
+    const double* p = m->params + (size_t)species * orc_params_per_species(m);
+    static __thread double z[MAXL][MAXW], zt[MAXL][MAXW], a[MAXL + 1][MAXW], at[MAXL + 1][MAXW];
+    static __thread double ab[MAXW], atb[MAXW], zb[MAXW], ztb[MAXW], nab[MAXW], natb[MAXW];
+    int widths[MAXL + 2];
+    widths[0] = F;
+    for (int l = 0; l < m->n_hidden; ++l) widths[l + 1] = m->hidden[l];
+    size_t offW[MAXL], offb[MAXL];
+    size_t off = 0;
+    for (int l = 0; l < m->n_hidden; ++l) {
+        offW[l] = off; off += (size_t)widths[l + 1] * widths[l];
+        offb[l] = off; off += widths[l + 1];
+    }
+    const int L = m->n_hidden, wl = widths[L];
+    const size_t off_wout = off, off_bout = off + wl;
+    for (int q = 0; q < F; ++q) { a[0][q] = G[q]; at[0][q] = w[q]; }
+    for (int l = 0; l < L; ++l) {
+        const int wi = widths[l], wo = widths[l + 1];
+        const double* W = p + offW[l];
+        for (int o = 0; o < wo; ++o) {
+            double s = p[offb[l] + o], st = 0.0;
+            for (int q = 0; q < wi; ++q) {
+                s += W[(size_t)o * wi + q] * a[l][q];
+                st += W[(size_t)o * wi + q] * at[l][q];
+            }
+            z[l][o] = s;
+            zt[l][o] = st;
+            a[l + 1][o] = act_f(m->activation, s);
+            at[l + 1][o] = act_df(m->activation, s) * st;
+        }
+    }
+    double E = p[off_bout], q = 0.0;
+    for (int o = 0; o < wl; ++o) {
+        E += p[off_wout + o] * a[L][o];
+        q += p[off_wout + o] * at[L][o];
+    }
+    *E_out = E;
+    *q_out = q;
+    /* output layer */
+    for (int o = 0; o < wl; ++o) {
+        g[off_wout + o] += e * a[L][o] - at[L][o];
+        ab[o] = e * p[off_wout + o];
+        atb[o] = -p[off_wout + o];
+    }
+    g[off_bout] += e;
+    for (int l = L - 1; l >= 0; --l) {
+        const int wi = widths[l], wo = widths[l + 1];
+        const double* W = p + offW[l];
+        for (int o = 0; o < wo; ++o) {
+            const double d1 = act_df(m->activation, z[l][o]), d2 = act_d2f(m->activation, z[l][o]);
+            ztb[o] = d1 * atb[o];
+            zb[o] = d1 * ab[o] + d2 * zt[l][o] * atb[o];
+        }
+        for (int o = 0; o < wo; ++o) {
+            for (int qq = 0; qq < wi; ++qq) g[offW[l] + (size_t)o * wi + qq] += zb[o] * a[l][qq] + ztb[o] * at[l][qq];
+            g[offb[l] + o] += zb[o];
+        }
+        if (l > 0) {
+            for (int qq = 0; qq < wi; ++qq) {
+                double s = 0.0, st = 0.0;
+                for (int o = 0; o < wo; ++o) {
+                    s += W[(size_t)o * wi + qq] * zb[o];
+                    st += W[(size_t)o * wi + qq] * ztb[o];
+                }
+                nab[qq] = s;
+                natb[qq] = st;
+            }
+            for (int qq = 0; qq < wi; ++qq) { ab[qq] = nab[qq]; atb[qq] = natb[qq]; }
+        }
+    }
+}
+
+/* E_a, q_a and grad = d/dtheta sum_a (e_a E_a - q_a), grad [S * params per
+ * species] overwritten; atoms are visited in index order. */
+int orc_mlp_second(const orc_model* m, int64_t n, const int32_t* species, const double* G, const double* w,
+                   const double* e, double* E, double* q, double* grad) {
+    if (check_model(m)) return ORC_ERR_ARG;
+    const int F = orc_n_features(m);
+    const size_t np = (size_t)m->n_species * orc_params_per_species(m);
+    memset(grad, 0, sizeof(double) * np);
+    for (int64_t i = 0; i < n; ++i) {
+        const int s = species[i];
+        double* g = grad + (size_t)s * orc_params_per_species(m);
+        mlp_second_atom(m, s, G + (size_t)i * F, w + (size_t)i * F, e[i], &E[i], &q[i], g);
+    }
+    return ORC_OK;
+}
+
+/* Force-matching loss over a batch of B periodic systems (system s holds atoms
+ * sys_off[s] .. sys_off[s+1]-1 in a box boxes[3s..3s+2]):
+ *   L = (1/B) sum_s ((E_s - Ehat_s)/N_s)^2 + lambda/(3 N) sum_i |F_i - Fhat_i|^2,
+ * N = total atoms.  The gradient is assembled from
+ *   dL/dE_a = e_a = (2/B)(E_s - Ehat_s)/N_s^2          (energy term)
+ *   dL/dF_i = r_i = (2 lambda/(3N)) (F_i - Fhat_i)     (force term)
+ * and F = -dE/dx: sum_i r_i . dF_i/dtheta = -d/dtheta sum_a q_a with q_a the
+ * network tangent along the descriptor tangent of the field r.  loss_e and
+ * loss_f receive the two terms (nullable); grad [S * params per species]. */
+int orc_train_loss_grad(const orc_model* m, int32_t n_sys, const int64_t* sys_off, const double* pos,
+                        const int32_t* sp, const double* boxes, const double* E_label, const double* F_label,
+                        double lambda, double* loss, double* loss_e, double* loss_f, double* grad) {
+    if (check_model(m) || n_sys < 1) return ORC_ERR_ARG;
+    const int F = orc_n_features(m);
+    const size_t np = (size_t)m->n_species * orc_params_per_species(m);
+    const int64_t N = sys_off[n_sys] - sys_off[0];
+    memset(grad, 0, sizeof(double) * np);
+    double* gs = (double*)malloc(sizeof(double) * np);
+    nsum le = {0.0, 0.0}, lf = {0.0, 0.0};
+    for (int32_t s = 0; s < n_sys; ++s) {
+        const int64_t o = sys_off[s], ns = sys_off[s + 1] - sys_off[s];
+        const double* x = pos + 3 * o;
+        const int32_t* spp = sp + o;
+        const double* box = boxes + 3 * s;
+        double Es;
+        double* Fs = (double*)malloc(sizeof(double) * 3 * ns);
+        double* r = (double*)malloc(sizeof(double) * 3 * ns);
+        double* G = (double*)malloc(sizeof(double) * ns * F);
+        double* w = (double*)malloc(sizeof(double) * ns * F);
+        double* e = (double*)malloc(sizeof(double) * ns);
+        double* Ea = (double*)malloc(sizeof(double) * ns);
+        double* qa = (double*)malloc(sizeof(double) * ns);
+        int st = orc_energy_forces(m, ns, x, spp, box, &Es, NULL, Fs, NULL);
+        if (!st) st = orc_descriptors(m, ns, x, spp, box, 0, NULL, G);
+        if (st) {
+            free(Fs); free(r); free(G); free(w); free(e); free(Ea); free(qa); free(gs);
+            return st;
+        }
+        const double de = (Es - E_label[s]) / (double)ns;
+        nsum_add(&le, de * de / (double)n_sys);
+        for (int64_t i = 0; i < ns; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double df = Fs[3 * i + a] - F_label[3 * (o + i) + a];
+                nsum_add(&lf, lambda * df * df / (3.0 * (double)N));
+                r[3 * i + a] = 2.0 * lambda / (3.0 * (double)N) * df;
+            }
+        for (int64_t i = 0; i < ns; ++i) e[i] = 2.0 / (double)n_sys * (Es - E_label[s]) / ((double)ns * (double)ns);
+        orc_descriptor_jvp(m, ns, x, spp, box, r, w);
+        orc_mlp_second(m, ns, spp, G, w, e, Ea, qa, gs);
+        for (size_t q = 0; q < np; ++q) grad[q] += gs[q];
+        free(Fs); free(r); free(G); free(w); free(e); free(Ea); free(qa);
+    }
+    free(gs);
+    if (loss_e) *loss_e = nsum_get(&le);
+    if (loss_f) *loss_f = nsum_get(&lf);
+    *loss = nsum_get(&le) + nsum_get(&lf);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Velocity-Verlet NVE                                                  */
+/* ------------------------------------------------------------------ */
+#define ORC_ACC_CONV 9.648533e-3   /* (eV/A)/amu -> A/fs^2 */
+#define ORC_KE_CONV 103.6427       /* amu (A/fs)^2 -> eV */
+
+static double kinetic(int64_t n, const double* vel, const int32_t* sp, const double* mass) {
+    nsum k = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i)
+        nsum_add(&k, 0.5 * ORC_KE_CONV * mass[sp[i]] *
+                         (vel[3 * i] * vel[3 * i] + vel[3 * i + 1] * vel[3 * i + 1] + vel[3 * i + 2] * vel[3 * i + 2]));
+    return nsum_get(&k);
+}
+
+/* n_steps of velocity Verlet in the microcanonical ensemble:
+ *   v += (dt/2) a(x);  x += dt v;  v += (dt/2) a(x),   a = ACC_CONV F / m,
+ * forces from the full FP64 evaluation at every step (neighbours rebuilt by
+ * brute force each time).  pos and vel [n][3] are advanced in place and never
+ * wrapped.  epot and ekin (nullable, n_steps + 1 entries) get the potential and
+ * kinetic energy before the first step and after each step. */
+int orc_nve(const orc_model* m, int64_t n, double* pos, double* vel, const int32_t* sp, const double* mass,
+            const double* box, double dt, int n_steps, double* epot, double* ekin) {
+    if (check_model(m) || n_steps < 0) return ORC_ERR_ARG;
+    double* F = (double*)malloc(sizeof(double) * 3 * n);
+    double E;
+    int st = orc_energy_forces(m, n, pos, sp, box, &E, NULL, F, NULL);
+    if (st) { free(F); return st; }
+    if (epot) epot[0] = E;
+    if (ekin) ekin[0] = kinetic(n, vel, sp, mass);
+    for (int t = 0; t < n_steps; ++t) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                vel[3 * i + a] += 0.5 * dt * ORC_ACC_CONV * F[3 * i + a] / mass[sp[i]];
+                pos[3 * i + a] += dt * vel[3 * i + a];
+            }
+        st = orc_energy_forces(m, n, pos, sp, box, &E, NULL, F, NULL);
+        if (st) { free(F); return st; }
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) vel[3 * i + a] += 0.5 * dt * ORC_ACC_CONV * F[3 * i + a] / mass[sp[i]];
+        if (epot) epot[t + 1] = E;
+        if (ekin) ekin[t + 1] = kinetic(n, vel, sp, mass);
+    }
+    free(F);
+    return ORC_OK;
 }

@@ -200,4 +200,60 @@ def workload(name: str):
         sysm = make_system("bcc", 3.16, (16, 16, 16), 0.08, 2, seed=20, masses=[183.84, 95.95])
         model = make_model(2, 12, 3, [128, 128], 6.0, seed=102)
         return sysm, model, 0.0
+    if name == "train_teacher":
+        model = make_model(1, 8, 3, [64, 64], 5.0, seed=1003)
+        return None, model, 0.0
+    if name == "train_student":
+        model = make_model(1, 8, 3, [64, 64], 5.0, seed=2003)
+        return None, model, 0.0
     raise KeyError(name)
+
+
+# Cell choices of the force-matching batch: single-element fcc (a = 3.61),
+# bcc (a = 3.16) and orthorhombic hcp (a = 2.553, c/a = sqrt(8/3)) supercells
+# of 108 to 500 atoms, every box edge longer than twice the 5 A cutoff.
+TRAIN_CELLS = (
+    ("fcc", 3.61, (3, 3, 3)), ("fcc", 3.61, (4, 4, 4)), ("fcc", 3.61, (5, 5, 5)),
+    ("bcc", 3.16, (4, 4, 4)), ("bcc", 3.16, (5, 5, 5)), ("bcc", 3.16, (6, 6, 6)),
+    ("hcp", 2.553, (4, 3, 3)), ("hcp", 2.553, (6, 4, 5)),
+)
+
+
+@dataclasses.dataclass
+class Batch:
+    """Ragged batch of periodic systems, concatenated."""
+    pos: np.ndarray        # [N,3] float64
+    species: np.ndarray    # [N] int32
+    sys_off: np.ndarray    # [B+1] int64
+    boxes: np.ndarray      # [B,3] float64
+    kinds: List[str]
+
+    @property
+    def n_systems(self) -> int:
+        return int(self.sys_off.shape[0] - 1)
+
+    @property
+    def n(self) -> int:
+        return int(self.sys_off[-1])
+
+    def system(self, s: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        a, b = int(self.sys_off[s]), int(self.sys_off[s + 1])
+        return self.pos[a:b], self.species[a:b], self.boxes[s]
+
+
+def train_batch(n_cells: int = 64, seed: int = 3, sigma: float = 0.15,
+                cells: Sequence[Tuple[str, float, Tuple[int, int, int]]] = TRAIN_CELLS) -> Batch:
+    """n_cells systems, each a uniformly drawn entry of `cells` with its own
+    Gaussian displacements (one species)."""
+    rng = np.random.default_rng(seed)
+    pos, sps, offs, boxes, kinds = [], [], [0], [], []
+    for c in range(n_cells):
+        kind, a, cl = cells[int(rng.integers(0, len(cells)))]
+        s = make_system(kind, a, cl, sigma, 1, seed=seed * 1000 + c)
+        pos.append(s.pos)
+        sps.append(s.species)
+        offs.append(offs[-1] + s.n)
+        boxes.append(s.box)
+        kinds.append(f"{kind}{cl[0]}x{cl[1]}x{cl[2]}")
+    return Batch(pos=np.ascontiguousarray(np.concatenate(pos)), species=np.concatenate(sps).astype(np.int32),
+                 sys_off=np.asarray(offs, dtype=np.int64), boxes=np.asarray(boxes, dtype=np.float64), kinds=kinds)
