@@ -131,6 +131,9 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
 /* Replace the weights of an existing model (same layout as tmd_model_create). */
 tmd_status tmd_model_set_params(tmd_model* model, const float* params);
 tmd_status tmd_model_set_precision(tmd_model* model, tmd_precision precision);
+/* Copy the current weights (host FP32, same layout as tmd_model_create) into
+ * params; reflects every tmd_train_step applied so far.  Synchronises. */
+tmd_status tmd_model_get_params(const tmd_model* model, float* params);
 /* Number of floats per species block of params. */
 int64_t tmd_model_params_per_species(const tmd_model* model);
 int32_t tmd_model_n_features(const tmd_model* model);
@@ -184,6 +187,76 @@ tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* model, const tmd
  * synchronise: totals7 is device FP64 [7] = (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz). */
 tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
                                    const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces);
+
+/* ---------------------------------------------------------------- training (force matching) */
+
+/* Force matching is not part of the paper's method (its potentials were
+ * trained elsewhere); it trains the same per-element MLP on energy and force
+ * labels.  Over a batch of B periodic systems with N atoms in total,
+ *   L = (1/B) sum_s ((E_s - Ehat_s)/N_s)^2 + lambda/(3N) sum_i |F_i - Fhat_i|^2,
+ * whose parameter gradient needs the derivative of the forces with respect to
+ * the weights: the forces' residual r = dL/dF is pushed through the
+ * descriptors as a tangent (forward mode, w_i = d/de G_i(x + e r)) and the
+ * network is differentiated twice (forward-over-reverse), so that
+ * dL/dtheta = sum_i [e_i dE_i/dtheta - d(grad_G E_i . w_i)/dtheta] with
+ * e_i = (2/B)(E_s - Ehat_s)/N_s^2 for the atoms of system s. */
+typedef struct tmd_batch tmd_batch;
+
+typedef enum { TMD_OPT_ADAM = 0, TMD_OPT_SGD = 1 } tmd_optimizer;
+
+/* lambda: force-term weight (0.1 in the reference setup); lr: step size, 0
+ * computes loss and gradient without touching the weights; beta1, beta2, eps:
+ * Adam constants (0.9, 0.999, 1e-8); optimizer: tmd_optimizer. */
+typedef struct {
+    double lambda;
+    double lr;
+    double beta1;
+    double beta2;
+    double eps;
+    int32_t optimizer;
+    int32_t reserved;
+} tmd_train_opts;
+
+/* Copy a labelled batch to the device and prepare it for training with
+ * models of the descriptor shape of `model` (S, K, M, rcut, mu, eta).
+ * System s holds atoms sys_off[s] .. sys_off[s+1]-1 (host int64 [B+1],
+ * sys_off[0] = 0) in the box boxes[3s .. 3s+2] (host FP64 [B][3]).
+ * pos: device FP64 [N][3]; species: device int32 [N]; energy_labels: host FP64
+ * [B]; force_labels: device FP32 [N][3].  Builds each system's neighbour list
+ * with the cell-list search (at least `capacity` entries per row, 0 for the
+ * default; grown as needed), stores the pair vectors D, the descriptors G and
+ * the tensors P (fixed for the batch, since training changes only the MLP).
+ * Synchronises. */
+tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* model, int32_t n_systems, const int64_t* sys_off,
+                            const double* pos, const int32_t* species, const double* boxes,
+                            const double* energy_labels, const float* force_labels, int32_t capacity,
+                            tmd_batch** out);
+void tmd_batch_destroy(tmd_batch* batch);
+
+/* One training step on the whole batch: energies and forces of the current
+ * model (FP32, the model's precision setting is ignored), the loss, its
+ * gradient and, when opts->lr > 0, one Adam or SGD update of the weights in
+ * place (Adam state lives in the model).  loss: host FP64 [3] = (L, energy
+ * term, force term) before the update; grad: device FP32 [S * params per
+ * species] in the tmd_model_create layout, or NULL.  Synchronises. */
+tmd_status tmd_train_step(tmd_context* ctx, tmd_model* model, const tmd_batch* batch, const tmd_train_opts* opts,
+                          double* loss, float* grad);
+
+/* Intermediate results of the last tmd_train_step (or of tmd_batch_create for
+ * TMD_BATCH_G), in the batch's atom order, copied to device `out`:
+ *   TMD_BATCH_G        [N][F] descriptors
+ *   TMD_BATCH_ENERGY   [N]    atomic energies
+ *   TMD_BATCH_FORCES   [N][3] forces
+ *   TMD_BATCH_RESIDUAL [N][3] r = dL/dF
+ *   TMD_BATCH_TANGENT  [N][F] descriptor tangents w along r */
+typedef enum {
+    TMD_BATCH_G = 0,
+    TMD_BATCH_ENERGY = 1,
+    TMD_BATCH_FORCES = 2,
+    TMD_BATCH_RESIDUAL = 3,
+    TMD_BATCH_TANGENT = 4
+} tmd_batch_field;
+tmd_status tmd_batch_read(tmd_context* ctx, const tmd_batch* batch, int32_t field, float* out);
 
 #ifdef __cplusplus
 }

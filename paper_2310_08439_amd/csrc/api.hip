@@ -134,6 +134,7 @@ tmd_status upload_params(tmd_model* m, const float* params) {
     TMD_HIP(ctx, hipMemcpy(m->bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
     TMD_HIP(ctx, hipMemcpy(m->wout, wout.data(), wout.size() * 4, hipMemcpyHostToDevice));
     TMD_HIP(ctx, hipMemcpy(m->bout, bout.data(), bout.size() * 4, hipMemcpyHostToDevice));
+    TMD_HIP(ctx, hipMemcpy(m->params32, params, (size_t)S * m->per_species * 4, hipMemcpyHostToDevice));
     return TMD_OK;
 }
 
@@ -187,7 +188,7 @@ tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_sys
     if (st != TMD_OK) return st;
     if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
     if ((st = launch_descriptors(ctx, m, nl, b.G, b.P)) != TMD_OK) return st;
-    if ((st = launch_mlp(ctx, m, nl, b.G, b.Ei, b.dG)) != TMD_OK) return st;
+    if ((st = launch_mlp(ctx, m, species_groups(nl), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
     int nvir = 0;
     if ((st = launch_adjoint(ctx, m, nl, b.dG, b.P, b.Fs, b.vir, &nvir)) != TMD_OK) return st;
     return launch_finalize(ctx, nl, b.Ei, b.Fs, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals);
@@ -337,6 +338,7 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
     alloc((void**)&m->bias, 4 * (size_t)S * L * H);
     alloc((void**)&m->wout, 4 * (size_t)S * H);
     alloc((void**)&m->bout, 4 * (size_t)S);
+    alloc((void**)&m->params32, 4 * (size_t)S * m->per_species);
     if (e == hipSuccess) e = hipMemcpy(m->mu, mu.data(), 4 * K, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->eta, eta.data(), 4 * K, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -355,7 +357,20 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
 tmd_status tmd_model_set_params(tmd_model* m, const float* params) {
     if (!m || !params) return TMD_ERR_INVALID_ARGUMENT;
     TMD_HIP(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    // new weights restart the optimiser
+    m->opt_t = 0;
+    const size_t bytes = (size_t)m->S * m->per_species * 4;
+    if (m->opt_m) TMD_HIP(m->ctx, hipMemset(m->opt_m, 0, bytes));
+    if (m->opt_v) TMD_HIP(m->ctx, hipMemset(m->opt_v, 0, bytes));
     return upload_params(m, params);
+}
+
+tmd_status tmd_model_get_params(const tmd_model* m, float* params) {
+    if (!m || !params) return TMD_ERR_INVALID_ARGUMENT;
+    TMD_HIP(m->ctx, hipMemcpyAsync(params, m->params32, (size_t)m->S * m->per_species * 4, hipMemcpyDeviceToHost,
+                                   m->ctx->stream));
+    TMD_HIP(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    return TMD_OK;
 }
 
 tmd_status tmd_model_set_precision(tmd_model* m, tmd_precision precision) {
@@ -373,7 +388,7 @@ void tmd_model_destroy(tmd_model* m) {
     if (!m) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)m->mu, (void*)m->eta, (void*)m->w32, (void*)m->wbf, (void*)m->bias, (void*)m->wout,
-                    (void*)m->bout})
+                    (void*)m->bout, (void*)m->params32, (void*)m->opt_m, (void*)m->opt_v})
         if (p) (void)hipFree(p);
     delete m;
 }

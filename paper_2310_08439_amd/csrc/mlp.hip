@@ -421,8 +421,16 @@ MlpFn pick_H(int H, int L, int* cb) {
 
 }  // namespace
 
-tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* G, float* Ei,
-                      float* dG) {
+SpeciesGroups species_groups(const tmd_nlist* nl) {
+    SpeciesGroups g;
+    g.S = nl->S;
+    for (int s = 0; s <= nl->S; ++s) g.off[s] = nl->sp_off[s];
+    g.idx = nl->sp_idx;
+    return g;
+}
+
+tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups& g, tmd_precision prec,
+                      const float* G, float* Ei, float* dG) {
     MlpArgs a{};
     a.S = m->S;
     a.F = m->F;
@@ -430,17 +438,17 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl,
     a.act = m->act;
     a.L = m->L;
     int cb = 2;
-    MlpFn fn = (m->prec == TMD_BF16_MLP) ? pick_H<true>(m->H, m->L, &cb) : pick_H<false>(m->H, m->L, &cb);
+    MlpFn fn = (prec == TMD_BF16_MLP) ? pick_H<true>(m->H, m->L, &cb) : pick_H<false>(m->H, m->L, &cb);
     const int kTileAtoms = kWaves * 16 * cb;
     int64_t tiles = 0;
     for (int s = 0; s < m->S; ++s) {
-        a.sp_off[s] = nl->sp_off[s];
+        a.sp_off[s] = g.off[s];
         a.tile_off[s] = tiles;
-        tiles += (nl->sp_count[s] + kTileAtoms - 1) / kTileAtoms;
+        tiles += (g.off[s + 1] - g.off[s] + kTileAtoms - 1) / kTileAtoms;
     }
-    a.sp_off[m->S] = nl->sp_off[m->S];
+    a.sp_off[m->S] = g.off[m->S];
     a.tile_off[m->S] = tiles;
-    a.sp_idx = nl->sp_idx;
+    a.sp_idx = g.idx;
     a.G = G;
     a.Ei = Ei;
     a.dG = dG;

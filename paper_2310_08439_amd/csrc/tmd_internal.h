@@ -94,6 +94,11 @@ struct tmd_model {
     float* bias = nullptr;   // [S][L][H]
     float* wout = nullptr;   // [S][H]
     float* bout = nullptr;   // [S]
+    // master copy in the ABI layout [S][per_species] and optimiser state
+    float* params32 = nullptr;
+    float* opt_m = nullptr;
+    float* opt_v = nullptr;
+    int64_t opt_t = 0;
 };
 
 struct tmd_nlist {
@@ -159,8 +164,17 @@ tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys
 // Descriptors G [n][F] (sorted order); when Pbuf is non-null the per-atom P
 // tensors [n][S][K][D] are kept there for the adjoint.
 tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf);
-tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* G, float* Ei,
-                      float* dG);
+// Atoms grouped by species: idx[off[s] .. off[s+1]) are the atoms of species s
+// (row indices into G, Ei and dG).
+struct SpeciesGroups {
+    int S = 1;
+    int64_t off[kMaxSpecies + 1] = {0};
+    const int32_t* idx = nullptr;
+};
+SpeciesGroups species_groups(const tmd_nlist* nl);
+// Per-element MLP: E_i and dE/dG for every grouped atom, in precision prec.
+tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups& g, tmd_precision prec,
+                      const float* G, float* Ei, float* dG);
 // Adjoint: forces accumulated into Fsorted [n][3] (zeroed by the launcher),
 // virial block partials into vir_partials (count returned in *nvir_out).
 tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Pbuf,
@@ -170,6 +184,10 @@ tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* E
 tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, int width, float* out);
 tmd_status launch_export_nlist(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt);
 tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row);
+
+// Regenerate the MLP operand copies (W, W^T in FP32 and BF16, biases, output
+// layer) of every species from the master parameters m->params32.
+tmd_status launch_unpack_params(tmd_context* ctx, tmd_model* m);
 
 // Upper bound on the virial partials the adjoint writes.
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl);

@@ -35,7 +35,12 @@ EXPORTS = (
     "tmd_nlist_stats",
     "tmd_descriptors", "tmd_energy_forces", "tmd_energy_forces_async",
     "tmd_profile_enable", "tmd_profile_reset", "tmd_profile_read",
+    "tmd_model_get_params", "tmd_batch_create", "tmd_batch_destroy", "tmd_train_step", "tmd_batch_read",
 )
+
+OPT_ADAM = 0
+OPT_SGD = 1
+BATCH_G, BATCH_ENERGY, BATCH_FORCES, BATCH_RESIDUAL, BATCH_TANGENT = 0, 1, 2, 3, 4
 
 
 class TMDError(RuntimeError):
@@ -55,6 +60,12 @@ class ModelSpecC(ctypes.Structure):
                 ("n_hidden", ctypes.c_int32), ("hidden", ctypes.c_int32 * MAX_HIDDEN),
                 ("activation", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rcut", ctypes.c_double),
                 ("mu", ctypes.c_void_p), ("eta", ctypes.c_void_p)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -100,6 +111,12 @@ def load_library(path: str = LIB_PATH):
     L.tmd_profile_reset.argtypes = [vp]
     L.tmd_profile_read.argtypes = [vp, i32, vp, vp, vp]
     L.tmd_profile_read.restype = i32
+    L.tmd_model_get_params.argtypes = [vp, vp]
+    L.tmd_batch_create.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, i32, P(vp)]
+    L.tmd_batch_destroy.argtypes = [vp]
+    L.tmd_batch_destroy.restype = None
+    L.tmd_train_step.argtypes = [vp, vp, vp, P(TrainOpts), vp, vp]
+    L.tmd_batch_read.argtypes = [vp, vp, i32, vp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -221,6 +238,16 @@ class Model:
     def set_params(self, params: np.ndarray):
         p = np.ascontiguousarray(params, dtype=np.float32)
         self.ctx.check(self.ctx.lib.tmd_model_set_params(self.h, p.ctypes.data), "tmd_model_set_params")
+
+    @property
+    def n_params(self) -> int:
+        return int(self.ctx.lib.tmd_model_params_per_species(self.h)) * self.spec.n_species
+
+    def get_params(self) -> np.ndarray:
+        """Current weights (host float32, tmd_model_create layout)."""
+        out = np.empty(self.n_params, dtype=np.float32)
+        self.ctx.check(self.ctx.lib.tmd_model_get_params(self.h, out.ctypes.data), "tmd_model_get_params")
+        return out
 
     def close(self):
         if getattr(self, "h", None):
@@ -365,3 +392,104 @@ class Evaluator:
         if rebuild:
             self.build(pos, species, box)
         return descriptors(self.ctx, self.model, pos, species, box, self.nl)
+
+
+# ---------------------------------------------------------------- training
+
+
+class Batch:
+    """A labelled batch of periodic systems on the device (tmd_batch_create)."""
+
+    def __init__(self, ctx: Context, model: Model, sys_off, pos, species, boxes, energy_labels, force_labels,
+                 capacity: int = 0):
+        torch = _torch()
+        self.ctx = ctx
+        self.sys_off = np.ascontiguousarray(sys_off, dtype=np.int64)
+        self.boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+        self.energy_labels = np.ascontiguousarray(energy_labels, dtype=np.float64)
+        if pos.dtype != torch.float64 or not pos.is_cuda or not pos.is_contiguous():
+            raise ValueError("pos must be a contiguous [N,3] float64 device tensor")
+        if species.dtype != torch.int32 or not species.is_cuda or not species.is_contiguous():
+            raise ValueError("species must be a contiguous int32 device tensor")
+        if force_labels.dtype != torch.float32 or not force_labels.is_cuda or not force_labels.is_contiguous():
+            raise ValueError("force_labels must be a contiguous [N,3] float32 device tensor")
+        self.n = int(self.sys_off[-1])
+        self.n_systems = int(self.sys_off.shape[0] - 1)
+        self.n_features = model.n_features
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.tmd_batch_create(ctx.h, model.h, self.n_systems, self.sys_off.ctypes.data, _ptr(pos),
+                                           _ptr(species), self.boxes.ctypes.data, self.energy_labels.ctypes.data,
+                                           _ptr(force_labels), int(capacity), ctypes.byref(h)), "tmd_batch_create")
+        self.h = h
+
+    def read(self, field: int):
+        """Device float32 copy of an intermediate of the last step (BATCH_* fields)."""
+        torch = _torch()
+        shape = {BATCH_G: (self.n, self.n_features), BATCH_ENERGY: (self.n,), BATCH_FORCES: (self.n, 3),
+                 BATCH_RESIDUAL: (self.n, 3), BATCH_TANGENT: (self.n, self.n_features)}[field]
+        out = torch.empty(shape, dtype=torch.float32, device=torch.device("cuda", self.ctx.device))
+        self.ctx.check(self.ctx.lib.tmd_batch_read(self.ctx.h, self.h, int(field), _ptr(out)), "tmd_batch_read")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tmd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def train_step(ctx: Context, model: Model, batch: Batch, lam: float = 0.1, lr: float = 0.0,
+               optimizer: int = OPT_ADAM, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+               grad=None) -> Tuple[float, float, float]:
+    """(loss, energy term, force term) before the update; grad (device float32) receives dL/dtheta."""
+    o = TrainOpts()
+    o.lambda_ = float(lam)
+    o.lr = float(lr)
+    o.beta1 = float(beta1)
+    o.beta2 = float(beta2)
+    o.eps = float(eps)
+    o.optimizer = int(optimizer)
+    loss = (ctypes.c_double * 3)()
+    ctx.check(ctx.lib.tmd_train_step(ctx.h, model.h, batch.h, ctypes.byref(o), loss, _ptr(grad)), "tmd_train_step")
+    return float(loss[0]), float(loss[1]), float(loss[2])
+
+
+# ---------------------------------------------------------------- autograd
+
+
+def _energy_function():
+    torch = _torch()
+
+    class TMDEnergy(torch.autograd.Function):
+        """Total energy E(x) (FP64 scalar) whose gradient dE/dx = -F comes from the
+        library's hand-written adjoint kernels (the forces of the same call)."""
+
+        @staticmethod
+        def forward(fctx, pos, species, box, evaluator, rebuild):
+            E, _, F, _ = evaluator.energy_forces(pos.detach().contiguous(), species, box, rebuild=rebuild,
+                                                 atom_energy=False)
+            fctx.save_for_backward(F)
+            return torch.tensor(E, dtype=torch.float64, device=pos.device)
+
+        @staticmethod
+        def backward(fctx, grad_e):
+            (F,) = fctx.saved_tensors
+            return -F.to(torch.float64) * grad_e, None, None, None, None
+
+    return TMDEnergy
+
+
+_TMDEnergy = None
+
+
+def energy(pos, species, box, evaluator: "Evaluator", rebuild: bool = True):
+    """Differentiable total energy: torch.autograd sees dE/dpos = -forces."""
+    global _TMDEnergy
+    if _TMDEnergy is None:
+        _TMDEnergy = _energy_function()
+    return _TMDEnergy.apply(pos, species, box, evaluator, rebuild)
