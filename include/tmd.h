@@ -258,6 +258,104 @@ typedef enum {
 } tmd_batch_field;
 tmd_status tmd_batch_read(tmd_context* ctx, const tmd_batch* batch, int32_t field, float* out);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A persistent request loop over resident systems (the MD protocol of
+ * Sec. IV.D, one velocity-Verlet NVE step being a full energy-and-force
+ * evaluation).  Systems are registered once and stay on the device: positions
+ * and velocities (FP64), species and, while memory allows, their neighbour
+ * list.  Requests are served by max_slots worker threads, each with its own
+ * HIP stream and workspace, so requests admitted together run concurrently on
+ * the device; a request is admitted when a slot is free, no other request on
+ * its system is running, and its neighbour list fits in hbm_budget_bytes
+ * (idle systems' lists are evicted, least recently used first).  Requests on
+ * one system run in submission order. */
+typedef struct tmd_server tmd_server;
+
+/* hbm_budget_bytes: device memory for system state and neighbour lists
+ * (0: 32 GiB); max_slots: concurrent requests, 1..64 (0: 8); max_atoms: the
+ * largest system accepted, which sizes each slot's workspace (0: 262,144);
+ * skin: neighbour-list skin of MD runs (A), lists are rebuilt when an atom has
+ * moved more than skin/2 since the last build; capacity: initial per-species
+ * list capacity (0: from the density). */
+typedef struct {
+    int64_t hbm_budget_bytes;
+    int32_t max_slots;
+    int32_t device;
+    int64_t max_atoms;
+    double skin;
+    int32_t capacity;
+    int32_t reserved;
+} tmd_serve_opts;
+
+typedef enum { TMD_REQ_ENERGY_FORCES = 0, TMD_REQ_MD = 1 } tmd_request_kind;
+
+/* kind: tmd_request_kind.  MD: n_steps velocity-Verlet steps of dt_fs
+ *   v += (dt/2) F/m;  x += dt v;  (rebuild the list if needed);  F = F(x);  v += (dt/2) F/m
+ * with accelerations 9.648533e-3 F[eV/A]/m[amu] A/fs^2, starting from the
+ * system's resident positions and either velocities (host FP64 [n][3], copied
+ * at submit: for instance Maxwell-Boltzmann draws) or, when NULL, the
+ * resident velocities; the final state is kept as the system's new resident
+ * state.  ENERGY_FORCES evaluates the resident positions. */
+typedef struct {
+    int64_t system_id;
+    int32_t kind;
+    int32_t n_steps;
+    double dt_fs;
+    const double* velocities;
+} tmd_request;
+
+/* status: tmd_status of the request; energy: potential energy (MD: at the
+ * final positions); kinetic: MD final kinetic energy (103.6427 * m v^2 / 2, eV);
+ * virial: at the final positions; t_submit, t_start, t_done: seconds on the
+ * host steady clock since the server was created; rebuilds: neighbour-list
+ * builds the request made. */
+typedef struct {
+    int32_t status;
+    int32_t kind;
+    int64_t system_id;
+    int64_t n_atoms;
+    int32_t n_steps;
+    int32_t rebuilds;
+    double energy;
+    double kinetic;
+    double virial[6];
+    double t_submit;
+    double t_start;
+    double t_done;
+} tmd_result;
+
+/* The server keeps `model` (not copied: it must outlive the server and not
+ * change while requests run) and uses its precision setting. */
+tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, tmd_server** out);
+/* Register a system: host FP64 positions [n][3], host int32 species [n], box,
+ * host FP64 masses per species [S] (amu).  Velocities start at zero.
+ * TMD_ERR_REJECTED when it is larger than max_atoms or its state cannot fit. */
+tmd_status tmd_serve_add_system(tmd_server* server, int64_t n_atoms, const double* pos, const int32_t* species,
+                                const double box[3], const double* masses, int64_t* system_id);
+/* Queue a request; *ticket identifies it.  Thread-safe. */
+tmd_status tmd_serve_submit(tmd_server* server, const tmd_request* request, uint64_t* ticket);
+/* TMD_ERR_NOT_READY until the request is done, then TMD_OK with *result
+ * filled (result->status holds the request's own outcome).  Thread-safe. */
+tmd_status tmd_serve_poll(tmd_server* server, uint64_t ticket, tmd_result* result);
+/* Block until done (or timeout_s seconds, then TMD_ERR_NOT_READY; < 0 waits forever). */
+tmd_status tmd_serve_wait(tmd_server* server, uint64_t ticket, double timeout_s, tmd_result* result);
+/* Host copies of a finished request's arrays, each nullable: forces [n][3]
+ * (at the final positions), pos and vel [n][3] (MD: final state), epot and
+ * ekin [n_steps + 1] (MD: before the first step and after each). */
+tmd_status tmd_serve_fetch(tmd_server* server, uint64_t ticket, float* forces, double* pos, double* vel,
+                           double* epot, double* ekin);
+/* Forget a finished request's result. */
+tmd_status tmd_serve_release(tmd_server* server, uint64_t ticket);
+/* Current resident positions / velocities of a system (host FP64 [n][3], nullable). */
+tmd_status tmd_serve_read_system(tmd_server* server, int64_t system_id, double* pos, double* vel);
+/* Device memory the server holds (system state, lists, slot workspaces) and
+ * its high-water mark, in bytes. */
+tmd_status tmd_serve_memory(tmd_server* server, int64_t* in_use, int64_t* peak);
+const char* tmd_serve_last_error(tmd_server* server);
+/* Finish the running requests, drop queued ones, free everything. */
+void tmd_serve_destroy(tmd_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -181,6 +181,31 @@ tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* n
     return TMD_OK;
 }
 
+}  // namespace
+
+tmd_status reserve_eval_workspace(tmd_context* ctx, const tmd_model* m, int64_t n) {
+    hipError_t e = hipSuccess;
+    const int64_t nch = m->K / m->kc;
+    (void)ctx->ws.get("ev.G", sizeof(float) * n * m->F, &e);
+    (void)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
+    (void)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
+    (void)ctx->ws.get("ev.Fs", sizeof(float) * 3 * n, &e);
+    (void)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->D, &e);
+    (void)ctx->ws.get("ev.vir",
+                      sizeof(double) * 6 * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock), &e);
+    (void)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "evaluation workspace allocation");
+    return TMD_OK;
+}
+
+size_t eval_workspace_bytes(const tmd_model* m, int64_t n) {
+    const int64_t nch = m->K / m->kc;
+    return (size_t)n * (8 * m->F + 4 + 12 + 4 * (size_t)m->S * m->K * m->D) +
+           48 * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock) + 64;
+}
+
+namespace {
+
 tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
                              double* totals7_dev, float* atom_energy, float* forces) {
     EvalBuffers b;

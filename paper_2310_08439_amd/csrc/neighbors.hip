@@ -642,6 +642,29 @@ tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys
     return TMD_OK;
 }
 
+tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S) {
+    (void)S;
+    hipError_t e = hipSuccess;
+    const int64_t nblk = (n + kBlock - 1) / kBlock, cells = std::max<int64_t>(64, 4 * n) + 1;
+    (void)ctx->ws.get("nb.wpos", sizeof(double) * 3 * n, &e);
+    (void)ctx->ws.get("nb.cell_of", sizeof(int32_t) * n, &e);
+    (void)ctx->ws.get("nb.cell_sorted", sizeof(int32_t) * n, &e);
+    (void)ctx->ws.get("nb.order", sizeof(int32_t) * n, &e);
+    (void)ctx->ws.get("nb.cellcount", sizeof(int32_t) * cells, &e);
+    (void)ctx->ws.get("nb.cellfill", sizeof(int32_t) * cells, &e);
+    (void)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
+    (void)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
+    (void)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
+    (void)ctx->ws.get("nb.sp_off", sizeof(int64_t) * (kMaxSpecies + 1), &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "neighbour workspace allocation");
+    return TMD_OK;
+}
+
+size_t nlist_workspace_bytes(int64_t n) {
+    const int64_t nblk = (n + kBlock - 1) / kBlock;
+    return (size_t)n * 36 + 8 * (size_t)(std::max<int64_t>(64, 4 * n) + 1) + 8 * (size_t)kMaxSpecies * (nblk + 1) + 512;
+}
+
 tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row) {
     hipError_t e = hipSuccess;
     void* buf = ctx->ws.get("nb.stats", 64, &e);

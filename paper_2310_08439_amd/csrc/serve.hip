@@ -1,0 +1,715 @@
+// Persistent request loop over resident systems: energy/force requests and
+// velocity-Verlet NVE runs (the MD protocol of Sec. IV.D), served by a pool of
+// worker threads with one HIP stream and one workspace each, so that requests
+// admitted together run concurrently on the device.
+//
+// Admission: a queued request is taken by a free worker when no earlier
+// request on the same system is still queued or running (requests on one
+// system keep their order) and the system's neighbour list fits in the memory
+// budget; idle systems' lists are evicted, least recently used first.  System
+// state (positions, velocities, forces, reference positions of the last list
+// build) stays resident from registration to destruction.
+#include "tmd_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <set>
+#include <thread>
+
+namespace tmd {
+namespace {
+
+constexpr double kAccConv = 9.648533e-3;  // (eV/A)/amu -> A/fs^2
+constexpr double kKeConv = 103.6427;      // amu (A/fs)^2 -> eV
+constexpr int kKeBlocks = 256;
+
+// v += (dt/2) a; x += dt v; and the largest squared displacement since the
+// last list build, as the bits of a non-negative double (ordered like the values).
+__global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double* __restrict__ x, double* __restrict__ v,
+                                                    const float* __restrict__ F, const int32_t* __restrict__ sp,
+                                                    const double* __restrict__ acc, double dt,
+                                                    const double* __restrict__ xref,
+                                                    unsigned long long* __restrict__ maxd2) {
+    __shared__ double red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0;
+    if (i < n) {
+        const double a = acc[sp[i]];
+        for (int c = 0; c < 3; ++c) {
+            const double vi = v[3 * i + c] + 0.5 * dt * a * (double)F[3 * i + c];
+            const double xi = x[3 * i + c] + dt * vi;
+            v[3 * i + c] = vi;
+            x[3 * i + c] = xi;
+            const double d = xi - xref[3 * i + c];
+            d2 += d * d;
+        }
+    }
+    red[threadIdx.x] = d2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(maxd2, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// v += (dt/2) a
+__global__ void k_kick(int64_t n, double* __restrict__ v, const float* __restrict__ F,
+                       const int32_t* __restrict__ sp, const double* __restrict__ acc, double dt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = acc[sp[i]];
+    for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * a * (double)F[3 * i + c];
+}
+
+// Kinetic energy in two fixed-order passes: kKeBlocks strided partials, then
+// one compensated sum.
+__global__ void __launch_bounds__(256) k_ke_partials(int64_t n, const double* __restrict__ v,
+                                                     const int32_t* __restrict__ sp,
+                                                     const double* __restrict__ mass, double* __restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s += 0.5 * kKeConv * mass[sp[i]] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_ke_total(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double x = part[b], t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    }
+    *out = s + c;
+}
+
+unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct System {
+    int64_t id = 0, n = 0;
+    double box[3] = {0, 0, 0};
+    double* x = nullptr;       // [n][3] positions (not wrapped)
+    double* v = nullptr;       // [n][3] velocities
+    double* xref = nullptr;    // [n][3] positions at the last list build
+    float* F = nullptr;        // [n][3] forces at x
+    int32_t* sp = nullptr;     // [n]
+    double* acc = nullptr;     // [S] kAccConv / m_s
+    double* mass = nullptr;    // [S]
+    size_t state_bytes = 0;
+    tmd_nlist* nl = nullptr;
+    int cap = 0;
+    size_t nl_bytes = 0;
+    bool nl_valid = false;     // built for the current positions (within skin/2)
+    bool busy = false;
+    uint64_t last_use = 0;
+};
+
+struct Pending {
+    uint64_t ticket = 0;
+    tmd_request req{};
+    std::vector<double> vel;
+    double t_submit = 0.0;
+};
+
+struct Finished {
+    tmd_result res{};
+    std::vector<float> F;
+    std::vector<double> x, v, epot, ekin;
+};
+
+}  // namespace
+}  // namespace tmd
+
+struct tmd_server {
+    const tmd_model* model = nullptr;
+    tmd_serve_opts opts{};
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<tmd::Pending> queue;
+    std::set<uint64_t> running;
+    std::map<uint64_t, tmd::Finished> done;
+    std::map<int64_t, std::unique_ptr<tmd::System>> systems;
+    int64_t next_system = 0;
+    uint64_t next_ticket = 1;
+    uint64_t clock = 0;
+    int64_t mem_in_use = 0, mem_peak = 0;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    std::vector<tmd_context*> ctxs;
+    bool stop = false;
+    std::string last_error;
+};
+
+namespace tmd {
+namespace {
+
+void account(tmd_server* sv, int64_t delta) {
+    sv->mem_in_use += delta;
+    sv->mem_peak = std::max(sv->mem_peak, sv->mem_in_use);
+}
+
+int density_capacity(int64_t n, const double* box, double rlist, int S) {
+    const double vol = box[0] * box[1] * box[2];
+    const double mean = (double)n / vol * 4.0 / 3.0 * M_PI * rlist * rlist * rlist;
+    int cap = (int)(mean * (1.0 / S + 0.3)) + 16;
+    return std::max(16, (cap + 7) / 8 * 8);
+}
+
+size_t nlist_bytes(int64_t n, int S, int cap) {
+    return (size_t)n * 56 + (size_t)n * S * cap * 8 + (size_t)S * n * 4 + 4 * (size_t)(4 * n + 65);
+}
+
+// Build (or rebuild) sys's list on ctx, growing it on overflow.
+tmd_status build_list(tmd_server* sv, tmd_context* ctx, System* sys, int* rebuilds) {
+    const tmd_model* m = sv->model;
+    tmd_system_view v{};
+    v.n_atoms = sys->n;
+    v.pos = sys->x;
+    v.species = sys->sp;
+    for (int a = 0; a < 3; ++a) v.box[a] = sys->box[a];
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        int32_t need = 0;
+        tmd_status st = tmd_build_neighbors(ctx, &v, m->rcut, sv->opts.skin, sys->nl, &need);
+        if (st == TMD_OK) {
+            TMD_HIP(ctx, hipMemcpyAsync(sys->xref, sys->x, 24 * (size_t)sys->n, hipMemcpyDeviceToDevice, ctx->stream));
+            sys->nl_valid = true;
+            ++*rebuilds;
+            return TMD_OK;
+        }
+        if (st != TMD_ERR_CAPACITY) return st;
+        // grow: the budget is exceeded briefly rather than failing the request
+        const int cap = (need + 8 + 7) / 8 * 8;
+        tmd_nlist* nl = nullptr;
+        if ((st = tmd_nlist_create(ctx, sys->n, m->S, cap, &nl)) != TMD_OK) return st;
+        tmd_nlist_destroy(sys->nl);
+        sys->nl = nl;
+        const size_t nb = nlist_bytes(sys->n, m->S, nl->cap);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            account(sv, (int64_t)nb - (int64_t)sys->nl_bytes);
+        }
+        sys->nl_bytes = nb;
+        sys->cap = nl->cap;
+    }
+    return fail(ctx, TMD_ERR_CAPACITY, "neighbour list kept overflowing");
+}
+
+struct SlotBuffers {
+    double* tot = nullptr;                 // [7 (n_steps + 1)]
+    double* ekin = nullptr;                // [n_steps + 1]
+    double* part = nullptr;                // [kKeBlocks]
+    unsigned long long* maxd2 = nullptr;   // [1]
+};
+
+tmd_status slot_buffers(tmd_context* ctx, int n_steps, SlotBuffers* b) {
+    hipError_t e = hipSuccess;
+    b->tot = (double*)ctx->ws.get("md.tot", sizeof(double) * 7 * (size_t)(n_steps + 1), &e);
+    b->ekin = (double*)ctx->ws.get("md.ekin", sizeof(double) * (size_t)(n_steps + 1), &e);
+    b->part = (double*)ctx->ws.get("md.part", sizeof(double) * kKeBlocks, &e);
+    b->maxd2 = (unsigned long long*)ctx->ws.get("md.maxd2", sizeof(unsigned long long), &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "MD workspace");
+    return TMD_OK;
+}
+
+tmd_status kinetic(tmd_context* ctx, const System* sys, double* part, double* out) {
+    k_ke_partials<<<kKeBlocks, 256, 0, ctx->stream>>>(sys->n, sys->v, sys->sp, sys->mass, part);
+    k_ke_total<<<1, 64, 0, ctx->stream>>>(part, kKeBlocks, out);
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
+}
+
+// Run one request to completion on the worker's context.
+tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pending& p, Finished* out) {
+    const tmd_model* m = sv->model;
+    tmd_result& r = out->res;
+    tmd_status st;
+    tmd_system_view view{};
+    view.n_atoms = sys->n;
+    view.pos = sys->x;
+    view.species = sys->sp;
+    for (int a = 0; a < 3; ++a) view.box[a] = sys->box[a];
+    int rebuilds = 0;
+    const int nsteps = (p.req.kind == TMD_REQ_MD) ? p.req.n_steps : 0;
+    SlotBuffers b;
+    if ((st = slot_buffers(ctx, nsteps, &b)) != TMD_OK) return st;
+    if (p.req.kind == TMD_REQ_MD && !p.vel.empty())
+        TMD_HIP(ctx, hipMemcpyAsync(sys->v, p.vel.data(), 24 * (size_t)sys->n, hipMemcpyHostToDevice, ctx->stream));
+    if (!sys->nl_valid && (st = build_list(sv, ctx, sys, &rebuilds)) != TMD_OK) return st;
+    if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot, nullptr, sys->F)) != TMD_OK) return st;
+    if (p.req.kind == TMD_REQ_MD) {
+        if ((st = kinetic(ctx, sys, b.part, b.ekin)) != TMD_OK) return st;
+        const double dt = p.req.dt_fs;
+        const double half_skin2 = 0.25 * sv->opts.skin * sv->opts.skin;
+        for (int s = 1; s <= nsteps; ++s) {
+            TMD_HIP(ctx, hipMemsetAsync(b.maxd2, 0, sizeof(unsigned long long), ctx->stream));
+            k_kick_drift<<<blocks(sys->n), kBlock, 0, ctx->stream>>>(sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc,
+                                                                     dt, sys->xref, b.maxd2);
+            TMD_HIP(ctx, hipGetLastError());
+            unsigned long long bits = 0;
+            TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, b.maxd2, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream));
+            TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            std::memcpy(&bits, ctx->h_flags, sizeof(bits));
+            double d2;
+            std::memcpy(&d2, &bits, sizeof(d2));
+            if (!(d2 <= half_skin2)) {
+                sys->nl_valid = false;
+                if ((st = build_list(sv, ctx, sys, &rebuilds)) != TMD_OK) return st;
+            }
+            if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F)) != TMD_OK)
+                return st;
+            k_kick<<<blocks(sys->n), kBlock, 0, ctx->stream>>>(sys->n, sys->v, sys->F, sys->sp, sys->acc, dt);
+            TMD_HIP(ctx, hipGetLastError());
+            if ((st = kinetic(ctx, sys, b.part, b.ekin + s)) != TMD_OK) return st;
+        }
+    }
+    std::vector<double> tot(7 * (size_t)(nsteps + 1));
+    out->F.resize(3 * (size_t)sys->n);
+    TMD_HIP(ctx, hipMemcpyAsync(tot.data(), b.tot, sizeof(double) * tot.size(), hipMemcpyDeviceToHost, ctx->stream));
+    TMD_HIP(ctx, hipMemcpyAsync(out->F.data(), sys->F, 12 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
+    if (p.req.kind == TMD_REQ_MD) {
+        out->ekin.resize(nsteps + 1);
+        out->x.resize(3 * (size_t)sys->n);
+        out->v.resize(3 * (size_t)sys->n);
+        TMD_HIP(ctx, hipMemcpyAsync(out->ekin.data(), b.ekin, sizeof(double) * (nsteps + 1), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        TMD_HIP(ctx, hipMemcpyAsync(out->x.data(), sys->x, 24 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
+        TMD_HIP(ctx, hipMemcpyAsync(out->v.data(), sys->v, 24 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    out->epot.resize(nsteps + 1);
+    for (int s = 0; s <= nsteps; ++s) out->epot[s] = tot[7 * s];
+    r.energy = tot[7 * nsteps];
+    for (int j = 0; j < 6; ++j) r.virial[j] = tot[7 * nsteps + 1 + j];
+    r.kinetic = p.req.kind == TMD_REQ_MD ? out->ekin[nsteps] : 0.0;
+    r.rebuilds = rebuilds;
+    return TMD_OK;
+}
+
+// Next admissible request (queue order, one per system at a time, list memory
+// within budget after evicting idle lists).  Caller holds sv->mu.
+bool pick(tmd_server* sv, Pending* out, System** sys_out, bool* rejected, Finished* rej) {
+    std::set<int64_t> blocked;
+    const int64_t budget = sv->opts.hbm_budget_bytes;
+    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+        const int64_t sid = it->req.system_id;
+        if (blocked.count(sid)) continue;
+        System* sys = sv->systems.at(sid).get();
+        if (sys->busy) {
+            blocked.insert(sid);
+            continue;
+        }
+        int64_t need = sys->nl ? 0 : (int64_t)nlist_bytes(sys->n, sv->model->S, sys->cap);
+        if (need > 0 && sv->mem_in_use + need > budget) {
+            // evict idle lists, least recently used first
+            std::vector<System*> idle;
+            for (auto& kv : sv->systems)
+                if (!kv.second->busy && kv.second->nl && kv.second.get() != sys) idle.push_back(kv.second.get());
+            std::sort(idle.begin(), idle.end(), [](System* a, System* b) { return a->last_use < b->last_use; });
+            for (System* s : idle) {
+                if (sv->mem_in_use + need <= budget) break;
+                tmd_nlist_destroy(s->nl);
+                s->nl = nullptr;
+                s->nl_valid = false;
+                account(sv, -(int64_t)s->nl_bytes);
+                s->nl_bytes = 0;
+            }
+        }
+        if (need > 0 && sv->mem_in_use + need > budget) {
+            if (sv->running.empty()) {
+                // nothing will ever free more: the request cannot be served
+                *rejected = true;
+                rej->res.status = TMD_ERR_REJECTED;
+                rej->res.kind = it->req.kind;
+                rej->res.system_id = sid;
+                rej->res.n_atoms = sys->n;
+                rej->res.t_submit = it->t_submit;
+                rej->res.t_start = rej->res.t_done = now_s(sv->t0);
+                *out = *it;
+                sv->queue.erase(it);
+                return true;
+            }
+            blocked.insert(sid);
+            continue;
+        }
+        *out = std::move(*it);
+        sv->queue.erase(it);
+        sys->busy = true;
+        *sys_out = sys;
+        *rejected = false;
+        if (need > 0) account(sv, need);  // reserved now, allocated by the worker
+        return true;
+    }
+    return false;
+}
+
+void worker_main(tmd_server* sv, int slot) {
+    (void)hipSetDevice(sv->opts.device);
+    tmd_context* ctx = sv->ctxs[slot];
+    for (;;) {
+        Pending p;
+        System* sys = nullptr;
+        bool rejected = false;
+        Finished fin;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait(lk, [&] { return sv->stop || pick(sv, &p, &sys, &rejected, &fin); });
+            if (sv->stop) break;
+            if (rejected) {
+                sv->done[p.ticket] = std::move(fin);
+                sv->cv_done.notify_all();
+                continue;
+            }
+            sv->running.insert(p.ticket);
+        }
+        Finished f;
+        f.res.kind = p.req.kind;
+        f.res.system_id = sys->id;
+        f.res.n_atoms = sys->n;
+        f.res.n_steps = p.req.kind == TMD_REQ_MD ? p.req.n_steps : 0;
+        f.res.t_submit = p.t_submit;
+        f.res.t_start = now_s(sv->t0);
+        tmd_status st = TMD_OK;
+        if (!sys->nl) {
+            tmd_nlist* nl = nullptr;
+            st = tmd_nlist_create(ctx, sys->n, sv->model->S, sys->cap, &nl);
+            if (st == TMD_OK) {
+                sys->nl = nl;
+                sys->nl_bytes = nlist_bytes(sys->n, sv->model->S, sys->cap);
+                sys->nl_valid = false;
+            }
+        }
+        if (st == TMD_OK) st = run_request(sv, ctx, sys, p, &f);
+        f.res.status = st;
+        f.res.t_done = now_s(sv->t0);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (st != TMD_OK) {
+                sv->last_error = ctx->last_error;
+                if (!sys->nl_bytes && sys->nl == nullptr) account(sv, -(int64_t)nlist_bytes(sys->n, sv->model->S, sys->cap));
+            }
+            sys->busy = false;
+            sys->last_use = ++sv->clock;
+            sv->running.erase(p.ticket);
+            sv->done[p.ticket] = std::move(f);
+        }
+        sv->cv_done.notify_all();
+        sv->cv_work.notify_all();
+    }
+}
+
+void release_slots(tmd_server* sv) {
+    for (tmd_context* c : sv->ctxs)
+        if (c) tmd_context_destroy(c);
+    for (hipStream_t st : sv->streams)
+        if (st) (void)hipStreamDestroy(st);
+    sv->ctxs.clear();
+    sv->streams.clear();
+}
+
+tmd_status sfail(tmd_server* sv, tmd_status st, const char* msg) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->last_error = msg;
+    return st;
+}
+
+}  // namespace
+}  // namespace tmd
+
+using namespace tmd;
+
+extern "C" {
+
+tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, tmd_server** out) {
+    if (!model || !out) return TMD_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    tmd_serve_opts o{};
+    if (opts) o = *opts;
+    if (o.hbm_budget_bytes <= 0) o.hbm_budget_bytes = (int64_t)32 << 30;
+    if (o.max_slots <= 0) o.max_slots = 8;
+    if (o.max_slots > 64) return TMD_ERR_INVALID_ARGUMENT;
+    if (o.max_atoms <= 0) o.max_atoms = 262144;
+    if (!(o.skin >= 0.0) || !std::isfinite(o.skin)) return TMD_ERR_INVALID_ARGUMENT;
+    tmd_server* sv = new (std::nothrow) tmd_server();
+    if (!sv) return TMD_ERR_OUT_OF_MEMORY;
+    sv->model = model;
+    sv->opts = o;
+    sv->t0 = std::chrono::steady_clock::now();
+    // one stream, context and workspace per slot, sized once for max_atoms
+    if (hipSetDevice(o.device) != hipSuccess) {
+        delete sv;
+        return TMD_ERR_DEVICE;
+    }
+    account(sv, (int64_t)o.max_slots *
+                    (int64_t)(eval_workspace_bytes(model, o.max_atoms) + nlist_workspace_bytes(o.max_atoms)));
+    if (sv->mem_in_use > o.hbm_budget_bytes) {
+        delete sv;
+        return TMD_ERR_REJECTED;
+    }
+    tmd_status st = TMD_OK;
+    for (int s = 0; s < o.max_slots && st == TMD_OK; ++s) {
+        hipStream_t stream = nullptr;
+        tmd_context* ctx = nullptr;
+        if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+            st = TMD_ERR_DEVICE;
+            break;
+        }
+        sv->streams.push_back(stream);
+        st = tmd_context_create(o.device, stream, &ctx);
+        if (st != TMD_OK) break;
+        sv->ctxs.push_back(ctx);
+        if ((st = reserve_eval_workspace(ctx, model, o.max_atoms)) != TMD_OK) break;
+        st = reserve_nlist_workspace(ctx, o.max_atoms, model->S);
+    }
+    if (st != TMD_OK) {
+        release_slots(sv);
+        delete sv;
+        return st;
+    }
+    for (int s = 0; s < o.max_slots; ++s) sv->workers.emplace_back(worker_main, sv, s);
+    *out = sv;
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_add_system(tmd_server* sv, int64_t n, const double* pos, const int32_t* species,
+                                const double box[3], const double* masses, int64_t* system_id) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    if (!pos || !species || !box || !masses || !system_id) return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "null argument");
+    const int S = sv->model->S;
+    if (n <= 0) return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "n_atoms must be positive");
+    if (n > sv->opts.max_atoms) return sfail(sv, TMD_ERR_REJECTED, "system larger than max_atoms");
+    for (int a = 0; a < 3; ++a)
+        if (!(box[a] > 0.0) || !std::isfinite(box[a])) return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "bad box");
+    for (int s = 0; s < S; ++s)
+        if (!(masses[s] > 0.0) || !std::isfinite(masses[s])) return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "bad mass");
+    for (int64_t i = 0; i < n; ++i)
+        if (species[i] < 0 || species[i] >= S) return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "species out of range");
+    auto sys = std::make_unique<System>();
+    sys->n = n;
+    for (int a = 0; a < 3; ++a) sys->box[a] = box[a];
+    sys->cap = density_capacity(n, box, sv->model->rcut + sv->opts.skin, S);
+    sys->state_bytes = (size_t)n * (24 * 3 + 12 + 4) + 16 * (size_t)S;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->mem_in_use + (int64_t)sys->state_bytes + (int64_t)nlist_bytes(n, S, sys->cap) > sv->opts.hbm_budget_bytes) {
+            sv->last_error = "system state does not fit in the memory budget";
+            return TMD_ERR_REJECTED;
+        }
+        account(sv, (int64_t)sys->state_bytes);
+    }
+    std::vector<double> acc(S);
+    for (int s = 0; s < S; ++s) acc[s] = kAccConv / masses[s];
+    hipError_t e = hipSetDevice(sv->opts.device);
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    };
+    alloc((void**)&sys->x, 24 * (size_t)n);
+    alloc((void**)&sys->v, 24 * (size_t)n);
+    alloc((void**)&sys->xref, 24 * (size_t)n);
+    alloc((void**)&sys->F, 12 * (size_t)n);
+    alloc((void**)&sys->sp, 4 * (size_t)n);
+    alloc((void**)&sys->acc, 8 * (size_t)S);
+    alloc((void**)&sys->mass, 8 * (size_t)S);
+    if (e == hipSuccess) e = hipMemcpy(sys->x, pos, 24 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sys->xref, pos, 24 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(sys->v, 0, 24 * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpy(sys->sp, species, 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sys->acc, acc.data(), 8 * (size_t)S, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sys->mass, masses, 8 * (size_t)S, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        for (void* p : {(void*)sys->x, (void*)sys->v, (void*)sys->xref, (void*)sys->F, (void*)sys->sp, (void*)sys->acc,
+                        (void*)sys->mass})
+            if (p) (void)hipFree(p);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        account(sv, -(int64_t)sys->state_bytes);
+        sv->last_error = std::string("system upload: ") + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? TMD_ERR_OUT_OF_MEMORY : TMD_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sys->id = sv->next_system++;
+    *system_id = sys->id;
+    sv->systems[sys->id] = std::move(sys);
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_submit(tmd_server* sv, const tmd_request* req, uint64_t* ticket) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    if (!req || !ticket) return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "null argument");
+    if (req->kind != TMD_REQ_ENERGY_FORCES && req->kind != TMD_REQ_MD)
+        return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "unknown request kind");
+    if (req->kind == TMD_REQ_MD && (req->n_steps < 0 || req->n_steps > 1000000 || !(req->dt_fs > 0.0) ||
+                                    !std::isfinite(req->dt_fs)))
+        return sfail(sv, TMD_ERR_INVALID_ARGUMENT, "MD needs 0 <= n_steps and dt_fs > 0");
+    Pending p;
+    p.req = *req;
+    p.req.velocities = nullptr;
+    int64_t n = 0;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->systems.find(req->system_id);
+        if (it == sv->systems.end()) {
+            sv->last_error = "unknown system id";
+            return TMD_ERR_INVALID_ARGUMENT;
+        }
+        n = it->second->n;
+    }
+    if (req->kind == TMD_REQ_MD && req->velocities) p.vel.assign(req->velocities, req->velocities + 3 * n);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    p.ticket = sv->next_ticket++;
+    p.t_submit = now_s(sv->t0);
+    *ticket = p.ticket;
+    sv->queue.push_back(std::move(p));
+    sv->cv_work.notify_one();
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_poll(tmd_server* sv, uint64_t ticket, tmd_result* result) {
+    if (!sv || !result) return TMD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) {
+        if (ticket == 0 || ticket >= sv->next_ticket) {
+            sv->last_error = "unknown ticket";
+            return TMD_ERR_INVALID_ARGUMENT;
+        }
+        return TMD_ERR_NOT_READY;
+    }
+    *result = it->second.res;
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_wait(tmd_server* sv, uint64_t ticket, double timeout_s, tmd_result* result) {
+    if (!sv || !result) return TMD_ERR_INVALID_ARGUMENT;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (ticket == 0 || ticket >= sv->next_ticket) {
+        sv->last_error = "unknown ticket";
+        return TMD_ERR_INVALID_ARGUMENT;
+    }
+    auto ready = [&] { return sv->done.count(ticket) > 0; };
+    if (timeout_s < 0) sv->cv_done.wait(lk, ready);
+    else if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) return TMD_ERR_NOT_READY;
+    *result = sv->done[ticket].res;
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_fetch(tmd_server* sv, uint64_t ticket, float* forces, double* pos, double* vel, double* epot,
+                           double* ekin) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) {
+        sv->last_error = "request not finished or unknown";
+        return TMD_ERR_NOT_READY;
+    }
+    const Finished& f = it->second;
+    if (f.res.status != TMD_OK) {
+        sv->last_error = "request failed";
+        return (tmd_status)f.res.status;
+    }
+    if (forces) std::memcpy(forces, f.F.data(), f.F.size() * sizeof(float));
+    if (pos && !f.x.empty()) std::memcpy(pos, f.x.data(), f.x.size() * sizeof(double));
+    if (vel && !f.v.empty()) std::memcpy(vel, f.v.data(), f.v.size() * sizeof(double));
+    if (epot) std::memcpy(epot, f.epot.data(), f.epot.size() * sizeof(double));
+    if (ekin && !f.ekin.empty()) std::memcpy(ekin, f.ekin.data(), f.ekin.size() * sizeof(double));
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_release(tmd_server* sv, uint64_t ticket) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->done.erase(ticket)) {
+        sv->last_error = "request not finished or unknown";
+        return TMD_ERR_INVALID_ARGUMENT;
+    }
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_read_system(tmd_server* sv, int64_t system_id, double* pos, double* vel) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    System* sys = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        auto it = sv->systems.find(system_id);
+        if (it == sv->systems.end()) {
+            sv->last_error = "unknown system id";
+            return TMD_ERR_INVALID_ARGUMENT;
+        }
+        sys = it->second.get();
+        // wait until no request on it is queued or running
+        sv->cv_done.wait(lk, [&] {
+            if (sys->busy) return false;
+            for (const auto& q : sv->queue)
+                if (q.req.system_id == system_id) return false;
+            return true;
+        });
+        sys->busy = true;
+    }
+    hipError_t e = hipSetDevice(sv->opts.device);
+    if (e == hipSuccess && pos) e = hipMemcpy(pos, sys->x, 24 * (size_t)sys->n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && vel) e = hipMemcpy(vel, sys->v, 24 * (size_t)sys->n, hipMemcpyDeviceToHost);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sys->busy = false;
+    }
+    sv->cv_work.notify_all();
+    return e == hipSuccess ? TMD_OK : TMD_ERR_DEVICE;
+}
+
+tmd_status tmd_serve_memory(tmd_server* sv, int64_t* in_use, int64_t* peak) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (in_use) *in_use = sv->mem_in_use;
+    if (peak) *peak = sv->mem_peak;
+    return TMD_OK;
+}
+
+const char* tmd_serve_last_error(tmd_server* sv) {
+    if (!sv) return "null server";
+    std::lock_guard<std::mutex> lk(sv->mu);
+    return sv->last_error.c_str();
+}
+
+void tmd_serve_destroy(tmd_server* sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->queue.clear();
+    }
+    sv->cv_work.notify_all();
+    for (auto& t : sv->workers) t.join();
+    (void)hipSetDevice(sv->opts.device);
+    (void)hipDeviceSynchronize();
+    release_slots(sv);
+    for (auto& kv : sv->systems) {
+        System* s = kv.second.get();
+        if (s->nl) tmd_nlist_destroy(s->nl);
+        for (void* p : {(void*)s->x, (void*)s->v, (void*)s->xref, (void*)s->F, (void*)s->sp, (void*)s->acc,
+                        (void*)s->mass})
+            if (p) (void)hipFree(p);
+    }
+    delete sv;
+}
+
+}  // extern "C"

@@ -189,6 +189,13 @@ tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* to
 // layer) of every species from the master parameters m->params32.
 tmd_status launch_unpack_params(tmd_context* ctx, tmd_model* m);
 
+// Pre-size a context's evaluation workspace for n atoms (avoids growth, and
+// the device-wide synchronisation it implies, later), and its size in bytes.
+tmd_status reserve_eval_workspace(tmd_context* ctx, const tmd_model* m, int64_t n);
+size_t eval_workspace_bytes(const tmd_model* m, int64_t n);
+tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S);
+size_t nlist_workspace_bytes(int64_t n);
+
 // Upper bound on the virial partials the adjoint writes.
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl);
 

@@ -36,7 +36,13 @@ EXPORTS = (
     "tmd_descriptors", "tmd_energy_forces", "tmd_energy_forces_async",
     "tmd_profile_enable", "tmd_profile_reset", "tmd_profile_read",
     "tmd_model_get_params", "tmd_batch_create", "tmd_batch_destroy", "tmd_train_step", "tmd_batch_read",
+    "tmd_serve_create", "tmd_serve_add_system", "tmd_serve_submit", "tmd_serve_poll", "tmd_serve_wait",
+    "tmd_serve_fetch", "tmd_serve_release", "tmd_serve_read_system", "tmd_serve_memory", "tmd_serve_last_error",
+    "tmd_serve_destroy",
 )
+TMD_ERR_NOT_READY = 6
+REQ_ENERGY_FORCES = 0
+REQ_MD = 1
 
 OPT_ADAM = 0
 OPT_SGD = 1
@@ -66,6 +72,30 @@ class TrainOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("max_atoms", ctypes.c_int64), ("skin", ctypes.c_double), ("capacity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("system_id", ctypes.c_int64), ("kind", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("dt_fs", ctypes.c_double), ("velocities", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("system_id", ctypes.c_int64),
+                ("n_atoms", ctypes.c_int64), ("n_steps", ctypes.c_int32), ("rebuilds", ctypes.c_int32),
+                ("energy", ctypes.c_double), ("kinetic", ctypes.c_double), ("virial", ctypes.c_double * 6),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"status": self.status, "kind": self.kind, "system_id": self.system_id, "n_atoms": self.n_atoms,
+                "n_steps": self.n_steps, "rebuilds": self.rebuilds, "energy": self.energy, "kinetic": self.kinetic,
+                "virial": list(self.virial), "t_submit": self.t_submit, "t_start": self.t_start,
+                "t_done": self.t_done}
 
 
 _lib = None
@@ -117,6 +147,19 @@ def load_library(path: str = LIB_PATH):
     L.tmd_batch_destroy.restype = None
     L.tmd_train_step.argtypes = [vp, vp, vp, P(TrainOpts), vp, vp]
     L.tmd_batch_read.argtypes = [vp, vp, i32, vp]
+    L.tmd_serve_create.argtypes = [vp, P(ServeOpts), P(vp)]
+    L.tmd_serve_add_system.argtypes = [vp, i64, vp, vp, vp, vp, P(i64)]
+    L.tmd_serve_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
+    L.tmd_serve_poll.argtypes = [vp, ctypes.c_uint64, P(Result)]
+    L.tmd_serve_wait.argtypes = [vp, ctypes.c_uint64, dbl, P(Result)]
+    L.tmd_serve_fetch.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, vp, vp]
+    L.tmd_serve_release.argtypes = [vp, ctypes.c_uint64]
+    L.tmd_serve_read_system.argtypes = [vp, i64, vp, vp]
+    L.tmd_serve_memory.argtypes = [vp, P(i64), P(i64)]
+    L.tmd_serve_last_error.argtypes = [vp]
+    L.tmd_serve_last_error.restype = ctypes.c_char_p
+    L.tmd_serve_destroy.argtypes = [vp]
+    L.tmd_serve_destroy.restype = None
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -493,3 +536,118 @@ def energy(pos, species, box, evaluator: "Evaluator", rebuild: bool = True):
     if _TMDEnergy is None:
         _TMDEnergy = _energy_function()
     return _TMDEnergy.apply(pos, species, box, evaluator, rebuild)
+
+
+# ---------------------------------------------------------------- serving
+
+
+class Server:
+    """Persistent request loop (tmd_serve_*): resident systems, worker slots with
+    their own streams, admission by memory budget."""
+
+    def __init__(self, model: Model, max_slots: int = 8, hbm_budget_bytes: int = 0, max_atoms: int = 0,
+                 skin: float = 1.0, device: int = 0):
+        self.lib = model.ctx.lib
+        self.model = model  # must outlive the server
+        o = ServeOpts()
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.max_slots = int(max_slots)
+        o.device = int(device)
+        o.max_atoms = int(max_atoms)
+        o.skin = float(skin)
+        h = ctypes.c_void_p()
+        st = self.lib.tmd_serve_create(model.h, ctypes.byref(o), ctypes.byref(h))
+        if st != TMD_OK:
+            raise TMDError(st, "tmd_serve_create failed")
+        self.h = h
+        self.n_atoms = {}
+
+    def _check(self, st: int, what: str):
+        if st != TMD_OK:
+            raise TMDError(st, f"{what}: {self.lib.tmd_serve_last_error(self.h).decode()}")
+
+    def add_system(self, pos, species, box, masses) -> int:
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        species = np.ascontiguousarray(species, dtype=np.int32)
+        box = np.ascontiguousarray(box, dtype=np.float64)
+        masses = np.ascontiguousarray(masses, dtype=np.float64)
+        sid = ctypes.c_int64(0)
+        self._check(self.lib.tmd_serve_add_system(self.h, pos.shape[0], pos.ctypes.data, species.ctypes.data,
+                                                  box.ctypes.data, masses.ctypes.data, ctypes.byref(sid)),
+                    "tmd_serve_add_system")
+        self.n_atoms[int(sid.value)] = int(pos.shape[0])
+        return int(sid.value)
+
+    def submit(self, system_id: int, kind: int = REQ_ENERGY_FORCES, n_steps: int = 0, dt_fs: float = 1.0,
+               velocities: Optional[np.ndarray] = None) -> int:
+        r = Request()
+        r.system_id = int(system_id)
+        r.kind = int(kind)
+        r.n_steps = int(n_steps)
+        r.dt_fs = float(dt_fs)
+        vel = None
+        if velocities is not None:
+            vel = np.ascontiguousarray(velocities, dtype=np.float64)
+            if vel.shape != (self.n_atoms[int(system_id)], 3):
+                raise ValueError("velocities must be [n_atoms, 3]")
+            r.velocities = vel.ctypes.data
+        t = ctypes.c_uint64(0)
+        self._check(self.lib.tmd_serve_submit(self.h, ctypes.byref(r), ctypes.byref(t)), "tmd_serve_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int) -> Optional[dict]:
+        res = Result()
+        st = self.lib.tmd_serve_poll(self.h, ticket, ctypes.byref(res))
+        if st == TMD_ERR_NOT_READY:
+            return None
+        self._check(st, "tmd_serve_poll")
+        return res.as_dict()
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> Optional[dict]:
+        res = Result()
+        st = self.lib.tmd_serve_wait(self.h, ticket, float(timeout_s), ctypes.byref(res))
+        if st == TMD_ERR_NOT_READY:
+            return None
+        self._check(st, "tmd_serve_wait")
+        return res.as_dict()
+
+    def fetch(self, ticket: int, result: dict) -> dict:
+        """Host arrays of a finished request: forces, and for MD pos, vel, epot, ekin."""
+        n = result["n_atoms"]
+        out = {"forces": np.empty((n, 3), dtype=np.float32), "epot": np.empty(result["n_steps"] + 1)}
+        ptrs = [out["forces"].ctypes.data, None, None, out["epot"].ctypes.data, None]
+        if result["kind"] == REQ_MD:
+            out["pos"] = np.empty((n, 3))
+            out["vel"] = np.empty((n, 3))
+            out["ekin"] = np.empty(result["n_steps"] + 1)
+            ptrs[1], ptrs[2], ptrs[4] = out["pos"].ctypes.data, out["vel"].ctypes.data, out["ekin"].ctypes.data
+        self._check(self.lib.tmd_serve_fetch(self.h, ticket, *ptrs), "tmd_serve_fetch")
+        return out
+
+    def release(self, ticket: int):
+        self._check(self.lib.tmd_serve_release(self.h, ticket), "tmd_serve_release")
+
+    def read_system(self, system_id: int):
+        n = self.n_atoms[int(system_id)]
+        pos = np.empty((n, 3))
+        vel = np.empty((n, 3))
+        self._check(self.lib.tmd_serve_read_system(self.h, int(system_id), pos.ctypes.data, vel.ctypes.data),
+                    "tmd_serve_read_system")
+        return pos, vel
+
+    def memory(self) -> Tuple[int, int]:
+        a = ctypes.c_int64(0)
+        b = ctypes.c_int64(0)
+        self._check(self.lib.tmd_serve_memory(self.h, ctypes.byref(a), ctypes.byref(b)), "tmd_serve_memory")
+        return int(a.value), int(b.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tmd_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -64,6 +64,18 @@ def test_null_argument_validation_without_device():
     assert L.tmd_last_error(None) == b"null context"
     v = tmd.SystemView()
     assert L.tmd_build_neighbors(None, ctypes.byref(v), 5.0, 0.0, None, None) == 1
+    assert L.tmd_train_step(None, None, None, None, None, None) == 1
+    assert L.tmd_batch_create(None, None, 1, None, None, None, None, None, None, 0, None) == 1
+    assert L.tmd_batch_read(None, None, 0, None) == 1
+    assert L.tmd_model_get_params(None, None) == 1
+    assert L.tmd_serve_create(None, None, None) == 1
+    assert L.tmd_serve_submit(None, None, None) == 1
+    assert L.tmd_serve_poll(None, 1, None) == 1
+    assert L.tmd_serve_wait(None, 1, 0.0, None) == 1
+    assert L.tmd_serve_fetch(None, 1, None, None, None, None, None) == 1
+    assert L.tmd_serve_release(None, 1) == 1
+    assert L.tmd_serve_memory(None, None, None) == 1
+    assert L.tmd_serve_last_error(None) == b"null server"
 
 
 def test_param_layout_matches_library_contract():
