@@ -99,6 +99,115 @@ def cpu_baseline(seconds: float) -> dict:
                       f"1M-atom workload's model, {reps} repetitions in {el:.1f} s"}
 
 
+def train_leg(tmd, torch, ctx, steps: int, warmup: int) -> dict:
+    """Force-matching training on the 64-cell fcc/bcc/hcp batch (about 18k atoms,
+    descriptor K 8 M 3 rc 5, MLP 32-64-64-1).  Labels come from the GPU FP32
+    path with the teacher network (the oracle is not used outside the CPU
+    baseline); each timed step is tmd_train_step with an Adam update."""
+    import numpy as np
+    from paper_2310_08439_amd import inputs
+    b = inputs.train_batch()
+    _, teacher, _ = inputs.workload("train_teacher")
+    _, student, _ = inputs.workload("train_student")
+    mt = tmd.Model(ctx, teacher)
+    E_l = np.empty(b.n_systems)
+    F_l = torch.empty((b.n, 3), dtype=torch.float32, device="cuda")
+    pos = torch.tensor(b.pos, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(b.species, dtype=torch.int32, device="cuda")
+    for s in range(b.n_systems):
+        a0, a1 = int(b.sys_off[s]), int(b.sys_off[s + 1])
+        nl = tmd.NeighborList(ctx, a1 - a0, 1, 96)
+        x, spp = pos[a0:a1].contiguous(), sp[a0:a1].contiguous()
+        tmd.build_neighbors(ctx, x, spp, b.boxes[s], teacher.rcut, 0.0, nl)
+        E_l[s], _, f, _ = tmd.energy_forces(ctx, mt, x, spp, b.boxes[s], nl, atom_energy=False)
+        F_l[a0:a1] = f
+        nl.close()
+    ms = tmd.Model(ctx, student)
+    t0 = time.perf_counter()
+    bt = tmd.Batch(ctx, ms, b.sys_off, pos, sp, b.boxes, E_l, F_l)
+    t_create = time.perf_counter() - t0
+    for _ in range(warmup):
+        tmd.train_step(ctx, ms, bt, lr=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = tmd.train_step(ctx, ms, bt, lr=1e-3)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    bt.close()
+    return {"workload": f"{b.n_systems} periodic fcc/bcc/hcp cells, {b.n} atoms, MLP 32-64-64-1, lambda 0.1, Adam lr 1e-3",
+            "ms_per_train_step": round(sec * 1e3, 4), "atoms_per_s": round(b.n / sec, 1),
+            "batch_setup_ms": round(t_create * 1e3, 2), "loss_after_warmup_and_steps": last[0]}
+
+
+def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: float, slots: int) -> dict:
+    """Open-loop Poisson stream against the serving loop: systems are fcc
+    (species 0, a = 3.61) or 50/50 bcc alloy (a = 3.16) cells with atom counts
+    log-uniform in 64..262,144 (nearest cubic supercell), a pool of `pool`
+    resident systems; requests are 50/50 energy+forces or 10 velocity-Verlet
+    steps of 1 fs from Maxwell-Boltzmann velocities at 300 K; BF16 MLP."""
+    import numpy as np
+    from paper_2310_08439_amd import inputs
+    rng = np.random.default_rng(4)
+    model = tmd.Model(ctx, spec, precision=tmd.BF16_MLP)
+    srv = tmd.Server(model, max_slots=slots, max_atoms=262144, skin=1.0)
+    systems = []
+    for q in range(pool):
+        target = math.exp(rng.uniform(math.log(64), math.log(262144)))
+        if rng.random() < 0.5:
+            c = min(40, max(2, int(round((target / 4) ** (1 / 3)))))
+            s = inputs.make_system("fcc", 3.61, (c, c, c), 0.05, 1, seed=1000 + q, masses=[63.546])
+            masses = np.array([63.546, 95.95])
+        else:
+            c = min(50, max(2, int(round((target / 2) ** (1 / 3)))))
+            s = inputs.make_system("bcc", 3.16, (c, c, c), 0.08, 2, seed=1000 + q, masses=[183.84, 95.95])
+            masses = np.array([183.84, 95.95])
+        sid = srv.add_system(s.pos, s.species, s.box, masses)
+        systems.append((sid, s.n, np.where(s.species == 0, masses[0], masses[1])))
+    total = n_warmup + n_requests
+    plan = []
+    t = 0.0
+    for k in range(total):
+        t += rng.exponential(1.0 / rate)
+        sid, n, m = systems[int(rng.integers(pool))]
+        md = rng.random() < 0.5
+        vel = inputs.maxwell_boltzmann(m, 300.0, seed=int(rng.integers(1 << 31))) if md else None
+        plan.append((t, sid, n, md, vel))
+    tickets = []
+    start = time.perf_counter()
+    for (ta, sid, n, md, vel) in plan:
+        delay = start + ta - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        if md:
+            tickets.append(srv.submit(sid, tmd.REQ_MD, 10, 1.0, vel))
+        else:
+            tickets.append(srv.submit(sid))
+    results = []
+    for tk in tickets:
+        r = srv.wait(tk, 300.0)
+        if r is None or r["status"] != 0:
+            raise RuntimeError(f"serving request failed: {r}")
+        results.append(r)
+        srv.release(tk)
+    mem, peak = srv.memory()
+    srv.close()
+    meas = results[n_warmup:]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in meas]) * 1e3
+    wall = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
+    atom_steps = sum(r["n_atoms"] * max(1, r["n_steps"]) for r in meas)
+    sizes = np.array([n for (_, n, _) in systems])
+    return {"workload": f"Poisson {rate:g} req/s, {n_requests} requests after {n_warmup} warm-up, pool of {pool} "
+                        f"resident fcc/bcc systems of {sizes.min()}..{sizes.max()} atoms (mean {sizes.mean():.0f}), "
+                        f"50% E+F / 50% 10 VV steps, {slots} slots, BF16 MLP",
+            "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_latency_ms": round(float(lat.mean()), 3),
+            "atom_steps_per_s": round(atom_steps / wall, 1),
+            "device_bytes_peak": int(peak)}
+
+
 def accuracy(tmd, ev, pos, sp, s, spec, n_sample: int, precision: int) -> dict:
     """Sampled per-atom energy and force errors against the FP64 oracle."""
     import numpy as np
@@ -143,6 +252,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-samples", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--no-extra", action="store_true", help="skip the training and serving legs")
     ap.add_argument("--mode", default="step", choices=["step", "copy"],
                     help="copy: 3 device copies of 1 GiB, to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -199,6 +315,14 @@ def main():
         for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
             acc[name] = accuracy(tmd, ev, pos, sp, s, spec, args.accuracy_samples, prec)
 
+    training = serving = None
+    if not args.no_extra:
+        training = train_leg(tmd, torch, ev.ctx, args.train_steps, 2)
+        print(f"[bench] training {training}", file=sys.stderr, flush=True)
+        serving = serve_leg(tmd, ev.ctx, spec, args.serve_requests, args.serve_warmup, args.serve_pool,
+                            args.serve_rate, args.serve_slots)
+        print(f"[bench] serving {serving}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -232,6 +356,8 @@ def main():
         "accuracy_vs_oracle": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
+        "training": training,
     }
     print(json.dumps(line), flush=True)
 
