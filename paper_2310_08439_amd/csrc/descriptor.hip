@@ -157,10 +157,24 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& x
     }
 }
 
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup b runs on
+// XCD b mod 8, each XCD with its own L2).  The logical block of a workgroup is
+// chosen so that each XCD walks one contiguous eighth of the blocks: sorted
+// atoms are cell-major, so an XCD's neighbour gathers stay in a compact slab
+// that its L2 holds.  The grid is rounded up to a multiple of 8; the padding
+// workgroups get -1.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+    const int64_t b = blockIdx.x, per = (nblocks + 7) / 8;
+    const int64_t l = (b % 8) * per + b / 8;
+    return l < nblocks ? l : -1;
+}
+
 template <int KC, int M>
-__global__ void __launch_bounds__(256) k_descriptor(PathArgs a) {
+__global__ void __launch_bounds__(256) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t lb = xcd_block(nblocks);
+    if (lb < 0) return;
+    const int64_t t = lb * blockDim.x + threadIdx.x;
     const int64_t p = t >> a.nch_log2;
     const int ch = (int)(t & ((1 << a.nch_log2) - 1));
     if (p >= a.n) return;
@@ -453,7 +467,7 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
     block_virial(W6, red, a.vir + (int64_t)blockIdx.x * 6);
 }
 
-using PathFn = void (*)(PathArgs);
+using PathFn = void (*)(PathArgs, int64_t);
 using AtomicFn = void (*)(PathArgs, float*);
 using BlockedFn = void (*)(PathArgs, BlockGeom);
 
@@ -540,7 +554,9 @@ constexpr size_t kMaxDynLds = 56 * 1024;
 
 // Largest block shape whose halo accumulators fit in LDS for the densest cell.
 bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
-    static const int shapes[][3] = {{4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+    // 4x2x2 cells per workgroup: enough workgroups (about 5,000 at 1 M atoms)
+    // for several rounds of them per CU; measured fastest of 4x4x4 .. 2x2x2.
+    static const int shapes[][3] = {{4, 2, 2}, {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
     for (const auto& sh : shapes) {
         int B[3], H = 1;
         for (int d = 0; d < 3; ++d) {
@@ -571,9 +587,10 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     a.G = G;
     a.Pbuf = Pbuf;
     auto fn = select_desc(m->kc, m->M);
+    const int64_t nblocks = path_grid(m, nl);
     {
         ProfScope ps_(ctx, "descriptor");
-        fn<<<path_grid(m, nl), kBlock, 0, ctx->stream>>>(a);
+        fn<<<(unsigned)((nblocks + 7) / 8 * 8), kBlock, 0, ctx->stream>>>(a, nblocks);
     }
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;

@@ -71,14 +71,19 @@ constexpr int lds_elems() {
     return 128 * (WT<BF16>::kChunk + WT<BF16>::kPad);
 }
 
-__device__ __forceinline__ float act_f(int act, float z) {
-    if (act == TMD_ACT_SQUAREPLUS) return 0.5f * (z + __builtin_sqrtf(z * z + 4.0f));
-    // tanh(z) = 1 - 2/(exp(2z)+1); saturates cleanly to +-1
+template <int ACT>
+__device__ __forceinline__ float act_f(float z) {
+    constexpr int act = ACT;
+    if constexpr (act == TMD_ACT_SQUAREPLUS) return 0.5f * (z + __builtin_amdgcn_sqrtf(z * z + 4.0f));
+    // tanh(z) = 1 - 2/(exp(2z)+1) with the hardware reciprocal (1 ulp); saturates
+    // cleanly to +-1 (exp2 overflows to inf, whose reciprocal is 0)
     const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * z);
-    return 1.0f - 2.0f / (e + 1.0f);
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
-__device__ __forceinline__ float act_df(int act, float z, float a) {
-    if (act == TMD_ACT_SQUAREPLUS) return 0.5f * (1.0f + z * __builtin_amdgcn_rsqf(z * z + 4.0f));
+template <int ACT>
+__device__ __forceinline__ float act_df(float z, float a) {
+    constexpr int act = ACT;
+    if constexpr (act == TMD_ACT_SQUAREPLUS) return 0.5f * (1.0f + z * __builtin_amdgcn_rsqf(z * z + 4.0f));
     return 1.0f - a * a;
 }
 
@@ -186,7 +191,7 @@ __device__ __forceinline__ void dense_hidden(const typename WT<BF16>::T* W, type
     }
 }
 
-template <bool BF16, int H, int L, int CB>
+template <bool BF16, int H, int L, int CB, int ACT>
 __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
     constexpr int NB = H / 16;
     constexpr int kTile = kWaves * 16 * CB;
@@ -235,8 +240,8 @@ __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float z = acc[ob][cb][r];
-                    const float y = act_f(a.act, z);
-                    dact[l][ob][cb][r] = act_df(a.act, z, y);
+                    const float y = act_f<ACT>(z);
+                    dact[l][ob][cb][r] = act_df<ACT>(z, y);
                     acc[ob][cb][r] = y;
                 }
     };
@@ -398,25 +403,31 @@ using MlpFn = void (*)(MlpArgs);
 
 // Column blocks per wave: two (32 atoms) unless the H = 128 network is deep
 // enough that two blocks' activation derivatives would not fit in registers.
-template <bool BF16, int H>
+template <bool BF16, int H, int ACT>
 MlpFn pick_L(int L, int* cb) {
     constexpr int C = (H == 128) ? 1 : 2;
     *cb = (L <= 2) ? 2 : C;
     switch (L) {
-        case 1: return k_mlp<BF16, H, 1, 2>;
-        case 2: return k_mlp<BF16, H, 2, 2>;
-        case 3: return k_mlp<BF16, H, 3, C>;
-        default: return k_mlp<BF16, H, 4, C>;
+        case 1: return k_mlp<BF16, H, 1, 2, ACT>;
+        case 2: return k_mlp<BF16, H, 2, 2, ACT>;
+        case 3: return k_mlp<BF16, H, 3, C, ACT>;
+        default: return k_mlp<BF16, H, 4, C, ACT>;
+    }
+}
+
+template <bool BF16, int ACT>
+MlpFn pick_H(int H, int L, int* cb) {
+    switch (H) {
+        case 32: return pick_L<BF16, 32, ACT>(L, cb);
+        case 64: return pick_L<BF16, 64, ACT>(L, cb);
+        default: return pick_L<BF16, 128, ACT>(L, cb);
     }
 }
 
 template <bool BF16>
-MlpFn pick_H(int H, int L, int* cb) {
-    switch (H) {
-        case 32: return pick_L<BF16, 32>(L, cb);
-        case 64: return pick_L<BF16, 64>(L, cb);
-        default: return pick_L<BF16, 128>(L, cb);
-    }
+MlpFn pick_act(int act, int H, int L, int* cb) {
+    return act == TMD_ACT_SQUAREPLUS ? pick_H<BF16, TMD_ACT_SQUAREPLUS>(H, L, cb)
+                                     : pick_H<BF16, TMD_ACT_TANH>(H, L, cb);
 }
 
 }  // namespace
@@ -438,7 +449,8 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups&
     a.act = m->act;
     a.L = m->L;
     int cb = 2;
-    MlpFn fn = (prec == TMD_BF16_MLP) ? pick_H<true>(m->H, m->L, &cb) : pick_H<false>(m->H, m->L, &cb);
+    MlpFn fn = (prec == TMD_BF16_MLP) ? pick_act<true>(m->act, m->H, m->L, &cb)
+                                      : pick_act<false>(m->act, m->H, m->L, &cb);
     const int kTileAtoms = kWaves * 16 * cb;
     int64_t tiles = 0;
     for (int s = 0; s < m->S; ++s) {
