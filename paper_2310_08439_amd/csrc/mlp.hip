@@ -16,7 +16,7 @@
 //         group g the 8 operand slots hold units {4g..4g+3, 16+4g..16+4g+3}.
 //   FP32: v_mfma_f32_16x16x4_f32.  One K-step covers 4 units, lane group g
 //         holding unit 16*blk + 4g + r in step (blk, r).
-// A workgroup of 4 waves takes 64 or 128 atoms of one species; each
+// A workgroup of 4 or 8 waves takes 128 atoms of one species; each
 // layer's weights (forward or transposed) are staged once per workgroup into
 // LDS in column chunks with padded rows, and all four waves read their MFMA
 // A operands from there.
@@ -29,7 +29,6 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-constexpr int kWaves = 4;
 
 struct MlpArgs {
     int S, F, Fpad, act;
@@ -191,10 +190,10 @@ __device__ __forceinline__ void dense_hidden(const typename WT<BF16>::T* W, type
     }
 }
 
-template <bool BF16, int H, int L, int CB, int ACT>
-__global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
+template <bool BF16, int H, int L, int CB, int ACT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs a) {
     constexpr int NB = H / 16;
-    constexpr int kTile = kWaves * 16 * CB;
+    constexpr int kTile = NW * 16 * CB;
     using T = typename WT<BF16>::T;
     constexpr int PAD = WT<BF16>::kPad, CHUNK = WT<BF16>::kChunk;
     __shared__ __attribute__((aligned(16))) T lds[lds_elems<BF16>()];
@@ -401,33 +400,40 @@ __global__ void __launch_bounds__(256) k_mlp(MlpArgs a) {
 
 using MlpFn = void (*)(MlpArgs);
 
-// Column blocks per wave: two (32 atoms) unless the H = 128 network is deep
-// enough that two blocks' activation derivatives would not fit in registers.
+// Shape of a workgroup: W waves of CB 16-atom column blocks each.  H <= 64:
+// 4 waves x 2 blocks.  H = 128: 1 block per wave, so that a wave's
+// activations and derivatives fit in far fewer registers (4 waves per SIMD
+// for two hidden layers), with 8 waves per workgroup so that each staged
+// weight panel is still shared by 128 atoms.
+struct MlpShape {
+    MlpFn fn;
+    int cb, waves;
+};
+
 template <bool BF16, int H, int ACT>
-MlpFn pick_L(int L, int* cb) {
+MlpShape pick_L(int L) {
     constexpr int C = (H == 128) ? 1 : 2;
-    *cb = (L <= 2) ? 2 : C;
+    constexpr int W = (H == 128) ? 8 : 4;  // deeper H = 128 nets: 4 waves, up to 512 registers
     switch (L) {
-        case 1: return k_mlp<BF16, H, 1, 2, ACT>;
-        case 2: return k_mlp<BF16, H, 2, 2, ACT>;
-        case 3: return k_mlp<BF16, H, 3, C, ACT>;
-        default: return k_mlp<BF16, H, 4, C, ACT>;
+        case 1: return {k_mlp<BF16, H, 1, C, ACT, W>, C, W};
+        case 2: return {k_mlp<BF16, H, 2, C, ACT, W>, C, W};
+        case 3: return {k_mlp<BF16, H, 3, C, ACT, 4>, C, 4};
+        default: return {k_mlp<BF16, H, 4, C, ACT, 4>, C, 4};
     }
 }
 
 template <bool BF16, int ACT>
-MlpFn pick_H(int H, int L, int* cb) {
+MlpShape pick_H(int H, int L) {
     switch (H) {
-        case 32: return pick_L<BF16, 32, ACT>(L, cb);
-        case 64: return pick_L<BF16, 64, ACT>(L, cb);
-        default: return pick_L<BF16, 128, ACT>(L, cb);
+        case 32: return pick_L<BF16, 32, ACT>(L);
+        case 64: return pick_L<BF16, 64, ACT>(L);
+        default: return pick_L<BF16, 128, ACT>(L);
     }
 }
 
 template <bool BF16>
-MlpFn pick_act(int act, int H, int L, int* cb) {
-    return act == TMD_ACT_SQUAREPLUS ? pick_H<BF16, TMD_ACT_SQUAREPLUS>(H, L, cb)
-                                     : pick_H<BF16, TMD_ACT_TANH>(H, L, cb);
+MlpShape pick_act(int act, int H, int L) {
+    return act == TMD_ACT_SQUAREPLUS ? pick_H<BF16, TMD_ACT_SQUAREPLUS>(H, L) : pick_H<BF16, TMD_ACT_TANH>(H, L);
 }
 
 }  // namespace
@@ -448,10 +454,9 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups&
     a.Fpad = m->Fpad;
     a.act = m->act;
     a.L = m->L;
-    int cb = 2;
-    MlpFn fn = (prec == TMD_BF16_MLP) ? pick_act<true>(m->act, m->H, m->L, &cb)
-                                      : pick_act<false>(m->act, m->H, m->L, &cb);
-    const int kTileAtoms = kWaves * 16 * cb;
+    const MlpShape sh = (prec == TMD_BF16_MLP) ? pick_act<true>(m->act, m->H, m->L)
+                                               : pick_act<false>(m->act, m->H, m->L);
+    const int kTileAtoms = sh.waves * 16 * sh.cb;
     int64_t tiles = 0;
     for (int s = 0; s < m->S; ++s) {
         a.sp_off[s] = g.off[s];
@@ -477,7 +482,7 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups&
     if (tiles == 0) return TMD_OK;
     {
         ProfScope ps_(ctx, "mlp");
-        fn<<<(unsigned)tiles, kWaves * 64, 0, ctx->stream>>>(a);
+        sh.fn<<<(unsigned)tiles, sh.waves * 64, 0, ctx->stream>>>(a);
     }
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;
