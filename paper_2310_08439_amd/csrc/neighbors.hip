@@ -295,8 +295,15 @@ constexpr int kMaxCellAtoms = 64;
 // accepted candidates are compacted with a ballot and written to its row as
 // one contiguous run per species, so the list is identical to k_fill's while
 // every load and store of the wave is coalesced.
+// Value of v in lane i (i uniform), as two 32-bit lane reads.
+__device__ __forceinline__ double bcast_double(double v, int i) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, i);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), i);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) {
-    __shared__ int32_t cnt_lds[kBlock / 64][kMaxCellAtoms][kMaxSpecies];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t cell = (int64_t)blockIdx.x * (kBlock / 64) + wv;
     if (cell >= ncells) return;  // whole wave
@@ -328,7 +335,13 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
     }
     const int total = __shfl(pre, 63);
     pre -= count;  // exclusive
-    for (int i = lane; i < natoms * kMaxSpecies; i += 64) cnt_lds[wv][i / kMaxSpecies][i % kMaxSpecies] = 0;
+    // the cell's own atoms, one per lane (natoms <= 64), broadcast with readlane
+    double4 xown = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (lane < natoms) xown = a.xs[a0 + lane];
+    // running row lengths: lane i holds atom i's count per species
+    int rowlen[kMaxSpecies];
+#pragma unroll
+    for (int b = 0; b < kMaxSpecies; ++b) rowlen[b] = 0;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool coincident = false;
     for (int k0 = 0; k0 < total; k0 += 64) {
@@ -354,17 +367,21 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         const int32_t word = pack_img(nx, ny, nz, a.narrow ? sk : 255);
         for (int i = 0; i < natoms; ++i) {
             const int p = a0 + i;
-            const double4 xi = a.xs[p];
+            const double xix = bcast_double(xown.x, i), xiy = bcast_double(xown.y, i),
+                         xiz = bcast_double(xown.z, i);
+            const double4 xi = make_double4(xix, xiy, xiz, 0.0);
             const double dx = __dadd_rn(__dsub_rn(xj.x, xi.x), sx);
             const double dy = __dadd_rn(__dsub_rn(xj.y, xi.y), sy);
             const double dz = __dadd_rn(__dsub_rn(xj.z, xi.z), sz);
             const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
             const bool acc = valid && !(zero_img && q == p) && d2 < a.rl2 && bq >= 0 && bq < a.S;
             if (acc && d2 == 0.0) coincident = true;
-            for (int b = 0; b < a.S; ++b) {
+#pragma unroll
+            for (int b = 0; b < kMaxSpecies; ++b) {
+                if (b >= a.S) break;
                 const unsigned long long m = __ballot(acc && bq == b);
                 if (!m) continue;
-                const int base = cnt_lds[wv][i][b];
+                const int base = __builtin_amdgcn_readlane(rowlen[b], i);
                 if (acc && bq == b) {
                     const int c = base + (int)__popcll(m & below);
                     if (c < a.cap) {
@@ -373,15 +390,17 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
                         a.img[off] = word;
                     }
                 }
-                if (lane == 0) cnt_lds[wv][i][b] = base + (int)__popcll(m);
+                if (lane == i) rowlen[b] = base + (int)__popcll(m);
             }
         }
     }
     int mx = 0;
     if (lane < natoms) {
         const int p = a0 + lane;
-        for (int b = 0; b < a.S; ++b) {
-            const int c = cnt_lds[wv][lane][b];
+#pragma unroll
+        for (int b = 0; b < kMaxSpecies; ++b) {
+            if (b >= a.S) break;
+            const int c = rowlen[b];
             a.cnt[(int64_t)b * a.n + p] = min(c, a.cap);
             mx = max(mx, c);
         }
