@@ -170,7 +170,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
 }
 
 template <int KC, int M>
-__global__ void __launch_bounds__(256) k_descriptor(PathArgs a, int64_t nblocks) {
+__global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D;
     const int64_t lb = xcd_block(nblocks);
     if (lb < 0) return;
