@@ -352,6 +352,25 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
         mu[k] = (float)spec->mu[k];
         eta[k] = (float)spec->eta[k];
     }
+    {
+        // recurrence for the Gaussians of a chunk on a uniform grid (see tmd_model)
+        const double d = spec->mu[1] - spec->mu[0], e0 = spec->eta[0];
+        bool ok = d > 0.0 && e0 > 0.0;
+        for (int k = 0; k < K && ok; ++k)
+            ok = std::fabs(spec->mu[k] - spec->mu[0] - k * d) <= 1e-9 * d &&
+                 std::fabs(spec->eta[k] - e0) <= 1e-12 * e0;
+        for (int k0 = 0; k0 < K && ok; k0 += kc) {
+            const double tmax = std::max(std::fabs(spec->rcut - spec->mu[k0]), std::fabs(spec->mu[k0]));
+            ok = e0 * tmax * tmax <= 80.0 && 2.0 * e0 * d * tmax <= 80.0;
+        }
+        if (ok) {
+            const double log2e = 1.4426950408889634;
+            m->rec = true;
+            m->rec_a = (float)(2.0 * e0 * d * log2e);
+            m->rec_b = (float)(-e0 * d * d * log2e);
+            m->rec_c = (float)std::exp(-2.0 * e0 * d * d);
+        }
+    }
     hipError_t e = hipSuccess;
     auto alloc = [&](void** p, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 256));

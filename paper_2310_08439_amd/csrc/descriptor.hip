@@ -34,6 +34,8 @@ struct PathArgs {
     int64_t n;
     int S, K, F, cap, nch_log2;
     float rc2, half_inv_rc, pi_over_rc;
+    int rec;
+    float rec_a, rec_b, rec_c;
     double L[3];
     const double4* xs;
     const int32_t* nbr;
@@ -122,6 +124,32 @@ __device__ __forceinline__ void load_tile(const float* src, int64_t n, float (&P
     for (int q = 0; q < KC * D; ++q) P[q / D][q % D] = src[(int64_t)q * n];
 }
 
+// Gaussians exp(-eta_k (R - mu_k)^2) of a chunk of KC radial functions
+// (mu, nef = -eta log2 e of the chunk).  On a uniform grid (a.rec) two
+// exponentials and a multiplicative recurrence replace the KC exponentials:
+// e_{k+1} = e_k r_k, r_k = exp2(rec_a (R - mu_k) + rec_b), r_{k+1} = r_k rec_c.
+template <int KC>
+__device__ __forceinline__ void gaussians(const PathArgs& a, float R, const float* mu, const float* nef,
+                                          float (&e)[KC]) {
+    if (a.rec) {
+        const float t0 = R - mu[0];
+        float ek = __builtin_amdgcn_exp2f(nef[0] * t0 * t0);
+        float rk = __builtin_amdgcn_exp2f(fmaf(a.rec_a, t0, a.rec_b));
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            e[kk] = ek;
+            ek *= rk;
+            rk *= a.rec_c;
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const float t = R - mu[kk];
+            e[kk] = __builtin_amdgcn_exp2f(nef[kk] * t * t);
+        }
+    }
+}
+
 // P tile of one species for this thread's radial chunk.
 template <int KC, int M>
 __device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& xi, int64_t p, int b,
@@ -144,12 +172,12 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& x
         const float R = pr.r2 * rinv;
         const float ux = pr.dx * rinv, uy = pr.dy * rinv, uz = pr.dz * rinv;
         const float fc = 0.5f * __builtin_amdgcn_cosf(R * a.half_inv_rc) + 0.5f;
-        float Mv[D];
+        float Mv[D], ev[KC];
         monomials<M>(ux, uy, uz, Mv);
+        gaussians<KC>(a, R, mu, nef, ev);
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
-            const float t = R - mu[kk];
-            const float h = __builtin_amdgcn_exp2f(nef[kk] * t * t) * fc;
+            const float h = ev[kk] * fc;
 #pragma unroll
             for (int d = 0; d < D; ++d) P[kk][d] = fmaf(h, Mv[d], P[kk][d]);
         }
@@ -263,11 +291,12 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int c
                 float V[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) V[d] = 0.0f;
-                float s1 = 0.0f;
+                float s1 = 0.0f, ev[KC];
+                gaussians<KC>(a, R, mu, nef, ev);
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
                     const float tt = R - mu[kk];
-                    const float e = __builtin_amdgcn_exp2f(nef[kk] * tt * tt);
+                    const float e = ev[kk];
                     const float h = e * fc;
                     const float dh = e * fmaf(m2eta[kk] * tt, fc, dfc);
                     float U = 0.0f;
@@ -535,6 +564,10 @@ PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
     a.rc2 = (float)(rc * rc);
     a.half_inv_rc = (float)(0.5 / rc);
     a.pi_over_rc = (float)(M_PI / rc);
+    a.rec = m->rec ? 1 : 0;
+    a.rec_a = m->rec_a;
+    a.rec_b = m->rec_b;
+    a.rec_c = m->rec_c;
     for (int q = 0; q < 3; ++q) a.L[q] = nl->box[q];
     a.xs = nl->xs;
     a.nbr = nl->nbr;

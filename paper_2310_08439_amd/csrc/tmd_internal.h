@@ -85,6 +85,12 @@ struct tmd_model {
     // device parameters
     float* mu = nullptr;   // [K]
     float* eta = nullptr;  // [K]
+    // Uniform radial grid (mu_k = mu_0 + k Delta, one eta): consecutive
+    // Gaussians differ by the factor r_k = exp2(rec_a t_k + rec_b), t_k = R - mu_k,
+    // with r_{k+1} = r_k * rec_c, so a chunk needs two exponentials.  Set only
+    // when no value of a chunk can underflow before the chunk's last one.
+    bool rec = false;
+    float rec_a = 0.0f, rec_b = 0.0f, rec_c = 0.0f;
     // Per species, per layer l = 0..L-1: forward W_l [H][in_pad] and transposed
     // W_l^T [in_pad][H] (in_pad = Fpad for l = 0, H otherwise), FP32 and BF16 copies.
     float* w32 = nullptr;

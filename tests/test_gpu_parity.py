@@ -247,6 +247,23 @@ def test_energy_forces_feature_count_not_multiple_of_4(tmd, ctx, torch, prec):
     _check_ef(E, Ea, F, W, s, spec, etol, ftol)
 
 
+@pytest.mark.parametrize("grid", ["jittered_mu", "varied_eta"])
+def test_energy_forces_non_uniform_radial_grid(tmd, ctx, torch, grid):
+    """Radial centres or widths off a uniform grid: the kernels evaluate every
+    Gaussian directly instead of by the uniform-grid recurrence."""
+    import dataclasses
+    s = inputs.make_system("bcc", 3.16, (4, 4, 4), 0.1, 2, seed=54)
+    spec = inputs.make_model(2, 12, 3, [64, 64], 6.0, seed=55)
+    rng = np.random.default_rng(56)
+    if grid == "jittered_mu":
+        spec = dataclasses.replace(spec, mu=spec.mu + rng.uniform(-0.05, 0.05, size=spec.mu.shape))
+    else:
+        spec = dataclasses.replace(spec, eta=spec.eta * rng.uniform(0.8, 1.2, size=spec.eta.shape))
+    _note(f"energy_forces non-uniform radial grid ({grid})")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
+    _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+
+
 def test_ragged_and_absent_species(tmd, ctx, torch):
     """61 atoms (ragged MLP tiles), species 1 of 2 absent, one isolated atom."""
     rng = np.random.default_rng(60)
