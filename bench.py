@@ -208,6 +208,31 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
             "device_bytes_peak": int(peak)}
 
 
+def paper_shapes_leg(tmd, torch, ctx, steps: int, warmup: int) -> dict:
+    """The paper's own potential shapes (bcc W, one species, K = 32 or 128,
+    SquarePlus 128-wide networks; 0 GPa and ~270 GPa lattice constants): E+F with
+    the on-device rebuild, ns/step/atom in BF16 and FP32 MLP precision."""
+    from paper_2310_08439_amd import inputs
+    out = {}
+    for name in ("w_k32", "w_k32_hp", "w_k128", "w_k128_hp"):
+        s, spec, skin = inputs.workload(name)
+        pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+        sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+        ev = tmd.Evaluator(spec, s.n, s.box, skin=skin, precision=tmd.BF16_MLP, ctx=ctx)
+        ev.build(pos, sp, s.box)
+        pairs, _ = tmd.nlist_stats(ctx, ev.nl)
+        row = {"atoms": s.n, "a_A": round(float(s.box[0] / 35 if s.n == 85750 else s.box[0] / 24), 4),
+               "K": spec.n_radial, "mlp": f"{spec.n_features}-{'-'.join(map(str, spec.hidden))}-1 squareplus",
+               "pairs_per_atom": round(pairs / s.n, 2)}
+        for pname, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
+            sec, _, _ = time_precision(tmd, torch, ev, pos, sp, s.box, prec, steps, warmup)
+            row[f"ns_per_step_atom_{pname}"] = round(sec / s.n * 1e9, 3)
+        out[name] = row
+        ev.model.close()
+        ev.nl.close()
+    return out
+
+
 def accuracy(tmd, ev, pos, sp, s, spec, n_sample: int, precision: int) -> dict:
     """Sampled per-atom energy and force errors against the FP64 oracle."""
     import numpy as np
@@ -315,8 +340,10 @@ def main():
         for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
             acc[name] = accuracy(tmd, ev, pos, sp, s, spec, args.accuracy_samples, prec)
 
-    training = serving = None
+    training = serving = shapes = None
     if not args.no_extra:
+        shapes = paper_shapes_leg(tmd, torch, ev.ctx, 10, 2)
+        print(f"[bench] paper shapes {shapes}", file=sys.stderr, flush=True)
         training = train_leg(tmd, torch, ev.ctx, args.train_steps, 2)
         print(f"[bench] training {training}", file=sys.stderr, flush=True)
         serving = serve_leg(tmd, ev.ctx, spec, args.serve_requests, args.serve_warmup, args.serve_pool,
@@ -358,6 +385,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "training": training,
+        "paper_shapes": shapes,
     }
     print(json.dumps(line), flush=True)
 

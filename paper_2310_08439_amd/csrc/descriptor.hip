@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
                 float s = 0.0f;
 #pragma unroll
                 for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
-                Gp[kk * (M + 1) + m] = (m == 0) ? __builtin_sqrtf(s) : s;
+                // m = 0 has the single component d = 0: sqrt(S) = |P_k0| exactly
+                Gp[kk * (M + 1) + m] = (m == 0) ? fabsf(P[kk][0]) : s;
             }
         }
     }
@@ -258,17 +259,15 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int c
 #pragma unroll
             for (int m = 0; m <= M; ++m) {
                 const float gbar = dGp[kk * (M + 1) + m];
-                float sbar;
                 if (m == 0) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
-                    sbar = s > 0.0f ? 0.5f * gbar * __builtin_amdgcn_rsqf(s) : 0.0f;
+                    // G = sqrt(P_k0^2) = |P_k0|, so P'_k0 = G' sign(P_k0) (0 where P_k0 = 0);
+                    // no reciprocal square root of a possibly denormal S
+                    const float pk = P[kk][0];
+                    P[kk][0] = pk > 0.0f ? gbar : (pk < 0.0f ? -gbar : 0.0f);
                 } else {
-                    sbar = gbar;
-                }
 #pragma unroll
-                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * sbar;
+                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * gbar;
+                }
             }
         }
         const int nb = a.cnt[(int64_t)b * a.n + p];

@@ -221,7 +221,8 @@ __global__ void __launch_bounds__(256) k_pt_forward(PtArgs a) {
                 float s = 0.0f;
 #pragma unroll
                 for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
-                a.G[i * a.F + (b * a.K + k) * (M + 1) + m] = (m == 0) ? __builtin_sqrtf(s) : s;
+                // m = 0 has the single component d = 0: sqrt(S) = |P_k0| exactly
+                a.G[i * a.F + (b * a.K + k) * (M + 1) + m] = (m == 0) ? fabsf(P[kk][0]) : s;
             }
         }
     }
@@ -261,17 +262,15 @@ __global__ void __launch_bounds__(256) k_pt_adjoint(PtArgs a) {
 #pragma unroll
             for (int m = 0; m <= M; ++m) {
                 const float gbar = dGp[kk * (M + 1) + m];
-                float sbar;
                 if (m == 0) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
-                    sbar = s > 0.0f ? 0.5f * gbar * __builtin_amdgcn_rsqf(s) : 0.0f;
+                    // G = sqrt(P_k0^2) = |P_k0|, so P'_k0 = G' sign(P_k0) (0 where P_k0 = 0);
+                    // no reciprocal square root of a possibly denormal S
+                    const float pk = P[kk][0];
+                    P[kk][0] = pk > 0.0f ? gbar : (pk < 0.0f ? -gbar : 0.0f);
                 } else {
-                    sbar = gbar;
-                }
 #pragma unroll
-                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * sbar;
+                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * gbar;
+                }
             }
         }
         const int64_t row = (i * a.S + b) * a.cap;
@@ -462,15 +461,12 @@ __global__ void __launch_bounds__(256) k_pt_tangent(PtArgs a) {
             const int k = ch * KC + kk;
 #pragma unroll
             for (int m = 0; m <= M; ++m) {
-                float s = 0.0f, st = 0.0f;
+                float st = 0.0f;
 #pragma unroll
-                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) {
-                    s += kMult[d] * P[kk][d] * P[kk][d];
-                    st += 2.0f * kMult[d] * P[kk][d] * Pt[kk][d];
-                }
-                float wv;
-                if (m == 0) wv = s > 0.0f ? 0.5f * st * __builtin_amdgcn_rsqf(s) : 0.0f;
-                else wv = st;
+                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) st += 2.0f * kMult[d] * P[kk][d] * Pt[kk][d];
+                // m = 0: G = |P_k0|, so its tangent is sign(P_k0) times that of P_k0
+                float wv = st;
+                if (m == 0) wv = P[kk][0] > 0.0f ? Pt[kk][0] : (P[kk][0] < 0.0f ? -Pt[kk][0] : 0.0f);
                 a.w[i * a.F + (b * a.K + k) * (M + 1) + m] = wv;
             }
         }

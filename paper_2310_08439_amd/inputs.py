@@ -183,6 +183,8 @@ def workload(name: str):
     fcc32k     : 32,000-atom fcc (20^3, a=3.61), sigma 0.05, rc 6.0, K 8, M 3, MLP 64-64.
     bcc1m      : 1,024,000-atom bcc alloy (80^3, a=3.16, 50/50), sigma 0.08, rc 6.0, K 12, M 3, 128-128.
     bcc4k      : 4,096-atom sub-cell of the bcc alloy workload (16^3), own seed.
+    w_k32[_hp] : bcc W 35^3 (N 85,750), a 3.1887 (2.8 for _hp), rc 6, K 32, M 3, SquarePlus 128-128-128.
+    w_k128[_hp]: bcc W 24x24x20 (N 23,040), a 3.1887 (2.8), rc 6, K 128, M 3, SquarePlus 128x4.
     """
     if name == "oracle32":
         sysm = make_system("fcc", 3.61, (2, 2, 2), 0.1, 1, seed=0, masses=[63.546])
@@ -199,6 +201,19 @@ def workload(name: str):
     if name == "bcc4k":
         sysm = make_system("bcc", 3.16, (16, 16, 16), 0.08, 2, seed=20, masses=[183.84, 95.95])
         model = make_model(2, 12, 3, [128, 128], 6.0, seed=102)
+        return sysm, model, 0.0
+    # Shapes of the paper's own tungsten potentials (Sec. IV: bcc W, one species,
+    # K = 32 or 128 radial functions, M = 3, SquarePlus networks), at 0 GPa
+    # (a = 3.1887 A) and ~270 GPa (a = 2.8 A); N = 2*35^3 and 2*24*24*20.
+    if name in ("w_k32", "w_k32_hp"):
+        a = 3.1887 if name == "w_k32" else 2.8
+        sysm = make_system("bcc", a, (35, 35, 35), 0.08, 1, seed=30, masses=[183.84])
+        model = make_model(1, 32, 3, [128, 128, 128], 6.0, seed=130, activation=ACT_SQUAREPLUS)
+        return sysm, model, 0.0
+    if name in ("w_k128", "w_k128_hp"):
+        a = 3.1887 if name == "w_k128" else 2.8
+        sysm = make_system("bcc", a, (24, 24, 20), 0.08, 1, seed=31, masses=[183.84])
+        model = make_model(1, 128, 3, [128, 128, 128, 128], 6.0, seed=131, activation=ACT_SQUAREPLUS)
         return sysm, model, 0.0
     if name == "train_teacher":
         model = make_model(1, 8, 3, [64, 64], 5.0, seed=1003)

@@ -178,6 +178,36 @@ def test_input_errors(tmd, ctx, torch, kind):
     assert ei.value.status == {"nan": 5, "coincident": 5, "species": 1}[kind]
 
 
+def test_empty_system_is_rejected(tmd, ctx, torch):
+    _note("empty system")
+    pos = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    sp = torch.zeros(0, dtype=torch.int32, device="cuda")
+    with pytest.raises(tmd.TMDError) as ei:
+        tmd.NeighborList(ctx, 0, 1, 16)
+    assert ei.value.status == 1
+    nl = tmd.NeighborList(ctx, 4, 1, 16)
+    with pytest.raises(tmd.TMDError) as ei:
+        tmd.build_neighbors(ctx, pos, sp, [10.0, 10.0, 10.0], 5.0, 0.0, nl)
+    assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("box", [30.0, 3.0])
+def test_single_atom(tmd, ctx, torch, box):
+    """One atom: in a large box it has no neighbours (G = 0, E = network at 0);
+    in a 3 A box only its own periodic images (zero force by symmetry)."""
+    _note(f"single atom box {box}")
+    spec = inputs.make_model(1, 8, 3, [32], 5.0, seed=57)
+    s = inputs.System(pos=np.array([[0.3, 1.1, 2.2]]), species=np.zeros(1, dtype=np.int32),
+                      box=np.array([box, box, box]), masses=np.array([63.546]))
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
+    Er, _, Fr, Wr = oracle.energy_forces(spec, s.pos, s.species, s.box)
+    assert abs(E - Er) <= 1e-5
+    assert np.abs(F).max() <= 1e-4 and np.abs(Fr).max() <= 1e-9
+    if box == 30.0:
+        E0, _ = oracle.mlp(spec, s.species, np.zeros((1, spec.n_features)))
+        assert abs(E - E0[0]) <= 1e-5
+
+
 # ------------------------------------------------------------------ descriptors
 
 @pytest.mark.parametrize("name", ["oracle32", "bcc4k"])
@@ -262,6 +292,27 @@ def test_energy_forces_non_uniform_radial_grid(tmd, ctx, torch, grid):
     _note(f"energy_forces non-uniform radial grid ({grid})")
     E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
     _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+
+
+@pytest.mark.parametrize("K,hidden", [(32, [128, 128, 128]), (128, [128, 128, 128, 128])])
+@pytest.mark.parametrize("a", [3.1887, 2.8])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paper_shaped_tungsten_models(tmd, ctx, torch, K, hidden, a, prec):
+    """The paper's potential shapes (one species, K = 32 or 128, M = 3, SquarePlus
+    128-wide networks) on a 4^3 bcc W cell at 0 GPa and ~270 GPa lattice constants."""
+    s = inputs.make_system("bcc", a, (4, 4, 4), 0.08, 1, seed=58, masses=[183.84])
+    spec = inputs.make_model(1, K, 3, hidden, 6.0, seed=59, activation=inputs.ACT_SQUAREPLUS)
+    _note(f"paper-shaped K={K} a={a} prec={prec}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, prec)
+    if prec == 0:
+        etol, ftol = E_TOL_FP32, F_TOL_FP32
+    else:
+        # The BF16 bars are stated for 96 input features.  Input rounding errors
+        # are independent, so they add like a random walk over the F inputs:
+        # the bars scale with sqrt(F / 96) (F = 128 and 512 here).
+        scale = math.sqrt(spec.n_features / 96.0)
+        etol, ftol = E_TOL_BF16 * scale, F_TOL_BF16 * scale
+    _check_ef(E, Ea, F, W, s, spec, etol, ftol)
 
 
 def test_ragged_and_absent_species(tmd, ctx, torch):
