@@ -67,6 +67,10 @@ def lib():
         L.orc_train_loss_grad.restype = i32
         L.orc_nve.argtypes = [vp, i64, vp, vp, vp, vp, vp, dbl, i32, vp, vp]
         L.orc_nve.restype = i32
+        L.orc_nvt.argtypes = [vp, i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, i32, vp, vp, vp, vp]
+        L.orc_nvt.restype = i32
+        L.orc_pressure.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        L.orc_pressure.restype = i32
         L.orc_params_per_species.argtypes = [vp]
         L.orc_params_per_species.restype = i32
         L.orc_num_threads.argtypes = []
@@ -277,3 +281,37 @@ def nve(spec, pos, vel, species, masses, box, dt: float, n_steps: int):
     if rc != 0:
         raise ValueError(f"oracle nve failed ({rc})")
     return pos, vel, epot, ekin
+
+
+def nvt(spec, pos, vel, species, masses, box, dt: float, T: float, tau_fs: float, n_steps: int, xi_eta=(0.0, 0.0)):
+    """Nose-Hoover NVT: (pos, vel, (xi, eta), epot, ekin, conserved), arrays [n_steps+1]."""
+    pos = np.array(pos, dtype=np.float64, copy=True)
+    vel = np.array(vel, dtype=np.float64, copy=True)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    masses = np.ascontiguousarray(masses, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    mref = _ModelRef(spec)
+    xe = np.array(xi_eta, dtype=np.float64)
+    epot = np.empty(n_steps + 1)
+    ekin = np.empty(n_steps + 1)
+    cons = np.empty(n_steps + 1)
+    rc = lib().orc_nvt(mref.ref, pos.shape[0], _p(pos), _p(vel), _p(species), _p(masses), _p(box), float(dt),
+                       float(T), float(tau_fs), int(n_steps), _p(xe), _p(epot), _p(ekin), _p(cons))
+    if rc != 0:
+        raise ValueError(f"oracle nvt failed ({rc})")
+    return pos, vel, (float(xe[0]), float(xe[1])), epot, ekin, cons
+
+
+def pressure(spec, pos, vel, species, masses, box):
+    """(p_xx, p_yy, p_zz, P) in GPa."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    masses = np.ascontiguousarray(masses, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    mref = _ModelRef(spec)
+    p4 = np.empty(4)
+    rc = lib().orc_pressure(mref.ref, pos.shape[0], _p(pos), _p(vel), _p(species), _p(masses), _p(box), _p(p4))
+    if rc != 0:
+        raise ValueError(f"oracle pressure failed ({rc})")
+    return p4

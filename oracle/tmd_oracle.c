@@ -856,3 +856,92 @@ int orc_nve(const orc_model* m, int64_t n, double* pos, double* vel, const int32
     free(F);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Nose-Hoover NVT (the MD protocol of Sec. IV.D runs NVT at 300 K; the */
+/* paper does not name its thermostat)                                  */
+/* ------------------------------------------------------------------ */
+#define ORC_KB 8.617333262e-5      /* eV/K */
+
+/* Kinetic energy and its diagonal tensor components (eV). */
+static void kinetic_tensor(int64_t n, const double* vel, const int32_t* sp, const double* mass, double* ke,
+                           double* kxyz) {
+    nsum k[3];
+    memset(k, 0, sizeof(k));
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) nsum_add(&k[a], 0.5 * ORC_KE_CONV * mass[sp[i]] * vel[3 * i + a] * vel[3 * i + a]);
+    for (int a = 0; a < 3; ++a) kxyz[a] = nsum_get(&k[a]);
+    *ke = kxyz[0] + kxyz[1] + kxyz[2];
+}
+
+/* One thermostat half step of the Nose-Hoover Trotter splitting (one
+ * thermostat variable xi with mass Q = g kB T tau^2, thermostat position eta):
+ *   xi += (dt/4) G;  v *= exp(-xi dt/2), eta += xi dt/2;  xi += (dt/4) G,
+ * G = (2 KE - g kB T) / Q with KE after the scaling for the second update.
+ * ke is updated. */
+static void nh_half(int64_t n, double* vel, double* ke, double g, double kT, double Q, double dt, double* xi,
+                    double* eta) {
+    *xi += 0.25 * dt * (2.0 * (*ke) - g * kT) / Q;
+    const double s = exp(-(*xi) * 0.5 * dt);
+    for (int64_t i = 0; i < 3 * n; ++i) vel[i] *= s;
+    *ke *= s * s;
+    *eta += 0.5 * dt * (*xi);
+    *xi += 0.25 * dt * (2.0 * (*ke) - g * kT) / Q;
+}
+
+/* n_steps of Nose-Hoover NVT: thermostat half step, velocity Verlet
+ * (v += dt/2 a, x += dt v, F(x), v += dt/2 a), thermostat half step.
+ * g = 3n degrees of freedom; tau_fs the thermostat period.  xi_eta [2] holds
+ * (xi, eta) in and out.  epot, ekin, conserved [n_steps + 1] (nullable):
+ * potential, kinetic and the conserved H = PE + KE + Q xi^2 / 2 + g kB T eta. */
+int orc_nvt(const orc_model* m, int64_t n, double* pos, double* vel, const int32_t* sp, const double* mass,
+            const double* box, double dt, double T, double tau_fs, int n_steps, double* xi_eta, double* epot,
+            double* ekin, double* conserved) {
+    if (check_model(m) || n_steps < 0 || !(T > 0.0) || !(tau_fs > 0.0)) return ORC_ERR_ARG;
+    const double g = 3.0 * (double)n, kT = ORC_KB * T, Q = g * kT * tau_fs * tau_fs;
+    double xi = xi_eta[0], eta = xi_eta[1];
+    double* F = (double*)malloc(sizeof(double) * 3 * n);
+    double E, ke, kx[3];
+    int st = orc_energy_forces(m, n, pos, sp, box, &E, NULL, F, NULL);
+    if (st) { free(F); return st; }
+    kinetic_tensor(n, vel, sp, mass, &ke, kx);
+    if (epot) epot[0] = E;
+    if (ekin) ekin[0] = ke;
+    if (conserved) conserved[0] = E + ke + 0.5 * Q * xi * xi + g * kT * eta;
+    for (int t = 0; t < n_steps; ++t) {
+        nh_half(n, vel, &ke, g, kT, Q, dt, &xi, &eta);
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                vel[3 * i + a] += 0.5 * dt * ORC_ACC_CONV * F[3 * i + a] / mass[sp[i]];
+                pos[3 * i + a] += dt * vel[3 * i + a];
+            }
+        st = orc_energy_forces(m, n, pos, sp, box, &E, NULL, F, NULL);
+        if (st) { free(F); return st; }
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) vel[3 * i + a] += 0.5 * dt * ORC_ACC_CONV * F[3 * i + a] / mass[sp[i]];
+        kinetic_tensor(n, vel, sp, mass, &ke, kx);
+        nh_half(n, vel, &ke, g, kT, Q, dt, &xi, &eta);
+        if (epot) epot[t + 1] = E;
+        if (ekin) ekin[t + 1] = ke;
+        if (conserved) conserved[t + 1] = E + ke + 0.5 * Q * xi * xi + g * kT * eta;
+    }
+    xi_eta[0] = xi;
+    xi_eta[1] = eta;
+    free(F);
+    return ORC_OK;
+}
+
+/* Instantaneous pressure tensor diagonal and pressure (GPa) from velocities and
+ * the virial: p_aa = (2 KE_aa + W_aa) / V, P = (p_xx + p_yy + p_zz)/3. */
+int orc_pressure(const orc_model* m, int64_t n, const double* pos, const double* vel, const int32_t* sp,
+                 const double* mass, const double* box, double* p4) {
+    if (check_model(m)) return ORC_ERR_ARG;
+    double E, W[9], ke, kx[3];
+    int st = orc_energy_forces(m, n, pos, sp, box, &E, NULL, NULL, W);
+    if (st) return st;
+    kinetic_tensor(n, vel, sp, mass, &ke, kx);
+    const double V = box[0] * box[1] * box[2], conv = 160.21766208; /* eV/A^3 -> GPa */
+    for (int a = 0; a < 3; ++a) p4[a] = (2.0 * kx[a] + W[4 * a]) / V * conv;
+    p4[3] = (p4[0] + p4[1] + p4[2]) / 3.0;
+    return ORC_OK;
+}

@@ -264,3 +264,56 @@ def test_nve_conserves_energy():
     etot = epot + ekin
     assert np.abs(etot - etot[0]).max() / s.n <= 1e-4
     assert np.std(ekin) > 1e-3  # the dynamics actually exchanged energy
+
+
+# ---------------------------------------------------------------- Nose-Hoover NVT
+
+KB = 8.617333262e-5
+
+
+def test_nvt_conserves_extended_energy_and_holds_temperature():
+    s, spec, _ = inputs.workload("oracle32")
+    v = inputs.maxwell_boltzmann(np.full(s.n, 63.546), 300.0, seed=48)
+    for tau in (20.0, 50.0):
+        _, _, _, epot, ekin, cons = oracle.nvt(spec, s.pos, v, s.species, s.masses, s.box, 1.0, 300.0, tau, 1000)
+        assert np.abs(cons - cons[0]).max() / s.n <= 1e-4
+        T = 2.0 * ekin / (3 * s.n * KB)
+        assert 255.0 <= T[500:].mean() <= 345.0
+    # without the thermostat the random network heats the lattice far above 300 K
+    _, _, epot, ekin = oracle.nve(spec, s.pos, v, s.species, s.masses, s.box, 1.0, 1000)
+    assert (2.0 * ekin / (3 * s.n * KB))[500:].mean() > 1000.0
+
+
+def test_nvt_with_a_very_slow_thermostat_is_nve():
+    s, spec, _ = inputs.workload("oracle32")
+    v = inputs.maxwell_boltzmann(np.full(s.n, 63.546), 300.0, seed=49)
+    x1, v1, xe, *_ = oracle.nvt(spec, s.pos, v, s.species, s.masses, s.box, 1.0, 300.0, 1e7, 50)
+    x2, v2, _, _ = oracle.nve(spec, s.pos, v, s.species, s.masses, s.box, 1.0, 50)
+    assert abs(xe[0]) < 1e-10
+    np.testing.assert_allclose(x1, x2, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(v1, v2, rtol=0, atol=1e-10)
+
+
+def test_nvt_time_reversible():
+    s, spec, _ = inputs.workload("oracle32")
+    v = inputs.maxwell_boltzmann(np.full(s.n, 63.546), 300.0, seed=50)
+    x1, v1, (xi, eta), *_ = oracle.nvt(spec, s.pos, v, s.species, s.masses, s.box, 1.0, 300.0, 20.0, 20,
+                                       xi_eta=(0.003, 0.0))
+    x2, v2, (xi2, _), *_ = oracle.nvt(spec, x1, -v1, s.species, s.masses, s.box, 1.0, 300.0, 20.0, 20,
+                                      xi_eta=(-xi, eta))
+    np.testing.assert_allclose(x2, s.pos, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(-v2, v, rtol=0, atol=1e-11)
+    assert abs(-xi2 - 0.003) <= 1e-11
+
+
+def test_pressure_of_a_free_gas_is_ideal():
+    """Zero network: W = 0, so P = 2 KE / (3 V) = N kB T_kin / V."""
+    import dataclasses
+    s, spec, _ = inputs.workload("oracle32")
+    spec0 = dataclasses.replace(spec, params=np.zeros_like(spec.params))
+    v = inputs.maxwell_boltzmann(np.full(s.n, 63.546), 300.0, seed=51)
+    p = oracle.pressure(spec0, s.pos, v, s.species, s.masses, s.box)
+    ke = 0.5 * 103.6427 * 63.546 * (v ** 2).sum(0)
+    V = np.prod(s.box)
+    np.testing.assert_allclose(p[:3], 2 * ke / V * 160.21766208, rtol=1e-12)
+    np.testing.assert_allclose(p[3], 2 * ke.sum() / (3 * V) * 160.21766208, rtol=1e-12)
