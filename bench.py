@@ -233,6 +233,35 @@ def paper_shapes_leg(tmd, torch, ctx, steps: int, warmup: int) -> dict:
     return out
 
 
+def md_leg(tmd, torch, ctx, s, spec, steps: int) -> dict:
+    """The paper's MD protocol on the 1M-atom alloy: Nose-Hoover NVT at 300 K
+    (tau 100 fs), 1 fs steps, 1 A skin rebuilt every 5 steps, thermodynamic
+    output every 10 steps, BF16 MLP; whole MD steps timed."""
+    import numpy as np
+    from paper_2310_08439_amd import inputs
+    model = tmd.Model(ctx, spec, precision=tmd.BF16_MLP)
+    m = np.where(s.species == 0, s.masses[0], s.masses[1])
+    v0 = inputs.maxwell_boltzmann(m, 300.0, seed=7)
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    vel = torch.tensor(v0, dtype=torch.float64, device="cuda")
+    md = tmd.MD(ctx, model, pos, sp, s.box, s.masses, vel, dt_fs=1.0, temperature_K=300.0, tau_fs=100.0,
+                skin=1.0, rebuild_every=5)
+    md.run(10, thermo_every=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = md.run(steps, thermo_every=10)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    last = th[-1]
+    md.close()
+    model.close()
+    return {"workload": f"{s.n} atoms, NVT Nose-Hoover 300 K tau 100 fs, dt 1 fs, skin 1 A rebuilt every 5 steps, "
+                        f"thermo every 10 steps, BF16 MLP, {steps} steps",
+            "ns_per_step_atom": round(sec / s.n * 1e9, 4), "ms_per_step": round(sec * 1e3, 4),
+            "last_thermo": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in last.items()}}
+
+
 def accuracy(tmd, ev, pos, sp, s, spec, n_sample: int, precision: int) -> dict:
     """Sampled per-atom energy and force errors against the FP64 oracle."""
     import numpy as np
@@ -278,6 +307,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-samples", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--md-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-pool", type=int, default=256)
@@ -340,8 +370,10 @@ def main():
         for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
             acc[name] = accuracy(tmd, ev, pos, sp, s, spec, args.accuracy_samples, prec)
 
-    training = serving = shapes = None
+    training = serving = shapes = md = None
     if not args.no_extra:
+        md = md_leg(tmd, torch, ev.ctx, s, spec, args.md_steps)
+        print(f"[bench] md {md}", file=sys.stderr, flush=True)
         shapes = paper_shapes_leg(tmd, torch, ev.ctx, 10, 2)
         print(f"[bench] paper shapes {shapes}", file=sys.stderr, flush=True)
         training = train_leg(tmd, torch, ev.ctx, args.train_steps, 2)
@@ -386,6 +418,7 @@ def main():
         "serving": serving,
         "training": training,
         "paper_shapes": shapes,
+        "md": md,
     }
     print(json.dumps(line), flush=True)
 

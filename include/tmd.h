@@ -258,6 +258,76 @@ typedef enum {
 } tmd_batch_field;
 tmd_status tmd_batch_read(tmd_context* ctx, const tmd_batch* batch, int32_t field, float* out);
 
+/* ---------------------------------------------------------------- molecular dynamics */
+
+/* Molecular dynamics of one system (the MD protocol of Sec. IV.D: NVT at
+ * 300 K, 1 fs steps, a 1 A skin rebuilt every 5 steps, thermodynamic output
+ * every 10 steps).  Velocity Verlet with accelerations 9.648533e-3 F/m A/fs^2;
+ * for NVT a Nose-Hoover thermostat (the paper does not name one): a single
+ * variable xi of mass Q = 3N kB T tau^2 in the symmetric Trotter splitting
+ *   half thermostat step: xi += dt/4 G; v *= exp(-xi dt/2); eta += xi dt/2; xi += dt/4 G
+ *   velocity Verlet step
+ *   half thermostat step,
+ * G = (2 KE - 3N kB T)/Q.  Positions stay FP64 on the device and are never
+ * wrapped (the list build wraps them). */
+typedef struct tmd_md tmd_md;
+
+typedef enum { TMD_ENSEMBLE_NVE = 0, TMD_ENSEMBLE_NVT_NOSE_HOOVER = 1 } tmd_ensemble;
+
+/* dt_fs > 0; temperature_K and tau_fs > 0 for NVT; skin >= 0 (A);
+ * rebuild_every > 0: rebuild the list every that many steps (the caller
+ * guarantees that no atom moves more than skin/2 in between); 0: rebuild when
+ * an atom has moved more than skin/2 since the last build (one host
+ * synchronisation per step). */
+typedef struct {
+    double dt_fs;
+    double temperature_K;
+    double tau_fs;
+    double skin;
+    int32_t ensemble;
+    int32_t rebuild_every;
+} tmd_md_opts;
+
+/* One line of thermodynamic output.  Energies in eV, temperature
+ * T = 2 KE / (3N kB), pressure tensor diagonal p_aa = (2 KE_aa + W_aa)/V in GPa
+ * and P its mean; conserved = PE + KE (+ Q xi^2/2 + 3N kB T eta for NVT);
+ * rebuilds = list builds so far (including the first). */
+typedef struct {
+    int64_t step;
+    double time_fs;
+    double epot;
+    double ekin;
+    double etotal;
+    double temperature_K;
+    double pressure_GPa;
+    double pxx_GPa;
+    double pyy_GPa;
+    double pzz_GPa;
+    double volume_A3;
+    double conserved;
+    double xi;
+    int32_t rebuilds;
+    int32_t reserved;
+} tmd_thermo;
+
+/* Start MD from the positions and species of sys (device, copied), host FP64
+ * masses per species [S] (amu) and device FP64 velocities [n][3] (copied; NULL
+ * for zero).  Builds the list and evaluates the initial forces.  model must
+ * outlive the handle.  Synchronises. */
+tmd_status tmd_md_create(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys, const double* masses,
+                         const double* velocities, const tmd_md_opts* opts, tmd_md** out);
+/* Advance n_steps.  When thermo_every > 0, a tmd_thermo record is written to
+ * the host array thermo (room for thermo_capacity records) at every step index
+ * divisible by thermo_every (step 0 on the first call included); *n_thermo
+ * (nullable) receives the number written.  Synchronises. */
+tmd_status tmd_md_run(tmd_md* md, int64_t n_steps, int32_t thermo_every, tmd_thermo* thermo, int32_t thermo_capacity,
+                      int32_t* n_thermo);
+/* Copy the current positions / velocities to device arrays [n][3] (nullable). */
+tmd_status tmd_md_read(tmd_md* md, double* pos, double* vel);
+/* Host FP64 [2] = (xi, eta) of the thermostat. */
+tmd_status tmd_md_thermostat_state(tmd_md* md, double* xi_eta);
+void tmd_md_destroy(tmd_md* md);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A persistent request loop over resident systems (the MD protocol of

@@ -28,79 +28,6 @@ namespace tmd {
 namespace {
 
 constexpr double kAccConv = 9.648533e-3;  // (eV/A)/amu -> A/fs^2
-constexpr double kKeConv = 103.6427;      // amu (A/fs)^2 -> eV
-constexpr int kKeBlocks = 256;
-
-// v += (dt/2) a; x += dt v; and the largest squared displacement since the
-// last list build, as the bits of a non-negative double (ordered like the values).
-__global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double* __restrict__ x, double* __restrict__ v,
-                                                    const float* __restrict__ F, const int32_t* __restrict__ sp,
-                                                    const double* __restrict__ acc, double dt,
-                                                    const double* __restrict__ xref,
-                                                    unsigned long long* __restrict__ maxd2) {
-    __shared__ double red[256];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double d2 = 0.0;
-    if (i < n) {
-        const double a = acc[sp[i]];
-        for (int c = 0; c < 3; ++c) {
-            const double vi = v[3 * i + c] + 0.5 * dt * a * (double)F[3 * i + c];
-            const double xi = x[3 * i + c] + dt * vi;
-            v[3 * i + c] = vi;
-            x[3 * i + c] = xi;
-            const double d = xi - xref[3 * i + c];
-            d2 += d * d;
-        }
-    }
-    red[threadIdx.x] = d2;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(maxd2, (unsigned long long)__double_as_longlong(red[0]));
-}
-
-// v += (dt/2) a
-__global__ void k_kick(int64_t n, double* __restrict__ v, const float* __restrict__ F,
-                       const int32_t* __restrict__ sp, const double* __restrict__ acc, double dt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double a = acc[sp[i]];
-    for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * a * (double)F[3 * i + c];
-}
-
-// Kinetic energy in two fixed-order passes: kKeBlocks strided partials, then
-// one compensated sum.
-__global__ void __launch_bounds__(256) k_ke_partials(int64_t n, const double* __restrict__ v,
-                                                     const int32_t* __restrict__ sp,
-                                                     const double* __restrict__ mass, double* __restrict__ part) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        s += 0.5 * kKeConv * mass[sp[i]] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-__global__ void k_ke_total(const double* __restrict__ part, int nb, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0, c = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        const double x = part[b], t = s + x;
-        if (fabs(s) >= fabs(x)) c += (s - t) + x;
-        else c += (x - t) + s;
-        s = t;
-    }
-    *out = s + c;
-}
-
-unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 double now_s(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -218,26 +145,23 @@ tmd_status build_list(tmd_server* sv, tmd_context* ctx, System* sys, int* rebuil
 
 struct SlotBuffers {
     double* tot = nullptr;                 // [7 (n_steps + 1)]
-    double* ekin = nullptr;                // [n_steps + 1]
-    double* part = nullptr;                // [kKeBlocks]
+    double* ekin = nullptr;                // [4 (n_steps + 1)] kinetic tensor diagonal and total
+    double* part = nullptr;                // [3 kKeBlocks]
     unsigned long long* maxd2 = nullptr;   // [1]
 };
 
 tmd_status slot_buffers(tmd_context* ctx, int n_steps, SlotBuffers* b) {
     hipError_t e = hipSuccess;
     b->tot = (double*)ctx->ws.get("md.tot", sizeof(double) * 7 * (size_t)(n_steps + 1), &e);
-    b->ekin = (double*)ctx->ws.get("md.ekin", sizeof(double) * (size_t)(n_steps + 1), &e);
-    b->part = (double*)ctx->ws.get("md.part", sizeof(double) * kKeBlocks, &e);
+    b->ekin = (double*)ctx->ws.get("md.ekin", sizeof(double) * 4 * (size_t)(n_steps + 1), &e);
+    b->part = (double*)ctx->ws.get("md.part", sizeof(double) * 3 * kKeBlocks, &e);
     b->maxd2 = (unsigned long long*)ctx->ws.get("md.maxd2", sizeof(unsigned long long), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "MD workspace");
     return TMD_OK;
 }
 
-tmd_status kinetic(tmd_context* ctx, const System* sys, double* part, double* out) {
-    k_ke_partials<<<kKeBlocks, 256, 0, ctx->stream>>>(sys->n, sys->v, sys->sp, sys->mass, part);
-    k_ke_total<<<1, 64, 0, ctx->stream>>>(part, kKeBlocks, out);
-    TMD_HIP(ctx, hipGetLastError());
-    return TMD_OK;
+tmd_status kinetic(tmd_context* ctx, const System* sys, double* part, double* out4) {
+    return launch_kinetic(ctx, sys->n, sys->v, sys->sp, sys->mass, part, out4);
 }
 
 // Run one request to completion on the worker's context.
@@ -259,14 +183,14 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
     if (!sys->nl_valid && (st = build_list(sv, ctx, sys, &rebuilds)) != TMD_OK) return st;
     if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot, nullptr, sys->F)) != TMD_OK) return st;
     if (p.req.kind == TMD_REQ_MD) {
-        if ((st = kinetic(ctx, sys, b.part, b.ekin)) != TMD_OK) return st;
+        if ((st = kinetic(ctx, sys, b.part, b.ekin)) != TMD_OK) return st;  // slot 0
         const double dt = p.req.dt_fs;
         const double half_skin2 = 0.25 * sv->opts.skin * sv->opts.skin;
         for (int s = 1; s <= nsteps; ++s) {
             TMD_HIP(ctx, hipMemsetAsync(b.maxd2, 0, sizeof(unsigned long long), ctx->stream));
-            k_kick_drift<<<blocks(sys->n), kBlock, 0, ctx->stream>>>(sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc,
-                                                                     dt, sys->xref, b.maxd2);
-            TMD_HIP(ctx, hipGetLastError());
+            if ((st = launch_kick_drift(ctx, sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc, dt, sys->xref,
+                                        b.maxd2)) != TMD_OK)
+                return st;
             unsigned long long bits = 0;
             TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, b.maxd2, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream));
             TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -279,9 +203,8 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
             }
             if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F)) != TMD_OK)
                 return st;
-            k_kick<<<blocks(sys->n), kBlock, 0, ctx->stream>>>(sys->n, sys->v, sys->F, sys->sp, sys->acc, dt);
-            TMD_HIP(ctx, hipGetLastError());
-            if ((st = kinetic(ctx, sys, b.part, b.ekin + s)) != TMD_OK) return st;
+            if ((st = launch_kick(ctx, sys->n, sys->v, sys->F, sys->sp, sys->acc, dt)) != TMD_OK) return st;
+            if ((st = kinetic(ctx, sys, b.part, b.ekin + 4 * s)) != TMD_OK) return st;
         }
     }
     std::vector<double> tot(7 * (size_t)(nsteps + 1));
@@ -289,11 +212,11 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
     TMD_HIP(ctx, hipMemcpyAsync(tot.data(), b.tot, sizeof(double) * tot.size(), hipMemcpyDeviceToHost, ctx->stream));
     TMD_HIP(ctx, hipMemcpyAsync(out->F.data(), sys->F, 12 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
     if (p.req.kind == TMD_REQ_MD) {
-        out->ekin.resize(nsteps + 1);
+        out->ekin.resize(4 * (size_t)(nsteps + 1));
         out->x.resize(3 * (size_t)sys->n);
         out->v.resize(3 * (size_t)sys->n);
-        TMD_HIP(ctx, hipMemcpyAsync(out->ekin.data(), b.ekin, sizeof(double) * (nsteps + 1), hipMemcpyDeviceToHost,
-                                    ctx->stream));
+        TMD_HIP(ctx, hipMemcpyAsync(out->ekin.data(), b.ekin, sizeof(double) * 4 * (nsteps + 1),
+                                    hipMemcpyDeviceToHost, ctx->stream));
         TMD_HIP(ctx, hipMemcpyAsync(out->x.data(), sys->x, 24 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
         TMD_HIP(ctx, hipMemcpyAsync(out->v.data(), sys->v, 24 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -302,6 +225,11 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
     for (int s = 0; s <= nsteps; ++s) out->epot[s] = tot[7 * s];
     r.energy = tot[7 * nsteps];
     for (int j = 0; j < 6; ++j) r.virial[j] = tot[7 * nsteps + 1 + j];
+    if (p.req.kind == TMD_REQ_MD) {
+        // keep the totals only
+        for (int s = 0; s <= nsteps; ++s) out->ekin[s] = out->ekin[4 * (size_t)s + 3];
+        out->ekin.resize(nsteps + 1);
+    }
     r.kinetic = p.req.kind == TMD_REQ_MD ? out->ekin[nsteps] : 0.0;
     r.rebuilds = rebuilds;
     return TMD_OK;

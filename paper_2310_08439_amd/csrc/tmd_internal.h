@@ -202,6 +202,18 @@ size_t eval_workspace_bytes(const tmd_model* m, int64_t n);
 tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S);
 size_t nlist_workspace_bytes(int64_t n);
 
+// Velocity Verlet pieces (md.hip).  acc[S] = 9.648533e-3 / m_s; maxd2
+// (nullable) receives the largest squared displacement from xref as ordered
+// bits; the kinetic tensor out4 = (KE_xx, KE_yy, KE_zz, KE) in eV, FP64 fixed
+// order, with part a [3 * kKeBlocks] scratch.
+constexpr int kKeBlocks = 256;
+tmd_status launch_kick_drift(tmd_context* ctx, int64_t n, double* x, double* v, const float* F, const int32_t* sp,
+                             const double* acc, double dt, const double* xref, unsigned long long* maxd2);
+tmd_status launch_kick(tmd_context* ctx, int64_t n, double* v, const float* F, const int32_t* sp, const double* acc,
+                       double dt);
+tmd_status launch_kinetic(tmd_context* ctx, int64_t n, const double* v, const int32_t* sp, const double* mass,
+                          double* part, double* out4);
+
 // Upper bound on the virial partials the adjoint writes.
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl);
 

@@ -39,7 +39,10 @@ EXPORTS = (
     "tmd_serve_create", "tmd_serve_add_system", "tmd_serve_submit", "tmd_serve_poll", "tmd_serve_wait",
     "tmd_serve_fetch", "tmd_serve_release", "tmd_serve_read_system", "tmd_serve_memory", "tmd_serve_last_error",
     "tmd_serve_destroy",
+    "tmd_md_create", "tmd_md_run", "tmd_md_read", "tmd_md_thermostat_state", "tmd_md_destroy",
 )
+ENSEMBLE_NVE = 0
+ENSEMBLE_NVT_NOSE_HOOVER = 1
 TMD_ERR_NOT_READY = 6
 REQ_ENERGY_FORCES = 0
 REQ_MD = 1
@@ -72,6 +75,22 @@ class TrainOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class MDOpts(ctypes.Structure):
+    _fields_ = [("dt_fs", ctypes.c_double), ("temperature_K", ctypes.c_double), ("tau_fs", ctypes.c_double),
+                ("skin", ctypes.c_double), ("ensemble", ctypes.c_int32), ("rebuild_every", ctypes.c_int32)]
+
+
+class Thermo(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("time_fs", ctypes.c_double), ("epot", ctypes.c_double),
+                ("ekin", ctypes.c_double), ("etotal", ctypes.c_double), ("temperature_K", ctypes.c_double),
+                ("pressure_GPa", ctypes.c_double), ("pxx_GPa", ctypes.c_double), ("pyy_GPa", ctypes.c_double),
+                ("pzz_GPa", ctypes.c_double), ("volume_A3", ctypes.c_double), ("conserved", ctypes.c_double),
+                ("xi", ctypes.c_double), ("rebuilds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 class ServeOpts(ctypes.Structure):
@@ -147,6 +166,12 @@ def load_library(path: str = LIB_PATH):
     L.tmd_batch_destroy.restype = None
     L.tmd_train_step.argtypes = [vp, vp, vp, P(TrainOpts), vp, vp]
     L.tmd_batch_read.argtypes = [vp, vp, i32, vp]
+    L.tmd_md_create.argtypes = [vp, vp, P(SystemView), vp, vp, P(MDOpts), P(vp)]
+    L.tmd_md_run.argtypes = [vp, i64, i32, vp, i32, P(i32)]
+    L.tmd_md_read.argtypes = [vp, vp, vp]
+    L.tmd_md_thermostat_state.argtypes = [vp, vp]
+    L.tmd_md_destroy.argtypes = [vp]
+    L.tmd_md_destroy.restype = None
     L.tmd_serve_create.argtypes = [vp, P(ServeOpts), P(vp)]
     L.tmd_serve_add_system.argtypes = [vp, i64, vp, vp, vp, vp, P(i64)]
     L.tmd_serve_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
@@ -644,6 +669,67 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             self.lib.tmd_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- molecular dynamics
+
+
+class MD:
+    """Molecular dynamics of one system (tmd_md_*): velocity Verlet, NVE or
+    Nose-Hoover NVT, neighbour list on a fixed period or a displacement rule."""
+
+    def __init__(self, ctx: Context, model: Model, pos, species, box, masses, velocities=None, dt_fs: float = 1.0,
+                 ensemble: int = ENSEMBLE_NVT_NOSE_HOOVER, temperature_K: float = 300.0, tau_fs: float = 100.0,
+                 skin: float = 1.0, rebuild_every: int = 5):
+        self.ctx = ctx
+        self.model = model  # must outlive the MD handle
+        self.n = int(pos.shape[0])
+        v = system_view(pos, species, box)
+        masses = np.ascontiguousarray(masses, dtype=np.float64)
+        o = MDOpts()
+        o.dt_fs, o.temperature_K, o.tau_fs, o.skin = float(dt_fs), float(temperature_K), float(tau_fs), float(skin)
+        o.ensemble, o.rebuild_every = int(ensemble), int(rebuild_every)
+        if velocities is not None:
+            torch = _torch()
+            if velocities.dtype != torch.float64 or not velocities.is_cuda or not velocities.is_contiguous():
+                raise ValueError("velocities must be a contiguous [n,3] float64 device tensor")
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.tmd_md_create(ctx.h, model.h, ctypes.byref(v), masses.ctypes.data, _ptr(velocities),
+                                        ctypes.byref(o), ctypes.byref(h)), "tmd_md_create")
+        self.h = h
+
+    def run(self, n_steps: int, thermo_every: int = 0) -> list:
+        """Advance n_steps; returns the thermo records (dicts) written."""
+        cap = (n_steps // thermo_every + 2) if thermo_every > 0 else 0
+        buf = (Thermo * max(cap, 1))()
+        nt = ctypes.c_int32(0)
+        self.ctx.check(self.ctx.lib.tmd_md_run(self.h, int(n_steps), int(thermo_every), buf, cap, ctypes.byref(nt)),
+                       "tmd_md_run")
+        return [buf[q].as_dict() for q in range(nt.value)]
+
+    def state(self):
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        pos = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        vel = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        self.ctx.check(self.ctx.lib.tmd_md_read(self.h, _ptr(pos), _ptr(vel)), "tmd_md_read")
+        return pos, vel
+
+    def thermostat(self) -> Tuple[float, float]:
+        xe = (ctypes.c_double * 2)()
+        self.ctx.check(self.ctx.lib.tmd_md_thermostat_state(self.h, xe), "tmd_md_thermostat_state")
+        return float(xe[0]), float(xe[1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tmd_md_destroy(self.h)
             self.h = None
 
     def __del__(self):
