@@ -29,6 +29,7 @@ class OrcModel(ctypes.Structure):
         ("activation", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
         ("rcut", ctypes.c_double),
+        ("tab_dr", ctypes.c_double),
         ("mu", ctypes.c_void_p),
         ("eta", ctypes.c_void_p),
         ("params", ctypes.c_void_p),
@@ -71,6 +72,8 @@ def lib():
         L.orc_nvt.restype = i32
         L.orc_pressure.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.orc_pressure.restype = i32
+        L.orc_radial.argtypes = [vp, dbl, vp, vp]
+        L.orc_radial.restype = None
         L.orc_params_per_species.argtypes = [vp]
         L.orc_params_per_species.restype = i32
         L.orc_num_threads.argtypes = []
@@ -99,6 +102,7 @@ class _ModelRef:
             m.hidden[q] = h
         m.activation = spec.activation
         m.rcut = spec.rcut
+        m.tab_dr = float(getattr(spec, "tab_dr", 0.0))
         m.mu = _p(self.mu)
         m.eta = _p(self.eta)
         m.params = _p(self.params)
@@ -147,6 +151,16 @@ def atom_neighbors(i: int, pos, species, box, rlist: float, cap: int = 4096):
     if c > cap:
         return atom_neighbors(i, pos, species, box, rlist, cap=c)
     return js[:c].copy(), imgs[:c].copy(), ds[:c].copy()
+
+
+def radial(spec, R: float):
+    """(h [K], h' [K]) of the model's radial functions at distance R (direct
+    or, when spec.tab_dr > 0, interpolated from the node table)."""
+    mref = _ModelRef(spec)
+    h = np.empty(spec.n_radial, dtype=np.float64)
+    dh = np.empty(spec.n_radial, dtype=np.float64)
+    lib().orc_radial(mref.ref, float(R), _p(h), _p(dh))
+    return h, dh
 
 
 def descriptors(spec, pos, species, box, sel: Optional[np.ndarray] = None) -> np.ndarray:

@@ -18,6 +18,8 @@
  *   - forces through the adjoint chain P' = 2 T sigma' P, U = P' M,
  *     V = P' H, F1 = U H' R', F2 = V M' and the scattered sum over pairs
  *     (Sec. III.A, eqns dP_abkd, U_abck, F1_abcx, F2_abcx);
+ *   - optionally, radial functions interpolated from a table of nodes with
+ *     the cutoff folded in (Sec. III.B), by cubic Hermite interpolation;
  *   - beyond the paper (its potentials were trained elsewhere): the
  *     force-matching loss and its parameter gradient, with the descriptor
  *     tangent and a second-order network pass written from their definitions,
@@ -60,6 +62,7 @@ typedef struct {
     int32_t activation;    /* 0 tanh, 1 squareplus */
     int32_t pad_;
     double rcut;
+    double tab_dr;         /* > 0: radial functions from a table of this spacing (at most) */
     const double* mu;      /* [K] */
     const double* eta;     /* [K] */
     const double* params;  /* per-species packed MLP parameters */
@@ -237,6 +240,55 @@ static double ipow(double x, int p) {
     return r;
 }
 
+/* Exact radial function h_k(R) = exp(-eta_k (R - mu_k)^2) f_c(R) and its
+ * derivative (Sec. III.A, H_abck). */
+static void radial_exact(const orc_model* m, int k, double R, double* h, double* dh) {
+    const double t = R - m->mu[k];
+    const double f = exp(-m->eta[k] * t * t);
+    const double fc = cutoff_fc(R, m->rcut), dfc = cutoff_dfc(R, m->rcut);
+    *h = f * fc;
+    *dh = (-2.0 * m->eta[k] * t) * f * fc + f * dfc;
+}
+
+/* Tabulated radial functions (Sec. III.B, batch 1-D interpolation of H and
+ * H' with the cutoff folded in).  The paper's rational scheme is not printed,
+ * so this is piecewise cubic Hermite interpolation, a named substitute: nodes
+ * r_j = j delta with delta = rc / ceil(rc / tab_dr) (so that rc is a node),
+ * node data (h_k(r_j), h_k'(r_j)) exact, both forced to 0 at r = 0 as the
+ * paper does, and 0 for R >= rc.  On [r_j, r_j+1) with t = R/delta - j:
+ *   h  = H00(t) f_j + H10(t) delta f'_j + H01(t) f_j+1 + H11(t) delta f'_j+1,
+ *   h' = dh/dR of the same cubic,
+ * H00 = 2t^3 - 3t^2 + 1, H10 = t^3 - 2t^2 + t, H01 = 3t^2 - 2t^3, H11 = t^3 - t^2
+ * (the textbook Hermite basis), so forces stay the exact gradient of the
+ * interpolated energy. */
+static void radial_node(const orc_model* m, int k, int64_t j, double delta, double* f, double* df) {
+    if (j == 0) { *f = 0.0; *df = 0.0; return; }
+    radial_exact(m, k, (double)j * delta, f, df);
+}
+
+static void radial(const orc_model* m, int k, double R, double* h, double* dh) {
+    if (!(m->tab_dr > 0.0)) { radial_exact(m, k, R, h, dh); return; }
+    if (!(R < m->rcut)) { *h = 0.0; *dh = 0.0; return; }
+    const double nint = ceil(m->rcut / m->tab_dr);
+    const double delta = m->rcut / nint;
+    int64_t j = (int64_t)floor(R / delta);
+    if (j > (int64_t)nint - 1) j = (int64_t)nint - 1;
+    const double t = R / delta - (double)j;
+    double f0, d0, f1, d1;
+    radial_node(m, k, j, delta, &f0, &d0);
+    radial_node(m, k, j + 1, delta, &f1, &d1);
+    const double t2 = t * t, t3 = t2 * t;
+    const double H00 = 2 * t3 - 3 * t2 + 1, H10 = t3 - 2 * t2 + t, H01 = 3 * t2 - 2 * t3, H11 = t3 - t2;
+    const double D00 = 6 * t2 - 6 * t, D10 = 3 * t2 - 4 * t + 1, D01 = 6 * t - 6 * t2, D11 = 3 * t2 - 2 * t;
+    *h = H00 * f0 + H10 * delta * d0 + H01 * f1 + H11 * delta * d1;
+    *dh = (D00 * f0 + D10 * delta * d0 + D01 * f1 + D11 * delta * d1) / delta;
+}
+
+/* h_k(R) and h_k'(R) for k = 0..K-1, as the model evaluates them. */
+void orc_radial(const orc_model* m, double R, double* h, double* dh) {
+    for (int k = 0; k < m->n_radial; ++k) radial(m, k, R, &h[k], &dh[k]);
+}
+
 /* M_d(u) = u_x^px u_y^py u_z^pz */
 static double moment(int d, const double* u) {
     return ipow(u[0], MONO[d][0]) * ipow(u[1], MONO[d][1]) * ipow(u[2], MONO[d][2]);
@@ -345,10 +397,10 @@ static void atom_P(const orc_model* m, const orc_pair* pr, int cnt, double* P) {
         const double R = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
         if (!(R < m->rcut)) continue;
         const double u[3] = {D[0] / R, D[1] / R, D[2] / R};
-        const double fc = cutoff_fc(R, m->rcut);
         const int b = pr[c].sj;
         for (int k = 0; k < dm.K; ++k) {
-            const double h = exp(-m->eta[k] * (R - m->mu[k]) * (R - m->mu[k])) * fc;
+            double h, dh;
+            radial(m, k, R, &h, &dh);
             for (int d = 0; d < dm.D; ++d) P[(b * dm.K + k) * dm.D + d] += h * moment(d, u);
         }
     }
@@ -399,15 +451,9 @@ static void atom_pair_grads(const orc_model* m, const orc_pair* pr, int cnt, con
         const double R = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
         if (!(R < m->rcut)) continue;
         const double u[3] = {D[0] / R, D[1] / R, D[2] / R};
-        const double fc = cutoff_fc(R, m->rcut), dfc = cutoff_dfc(R, m->rcut);
         const int b = pr[c].sj;
         double H[128], dH[128], Mv[20], dM[20][3];
-        for (int k = 0; k < dm.K; ++k) {
-            const double t = R - m->mu[k];
-            const double f = exp(-m->eta[k] * t * t);
-            H[k] = f * fc;
-            dH[k] = (-2.0 * m->eta[k] * t) * f * fc + f * dfc;
-        }
+        for (int k = 0; k < dm.K; ++k) radial(m, k, R, &H[k], &dH[k]);
         for (int d = 0; d < dm.D; ++d) {
             Mv[d] = moment(d, u);
             for (int x = 0; x < 3; ++x) {
@@ -443,6 +489,7 @@ static int check_model(const orc_model* m) {
     if (m->n_hidden < 0 || m->n_hidden > MAXL || orc_n_features(m) > MAXW || !(m->rcut > 0.0)) return ORC_ERR_ARG;
     for (int l = 0; l < m->n_hidden; ++l)
         if (m->hidden[l] < 1 || m->hidden[l] > MAXW) return ORC_ERR_ARG;
+    if (!(m->tab_dr >= 0.0) || m->tab_dr > m->rcut) return ORC_ERR_ARG;
     return ORC_OK;
 }
 
@@ -606,13 +653,10 @@ static void atom_G_tangent(const orc_model* m, int64_t i, const orc_pair* pr, in
         const double t[3] = {r[3 * j] - r[3 * i], r[3 * j + 1] - r[3 * i + 1], r[3 * j + 2] - r[3 * i + 2]};
         const double Rt = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
         const double ut[3] = {(t[0] - u[0] * Rt) / R, (t[1] - u[1] * Rt) / R, (t[2] - u[2] * Rt) / R};
-        const double fc = cutoff_fc(R, m->rcut), dfc = cutoff_dfc(R, m->rcut);
         const int b = pr[c].sj;
         for (int k = 0; k < dm.K; ++k) {
-            const double tk = R - m->mu[k];
-            const double f = exp(-m->eta[k] * tk * tk);
-            const double h = f * fc;
-            const double dh = (-2.0 * m->eta[k] * tk) * f * fc + f * dfc;
+            double h, dh;
+            radial(m, k, R, &h, &dh);
             for (int d = 0; d < dm.D; ++d) {
                 double Mt = 0.0;
                 for (int a = 0; a < 3; ++a) Mt += dmoment_du(d, a, u) * ut[a];

@@ -103,6 +103,7 @@ class ModelSpec:
     eta: np.ndarray            # [K]
     params: np.ndarray         # float64, all species packed (see param_layout)
     activation: int = ACT_TANH
+    tab_dr: float = 0.0        # > 0: radial functions interpolated from nodes at most this far apart
 
     @property
     def n_features(self) -> int:
