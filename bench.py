@@ -262,6 +262,80 @@ def md_leg(tmd, torch, ctx, s, spec, steps: int) -> dict:
             "last_thermo": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in last.items()}}
 
 
+def interpolation_leg(tmd, torch, ev, pos, sp, s, spec, steps: int, warmup: int) -> dict:
+    """Tabulated radial functions (cubic Hermite table, cutoff folded in) against
+    direct evaluation: speed on the main workload (BF16 MLP), for the uniform
+    grid (two exponentials per chunk) and for jittered centres (one exponential
+    per radial function); static error on 16,000 atoms; dynamic error of E, T
+    and P over a 54,000-atom NVT run (the paper's static and dynamic test sizes)."""
+    import dataclasses
+    import numpy as np
+    from paper_2310_08439_amd import inputs
+    out = {"scheme": "cubic Hermite, nodes rcut/ceil(rcut/dr) apart, FP32 coefficients"}
+    speed = {}
+
+    def timed(evx, label):
+        sec, prof, _ = time_precision(tmd, torch, evx, pos, sp, s.box, tmd.BF16_MLP, steps, warmup)
+        speed[label] = {"ns_per_step_atom": round(sec / s.n * 1e9, 4),
+                        "descriptor_ms": round(prof["descriptor"][0] / prof["descriptor"][1], 4),
+                        "adjoint_ms": round(prof["adjoint"][0] / prof["adjoint"][1], 4)}
+
+    timed(ev, "direct_uniform_grid")
+    for dr in (0.01, 0.001):
+        ev.model.tabulate(dr)
+        timed(ev, f"table_dr{dr:g}")
+    ev.model.tabulate(0.0)
+    rng = np.random.default_rng(9)
+    jit = dataclasses.replace(spec, mu=spec.mu + rng.uniform(-0.02, 0.02, size=spec.mu.shape))
+    evj = tmd.Evaluator(jit, s.n, s.box, precision=tmd.BF16_MLP, ctx=ev.ctx)
+    timed(evj, "direct_jittered_grid")
+    evj.model.tabulate(0.01)
+    timed(evj, "table_dr0.01_jittered_grid")
+    evj.model.close()
+    evj.nl.close()
+    out["speed"] = speed
+
+    st = inputs.make_system("bcc", 3.16, (20, 20, 20), 0.08, 2, seed=155)
+    pst = torch.tensor(st.pos, dtype=torch.float64, device="cuda")
+    sst = torch.tensor(st.species, dtype=torch.int32, device="cuda")
+    evs = tmd.Evaluator(spec, st.n, st.box, precision=tmd.FP32, ctx=ev.ctx)
+    E0, _, F0, _ = evs.energy_forces(pst, sst, st.box)
+    F0 = F0.cpu().numpy().astype(np.float64)
+    static = {}
+    for dr in (0.1, 0.05, 0.01, 0.005, 0.001):
+        evs.model.tabulate(dr)
+        E, _, F, _ = evs.energy_forces(pst, sst, st.box)
+        F = F.cpu().numpy().astype(np.float64)
+        static[f"{dr:g}"] = {"force_rmse_eV_per_A": float(math.sqrt(np.mean((F - F0) ** 2))),
+                             "energy_err_eV_per_atom": float(abs(E - E0) / st.n)}
+    evs.model.close()
+    evs.nl.close()
+    out["static_16000_atoms_fp32"] = static
+
+    sd = inputs.make_system("bcc", 3.16, (30, 30, 30), 0.05, 2, seed=160, masses=[183.84, 95.95])
+    m = np.where(sd.species == 0, sd.masses[0], sd.masses[1])
+    v0 = inputs.maxwell_boltzmann(m, 300.0, seed=161)
+    series = {}
+    for dr in (0.0, 0.01, 0.001):
+        model = tmd.Model(ev.ctx, dataclasses.replace(spec, tab_dr=dr), precision=tmd.FP32)
+        md = tmd.MD(ev.ctx, model, torch.tensor(sd.pos, dtype=torch.float64, device="cuda"),
+                    torch.tensor(sd.species, dtype=torch.int32, device="cuda"), sd.box, sd.masses,
+                    torch.tensor(v0, dtype=torch.float64, device="cuda"), dt_fs=1.0, temperature_K=300.0,
+                    tau_fs=100.0, skin=1.0, rebuild_every=5)
+        th = md.run(1000, thermo_every=10)
+        series[dr] = np.array([[t["etotal"] / sd.n, t["temperature_K"], t["pressure_GPa"]] for t in th])
+        md.close()
+        model.close()
+    dyn = {}
+    for dr in (0.01, 0.001):
+        d = series[dr] - series[0.0]
+        dyn[f"{dr:g}"] = {"etotal_rmse_eV_per_atom": float(math.sqrt(np.mean(d[:, 0] ** 2))),
+                          "temperature_rmse_K": float(math.sqrt(np.mean(d[:, 1] ** 2))),
+                          "pressure_rmse_GPa": float(math.sqrt(np.mean(d[:, 2] ** 2)))}
+    out["dynamic_54000_atoms_nvt_1000_steps_fp32"] = dyn
+    return out
+
+
 def accuracy(tmd, ev, pos, sp, s, spec, n_sample: int, precision: int) -> dict:
     """Sampled per-atom energy and force errors against the FP64 oracle."""
     import numpy as np
@@ -370,10 +444,12 @@ def main():
         for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
             acc[name] = accuracy(tmd, ev, pos, sp, s, spec, args.accuracy_samples, prec)
 
-    training = serving = shapes = md = None
+    training = serving = shapes = md = interp = None
     if not args.no_extra:
         md = md_leg(tmd, torch, ev.ctx, s, spec, args.md_steps)
         print(f"[bench] md {md}", file=sys.stderr, flush=True)
+        interp = interpolation_leg(tmd, torch, ev, pos, sp, s, spec, 10, 2)
+        print(f"[bench] interpolation {interp}", file=sys.stderr, flush=True)
         shapes = paper_shapes_leg(tmd, torch, ev.ctx, 10, 2)
         print(f"[bench] paper shapes {shapes}", file=sys.stderr, flush=True)
         training = train_leg(tmd, torch, ev.ctx, args.train_steps, 2)
@@ -419,6 +495,7 @@ def main():
         "training": training,
         "paper_shapes": shapes,
         "md": md,
+        "interpolation": interp,
     }
     print(json.dumps(line), flush=True)
 

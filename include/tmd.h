@@ -134,6 +134,26 @@ tmd_status tmd_model_set_precision(tmd_model* model, tmd_precision precision);
 /* Copy the current weights (host FP32, same layout as tmd_model_create) into
  * params; reflects every tmd_train_step applied so far.  Synchronises. */
 tmd_status tmd_model_get_params(const tmd_model* model, float* params);
+/* Tabulated radial functions (Sec. III.B: the radial tensor H and its
+ * derivative H' interpolated from a 1-D table, with the cutoff folded into the
+ * table and nothing evaluated past rcut).  The paper's rational-interpolation
+ * formula is not printed; this uses piecewise cubic Hermite interpolation:
+ * nodes r_j = j * delta with delta = rcut / ceil(rcut / dr) (so rcut is a
+ * node), node values and derivatives of h_k = exp(-eta_k (R - mu_k)^2) f_c(R)
+ * computed exactly in FP64, both forced to 0 at r = 0 as the paper does, and
+ * stored per interval as four FP32 polynomial coefficients, interval-major
+ * ([interval][k], 16 bytes per entry).  h_k' is the derivative of the same
+ * cubic, so forces stay the exact gradient of the tabulated energy.
+ * dr = 0 returns to direct evaluation.  The table serves tmd_descriptors,
+ * tmd_energy_forces(_async), tmd_md_* and tmd_serve_*; tmd_train_step rejects a
+ * tabulated model (training uses the exact functions).
+ * Errors: dr < 0, not finite, > rcut, or more than 2^20 intervals ->
+ * TMD_ERR_INVALID_ARGUMENT (the model keeps its previous mode); allocation ->
+ * TMD_ERR_OUT_OF_MEMORY.  Synchronises the model's stream; must not run while
+ * other work that uses the model is in flight. */
+tmd_status tmd_model_tabulate(tmd_model* model, double dr);
+/* Node spacing delta of the table in use (0 for direct evaluation). */
+double tmd_model_tab_spacing(const tmd_model* model);
 /* Number of floats per species block of params. */
 int64_t tmd_model_params_per_species(const tmd_model* model);
 int32_t tmd_model_n_features(const tmd_model* model);

@@ -348,6 +348,8 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
     }
     m->w_species_stride = off;
     std::vector<float> mu(K), eta(K);
+    m->mu_h.assign(spec->mu, spec->mu + K);
+    m->eta_h.assign(spec->eta, spec->eta + K);
     for (int k = 0; k < K; ++k) {
         mu[k] = (float)spec->mu[k];
         eta[k] = (float)spec->eta[k];
@@ -425,6 +427,60 @@ tmd_status tmd_model_set_precision(tmd_model* m, tmd_precision precision) {
     return TMD_OK;
 }
 
+tmd_status tmd_model_tabulate(tmd_model* m, double dr) {
+    if (!m) return TMD_ERR_INVALID_ARGUMENT;
+    if (!std::isfinite(dr) || dr < 0.0 || dr > m->rcut)
+        return fail(m->ctx, TMD_ERR_INVALID_ARGUMENT, "table spacing must be in [0, rcut]");
+    const double nint_d = dr > 0.0 ? std::ceil(m->rcut / dr) : 0.0;
+    if (nint_d > (double)(1 << 20)) return fail(m->ctx, TMD_ERR_INVALID_ARGUMENT, "more than 2^20 table intervals");
+    TMD_HIP(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    if (dr == 0.0) {
+        if (m->tab) TMD_HIP(m->ctx, hipFree(m->tab));
+        m->tab = nullptr;
+        m->tab_n = 0;
+        m->tab_delta = 0.0;
+        return TMD_OK;
+    }
+    const int n = (int)nint_d, K = m->K;
+    const double rc = m->rcut, delta = rc / n;
+    // node data: exact h_k and h_k' (FP64) at r_j = j delta, zero at r = 0 and r = rc
+    std::vector<double> f((size_t)(n + 1) * K), df((size_t)(n + 1) * K);
+    for (int j = 0; j <= n; ++j) {
+        const double R = j * delta;
+        const double fc = (j > 0 && j < n) ? 0.5 * (std::cos(M_PI * R / rc) + 1.0) : 0.0;
+        const double dfc = (j > 0 && j < n) ? -0.5 * (M_PI / rc) * std::sin(M_PI * R / rc) : 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double t = R - m->mu_h[k], e = std::exp(-m->eta_h[k] * t * t);
+            f[(size_t)j * K + k] = e * fc;
+            df[(size_t)j * K + k] = e * (dfc - 2.0 * m->eta_h[k] * t * fc);
+        }
+    }
+    // per interval the cubic with these end values and slopes, in powers of t
+    std::vector<float4> tab((size_t)(n + 1) * K, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < K; ++k) {
+            const double f0 = f[(size_t)j * K + k], f1 = f[(size_t)(j + 1) * K + k];
+            const double s0 = delta * df[(size_t)j * K + k], s1 = delta * df[(size_t)(j + 1) * K + k];
+            tab[(size_t)j * K + k] = make_float4((float)f0, (float)s0, (float)(3.0 * (f1 - f0) - 2.0 * s0 - s1),
+                                                 (float)(2.0 * (f0 - f1) + s0 + s1));
+        }
+    float4* d = nullptr;
+    const size_t bytes = tab.size() * sizeof(float4);
+    if (hipMalloc((void**)&d, bytes) != hipSuccess) return fail(m->ctx, TMD_ERR_OUT_OF_MEMORY, "radial table");
+    const hipError_t e = hipMemcpy(d, tab.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(m->ctx, e, "radial table upload");
+    }
+    if (m->tab) (void)hipFree(m->tab);
+    m->tab = d;
+    m->tab_n = n;
+    m->tab_delta = delta;
+    return TMD_OK;
+}
+
+double tmd_model_tab_spacing(const tmd_model* m) { return m ? m->tab_delta : 0.0; }
+
 int64_t tmd_model_params_per_species(const tmd_model* m) { return m ? m->per_species : 0; }
 int32_t tmd_model_n_features(const tmd_model* m) { return m ? m->F : 0; }
 
@@ -432,7 +488,7 @@ void tmd_model_destroy(tmd_model* m) {
     if (!m) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)m->mu, (void*)m->eta, (void*)m->w32, (void*)m->wbf, (void*)m->bias, (void*)m->wout,
-                    (void*)m->bout, (void*)m->params32, (void*)m->opt_m, (void*)m->opt_v})
+                    (void*)m->bout, (void*)m->params32, (void*)m->opt_m, (void*)m->opt_v, (void*)m->tab})
         if (p) (void)hipFree(p);
     delete m;
 }
@@ -463,6 +519,8 @@ tmd_status tmd_nlist_create(tmd_context* ctx, int64_t n_atoms, int32_t n_species
     alloc((void**)&nl->img, 4 * lst);
     alloc((void**)&nl->cnt, 4 * (size_t)n_species * n);
     alloc((void**)&nl->sp_idx, 4 * n);
+    alloc((void**)&nl->wperm, 4 * n);
+    alloc((void**)&nl->wcell, n);
     if (e != hipSuccess) {
         tmd_nlist_destroy(nl);
         return hip_fail(ctx, e, "neighbour list allocation");
@@ -475,7 +533,8 @@ void tmd_nlist_destroy(tmd_nlist* nl) {
     if (!nl) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)nl->perm, (void*)nl->shift, (void*)nl->xs, (void*)nl->sp, (void*)nl->nbr, (void*)nl->img,
-                    (void*)nl->cnt, (void*)nl->sp_idx, (void*)nl->cellstart})
+                    (void*)nl->cnt, (void*)nl->sp_idx, (void*)nl->cellstart, (void*)nl->wperm, (void*)nl->wcell,
+                    (void*)nl->wbase})
         if (p) (void)hipFree(p);
     delete nl;
 }

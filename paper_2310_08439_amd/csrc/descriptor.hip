@@ -20,6 +20,11 @@
 // pass also stores P (K x D floats per atom and element) so that the adjoint
 // pass can form P' without a second neighbour sweep.
 // Per-pair force partials of the chunks are summed with lane shuffles.
+//
+// Radial functions: direct (Gaussian x cosine cutoff, exp2 recurrence on a
+// uniform grid) or, in the TAB instantiations, a cubic-Hermite table lookup
+// with the cutoff folded in (Sec. III.B's tabulated H and H'): per pair one
+// contiguous run of KC coefficient quadruples, no transcendental.
 #include "tmd_internal.h"
 #include "tensor_ops.h"
 
@@ -36,11 +41,17 @@ struct PathArgs {
     float rc2, half_inv_rc, pi_over_rc;
     int rec;
     float rec_a, rec_b, rec_c;
+    // radial table (TAB kernels): [(tab_n + 1)][K] cubic coefficients, spacing 1/tab_inv
+    const float4* tab;
+    float tab_inv;
+    int tab_n;
     double L[3];
     const double4* xs;
     const int32_t* nbr;
     const int32_t* img;
     const int32_t* cnt;
+    // work slot -> sorted atom (nullptr: identity); P is stored by work slot
+    const int32_t* wperm;
     const float* mu;
     const float* eta;
     // forward output / backward input
@@ -150,9 +161,30 @@ __device__ __forceinline__ void gaussians(const PathArgs& a, float R, const floa
     }
 }
 
+// Chunk k0 .. k0+KC-1 of the tabulated radial functions at distance R (the
+// caller has R < rc): interval j = floor(R / delta), clamped to the zero row
+// tab_n, local t = R / delta - j, h = c0 + t(c1 + t(c2 + t c3)) and, with DH,
+// h' = (c1 + t(2 c2 + 3 t c3)) / delta.  The KC coefficient quadruples of a
+// thread are one contiguous 16*KC-byte run of the table.
+template <int KC, bool DH>
+__device__ __forceinline__ void tabulated(const PathArgs& a, float R, int k0, float (&h)[KC], float (&dh)[KC]) {
+    const float x = R * a.tab_inv;
+    const float jf = fminf(floorf(x), (float)a.tab_n);
+    const float t = x - jf;
+    const float4* row = a.tab + (int64_t)jf * a.K + k0;
+    float4 c[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) c[kk] = row[kk];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        h[kk] = fmaf(t, fmaf(t, fmaf(t, c[kk].w, c[kk].z), c[kk].y), c[kk].x);
+        if (DH) dh[kk] = fmaf(t, fmaf(3.0f * t, c[kk].w, 2.0f * c[kk].z), c[kk].y) * a.tab_inv;
+    }
+}
+
 // P tile of one species for this thread's radial chunk.
-template <int KC, int M>
-__device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& xi, int64_t p, int b,
+template <int KC, int M, bool TAB>
+__device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& xi, int64_t p, int b, int k0,
                                              const float* mu, const float* nef, float (&P)[KC][Moments<M>::D]) {
     constexpr int D = Moments<M>::D;
 #pragma unroll
@@ -171,15 +203,20 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& x
         const float rinv = __builtin_amdgcn_rsqf(pr.r2);
         const float R = pr.r2 * rinv;
         const float ux = pr.dx * rinv, uy = pr.dy * rinv, uz = pr.dz * rinv;
-        const float fc = 0.5f * __builtin_amdgcn_cosf(R * a.half_inv_rc) + 0.5f;
-        float Mv[D], ev[KC];
+        float Mv[D], hv[KC];
         monomials<M>(ux, uy, uz, Mv);
-        gaussians<KC>(a, R, mu, nef, ev);
+        if (TAB) {
+            tabulated<KC, false>(a, R, k0, hv, hv);
+        } else {
+            const float fc = 0.5f * __builtin_amdgcn_cosf(R * a.half_inv_rc) + 0.5f;
+            gaussians<KC>(a, R, mu, nef, hv);
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) hv[kk] *= fc;
+        }
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
-            const float h = ev[kk] * fc;
 #pragma unroll
-            for (int d = 0; d < D; ++d) P[kk][d] = fmaf(h, Mv[d], P[kk][d]);
+            for (int d = 0; d < D; ++d) P[kk][d] = fmaf(hv[kk], Mv[d], P[kk][d]);
         }
       }
     }
@@ -197,15 +234,16 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
     return l < nblocks ? l : -1;
 }
 
-template <int KC, int M>
+template <int KC, int M, bool TAB>
 __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D;
     const int64_t lb = xcd_block(nblocks);
     if (lb < 0) return;
     const int64_t t = lb * blockDim.x + threadIdx.x;
-    const int64_t p = t >> a.nch_log2;
+    const int64_t w = t >> a.nch_log2;  // work slot
     const int ch = (int)(t & ((1 << a.nch_log2) - 1));
-    if (p >= a.n) return;
+    if (w >= a.n) return;
+    const int64_t p = a.wperm ? a.wperm[w] : w;
     float mu[KC], nef[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
@@ -215,8 +253,8 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
     const double4 xi = a.xs[p];
     for (int b = 0; b < a.S; ++b) {
         float P[KC][D];
-        accumulate_P<KC, M>(a, xi, p, b, mu, nef, P);
-        if (a.Pbuf) store_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + p, a.n, P);
+        accumulate_P<KC, M, TAB>(a, xi, p, b, ch * KC, mu, nef, P);
+        if (a.Pbuf) store_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
         float* Gp = a.G + p * a.F + (b * a.K + ch * KC) * (M + 1);
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
@@ -237,9 +275,9 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
 // chunk-0 lane hands each pair's g to sink(q, code, gx, gy, gz) (code = the
 // pair's stencil-offset code), accumulates the
 // atom's own force sum in Fo and the virial in W6.
-template <int KC, int M, class Sink>
-__device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int ch, int nch, float (&W6)[6],
-                                             float (&Fo)[3], Sink&& sink) {
+template <int KC, int M, bool TAB, class Sink>
+__device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64_t w, int ch, int nch,
+                                             float (&W6)[6], float (&Fo)[3], Sink&& sink) {
     constexpr int D = Moments<M>::D;
     float mu[KC], nef[KC], m2eta[KC];
 #pragma unroll
@@ -251,7 +289,7 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int c
     const double4 xi = a.xs[p];
     for (int b = 0; b < a.S; ++b) {
         float P[KC][D];
-        load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + p, a.n, P);
+        load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
         // P' = 2 T sigma' P in place (sigma' = dE/dS from dE/dG).
         const float* dGp = a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1);
 #pragma unroll
@@ -282,22 +320,30 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int c
                 const float rinv = __builtin_amdgcn_rsqf(pr.r2);
                 const float R = pr.r2 * rinv;
                 const float ux = pr.dx * rinv, uy = pr.dy * rinv, uz = pr.dz * rinv;
-                const float ang = R * a.half_inv_rc;
-                const float fc = 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f;
-                const float dfc = -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang);
                 float Mv[D];
                 monomials<M>(ux, uy, uz, Mv);
                 float V[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) V[d] = 0.0f;
-                float s1 = 0.0f, ev[KC];
-                gaussians<KC>(a, R, mu, nef, ev);
+                float s1 = 0.0f, hv[KC], dhv[KC];
+                if (TAB) {
+                    tabulated<KC, true>(a, R, ch * KC, hv, dhv);
+                } else {
+                    const float ang = R * a.half_inv_rc;
+                    const float fc = 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f;
+                    const float dfc = -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang);
+                    gaussians<KC>(a, R, mu, nef, hv);
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) {
+                        const float e = hv[kk];
+                        hv[kk] = e * fc;
+                        dhv[kk] = e * fmaf(m2eta[kk] * (R - mu[kk]), fc, dfc);
+                    }
+                }
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
-                    const float tt = R - mu[kk];
-                    const float e = ev[kk];
-                    const float h = e * fc;
-                    const float dh = e * fmaf(m2eta[kk] * tt, fc, dfc);
+                    const float h = hv[kk];
+                    const float dh = dhv[kk];
                     float U = 0.0f;
 #pragma unroll
                     for (int d = 0; d < D; ++d) {
@@ -352,17 +398,18 @@ __device__ __forceinline__ void block_virial(const float (&W6)[6], double (*red)
 
 // Adjoint with the force scatter done by device-scope atomics: used only when
 // the stencil is wider than 3x3x3 (a box edge shorter than two list cutoffs).
-template <int KC, int M>
+template <int KC, int M, bool TAB>
 __global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, float* F) {
     __shared__ double red[6][kBlock / 64];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = t >> a.nch_log2;
+    const int64_t w = t >> a.nch_log2;
     const int nch = 1 << a.nch_log2;
     const int ch = (int)(t & (nch - 1));
     float W6[6] = {0, 0, 0, 0, 0, 0};
-    if (p < a.n) {
+    if (w < a.n) {
+        const int64_t p = a.wperm ? a.wperm[w] : w;
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M>(a, p, ch, nch, W6, Fo, [&](int q, int, float gx, float gy, float gz) {
+        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, [&](int q, int, float gx, float gy, float gz) {
             unsafeAtomicAdd(&F[3 * (int64_t)q + 0], -gx);
             unsafeAtomicAdd(&F[3 * (int64_t)q + 1], -gy);
             unsafeAtomicAdd(&F[3 * (int64_t)q + 2], -gz);
@@ -383,6 +430,9 @@ struct BlockGeom {
     int hmax;    // capacity of the LDS force accumulators (atoms)
     const int32_t* cellstart;
     float* F;
+    const int32_t* wbase;  // [blocks + 1] first work slot of each block
+    const int32_t* wperm;  // work slot -> sorted atom
+    const uint8_t* wcell;  // work slot -> cell inside its block
 };
 
 constexpr int kMaxHaloCells = 216;    // (4 + 2)^3
@@ -416,11 +466,10 @@ __device__ __forceinline__ void scan256(int v, int32_t* out, int32_t* wtmp) {
 // atomics, located through the stencil offset each list entry recorded; the
 // block then adds its accumulators to F with coalesced device atomics, one
 // range per halo cell.
-template <int KC, int M>
+template <int KC, int M, bool TAB>
 __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom bg) {
     extern __shared__ float sF[];  // [3][hmax]
     __shared__ int32_t h_base[257], h_first[kMaxHaloCells];
-    __shared__ int32_t i_base[257], i_first[kMaxBlockCells];
     __shared__ int32_t wtmp[kBlock / 64];
     __shared__ double red[6][kBlock / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -428,8 +477,8 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
     const int bx = blk % bg.nb[0], by = (blk / bg.nb[0]) % bg.nb[1], bz = blk / (bg.nb[0] * bg.nb[1]);
     const int x0 = bx * bg.B[0], y0 = by * bg.B[1], z0 = bz * bg.B[2];
     const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
-    const int nh = HX * HY * HZ, nI = bg.B[0] * bg.B[1] * bg.B[2];
-    int hcount = 0, icount = 0;
+    const int nh = HX * HY * HZ;
+    int hcount = 0;
     if (t < nh) {
         const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
         const int gc = (wrap_cell(z0 - 1 + hz, bg.nc[2]) * bg.nc[1] + wrap_cell(y0 - 1 + hy, bg.nc[1])) * bg.nc[0] +
@@ -437,17 +486,7 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         h_first[t] = bg.cellstart[gc];
         hcount = bg.cellstart[gc + 1] - h_first[t];
     }
-    if (t < nI) {
-        const int cx = x0 + t % bg.B[0], cy = y0 + (t / bg.B[0]) % bg.B[1], cz = z0 + t / (bg.B[0] * bg.B[1]);
-        i_first[t] = 0;
-        if (cx < bg.nc[0] && cy < bg.nc[1] && cz < bg.nc[2]) {
-            const int gc = (cz * bg.nc[1] + cy) * bg.nc[0] + cx;
-            i_first[t] = bg.cellstart[gc];
-            icount = bg.cellstart[gc + 1] - i_first[t];
-        }
-    }
     scan256(hcount, h_base, wtmp);
-    scan256(icount, i_base, wtmp);
     const int htot = h_base[nh];
     for (int i = t; i < htot; i += kBlock) {
         sF[i] = 0.0f;
@@ -455,18 +494,20 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         sF[2 * bg.hmax + i] = 0.0f;
     }
     __syncthreads();
+    // the block's atoms are work slots wbase[blk] .. wbase[blk+1], ordered by row length
     const int nch = 1 << a.nch_log2;
-    const int items = i_base[nI] << a.nch_log2;
+    const int64_t w0 = bg.wbase[blk];
+    const int items = (int)(bg.wbase[blk + 1] - w0) << a.nch_log2;
     float W6[6] = {0, 0, 0, 0, 0, 0};
     for (int item = t; item < ((items + kBlock - 1) / kBlock) * kBlock; item += kBlock) {
         if (item >= items) continue;
-        const int la = item >> a.nch_log2, ch = item & (nch - 1);
-        int ic = 0;
-        while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
-        const int64_t p = i_first[ic] + (la - i_base[ic]);
+        const int ch = item & (nch - 1);
+        const int64_t w = w0 + (item >> a.nch_log2);
+        const int64_t p = bg.wperm[w];
+        const int ic = bg.wcell[w];
         const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M>(a, p, ch, nch, W6, Fo, [&](int q, int o, float gx, float gy, float gz) {
+        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, [&](int q, int o, float gx, float gy, float gz) {
             const int hq = ((iz + o / 9 - 1) * HY + (iy + (o / 3) % 3 - 1)) * HX + (ix + o % 3 - 1);
             const int idx = h_base[hq] + (q - h_first[hq]);
             atomicAdd(&sF[idx], -gx);
@@ -495,57 +536,165 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
     block_virial(W6, red, a.vir + (int64_t)blockIdx.x * 6);
 }
 
+// ---- work order ----------------------------------------------------------
+//
+// Rows of one wave run in lockstep, so a wave costs the longest of its rows.
+// In a two-species alloy the per-species row lengths of neighbouring atoms
+// vary by several entries (the total hardly does), so each cell block's atoms
+// are put in descending order of (species-0 row, species-1 row) length; the
+// descriptor and adjoint kernels walk atoms in this order (and P is stored in
+// it, which keeps its loads and stores coalesced).
+
+struct WorkGeom {
+    int nc[3], B[3], nb[3];
+    int64_t n;
+    int S;
+    const int32_t* cellstart;
+    const int32_t* cnt;
+};
+
+__device__ __forceinline__ void block_origin(const WorkGeom& g, int64_t blk, int& x0, int& y0, int& z0) {
+    const int bx = (int)(blk % g.nb[0]), by = (int)((blk / g.nb[0]) % g.nb[1]), bz = (int)(blk / (g.nb[0] * g.nb[1]));
+    x0 = bx * g.B[0];
+    y0 = by * g.B[1];
+    z0 = bz * g.B[2];
+}
+
+// Global cell index of interior cell ic of the block at (x0, y0, z0), or -1
+// past the grid edge (the last block along an axis may be partial).
+__device__ __forceinline__ int block_cell(const WorkGeom& g, int x0, int y0, int z0, int ic) {
+    const int cx = x0 + ic % g.B[0], cy = y0 + (ic / g.B[0]) % g.B[1], cz = z0 + ic / (g.B[0] * g.B[1]);
+    if (cx >= g.nc[0] || cy >= g.nc[1] || cz >= g.nc[2]) return -1;
+    return (cz * g.nc[1] + cy) * g.nc[0] + cx;
+}
+
+__global__ void k_wo_count(WorkGeom g, int64_t nblocks, int32_t* __restrict__ count) {
+    const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blk >= nblocks) return;
+    int x0, y0, z0;
+    block_origin(g, blk, x0, y0, z0);
+    int c = 0;
+    for (int ic = 0; ic < g.B[0] * g.B[1] * g.B[2]; ++ic) {
+        const int gc = block_cell(g, x0, y0, z0, ic);
+        if (gc >= 0) c += g.cellstart[gc + 1] - g.cellstart[gc];
+    }
+    count[blk] = c;
+}
+
+// Exclusive scan of the block counts by one workgroup; base[nblocks] = n.
+__global__ void __launch_bounds__(256) k_wo_scan(int64_t nblocks, const int32_t* __restrict__ count,
+                                                 int32_t* __restrict__ base) {
+    __shared__ int32_t out[257], wtmp[kBlock / 64];
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += kBlock) {
+        const int64_t q = b0 + threadIdx.x;
+        scan256(q < nblocks ? count[q] : 0, out, wtmp);
+        if (q < nblocks) base[q] = carry + out[threadIdx.x];
+        carry += out[256];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) base[nblocks] = carry;
+}
+
+// One workgroup per block: rank every atom of the block by descending key
+// (ties by cell order, so the order is deterministic) with an all-pairs count
+// over the keys held in LDS, then scatter to the block's slots.
+__global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, const int32_t* __restrict__ base,
+                                                  int32_t* __restrict__ wperm, uint8_t* __restrict__ wcell) {
+    extern __shared__ int32_t skey[];  // [atoms of the block]
+    __shared__ int32_t i_base[257], i_first[kMaxBlockCells], wtmp[kBlock / 64];
+    const int t = threadIdx.x;
+    const int64_t blk = blockIdx.x;
+    int x0, y0, z0;
+    block_origin(g, blk, x0, y0, z0);
+    const int nI = g.B[0] * g.B[1] * g.B[2];
+    int icount = 0;
+    if (t < nI) {
+        const int gc = block_cell(g, x0, y0, z0, t);
+        i_first[t] = gc >= 0 ? g.cellstart[gc] : 0;
+        icount = gc >= 0 ? g.cellstart[gc + 1] - i_first[t] : 0;
+    }
+    scan256(icount, i_base, wtmp);
+    const int m = i_base[nI];
+    for (int la = t; la < m; la += kBlock) {
+        int ic = 0;
+        while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
+        const int64_t p = i_first[ic] + (la - i_base[ic]);
+        const int n0 = g.cnt[p];
+        const int n1 = g.S > 1 ? g.cnt[g.n + p] : 0;
+        skey[la] = (n0 << 13) | n1;  // row lengths < 4096
+    }
+    __syncthreads();
+    const int64_t w0 = base[blk];
+    for (int la = t; la < m; la += kBlock) {
+        const int key = skey[la];
+        int r = 0;
+        for (int j = 0; j < m; ++j) {
+            const int kj = skey[j];
+            r += (kj > key || (kj == key && j < la)) ? 1 : 0;
+        }
+        int ic = 0;
+        while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
+        wperm[w0 + r] = (int32_t)(i_first[ic] + (la - i_base[ic]));
+        wcell[w0 + r] = (uint8_t)ic;
+    }
+}
+
 using PathFn = void (*)(PathArgs, int64_t);
 using AtomicFn = void (*)(PathArgs, float*);
 using BlockedFn = void (*)(PathArgs, BlockGeom);
 
-template <int KC>
+template <int KC, bool TAB>
 PathFn pick_desc(int M) {
     switch (M) {
-        case 0: return k_descriptor<KC, 0>;
-        case 1: return k_descriptor<KC, 1>;
-        case 2: return k_descriptor<KC, 2>;
-        default: return k_descriptor<KC, 3>;
+        case 0: return k_descriptor<KC, 0, TAB>;
+        case 1: return k_descriptor<KC, 1, TAB>;
+        case 2: return k_descriptor<KC, 2, TAB>;
+        default: return k_descriptor<KC, 3, TAB>;
     }
 }
-template <int KC>
+template <int KC, bool TAB>
 AtomicFn pick_atomic(int M) {
     switch (M) {
-        case 0: return k_adjoint_atomic<KC, 0>;
-        case 1: return k_adjoint_atomic<KC, 1>;
-        case 2: return k_adjoint_atomic<KC, 2>;
-        default: return k_adjoint_atomic<KC, 3>;
+        case 0: return k_adjoint_atomic<KC, 0, TAB>;
+        case 1: return k_adjoint_atomic<KC, 1, TAB>;
+        case 2: return k_adjoint_atomic<KC, 2, TAB>;
+        default: return k_adjoint_atomic<KC, 3, TAB>;
     }
 }
-template <int KC>
+template <int KC, bool TAB>
 BlockedFn pick_blocked(int M) {
     switch (M) {
-        case 0: return k_adjoint_blocked<KC, 0>;
-        case 1: return k_adjoint_blocked<KC, 1>;
-        case 2: return k_adjoint_blocked<KC, 2>;
-        default: return k_adjoint_blocked<KC, 3>;
+        case 0: return k_adjoint_blocked<KC, 0, TAB>;
+        case 1: return k_adjoint_blocked<KC, 1, TAB>;
+        case 2: return k_adjoint_blocked<KC, 2, TAB>;
+        default: return k_adjoint_blocked<KC, 3, TAB>;
     }
 }
 
+template <bool TAB>
 PathFn select_desc(int kc, int M) {
     switch (kc) {
-        case 4: return pick_desc<4>(M);
-        case 6: return pick_desc<6>(M);
-        default: return pick_desc<8>(M);
+        case 3: return pick_desc<3, TAB>(M);
+        case 4: return pick_desc<4, TAB>(M);
+        case 6: return pick_desc<6, TAB>(M);
+        default: return pick_desc<8, TAB>(M);
     }
 }
+template <bool TAB>
 AtomicFn select_atomic(int kc, int M) {
     switch (kc) {
-        case 4: return pick_atomic<4>(M);
-        case 6: return pick_atomic<6>(M);
-        default: return pick_atomic<8>(M);
+        case 4: return pick_atomic<4, TAB>(M);
+        case 6: return pick_atomic<6, TAB>(M);
+        default: return pick_atomic<8, TAB>(M);
     }
 }
+template <bool TAB>
 BlockedFn select_blocked(int kc, int M) {
     switch (kc) {
-        case 4: return pick_blocked<4>(M);
-        case 6: return pick_blocked<6>(M);
-        default: return pick_blocked<8>(M);
+        case 4: return pick_blocked<4, TAB>(M);
+        case 6: return pick_blocked<6, TAB>(M);
+        default: return pick_blocked<8, TAB>(M);
     }
 }
 
@@ -567,11 +716,15 @@ PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
     a.rec_a = m->rec_a;
     a.rec_b = m->rec_b;
     a.rec_c = m->rec_c;
+    a.tab = m->tab;
+    a.tab_inv = m->tab ? (float)(1.0 / m->tab_delta) : 0.0f;
+    a.tab_n = m->tab_n;
     for (int q = 0; q < 3; ++q) a.L[q] = nl->box[q];
     a.xs = nl->xs;
     a.nbr = nl->nbr;
     a.img = nl->img;
     a.cnt = nl->cnt;
+    a.wperm = nl->wo_valid ? nl->wperm : nullptr;
     a.mu = m->mu;
     a.eta = m->eta;
     return a;
@@ -580,6 +733,16 @@ PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
 unsigned path_grid(const tmd_model* m, const tmd_nlist* nl) {
     const int64_t threads = nl->n * (m->K / m->kc);
     return (unsigned)((threads + kBlock - 1) / kBlock);
+}
+
+// Radial functions per descriptor thread.  P is stored per radial function,
+// so the descriptor's chunking need not match the adjoint's (m->kc).
+int desc_kc(const tmd_model* m) { return m->kc; }
+
+int log2_int(int v) {
+    int lg = 0;
+    while ((1 << lg) < v) ++lg;
+    return lg;
 }
 
 constexpr size_t kMaxDynLds = 56 * 1024;
@@ -610,6 +773,50 @@ bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
 
 }  // namespace
 
+tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl) {
+    nl->wo_valid = false;
+    BlockGeom bg{};
+    if (!nl->narrow || !choose_blocks(nl, &bg)) return TMD_OK;  // atomic adjoint, identity order
+    const int64_t nblocks = (int64_t)bg.nb[0] * bg.nb[1] * bg.nb[2];
+    if (nl->wbase_cap < nblocks + 1) {
+        if (nl->wbase) TMD_HIP(ctx, hipFree(nl->wbase));
+        nl->wbase = nullptr;
+        nl->wbase_cap = 0;
+        TMD_HIP(ctx, hipMalloc((void**)&nl->wbase, sizeof(int32_t) * (nblocks + 1)));
+        nl->wbase_cap = nblocks + 1;
+    }
+    hipError_t e = hipSuccess;
+    int32_t* count = (int32_t*)ctx->ws.get("wo.count", sizeof(int32_t) * nblocks, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "work order workspace");
+    WorkGeom g{};
+    for (int d = 0; d < 3; ++d) {
+        g.nc[d] = bg.nc[d];
+        g.B[d] = bg.B[d];
+        g.nb[d] = bg.nb[d];
+    }
+    g.n = nl->n;
+    g.S = nl->S;
+    g.cellstart = nl->cellstart;
+    g.cnt = nl->cnt;
+    // keys of a block's atoms in LDS: at most (cells per block) x (densest cell)
+    const size_t lds = sizeof(int32_t) * (size_t)bg.B[0] * bg.B[1] * bg.B[2] * std::max(1, nl->max_occ);
+    if (lds > 64 * 1024) return TMD_OK;  // a pathological density: keep the atomic adjoint
+    {
+        ProfScope ps_(ctx, "work_order");
+        k_wo_count<<<(unsigned)((nblocks + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(g, nblocks, count);
+        k_wo_scan<<<1, kBlock, 0, ctx->stream>>>(nblocks, count, nl->wbase);
+        k_wo_order<<<(unsigned)nblocks, kBlock, lds, ctx->stream>>>(g, nl->wbase, nl->wperm, nl->wcell);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    for (int d = 0; d < 3; ++d) {
+        nl->wo_B[d] = bg.B[d];
+        nl->wo_nb[d] = bg.nb[d];
+    }
+    nl->wo_hmax = bg.hmax;
+    nl->wo_valid = true;
+    return TMD_OK;
+}
+
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl) {
     return std::max<int64_t>((int64_t)path_grid(m, nl), nl->ncells);
 }
@@ -618,8 +825,10 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     PathArgs a = make_args(m, nl);
     a.G = G;
     a.Pbuf = Pbuf;
-    auto fn = select_desc(m->kc, m->M);
-    const int64_t nblocks = path_grid(m, nl);
+    const int kcd = desc_kc(m);
+    a.nch_log2 = log2_int(m->K / kcd);
+    auto fn = m->tab ? select_desc<true>(kcd, m->M) : select_desc<false>(kcd, m->M);
+    const int64_t nblocks = (nl->n * (m->K / kcd) + kBlock - 1) / kBlock;
     {
         ProfScope ps_(ctx, "descriptor");
         fn<<<(unsigned)((nblocks + 7) / 8 * 8), kBlock, 0, ctx->stream>>>(a, nblocks);
@@ -635,12 +844,21 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
     a.Pbuf = Pbuf;
     a.vir = vir_partials;
     TMD_HIP(ctx, hipMemsetAsync(Fsorted, 0, sizeof(float) * 3 * nl->n, ctx->stream));
-    BlockGeom bg{};
-    if (nl->narrow && choose_blocks(nl, &bg)) {
+    if (nl->wo_valid) {
+        BlockGeom bg{};
+        for (int d = 0; d < 3; ++d) {
+            bg.nc[d] = nl->nc[d];
+            bg.B[d] = nl->wo_B[d];
+            bg.nb[d] = nl->wo_nb[d];
+        }
+        bg.hmax = nl->wo_hmax;
         bg.cellstart = nl->cellstart;
         bg.F = Fsorted;
+        bg.wbase = nl->wbase;
+        bg.wperm = nl->wperm;
+        bg.wcell = nl->wcell;
         const unsigned grid = (unsigned)bg.nb[0] * bg.nb[1] * bg.nb[2];
-        auto fn = select_blocked(m->kc, m->M);
+        auto fn = m->tab ? select_blocked<true>(m->kc, m->M) : select_blocked<false>(m->kc, m->M);
         {
             ProfScope ps_(ctx, "adjoint");
             fn<<<grid, kBlock, sizeof(float) * 3 * (size_t)bg.hmax, ctx->stream>>>(a, bg);
@@ -648,7 +866,7 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
         *nvir_out = (int)grid;
     } else {
         const unsigned grid = path_grid(m, nl);
-        auto fn = select_atomic(m->kc, m->M);
+        auto fn = m->tab ? select_atomic<true>(m->kc, m->M) : select_atomic<false>(m->kc, m->M);
         {
             ProfScope ps_(ctx, "adjoint");
             fn<<<grid, kBlock, 0, ctx->stream>>>(a, Fsorted);

@@ -647,7 +647,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         nl->reach[a] = g.reach[a];
     }
     nl->built = true;
-    return TMD_OK;
+    return launch_work_order(ctx, nl);
 }
 
 tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl) {

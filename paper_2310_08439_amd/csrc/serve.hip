@@ -105,7 +105,7 @@ int density_capacity(int64_t n, const double* box, double rlist, int S) {
 }
 
 size_t nlist_bytes(int64_t n, int S, int cap) {
-    return (size_t)n * 56 + (size_t)n * S * cap * 8 + (size_t)S * n * 4 + 4 * (size_t)(4 * n + 65);
+    return (size_t)n * 61 + (size_t)n * S * cap * 8 + (size_t)S * n * 4 + 8 * (size_t)(4 * n + 65);
 }
 
 // Build (or rebuild) sys's list on ctx, growing it on overflow.

@@ -91,6 +91,13 @@ struct tmd_model {
     // when no value of a chunk can underflow before the chunk's last one.
     bool rec = false;
     float rec_a = 0.0f, rec_b = 0.0f, rec_c = 0.0f;
+    std::vector<double> mu_h, eta_h;  // host FP64 copies (table construction)
+    // Tabulated radial functions (cubic Hermite on nodes tab_delta apart):
+    // tab [(tab_n + 1)][K] float4 = (c0, c1, c2, c3) of h_k = c0 + t(c1 + t(c2 + t c3))
+    // on interval j, t = R/delta - j; row tab_n is all zero (R >= rcut).
+    float4* tab = nullptr;
+    int tab_n = 0;
+    double tab_delta = 0.0;
     // Per species, per layer l = 0..L-1: forward W_l [H][in_pad] and transposed
     // W_l^T [in_pad][H] (in_pad = Fpad for l = 0, H otherwise), FP32 and BF16 copies.
     float* w32 = nullptr;
@@ -136,6 +143,18 @@ struct tmd_nlist {
     int64_t ncells = 0;
     int max_occ = 0;               // most atoms in one cell
     bool narrow = false;           // 3x3x3 stencil (every reach is 1)
+    // Work order of the descriptor and adjoint kernels, set by every build
+    // when the adjoint runs over cell blocks (wo_valid): blocks of wo_B cells
+    // in block-major order, each block's atoms by descending row length of
+    // species 0, then of species 1 (so that a wave's rows are alike);
+    // wperm[w] = sorted atom index of work slot w, wcell[w] = its cell inside
+    // the block, wbase[blk] = first slot of block blk.  P is stored by slot.
+    bool wo_valid = false;
+    int wo_B[3] = {1, 1, 1}, wo_nb[3] = {1, 1, 1}, wo_hmax = 0;
+    int32_t* wperm = nullptr;      // [nmax]
+    uint8_t* wcell = nullptr;      // [nmax]
+    int32_t* wbase = nullptr;      // [wbase_cap]
+    int64_t wbase_cap = 0;
 };
 
 namespace tmd {
@@ -213,6 +232,10 @@ tmd_status launch_kick(tmd_context* ctx, int64_t n, double* v, const float* F, c
                        double dt);
 tmd_status launch_kinetic(tmd_context* ctx, int64_t n, const double* v, const int32_t* sp, const double* mass,
                           double* part, double* out4);
+
+// Work order for the descriptor and adjoint (see tmd_nlist::wo_valid); called
+// at the end of every successful list build.
+tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl);
 
 // Upper bound on the virial partials the adjoint writes.
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl);

@@ -981,12 +981,13 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     if (m->S != b->S || m->K != b->K || m->M != b->M || m->rcut != b->rcut || m->kc != b->kc)
         return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "model descriptor shape differs from the batch's");
     {
-        std::vector<float> mu(m->K), eta(m->K);
-        TMD_HIP(ctx, hipMemcpy(mu.data(), m->mu, 4 * m->K, hipMemcpyDeviceToHost));
-        TMD_HIP(ctx, hipMemcpy(eta.data(), m->eta, 4 * m->K, hipMemcpyDeviceToHost));
+        std::vector<float> mu(m->mu_h.begin(), m->mu_h.end()), eta(m->eta_h.begin(), m->eta_h.end());
         if (mu != b->mu || eta != b->eta)
             return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "model radial functions differ from the batch's");
     }
+    if (m->tab)
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT,
+                    "training uses the exact radial functions: drop the table (tmd_model_tabulate(m, 0)) first");
     if (!(opts->lambda >= 0.0) || !(opts->lr >= 0.0) || !std::isfinite(opts->lr))
         return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "lambda and lr must be non-negative");
     if (opts->optimizer != TMD_OPT_ADAM && opts->optimizer != TMD_OPT_SGD)

@@ -40,6 +40,7 @@ EXPORTS = (
     "tmd_serve_fetch", "tmd_serve_release", "tmd_serve_read_system", "tmd_serve_memory", "tmd_serve_last_error",
     "tmd_serve_destroy",
     "tmd_md_create", "tmd_md_run", "tmd_md_read", "tmd_md_thermostat_state", "tmd_md_destroy",
+    "tmd_model_tabulate", "tmd_model_tab_spacing",
 )
 ENSEMBLE_NVE = 0
 ENSEMBLE_NVT_NOSE_HOOVER = 1
@@ -145,6 +146,9 @@ def load_library(path: str = LIB_PATH):
     L.tmd_model_n_features.restype = i32
     L.tmd_model_destroy.argtypes = [vp]
     L.tmd_model_destroy.restype = None
+    L.tmd_model_tabulate.argtypes = [vp, dbl]
+    L.tmd_model_tab_spacing.argtypes = [vp]
+    L.tmd_model_tab_spacing.restype = dbl
     L.tmd_nlist_create.argtypes = [vp, i64, i32, i32, P(vp)]
     L.tmd_nlist_destroy.argtypes = [vp]
     L.tmd_nlist_destroy.restype = None
@@ -294,6 +298,18 @@ class Model:
                   "tmd_model_create")
         self.h = h
         self.set_precision(precision)
+        if getattr(spec, "tab_dr", 0.0) > 0.0:
+            self.tabulate(spec.tab_dr)
+
+    def tabulate(self, dr: float) -> float:
+        """Interpolate the radial functions from a node table of spacing at
+        most dr (0: direct evaluation); returns the spacing in use."""
+        self.ctx.check(self.ctx.lib.tmd_model_tabulate(self.h, ctypes.c_double(dr)), "tmd_model_tabulate")
+        return self.tab_spacing
+
+    @property
+    def tab_spacing(self) -> float:
+        return float(self.ctx.lib.tmd_model_tab_spacing(self.h))
 
     @property
     def n_features(self) -> int:

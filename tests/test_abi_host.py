@@ -68,6 +68,8 @@ def test_null_argument_validation_without_device():
     assert L.tmd_batch_create(None, None, 1, None, None, None, None, None, None, 0, None) == 1
     assert L.tmd_batch_read(None, None, 0, None) == 1
     assert L.tmd_model_get_params(None, None) == 1
+    assert L.tmd_model_tabulate(None, 0.01) == 1
+    assert L.tmd_model_tab_spacing(None) == 0.0
     assert L.tmd_serve_create(None, None, None) == 1
     assert L.tmd_serve_submit(None, None, None) == 1
     assert L.tmd_serve_poll(None, 1, None) == 1
