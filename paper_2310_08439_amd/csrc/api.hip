@@ -236,6 +236,9 @@ tmd_status tmd_context_create(int device, void* hip_stream, tmd_context** out) {
     if (!ctx) return TMD_ERR_OUT_OF_MEMORY;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->num_cus = cus;
     if (hipHostMalloc((void**)&ctx->h_totals, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_flags, sizeof(int32_t) * 64, hipHostMallocDefault) != hipSuccess) {
         delete ctx;

@@ -82,14 +82,54 @@ struct IntVec<4> {
     __device__ static void split(const int4& v, int* o) { o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w; }
 };
 
+// Neighbour positions of list entries, in one of two places.  GlobalPos
+// reads the sorted FP64 positions from HBM and forms D = (x_q - x_i) + n L in
+// FP64.  LdsPos reads a workgroup's LDS copy of its cell block and one-cell
+// halo, held as FP32 offsets from each atom's own cell origin: the entry's
+// stencil code names the halo slot (slot = centre's slot + delta[code]; atom
+// q of slot h sits at hoff[h] + q) and the cell offset o, and
+// D = (x_q - x_i) + o w with w the cell edge.  Both hand D to the caller in
+// FP32 (the LDS form carries about 3e-7 A more rounding on |D| < 8 A).
+struct GlobalPos {
+    const double4* xs;
+    double L0, L1, L2;
+    double4 xi;
+    __device__ double4 fetch(int q, int32_t) const { return xs[q]; }
+    __device__ float3 disp(const double4& xj, int32_t im) const {
+        int nx, ny, nz;
+        unpack_img(im, nx, ny, nz);
+        return make_float3((float)((xj.x - xi.x) + (double)nx * L0), (float)((xj.y - xi.y) + (double)ny * L1),
+                           (float)((xj.z - xi.z) + (double)nz * L2));
+    }
+};
+struct LdsPos {
+    const float* sx;
+    const float* sy;
+    const float* sz;
+    const int32_t* hoff;
+    const int32_t* delta;
+    int hp;
+    float xi, yi, zi;  // centre atom, from its cell origin
+    float wx, wy, wz;  // cell edges
+    __device__ float4 fetch(int q, int32_t im) const {
+        const int i = hoff[hp + delta[img_ocode(im)]] + q;
+        return make_float4(sx[i], sy[i], sz[i], 0.0f);
+    }
+    __device__ float3 disp(const float4& xj, int32_t im) const {
+        const int o = img_ocode(im);
+        return make_float3((xj.x - xi) + (float)(o % 3 - 1) * wx, (xj.y - yi) + (float)((o / 3) % 3 - 1) * wy,
+                           (xj.z - zi) + (float)(o / 9 - 1) * wz);
+    }
+};
+
 // NB consecutive entries c0 .. c0+NB-1 (c0 a multiple of NB) of a list row of
 // nb (>= 1) entries starting at `row` (16-byte aligned): one vector load each
 // for indices and image words, then all position loads, so the loads overlap.
 // Entries past the row end are replaced by the last valid entry (never a
 // stale slot) and marked with r2 = +inf so that every consumer skips them.
-template <int NB>
-__device__ __forceinline__ void load_pairs(const PathArgs& a, const double4& xi, int64_t row, int c0, int nb,
-                                           Pair (&pr)[NB]) {
+template <int NB, class Pos>
+__device__ __forceinline__ void load_pairs(const PathArgs& a, int64_t row, int c0, int nb, Pair (&pr)[NB],
+                                           const Pos& pos) {
     int q[NB], im[NB];
     IntVec<NB>::split(*reinterpret_cast<const typename IntVec<NB>::T*>(a.nbr + row + c0), q);
     IntVec<NB>::split(*reinterpret_cast<const typename IntVec<NB>::T*>(a.img + row + c0), im);
@@ -99,16 +139,15 @@ __device__ __forceinline__ void load_pairs(const PathArgs& a, const double4& xi,
             q[j] = q[0];
             im[j] = im[0];
         }
-    double4 xj[NB];
+    decltype(pos.fetch(0, 0)) xj[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) xj[j] = a.xs[q[j]];
+    for (int j = 0; j < NB; ++j) xj[j] = pos.fetch(q[j], im[j]);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-        int nx, ny, nz;
-        unpack_img(im[j], nx, ny, nz);
-        pr[j].dx = (float)((xj[j].x - xi.x) + (double)nx * a.L[0]);
-        pr[j].dy = (float)((xj[j].y - xi.y) + (double)ny * a.L[1]);
-        pr[j].dz = (float)((xj[j].z - xi.z) + (double)nz * a.L[2]);
+        const float3 d = pos.disp(xj[j], im[j]);
+        pr[j].dx = d.x;
+        pr[j].dy = d.y;
+        pr[j].dz = d.z;
         pr[j].r2 = (c0 + j < nb) ? pr[j].dx * pr[j].dx + pr[j].dy * pr[j].dy + pr[j].dz * pr[j].dz
                                  : __builtin_inff();
         pr[j].q = q[j];
@@ -183,9 +222,9 @@ __device__ __forceinline__ void tabulated(const PathArgs& a, float R, int k0, fl
 }
 
 // P tile of one species for this thread's radial chunk.
-template <int KC, int M, bool TAB>
-__device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& xi, int64_t p, int b, int k0,
-                                             const float* mu, const float* nef, float (&P)[KC][Moments<M>::D]) {
+template <int KC, int M, bool TAB, class Pos>
+__device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b, int k0, const float* mu,
+                                             const float* nef, float (&P)[KC][Moments<M>::D], const Pos& pos) {
     constexpr int D = Moments<M>::D;
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
@@ -195,7 +234,7 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, const double4& x
     const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
     for (int c0 = 0; c0 < nb; c0 += kBatchFwd) {
       Pair prs[kBatchFwd];
-      load_pairs<kBatchFwd>(a, xi, base, c0, nb, prs);
+      load_pairs<kBatchFwd>(a, base, c0, nb, prs, pos);
 #pragma unroll
       for (int j = 0; j < kBatchFwd; ++j) {
         const Pair& pr = prs[j];
@@ -250,10 +289,10 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
         mu[kk] = a.mu[ch * KC + kk];
         nef[kk] = -a.eta[ch * KC + kk] * kLog2e;
     }
-    const double4 xi = a.xs[p];
+    const GlobalPos pos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]};
     for (int b = 0; b < a.S; ++b) {
         float P[KC][D];
-        accumulate_P<KC, M, TAB>(a, xi, p, b, ch * KC, mu, nef, P);
+        accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, P, pos);
         if (a.Pbuf) store_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
         float* Gp = a.G + p * a.F + (b * a.K + ch * KC) * (M + 1);
 #pragma unroll
@@ -275,9 +314,9 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
 // chunk-0 lane hands each pair's g to sink(q, code, gx, gy, gz) (code = the
 // pair's stencil-offset code), accumulates the
 // atom's own force sum in Fo and the virial in W6.
-template <int KC, int M, bool TAB, class Sink>
+template <int KC, int M, bool TAB, class Pos, class Sink>
 __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64_t w, int ch, int nch,
-                                             float (&W6)[6], float (&Fo)[3], Sink&& sink) {
+                                             float (&W6)[6], float (&Fo)[3], const Pos& pos, Sink&& sink) {
     constexpr int D = Moments<M>::D;
     float mu[KC], nef[KC], m2eta[KC];
 #pragma unroll
@@ -286,7 +325,6 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
         nef[kk] = -a.eta[ch * KC + kk] * kLog2e;
         m2eta[kk] = -2.0f * a.eta[ch * KC + kk];
     }
-    const double4 xi = a.xs[p];
     for (int b = 0; b < a.S; ++b) {
         float P[KC][D];
         load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
@@ -312,7 +350,7 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
         const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
         for (int c0 = 0; c0 < nb; c0 += kBatchAdj) {
             Pair prs[kBatchAdj];
-            load_pairs<kBatchAdj>(a, xi, base, c0, nb, prs);
+            load_pairs<kBatchAdj>(a, base, c0, nb, prs, pos);
 #pragma unroll
             for (int j = 0; j < kBatchAdj; ++j) {
                 const Pair& pr = prs[j];
@@ -409,7 +447,8 @@ __global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, float* F) {
     if (w < a.n) {
         const int64_t p = a.wperm ? a.wperm[w] : w;
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, [&](int q, int, float gx, float gy, float gz) {
+        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, GlobalPos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]},
+                                 [&](int q, int, float gx, float gy, float gz) {
             unsafeAtomicAdd(&F[3 * (int64_t)q + 0], -gx);
             unsafeAtomicAdd(&F[3 * (int64_t)q + 1], -gy);
             unsafeAtomicAdd(&F[3 * (int64_t)q + 2], -gz);
@@ -460,22 +499,18 @@ __device__ __forceinline__ void scan256(int v, int32_t* out, int32_t* wtmp) {
     __syncthreads();
 }
 
-// Adjoint over one block of B0 x B1 x B2 cells (ScatterSum, Sec. III.A, done
-// in two levels like the paper's partial-then-global reduction): the forces on
-// the block's atoms and on its one-cell halo accumulate in LDS with LDS
-// atomics, located through the stencil offset each list entry recorded; the
-// block then adds its accumulators to F with coalesced device atomics, one
-// range per halo cell.
-template <int KC, int M, bool TAB>
-__global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom bg) {
-    extern __shared__ float sF[];  // [3][hmax]
-    __shared__ int32_t h_base[257], h_first[kMaxHaloCells];
-    __shared__ int32_t wtmp[kBlock / 64];
-    __shared__ double red[6][kBlock / 64];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int blk = blockIdx.x;
-    const int bx = blk % bg.nb[0], by = (blk / bg.nb[0]) % bg.nb[1], bz = blk / (bg.nb[0] * bg.nb[1]);
-    const int x0 = bx * bg.B[0], y0 = by * bg.B[1], z0 = bz * bg.B[2];
+// Halo slots of block lb: h_first[h] = first sorted atom of slot h's cell,
+// h_base = exclusive scan of the slot counts (h_base[nh] = halo atoms),
+// hoff[h] = h_base[h] - h_first[h]; sdelta[o] = slot offset of stencil code o.
+// Ends with a barrier.
+__device__ __forceinline__ void halo_slots(const BlockGeom& bg, int64_t lb, int32_t* h_first, int32_t* h_base,
+                                           int32_t* hoff, int32_t* sdelta, int32_t* wtmp, int& x0, int& y0,
+                                           int& z0) {
+    const int t = threadIdx.x;
+    const int bx = (int)(lb % bg.nb[0]), by = (int)((lb / bg.nb[0]) % bg.nb[1]), bz = (int)(lb / (bg.nb[0] * bg.nb[1]));
+    x0 = bx * bg.B[0];
+    y0 = by * bg.B[1];
+    z0 = bz * bg.B[2];
     const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
     const int nh = HX * HY * HZ;
     int hcount = 0;
@@ -486,14 +521,69 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         h_first[t] = bg.cellstart[gc];
         hcount = bg.cellstart[gc + 1] - h_first[t];
     }
+    if (t < 27) sdelta[t] = ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * HX + (t % 3 - 1);
     scan256(hcount, h_base, wtmp);
+    if (t < nh) hoff[t] = h_base[t] - h_first[t];
+    __syncthreads();
+}
+
+// Positions of the halo atoms into sx, sy, sz (slot order) as FP32 offsets
+// from the origin of the atom's own cell (cell c spans [c w, (c+1) w)).
+// Ends with a barrier.
+__device__ __forceinline__ void halo_positions(const BlockGeom& bg, const PathArgs& a, int x0, int y0, int z0,
+                                               const int32_t* h_first, const int32_t* h_base, float* sx, float* sy,
+                                               float* sz) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
+    for (int hc = wv; hc < HX * HY * HZ; hc += kBlock / 64) {
+        const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+        const double ox = (double)wrap_cell(x0 - 1 + hx, bg.nc[0]) * (a.L[0] / bg.nc[0]);
+        const double oy = (double)wrap_cell(y0 - 1 + hy, bg.nc[1]) * (a.L[1] / bg.nc[1]);
+        const double oz = (double)wrap_cell(z0 - 1 + hz, bg.nc[2]) * (a.L[2] / bg.nc[2]);
+        const int lo = h_base[hc], cnt = h_base[hc + 1] - lo;
+        for (int k = lane; k < cnt; k += 64) {
+            const double4 x = a.xs[h_first[hc] + k];
+            sx[lo + k] = (float)(x.x - ox);
+            sy[lo + k] = (float)(x.y - oy);
+            sz[lo + k] = (float)(x.z - oz);
+        }
+    }
+    __syncthreads();
+}
+
+// Adjoint over one block of B0 x B1 x B2 cells (ScatterSum, Sec. III.A, done
+// in two levels like the paper's partial-then-global reduction).  The
+// workgroup first copies the positions of the block and its one-cell halo
+// into LDS, each halo slot shifted by its periodic image, and its pair loops
+// read neighbour positions there (LdsPos) instead of gathering them from HBM.
+// The forces on the block's atoms and on its halo accumulate in LDS with LDS
+// atomics, located through the stencil offset each list entry recorded; the
+// block then adds its accumulators to F with coalesced device atomics, one
+// range per halo cell.
+template <int KC, int M, bool TAB>
+__global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom bg) {
+    extern __shared__ float spos[];  // [3][hmax] halo positions, then sF[3][hmax] force accumulators
+    __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells], sdelta[27];
+    __shared__ int32_t wtmp[kBlock / 64];
+    __shared__ double red[6][kBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int blk = blockIdx.x;
+    int x0, y0, z0;
+    halo_slots(bg, blk, h_first, h_base, hoff, sdelta, wtmp, x0, y0, z0);
+    const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
+    const int nh = HX * HY * HZ;
+    float* sx = spos;
+    float* sy = spos + bg.hmax;
+    float* sz = spos + 2 * bg.hmax;
+    float* sF = spos + 3 * bg.hmax;
     const int htot = h_base[nh];
     for (int i = t; i < htot; i += kBlock) {
         sF[i] = 0.0f;
         sF[bg.hmax + i] = 0.0f;
         sF[2 * bg.hmax + i] = 0.0f;
     }
-    __syncthreads();
+    halo_positions(bg, a, x0, y0, z0, h_first, h_base, sx, sy, sz);  // ends with a barrier
+    const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
     // the block's atoms are work slots wbase[blk] .. wbase[blk+1], ordered by row length
     const int nch = 1 << a.nch_log2;
     const int64_t w0 = bg.wbase[blk];
@@ -506,17 +596,19 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         const int64_t p = bg.wperm[w];
         const int ic = bg.wcell[w];
         const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
+        const int hp = (iz * HY + iy) * HX + ix;
+        const int ip = hoff[hp] + (int)p;
+        const LdsPos pos{sx, sy, sz, hoff, sdelta, hp, sx[ip], sy[ip], sz[ip], cw[0], cw[1], cw[2]};
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, [&](int q, int o, float gx, float gy, float gz) {
-            const int hq = ((iz + o / 9 - 1) * HY + (iy + (o / 3) % 3 - 1)) * HX + (ix + o % 3 - 1);
-            const int idx = h_base[hq] + (q - h_first[hq]);
+        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, pos,
+                                 [&](int q, int o, float gx, float gy, float gz) {
+            const int idx = hoff[hp + sdelta[o]] + q;
             atomicAdd(&sF[idx], -gx);
             atomicAdd(&sF[bg.hmax + idx], -gy);
             atomicAdd(&sF[2 * bg.hmax + idx], -gz);
         });
         if (ch == 0) {
-            const int hp = (iz * HY + iy) * HX + ix;
-            const int idx = h_base[hp] + (int)(p - h_first[hp]);
+            const int idx = ip;
             atomicAdd(&sF[idx], Fo[0]);
             atomicAdd(&sF[bg.hmax + idx], Fo[1]);
             atomicAdd(&sF[2 * bg.hmax + idx], Fo[2]);
@@ -541,16 +633,14 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
 // Rows of one wave run in lockstep, so a wave costs the longest of its rows.
 // In a two-species alloy the per-species row lengths of neighbouring atoms
 // vary by several entries (the total hardly does), so each cell block's atoms
-// are put in descending order of (species-0 row, species-1 row) length; the
-// descriptor and adjoint kernels walk atoms in this order (and P is stored in
-// it, which keeps its loads and stores coalesced).
+// are put in descending order of species-0 row length; the descriptor and
+// adjoint kernels walk atoms in this order (and P is stored in it, which
+// keeps its loads and stores coalesced).
 
 struct WorkGeom {
     int nc[3], B[3], nb[3];
-    int64_t n;
-    int S;
     const int32_t* cellstart;
-    const int32_t* cnt;
+    const int32_t* cnt;  // species-0 row lengths [n]
 };
 
 __device__ __forceinline__ void block_origin(const WorkGeom& g, int64_t blk, int& x0, int& y0, int& z0) {
@@ -568,40 +658,60 @@ __device__ __forceinline__ int block_cell(const WorkGeom& g, int x0, int y0, int
     return (cz * g.nc[1] + cy) * g.nc[0] + cx;
 }
 
+// Atoms per block: one wave per block, lanes over its cells.
 __global__ void k_wo_count(WorkGeom g, int64_t nblocks, int32_t* __restrict__ count) {
-    const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (blk >= nblocks) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (blk >= nblocks) return;  // whole wave
     int x0, y0, z0;
     block_origin(g, blk, x0, y0, z0);
     int c = 0;
-    for (int ic = 0; ic < g.B[0] * g.B[1] * g.B[2]; ++ic) {
+    for (int ic = lane; ic < g.B[0] * g.B[1] * g.B[2]; ic += 64) {
         const int gc = block_cell(g, x0, y0, z0, ic);
         if (gc >= 0) c += g.cellstart[gc + 1] - g.cellstart[gc];
     }
-    count[blk] = c;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) count[blk] = c;
 }
 
-// Exclusive scan of the block counts by one workgroup; base[nblocks] = n.
-__global__ void __launch_bounds__(256) k_wo_scan(int64_t nblocks, const int32_t* __restrict__ count,
-                                                 int32_t* __restrict__ base) {
-    __shared__ int32_t out[257], wtmp[kBlock / 64];
+// Exclusive scan of the block counts by one workgroup of 1024 threads;
+// base[nblocks] = n.
+__global__ void __launch_bounds__(1024) k_wo_scan(int64_t nblocks, const int32_t* __restrict__ count,
+                                                  int32_t* __restrict__ base) {
+    __shared__ int32_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     int32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nblocks; b0 += kBlock) {
-        const int64_t q = b0 + threadIdx.x;
-        scan256(q < nblocks ? count[q] : 0, out, wtmp);
-        if (q < nblocks) base[q] = carry + out[threadIdx.x];
-        carry += out[256];
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
+        const int64_t q = b0 + t;
+        const int32_t v = q < nblocks ? count[q] : 0;
+        int32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const int32_t sw = wsum[w];
+            pre += (w < wv) ? sw : 0;
+            tot += sw;
+        }
+        if (q < nblocks) base[q] = carry + pre + x - v;
+        carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) base[nblocks] = carry;
+    if (t == 0) base[nblocks] = carry;
 }
 
-// One workgroup per block: rank every atom of the block by descending key
-// (ties by cell order, so the order is deterministic) with an all-pairs count
-// over the keys held in LDS, then scatter to the block's slots.
-__global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, const int32_t* __restrict__ base,
+// One workgroup per block: counting sort of the block's atoms by descending
+// species-0 row length (for one species, the row length).  In a two-species
+// alloy the total row length hardly varies, so this orders the species-1 rows
+// too.  Atoms of equal length land in arbitrary order.
+__global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, int cap, const int32_t* __restrict__ base,
                                                   int32_t* __restrict__ wperm, uint8_t* __restrict__ wcell) {
-    extern __shared__ int32_t skey[];  // [atoms of the block]
+    extern __shared__ int32_t hist[];  // [cap + 2]: counts, then first slot per length
     __shared__ int32_t i_base[257], i_first[kMaxBlockCells], wtmp[kBlock / 64];
     const int t = threadIdx.x;
     const int64_t blk = blockIdx.x;
@@ -614,28 +724,33 @@ __global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, const int32_t* __r
         i_first[t] = gc >= 0 ? g.cellstart[gc] : 0;
         icount = gc >= 0 ? g.cellstart[gc + 1] - i_first[t] : 0;
     }
-    scan256(icount, i_base, wtmp);
+    for (int k = t; k <= cap + 1; k += kBlock) hist[k] = 0;
+    scan256(icount, i_base, wtmp);  // ends with a barrier
     const int m = i_base[nI];
     for (int la = t; la < m; la += kBlock) {
         int ic = 0;
         while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
-        const int64_t p = i_first[ic] + (la - i_base[ic]);
-        const int n0 = g.cnt[p];
-        const int n1 = g.S > 1 ? g.cnt[g.n + p] : 0;
-        skey[la] = (n0 << 13) | n1;  // row lengths < 4096
+        const int len = min(g.cnt[i_first[ic] + (la - i_base[ic])], cap);
+        atomicAdd(&hist[len], 1);
+    }
+    __syncthreads();
+    if (t == 0) {  // descending lengths: first slot of length L = atoms longer than L
+        int run = 0;
+        for (int L = cap; L >= 0; --L) {
+            const int c = hist[L];
+            hist[L] = run;
+            run += c;
+        }
     }
     __syncthreads();
     const int64_t w0 = base[blk];
     for (int la = t; la < m; la += kBlock) {
-        const int key = skey[la];
-        int r = 0;
-        for (int j = 0; j < m; ++j) {
-            const int kj = skey[j];
-            r += (kj > key || (kj == key && j < la)) ? 1 : 0;
-        }
         int ic = 0;
         while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
-        wperm[w0 + r] = (int32_t)(i_first[ic] + (la - i_base[ic]));
+        const int64_t p = i_first[ic] + (la - i_base[ic]);
+        const int len = min(g.cnt[p], cap);
+        const int r = atomicAdd(&hist[len], 1);
+        wperm[w0 + r] = (int32_t)p;
         wcell[w0 + r] = (uint8_t)ic;
     }
 }
@@ -737,7 +852,8 @@ unsigned path_grid(const tmd_model* m, const tmd_nlist* nl) {
 
 // Radial functions per descriptor thread.  P is stored per radial function,
 // so the descriptor's chunking need not match the adjoint's (m->kc).
-int desc_kc(const tmd_model* m) { return m->kc; }
+// Measured: four per thread beat eight for K = 32 and 128 with M = 3.
+int desc_kc(const tmd_model* m) { return (m->M == 3 && m->kc == 8) ? 4 : m->kc; }
 
 int log2_int(int v) {
     int lg = 0;
@@ -745,21 +861,49 @@ int log2_int(int v) {
     return lg;
 }
 
-constexpr size_t kMaxDynLds = 56 * 1024;
+// Per halo atom the blocked adjoint keeps its position and force accumulator
+// (3 + 3 floats) in LDS; capped so that two workgroups fit on a CU.
+constexpr size_t kHaloBytes = 6 * sizeof(float);
+constexpr size_t kMaxDynLds = 76 * 1024;
+
+// Block geometry of the work order of a built list.
+BlockGeom wo_geom(const tmd_nlist* nl) {
+    BlockGeom bg{};
+    for (int d = 0; d < 3; ++d) {
+        bg.nc[d] = nl->nc[d];
+        bg.B[d] = nl->wo_B[d];
+        bg.nb[d] = nl->wo_nb[d];
+    }
+    bg.hmax = nl->wo_hmax;
+    bg.cellstart = nl->cellstart;
+    bg.wbase = nl->wbase;
+    bg.wperm = nl->wperm;
+    bg.wcell = nl->wcell;
+    return bg;
+}
 
 // Largest block shape whose halo accumulators fit in LDS for the densest cell.
 bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
     // 4x2x2 cells per workgroup: enough workgroups (about 5,000 at 1 M atoms)
     // for several rounds of them per CU; measured fastest of 4x4x4 .. 2x2x2.
-    static const int shapes[][3] = {{4, 2, 2}, {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+    // The preferred shape's largest halo is counted exactly during the build;
+    // the fallbacks use (halo cells) x (densest cell).
+    static const int shapes[][3] = {{kBlockShape[0], kBlockShape[1], kBlockShape[2]}, {2, 2, 2}, {2, 2, 1},
+                                    {2, 1, 1}, {1, 1, 1}};
     for (const auto& sh : shapes) {
         int B[3], H = 1;
         for (int d = 0; d < 3; ++d) {
             B[d] = std::min(sh[d], nl->nc[d]);
             H *= B[d] + 2;
         }
-        const int64_t hmax = (int64_t)H * std::max(1, nl->max_occ);
-        if (hmax * 3 * (int64_t)sizeof(float) > (int64_t)kMaxDynLds) continue;
+        const bool pref = &sh == &shapes[0], last = &sh == &shapes[4];
+        const int64_t hmax = (pref && nl->halo_max >= 0) ? (int64_t)std::max(1, nl->halo_max)
+                                                          : (int64_t)H * std::max(1, nl->max_occ);
+        // small systems: smaller blocks until every CU gets two workgroups
+        int64_t nblocks = 1;
+        for (int d = 0; d < 3; ++d) nblocks *= (nl->nc[d] + B[d] - 1) / B[d];
+        if (!last && nblocks < 2 * (int64_t)nl->ctx->num_cus) continue;
+        if (hmax * (int64_t)kHaloBytes > (int64_t)kMaxDynLds) continue;
         for (int d = 0; d < 3; ++d) {
             bg->nc[d] = nl->nc[d];
             bg->B[d] = B[d];
@@ -794,18 +938,16 @@ tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl) {
         g.B[d] = bg.B[d];
         g.nb[d] = bg.nb[d];
     }
-    g.n = nl->n;
-    g.S = nl->S;
     g.cellstart = nl->cellstart;
     g.cnt = nl->cnt;
-    // keys of a block's atoms in LDS: at most (cells per block) x (densest cell)
-    const size_t lds = sizeof(int32_t) * (size_t)bg.B[0] * bg.B[1] * bg.B[2] * std::max(1, nl->max_occ);
-    if (lds > 64 * 1024) return TMD_OK;  // a pathological density: keep the atomic adjoint
+    // length histogram in LDS: one counter per possible row length
+    const size_t lds = sizeof(int32_t) * ((size_t)nl->cap + 2);
     {
         ProfScope ps_(ctx, "work_order");
-        k_wo_count<<<(unsigned)((nblocks + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(g, nblocks, count);
-        k_wo_scan<<<1, kBlock, 0, ctx->stream>>>(nblocks, count, nl->wbase);
-        k_wo_order<<<(unsigned)nblocks, kBlock, lds, ctx->stream>>>(g, nl->wbase, nl->wperm, nl->wcell);
+        k_wo_count<<<(unsigned)((nblocks + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, ctx->stream>>>(g, nblocks,
+                                                                                                   count);
+        k_wo_scan<<<1, 1024, 0, ctx->stream>>>(nblocks, count, nl->wbase);
+        k_wo_order<<<(unsigned)nblocks, kBlock, lds, ctx->stream>>>(g, nl->cap, nl->wbase, nl->wperm, nl->wcell);
     }
     TMD_HIP(ctx, hipGetLastError());
     for (int d = 0; d < 3; ++d) {
@@ -845,23 +987,13 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
     a.vir = vir_partials;
     TMD_HIP(ctx, hipMemsetAsync(Fsorted, 0, sizeof(float) * 3 * nl->n, ctx->stream));
     if (nl->wo_valid) {
-        BlockGeom bg{};
-        for (int d = 0; d < 3; ++d) {
-            bg.nc[d] = nl->nc[d];
-            bg.B[d] = nl->wo_B[d];
-            bg.nb[d] = nl->wo_nb[d];
-        }
-        bg.hmax = nl->wo_hmax;
-        bg.cellstart = nl->cellstart;
+        BlockGeom bg = wo_geom(nl);
         bg.F = Fsorted;
-        bg.wbase = nl->wbase;
-        bg.wperm = nl->wperm;
-        bg.wcell = nl->wcell;
         const unsigned grid = (unsigned)bg.nb[0] * bg.nb[1] * bg.nb[2];
         auto fn = m->tab ? select_blocked<true>(m->kc, m->M) : select_blocked<false>(m->kc, m->M);
         {
             ProfScope ps_(ctx, "adjoint");
-            fn<<<grid, kBlock, sizeof(float) * 3 * (size_t)bg.hmax, ctx->stream>>>(a, bg);
+            fn<<<grid, kBlock, kHaloBytes * (size_t)bg.hmax, ctx->stream>>>(a, bg);
         }
         *nvir_out = (int)grid;
     } else {

@@ -2,11 +2,10 @@
 //
 // The paper updates its neighbour table with a binning method (Sec. IV.D) and
 // stores it as the padded, per-pair-type tensor R_abc with a mask (Sec. III.A).
-// Here the table is kept per neighbour species b as a column-major padded list
-// nbr[b][c][atom] (atom fastest, so a wave of consecutive atoms reads one
-// contiguous segment per neighbour slot) with a count per (b, atom) in place of
-// the mask.  Atoms are renumbered in cell-major order so that the atoms a wave
-// visits are spatially close and their neighbours share cache lines.
+// Here the table is kept as one padded row per (atom, neighbour species b),
+// nbr[atom][b][c] with `cap` slots per row, and a count per (b, atom) in place
+// of the mask.  Atoms are renumbered in cell-major order so that the atoms a
+// wave visits are spatially close and their neighbours share cache lines.
 //
 // Inclusion predicate (evaluated in FP64, every operation separately rounded):
 //   w = x - L*floor(x/L) (then folded into [0, L)),
@@ -18,6 +17,10 @@
 #include <cmath>
 #include <cstring>
 
+// No fused multiply-adds anywhere in this file: the predicate must round every
+// product and sum separately, like its FP64 definition.
+#pragma clang fp contract(off)
+
 namespace tmd {
 namespace {
 
@@ -26,9 +29,9 @@ constexpr int kErrSpecies = 2;
 constexpr int kErrCoincident = 4;
 
 __device__ inline double wrap_exact(double x, double L) {
-    double w = __dsub_rn(x, __dmul_rn(L, floor(__ddiv_rn(x, L))));
-    if (w < 0.0) w = __dadd_rn(w, L);
-    if (w >= L) w = __dsub_rn(w, L);
+    double w = x - L * floor(x / L);
+    if (w < 0.0) w = w + L;
+    if (w >= L) w = w - L;
     return w;
 }
 
@@ -98,13 +101,49 @@ __device__ void block_exclusive_scan(int64_t n, const int32_t* __restrict__ in, 
 }
 
 // Exclusive scan of the cell counts (cells are few: about N/14).
-__global__ void __launch_bounds__(1024) k_scan_cells(int64_t ncells, const int32_t* __restrict__ count,
-                                                     int32_t* __restrict__ start, int32_t* __restrict__ max_occ) {
-    block_exclusive_scan(ncells, count, 1, start, 1);
-    int32_t m = 0;
-    for (int64_t q = threadIdx.x; q < ncells; q += 1024) m = max(m, count[q]);
+// Cell starts in three passes (any cell count): k_scan_tiles scans each tile
+// of 1024 cells and records its total and the largest count; k_scan_tile_sums
+// scans the tile totals in one workgroup; k_scan_add adds each tile's offset.
+__global__ void __launch_bounds__(1024) k_scan_tiles(int64_t ncells, const int32_t* __restrict__ count,
+                                                     int32_t* __restrict__ start, int32_t* __restrict__ tile_sum,
+                                                     int32_t* __restrict__ max_occ) {
+    __shared__ int32_t wsum[16], wmax[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 1024 + t;
+    const int32_t v = q < ncells ? count[q] : 0;
+    int32_t x = v, m = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(max_occ, m);
+    if (lane == 63) wsum[wv] = x;
+    if (lane == 0) wmax[wv] = m;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const int32_t sw = wsum[w];
+        pre += (w < wv) ? sw : 0;
+        tot += sw;
+    }
+    if (q < ncells) start[q] = pre + x - v;
+    if (t == 0) {
+        tile_sum[blockIdx.x] = tot;
+        int32_t mm = wmax[0];
+        for (int w = 1; w < 16; ++w) mm = max(mm, wmax[w]);
+        atomicMax(max_occ, mm);
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_tile_sums(int64_t ntiles, int32_t* __restrict__ tile_sum) {
+    block_exclusive_scan(ntiles, tile_sum, 1, tile_sum, 1);
+}
+
+__global__ void k_scan_add(int64_t ncells, const int32_t* __restrict__ tile_off, int32_t* __restrict__ start) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ncells) start[q] += tile_off[q >> 10];
+    if (q == ncells) start[q] = tile_off[(ncells + 1023) >> 10];
 }
 
 // Per-species exclusive scans over the per-block species counts; the totals
@@ -205,6 +244,43 @@ __device__ inline int floor_div(int a, int b) {
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+// Largest atom count of a cell block of B0 x B1 x B2 cells plus its one-cell
+// periodic halo into *out: waves stride over the blocks (lanes over a block's
+// halo cells); one atomic per workgroup.
+constexpr int kHaloMaxGroups = 256;
+__global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int B0, int B1, int B2, int64_t nblocks,
+                                                  const int32_t* __restrict__ start, int32_t* __restrict__ out) {
+    __shared__ int32_t wmax[kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nb0 = (g.nc[0] + B0 - 1) / B0, nb1 = (g.nc[1] + B1 - 1) / B1;
+    const int HX = B0 + 2, HY = B1 + 2, nh = HX * HY * (B2 + 2);
+    int best = 0;
+    for (int64_t blk = (int64_t)blockIdx.x * (kBlock / 64) + wv; blk < nblocks;
+         blk += (int64_t)gridDim.x * (kBlock / 64)) {
+        const int x0 = (int)(blk % nb0) * B0, y0 = (int)((blk / nb0) % nb1) * B1,
+                  z0 = (int)(blk / ((int64_t)nb0 * nb1)) * B2;
+        int c = 0;
+        for (int h = lane; h < nh; h += 64) {
+            const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+            const int wx = x - floor_div(x, g.nc[0]) * g.nc[0];
+            const int wy = y - floor_div(y, g.nc[1]) * g.nc[1];
+            const int wz = z - floor_div(z, g.nc[2]) * g.nc[2];
+            const int cell = (wz * g.nc[1] + wy) * g.nc[0] + wx;
+            c += start[cell + 1] - start[cell];
+        }
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        best = max(best, c);
+    }
+    if (lane == 0) wmax[wv] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = wmax[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, wmax[w]);
+        atomicMax(out, m);
+    }
+}
+
+
 // One thread per atom (cell-major order): scan the stencil of cells within
 // `reach` (periodic images folded in), append accepted neighbours to the
 // list of their species.
@@ -226,17 +302,17 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
         const int zz = cz + oz;
         const int nz = floor_div(zz, g.nc[2]);
         const int wz = zz - nz * g.nc[2];
-        const double sz = __dmul_rn((double)nz, g.L[2]);
+        const double sz = (double)nz * g.L[2];
         for (int oy = -g.reach[1]; oy <= g.reach[1]; ++oy) {
             const int yy = cy + oy;
             const int ny = floor_div(yy, g.nc[1]);
             const int wy = yy - ny * g.nc[1];
-            const double sy = __dmul_rn((double)ny, g.L[1]);
+            const double sy = (double)ny * g.L[1];
             for (int ox = -g.reach[0]; ox <= g.reach[0]; ++ox) {
                 const int xx = cx + ox;
                 const int nx = floor_div(xx, g.nc[0]);
                 const int wx = xx - nx * g.nc[0];
-                const double sx = __dmul_rn((double)nx, g.L[0]);
+                const double sx = (double)nx * g.L[0];
                 const int c2 = (wz * g.nc[1] + wy) * g.nc[0] + wx;
                 const int lo = a.cellstart[c2], hi = a.cellstart[c2 + 1];
                 const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
@@ -252,11 +328,10 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
                     for (int j = 0; j < 4; ++j) {
                         const int q = q0 + j;
                         if (q >= hi || (zero_img && q == p)) continue;
-                        const double dx = __dadd_rn(__dsub_rn(xj[j].x, xi.x), sx);
-                        const double dy = __dadd_rn(__dsub_rn(xj[j].y, xi.y), sy);
-                        const double dz = __dadd_rn(__dsub_rn(xj[j].z, xi.z), sz);
-                        const double d2 =
-                            __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+                        const double dx = (xj[j].x - xi.x) + sx;
+                        const double dy = (xj[j].y - xi.y) + sy;
+                        const double dz = (xj[j].z - xi.z) + sz;
+                        const double d2 = (dx * dx + dy * dy) + dz * dz;
                         if (!(d2 < a.rl2)) continue;
                         if (d2 == 0.0) coincident = true;
                         const int b = a.sp[q];
@@ -287,41 +362,51 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
 }
 
 constexpr int kMaxCellAtoms = 64;
+constexpr int kMaxCandidates = 27 * kMaxCellAtoms;
 
-// One wave per cell (stencils of at most 64 cells, cells of at most 64 atoms).
-// Each round the wave holds 64 candidates of the cell's stencil, in the same
-// order as k_fill visits them (stencil cell, then atom), and tests them with
-// the same FP64 predicate against every atom of the cell in turn.  An atom's
-// accepted candidates are compacted with a ballot and written to its row as
+// One wave per cell (stencils of at most 64 cells, cells of at most 64 atoms,
+// at most kMaxCandidates candidates).  Each round the wave holds 64
+// candidates of the cell's stencil, in the same order as k_fill visits them
+// (stencil cell, then atom), and tests them with the same FP64 predicate
+// against every atom of the cell in turn (the atom's position is a uniform,
+// scalar load).  An atom's accepted candidates are compacted with one ballot
+// (split by species with per-round species masks) and written to its rows as
 // one contiguous run per species, so the list is identical to k_fill's while
 // every load and store of the wave is coalesced.
-// Value of v in lane i (i uniform), as two 32-bit lane reads.
-__device__ __forceinline__ double bcast_double(double v, int i) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, i);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), i);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
+// Image of cell coordinate c (in -1 .. n) when the stencil reaches one cell.
+__device__ __forceinline__ int near_image(int c, int n) { return c < 0 ? -1 : (c >= n ? 1 : 0); }
 
+template <int SMAX, bool NARROW>  // a.S <= SMAX; NARROW: 3x3x3 stencil
 __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) {
+    // per wave: stencil cell of every candidate, and the cell's own positions
+    __shared__ uint8_t s_cell[kBlock / 64][kMaxCandidates];
+    __shared__ double s_xi[kBlock / 64][3][kMaxCellAtoms];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t cell = (int64_t)blockIdx.x * (kBlock / 64) + wv;
     if (cell >= ncells) return;  // whole wave
     const GridArgs& g = a.g;
     const int cx = (int)(cell % g.nc[0]), cy = (int)((cell / g.nc[0]) % g.nc[1]),
               cz = (int)(cell / ((int64_t)g.nc[0] * g.nc[1]));
-    const int a0 = a.cellstart[cell], natoms = a.cellstart[cell + 1] - a0;
+    const int a0 = __builtin_amdgcn_readfirstlane(a.cellstart[cell]);
+    const int natoms = __builtin_amdgcn_readfirstlane(a.cellstart[cell + 1]) - a0;
     if (natoms == 0) return;  // nothing to list (and a0 may equal n)
     if (natoms > kMaxCellAtoms) {  // the host reruns the build with k_fill
         if (lane == 0) atomicOr(&a.flags[2], 1);
         return;
     }
-    const int wx = 2 * g.reach[0] + 1, wy = 2 * g.reach[1] + 1, wz = 2 * g.reach[2] + 1;
+    const int rx = NARROW ? 1 : g.reach[0], ry = NARROW ? 1 : g.reach[1], rz = NARROW ? 1 : g.reach[2];
+    const int wx = 2 * rx + 1, wy = 2 * ry + 1, wz = 2 * rz + 1;
     const int ns = wx * wy * wz;
+    if (lane < natoms) {
+        const double4 x = a.xs[a0 + lane];
+        s_xi[wv][0][lane] = x.x;
+        s_xi[wv][1][lane] = x.y;
+        s_xi[wv][2][lane] = x.z;
+    }
     // stencil cell of this lane (traversal order: z outer, x inner)
     int first = 0, count = 0;
     if (lane < ns) {
-        const int ox = lane % wx - g.reach[0], oy = (lane / wx) % wy - g.reach[1], oz = lane / (wx * wy) - g.reach[2];
+        const int ox = lane % wx - rx, oy = (lane / wx) % wy - ry, oz = lane / (wx * wy) - rz;
         const int xx = cx + ox, yy = cy + oy, zz = cz + oz;
         const int nx = floor_div(xx, g.nc[0]), ny = floor_div(yy, g.nc[1]), nz = floor_div(zz, g.nc[2]);
         const int c2 = ((zz - nz * g.nc[2]) * g.nc[1] + (yy - ny * g.nc[1])) * g.nc[0] + (xx - nx * g.nc[0]);
@@ -335,27 +420,32 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
     }
     const int total = __shfl(pre, 63);
     pre -= count;  // exclusive
-    // the cell's own atoms, one per lane (natoms <= 64), broadcast with readlane
-    double4 xown = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (lane < natoms) xown = a.xs[a0 + lane];
+    if (total > kMaxCandidates) {  // the host reruns the build with k_fill
+        if (lane == 0) atomicOr(&a.flags[2], 1);
+        return;
+    }
+    // candidate -> stencil cell table: stencil cell s owns candidates [pre_s, pre_s + count_s)
+    for (int j = 0; j < count; ++j) s_cell[wv][pre + j] = (uint8_t)lane;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // running row lengths: lane i holds atom i's count per species
-    int rowlen[kMaxSpecies];
+    int rowlen[SMAX];
 #pragma unroll
-    for (int b = 0; b < kMaxSpecies; ++b) rowlen[b] = 0;
+    for (int b = 0; b < SMAX; ++b) rowlen[b] = 0;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool coincident = false;
     for (int k0 = 0; k0 < total; k0 += 64) {
         const int k = k0 + lane;
         const bool valid = k < total;
-        // stencil cell holding candidate k: the last cell whose start is <= k
-        int sk = 0;
-        for (int s = 1; s < ns; ++s)
-            if (__builtin_amdgcn_readlane(pre, s) <= k) sk = s;
-        const int ox = sk % wx - g.reach[0], oy = (sk / wx) % wy - g.reach[1], oz = sk / (wx * wy) - g.reach[2];
-        const int nx = floor_div(cx + ox, g.nc[0]), ny = floor_div(cy + oy, g.nc[1]), nz = floor_div(cz + oz, g.nc[2]);
-        const double sx = __dmul_rn((double)nx, g.L[0]);
-        const double sy = __dmul_rn((double)ny, g.L[1]);
-        const double sz = __dmul_rn((double)nz, g.L[2]);
+        const int sk = valid ? (int)s_cell[wv][k] : 0;
+        const int ox = sk % wx - rx, oy = (sk / wx) % wy - ry, oz = sk / (wx * wy) - rz;
+        const int nx = NARROW ? near_image(cx + ox, g.nc[0]) : floor_div(cx + ox, g.nc[0]);
+        const int ny = NARROW ? near_image(cy + oy, g.nc[1]) : floor_div(cy + oy, g.nc[1]);
+        const int nz = NARROW ? near_image(cz + oz, g.nc[2]) : floor_div(cz + oz, g.nc[2]);
+        const double sx = (double)nx * g.L[0];
+        const double sy = (double)ny * g.L[1];
+        const double sz = (double)nz * g.L[2];
         // every lane takes part in both shuffles (a shuffle from a lane that
         // is inactive in a branch yields undefined data); select afterwards
         const int first_sk = __shfl(first, sk);
@@ -363,34 +453,44 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         const int q = valid ? first_sk + (k - pre_sk) : a0;
         const double4 xj = a.xs[q];
         const int bq = valid ? a.sp[q] : -1;
+        const bool okq = valid && bq >= 0 && bq < a.S;
         const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
         const int32_t word = pack_img(nx, ny, nz, a.narrow ? sk : 255);
+        // candidates of each species this round, and this lane's own species' mask
+        unsigned long long spm[SMAX], mine = 0;
+#pragma unroll
+        for (int b = 0; b < SMAX; ++b) {
+            spm[b] = __ballot(okq && bq == b);
+            if (bq == b) mine = spm[b];
+        }
+        // this lane's entry offset inside a (atom, species) row block
+        const int lane_row = okq ? bq * a.cap : 0;
         for (int i = 0; i < natoms; ++i) {
             const int p = a0 + i;
-            const double xix = bcast_double(xown.x, i), xiy = bcast_double(xown.y, i),
-                         xiz = bcast_double(xown.z, i);
-            const double4 xi = make_double4(xix, xiy, xiz, 0.0);
-            const double dx = __dadd_rn(__dsub_rn(xj.x, xi.x), sx);
-            const double dy = __dadd_rn(__dsub_rn(xj.y, xi.y), sy);
-            const double dz = __dadd_rn(__dsub_rn(xj.z, xi.z), sz);
-            const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-            const bool acc = valid && !(zero_img && q == p) && d2 < a.rl2 && bq >= 0 && bq < a.S;
+            const double4 xi = make_double4(s_xi[wv][0][i], s_xi[wv][1][i], s_xi[wv][2][i], 0.0);
+            const double dx = (xj.x - xi.x) + sx;
+            const double dy = (xj.y - xi.y) + sy;
+            const double dz = (xj.z - xi.z) + sz;
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            const bool acc = okq && !(zero_img && q == p) && d2 < a.rl2;
             if (acc && d2 == 0.0) coincident = true;
+            const unsigned long long m = __ballot(acc);
+            if (!m) continue;
+            // atom i's row lengths (held by lane i), this lane's species picked out
+            int base = 0;
 #pragma unroll
-            for (int b = 0; b < kMaxSpecies; ++b) {
-                if (b >= a.S) break;
-                const unsigned long long m = __ballot(acc && bq == b);
-                if (!m) continue;
-                const int base = __builtin_amdgcn_readlane(rowlen[b], i);
-                if (acc && bq == b) {
-                    const int c = base + (int)__popcll(m & below);
-                    if (c < a.cap) {
-                        const int64_t off = ((int64_t)p * a.S + b) * a.cap + c;
-                        a.nbr[off] = q;
-                        a.img[off] = word;
-                    }
+            for (int b = 0; b < SMAX; ++b) {
+                const int rb = __builtin_amdgcn_readlane(rowlen[b], i);
+                if (bq == b) base = rb;
+                if (lane == i) rowlen[b] = rb + (int)__popcll(m & spm[b]);
+            }
+            if (acc) {
+                const int c = base + (int)__popcll(m & mine & below);
+                if (c < a.cap) {
+                    const int64_t rows = (int64_t)p * a.S * a.cap;  // uniform
+                    a.nbr[rows + (lane_row + c)] = q;
+                    a.img[rows + (lane_row + c)] = word;
                 }
-                if (lane == i) rowlen[b] = base + (int)__popcll(m);
             }
         }
     }
@@ -398,7 +498,7 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
     if (lane < natoms) {
         const int p = a0 + lane;
 #pragma unroll
-        for (int b = 0; b < kMaxSpecies; ++b) {
+        for (int b = 0; b < SMAX; ++b) {
             if (b >= a.S) break;
             const int c = rowlen[b];
             a.cnt[(int64_t)b * a.n + p] = min(c, a.cap);
@@ -536,6 +636,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     int32_t* cell_sorted = (int32_t*)ctx->ws.get("nb.cell_sorted", sizeof(int32_t) * n, &e);
     int32_t* order = (int32_t*)ctx->ws.get("nb.order", sizeof(int32_t) * n, &e);
     int32_t* cellcount = (int32_t*)ctx->ws.get("nb.cellcount", sizeof(int32_t) * (ncells + 1), &e);
+    int32_t* tiles = (int32_t*)ctx->ws.get("nb.tiles", sizeof(int32_t) * ((ncells + 1023) / 1024 + 1), &e);
     int32_t* cellfill = (int32_t*)ctx->ws.get("nb.cellfill", sizeof(int32_t) * (ncells + 1), &e);
     int32_t* blkcnt = (int32_t*)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
     int32_t* blkoff = (int32_t*)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
@@ -554,7 +655,19 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     }
     {
         ProfScope ps_(ctx, "nb_scan");
-        k_scan_cells<<<1, 1024, 0, st>>>(ncells, cellcount, cellstart, flags + 4);
+        const int64_t ntiles = (ncells + 1023) / 1024;
+        k_scan_tiles<<<(unsigned)ntiles, 1024, 0, st>>>(ncells, cellcount, cellstart, tiles, flags + 4);
+        k_scan_tile_sums<<<1, 1024, 0, st>>>(ntiles, tiles);
+        k_scan_add<<<grid_for(ncells + 1), kBlock, 0, st>>>(ncells, tiles, cellstart);
+    }
+    int hb[3] = {1, 1, 1};
+    if (narrow) {
+        for (int d = 0; d < 3; ++d) hb[d] = std::min(kBlockShape[d], g.nc[d]);
+        const int64_t nbk = (int64_t)((g.nc[0] + hb[0] - 1) / hb[0]) * ((g.nc[1] + hb[1] - 1) / hb[1]) *
+                            ((g.nc[2] + hb[2] - 1) / hb[2]);
+        ProfScope ps_(ctx, "nb_halo_max");
+        const int64_t groups = std::min<int64_t>(kHaloMaxGroups, (nbk + kBlock / 64 - 1) / (kBlock / 64));
+        k_halo_max<<<(unsigned)groups, kBlock, 0, st>>>(g, hb[0], hb[1], hb[2], nbk, cellstart, flags + 5);
     }
     {
         ProfScope ps_(ctx, "nb_place");
@@ -592,7 +705,18 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     const bool by_cell = stencil_cells <= 64;
     if (by_cell) {
         ProfScope ps_(ctx, "nb_fill");
-        k_fill_cells<<<(unsigned)((ncells + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(fa, ncells);
+        const unsigned grid = (unsigned)((ncells + kBlock / 64 - 1) / (kBlock / 64));
+        using FillFn = void (*)(FillArgs, int64_t);
+        FillFn fn;
+        if (nl->S == 1)
+            fn = narrow ? k_fill_cells<1, true> : k_fill_cells<1, false>;
+        else if (nl->S == 2)
+            fn = narrow ? k_fill_cells<2, true> : k_fill_cells<2, false>;
+        else if (nl->S <= 4)
+            fn = narrow ? k_fill_cells<4, true> : k_fill_cells<4, false>;
+        else
+            fn = narrow ? k_fill_cells<kMaxSpecies, true> : k_fill_cells<kMaxSpecies, false>;
+        fn<<<grid, kBlock, 0, st>>>(fa, ncells);
     } else {
         ProfScope ps_(ctx, "nb_fill");
         k_fill<<<grid_for(n), kBlock, 0, st>>>(fa);
@@ -640,6 +764,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     nl->rlist = rlist;
     nl->ncells = ncells;
     nl->max_occ = ctx->h_flags[4];
+    nl->halo_max = narrow ? ctx->h_flags[5] : -1;
     nl->narrow = narrow;
     for (int a = 0; a < 3; ++a) {
         nl->box[a] = sys->box[a];
@@ -670,6 +795,8 @@ tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S) {
     (void)ctx->ws.get("nb.cell_sorted", sizeof(int32_t) * n, &e);
     (void)ctx->ws.get("nb.order", sizeof(int32_t) * n, &e);
     (void)ctx->ws.get("nb.cellcount", sizeof(int32_t) * cells, &e);
+    (void)ctx->ws.get("nb.tiles", sizeof(int32_t) * ((cells + 1023) / 1024 + 1), &e);
+    (void)ctx->ws.get("wo.count", sizeof(int32_t) * cells, &e);
     (void)ctx->ws.get("nb.cellfill", sizeof(int32_t) * cells, &e);
     (void)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
     (void)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
@@ -681,7 +808,8 @@ tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S) {
 
 size_t nlist_workspace_bytes(int64_t n) {
     const int64_t nblk = (n + kBlock - 1) / kBlock;
-    return (size_t)n * 36 + 8 * (size_t)(std::max<int64_t>(64, 4 * n) + 1) + 8 * (size_t)kMaxSpecies * (nblk + 1) + 512;
+    const size_t cells = (size_t)std::max<int64_t>(64, 4 * n) + 1;
+    return (size_t)n * 36 + 12 * cells + 4 * (cells / 1024 + 2) + 8 * (size_t)kMaxSpecies * (nblk + 1) + 512;
 }
 
 tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row) {

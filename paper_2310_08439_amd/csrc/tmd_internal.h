@@ -15,6 +15,8 @@
 namespace tmd {
 
 constexpr int kMaxSpecies = 8;
+// Preferred cell block of the blocked adjoint (cells per axis, clamped to the grid).
+constexpr int kBlockShape[3] = {4, 2, 2};
 constexpr int kBlock = 256;
 
 // Grow-only device buffers owned by a context, keyed by purpose.
@@ -47,6 +49,7 @@ struct Profiler {
 
 struct tmd_context {
     int device = 0;
+    int num_cus = 256;  // compute units of the device
     hipStream_t stream = nullptr;
     std::string last_error;
     tmd::Workspace ws;
@@ -142,11 +145,12 @@ struct tmd_nlist {
     int64_t cellstart_cap = 0;
     int64_t ncells = 0;
     int max_occ = 0;               // most atoms in one cell
+    int halo_max = -1;             // most atoms in one kBlockShape block plus halo (-1: not counted)
     bool narrow = false;           // 3x3x3 stencil (every reach is 1)
     // Work order of the descriptor and adjoint kernels, set by every build
     // when the adjoint runs over cell blocks (wo_valid): blocks of wo_B cells
-    // in block-major order, each block's atoms by descending row length of
-    // species 0, then of species 1 (so that a wave's rows are alike);
+    // in block-major order, each block's atoms by descending species-0 row
+    // length (so that a wave's rows are alike);
     // wperm[w] = sorted atom index of work slot w, wcell[w] = its cell inside
     // the block, wbase[blk] = first slot of block blk.  P is stored by slot.
     bool wo_valid = false;
