@@ -159,13 +159,23 @@ constexpr int kBatchFwd = 4;
 constexpr int kBatchAdj = 2;
 
 // A thread's KC x D tile of P in the element-major buffer [S][K][D][n]: element
-// (k, d) of atom p lives at ((b*K + k)*D + d)*n + p, so for a fixed element
-// the lanes of a wave (consecutive atoms, two chunks) write and read whole
-// contiguous cache lines.
-template <int KC, int D>
+// (k, d) of work slot w lives at ((b*K + k)*D + d)*n + w, so for a fixed
+// element the lanes of a wave (consecutive slots, two chunks) write and read
+// whole contiguous cache lines.  P (2 GB at 1 M atoms) is written once and
+// read once by the adjoint, far more than the L2 holds.  With at most two
+// chunk lanes per atom every store instruction writes whole 128-byte lines,
+// and those go out non-temporally (measured: less L2 pollution for the next
+// kernel); with more chunks a store covers 32-byte pieces, which must merge in
+// L2 (non-temporal stores were up to five times slower there).
+template <int KC, int D, bool NT>
 __device__ __forceinline__ void store_tile(float* dst, int64_t n, const float (&P)[KC][D]) {
 #pragma unroll
-    for (int q = 0; q < KC * D; ++q) dst[(int64_t)q * n] = P[q / D][q % D];
+    for (int q = 0; q < KC * D; ++q) {
+        if constexpr (NT)
+            __builtin_nontemporal_store(P[q / D][q % D], dst + (int64_t)q * n);
+        else
+            dst[(int64_t)q * n] = P[q / D][q % D];
+    }
 }
 
 template <int KC, int D>
@@ -273,16 +283,26 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
     return l < nblocks ? l : -1;
 }
 
-template <int KC, int M, bool TAB>
+template <int KC, int M, bool TAB, bool NT>
 __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D;
+    constexpr int GW = KC * (M + 1);  // features of one thread's chunk
+    // Per wave: its atoms' feature segments of one species, so that G's rows
+    // go out as consecutive floats (a lane-per-atom store would touch one
+    // cache line per lane), and the atoms' sorted indices.
+    __shared__ float sg[kBlock / 64][64 * GW];
+    __shared__ int32_t sp_row[kBlock / 64][64];
     const int64_t lb = xcd_block(nblocks);
     if (lb < 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t t = lb * blockDim.x + threadIdx.x;
     const int64_t w = t >> a.nch_log2;  // work slot
     const int ch = (int)(t & ((1 << a.nch_log2) - 1));
-    if (w >= a.n) return;
-    const int64_t p = a.wperm ? a.wperm[w] : w;
+    const bool active = w < a.n;
+    const int64_t p = active ? (a.wperm ? a.wperm[w] : w) : 0;
+    if (ch == 0) sp_row[wv][lane >> a.nch_log2] = (int32_t)p;
+    const int64_t wave_w0 = (lb * blockDim.x + (threadIdx.x & ~63)) >> a.nch_log2;
+    const int KM = a.K * (M + 1);  // features of one species
     float mu[KC], nef[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
@@ -291,21 +311,38 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
     }
     const GlobalPos pos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]};
     for (int b = 0; b < a.S; ++b) {
-        float P[KC][D];
-        accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, P, pos);
-        if (a.Pbuf) store_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
-        float* Gp = a.G + p * a.F + (b * a.K + ch * KC) * (M + 1);
+        if (active) {
+            float P[KC][D];
+            accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, P, pos);
+            if (a.Pbuf) store_tile<KC, D, NT>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
+            float* seg = &sg[wv][(lane >> a.nch_log2) * KM + ch * GW];
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
+            for (int kk = 0; kk < KC; ++kk) {
 #pragma unroll
-            for (int m = 0; m <= M; ++m) {
-                float s = 0.0f;
+                for (int m = 0; m <= M; ++m) {
+                    float s = 0.0f;
 #pragma unroll
-                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
-                // m = 0 has the single component d = 0: sqrt(S) = |P_k0| exactly
-                Gp[kk * (M + 1) + m] = (m == 0) ? fabsf(P[kk][0]) : s;
+                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) s += kMult[d] * P[kk][d] * P[kk][d];
+                    // m = 0 has the single component d = 0: sqrt(S) = |P_k0| exactly
+                    seg[kk * (M + 1) + m] = (m == 0) ? fabsf(P[kk][0]) : s;
+                }
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the wave's (64 / chunks) atoms x KM features, 64 consecutive floats per store
+#pragma unroll
+        for (int it = 0; it < GW; ++it) {
+            const int f = it * 64 + lane;
+            const int al = (f / GW) >> a.nch_log2;  // atom of the wave
+            const int e = f - al * KM;
+            if (wave_w0 + al < a.n)
+                a.G[(int64_t)sp_row[wv][al] * a.F + b * KM + e] = sg[wv][f];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -759,14 +796,18 @@ using PathFn = void (*)(PathArgs, int64_t);
 using AtomicFn = void (*)(PathArgs, float*);
 using BlockedFn = void (*)(PathArgs, BlockGeom);
 
-template <int KC, bool TAB>
-PathFn pick_desc(int M) {
+template <int KC, bool TAB, bool NT>
+PathFn pick_desc_nt(int M) {
     switch (M) {
-        case 0: return k_descriptor<KC, 0, TAB>;
-        case 1: return k_descriptor<KC, 1, TAB>;
-        case 2: return k_descriptor<KC, 2, TAB>;
-        default: return k_descriptor<KC, 3, TAB>;
+        case 0: return k_descriptor<KC, 0, TAB, NT>;
+        case 1: return k_descriptor<KC, 1, TAB, NT>;
+        case 2: return k_descriptor<KC, 2, TAB, NT>;
+        default: return k_descriptor<KC, 3, TAB, NT>;
     }
+}
+template <int KC, bool TAB>
+PathFn pick_desc(int M, bool nt) {
+    return nt ? pick_desc_nt<KC, TAB, true>(M) : pick_desc_nt<KC, TAB, false>(M);
 }
 template <int KC, bool TAB>
 AtomicFn pick_atomic(int M) {
@@ -788,12 +829,12 @@ BlockedFn pick_blocked(int M) {
 }
 
 template <bool TAB>
-PathFn select_desc(int kc, int M) {
+PathFn select_desc(int kc, int M, bool nt) {
     switch (kc) {
-        case 3: return pick_desc<3, TAB>(M);
-        case 4: return pick_desc<4, TAB>(M);
-        case 6: return pick_desc<6, TAB>(M);
-        default: return pick_desc<8, TAB>(M);
+        case 3: return pick_desc<3, TAB>(M, nt);
+        case 4: return pick_desc<4, TAB>(M, nt);
+        case 6: return pick_desc<6, TAB>(M, nt);
+        default: return pick_desc<8, TAB>(M, nt);
     }
 }
 template <bool TAB>
@@ -969,7 +1010,9 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     a.Pbuf = Pbuf;
     const int kcd = desc_kc(m);
     a.nch_log2 = log2_int(m->K / kcd);
-    auto fn = m->tab ? select_desc<true>(kcd, m->M) : select_desc<false>(kcd, m->M);
+    // P stores cover whole 128-byte lines (and go out non-temporally) with at most two chunks per atom
+    const bool nt = a.nch_log2 <= 1;
+    auto fn = m->tab ? select_desc<true>(kcd, m->M, nt) : select_desc<false>(kcd, m->M, nt);
     const int64_t nblocks = (nl->n * (m->K / kcd) + kBlock - 1) / kBlock;
     {
         ProfScope ps_(ctx, "descriptor");

@@ -410,6 +410,32 @@ def test_repeat_runs(tmd, ctx, torch):
     assert (F1 - F2).abs().max().item() <= 1e-5
 
 
+@pytest.mark.parametrize("hidden", [[64, 64], [64, 64, 64], [128]])
+def test_bf16_resident_weight_mlp(tmd, ctx, torch, hidden):
+    """Systems of 64k+ atoms run the BF16 network with every weight resident in
+    LDS (one workgroup per CU looping over 16-atom tiles): sampled atoms
+    against the oracle and the whole system against the FP32 path."""
+    s = inputs.make_system("fcc", 3.61, (26, 26, 26), 0.05, 2, seed=96)
+    spec = inputs.make_model(2, 8, 3, hidden, 5.5, seed=97)
+    _note(f"bf16 resident MLP hidden={hidden} n={s.n}")
+    E16, Ea16, F16, W16, ev = _gpu_eval(tmd, ctx, spec, s, tmd.BF16_MLP)
+    sel = np.random.default_rng(98).choice(s.n, 12, replace=False)
+    _check_ef(E16, Ea16, F16, W16, s, spec, E_TOL_BF16, F_TOL_BF16, sel=sel)
+    ev.model.set_precision(tmd.FP32)
+    pos, sp = _dev(torch, s)
+    E32, Ea32, F32, _ = ev.energy_forces(pos, sp, s.box)
+    Ea32 = Ea32.cpu().numpy().astype(np.float64)
+    F32 = F32.cpu().numpy().astype(np.float64)
+    # The BF16 bars are stated for the configurations' networks (|E_i| ~ 0.1 eV);
+    # this one's atomic energies are several times larger and BF16 rounding is
+    # relative, so the energy bars add 2^-8 of the mean |E_i|.
+    etol = E_TOL_BF16 + 2.0 ** -8 * np.abs(Ea32).mean()
+    print(f"  |E16-E32|/N={abs(E16 - E32) / s.n:.3e} (bar {etol:.3e})", flush=True)
+    assert abs(E16 - E32) / s.n <= etol
+    assert np.abs(Ea16 - Ea32).max() <= 20 * etol
+    assert math.sqrt(np.mean((F16 - F32) ** 2)) <= F_TOL_BF16
+
+
 # ------------------------------------------------------------------ full size (1,024,000 atoms)
 
 def test_bcc1m_sampled_parity(tmd, ctx, torch):
