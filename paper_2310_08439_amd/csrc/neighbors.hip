@@ -167,49 +167,56 @@ __global__ void k_place(int64_t n, const int32_t* __restrict__ cell_of, const in
     order[slot] = (int32_t)i;
 }
 
-// Insertion sort of each cell's atoms by original index: a deterministic order
-// independent of the atomic placement above.
-__global__ void k_sort_cells(int64_t ncells, const int32_t* __restrict__ start, int32_t* __restrict__ order) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
-    const int lo = start[c], hi = start[c + 1];
-    for (int a = lo + 1; a < hi; ++a) {
-        int32_t v = order[a];
-        int b = a - 1;
-        while (b >= lo && order[b] > v) {
-            order[b + 1] = order[b];
-            --b;
+// One wave per cell: the cell's atoms (in the arbitrary order the atomic
+// placement left) are ranked by original index, which fixes a deterministic
+// order, and each atom's wrapped position, image shift, species and cell are
+// gathered straight to its sorted slot start[cell] + rank.
+__global__ void __launch_bounds__(256) k_sort_gather(int64_t ncells, const int32_t* __restrict__ start,
+                                                     const int32_t* __restrict__ order, const double* __restrict__ wpos,
+                                                     const double* __restrict__ pos,
+                                                     const int32_t* __restrict__ species, GridArgs g,
+                                                     int32_t* __restrict__ perm, int32_t* __restrict__ shift,
+                                                     double4* __restrict__ xs, int32_t* __restrict__ sp,
+                                                     int32_t* __restrict__ cell_sorted) {
+    const int lane = threadIdx.x & 63;
+    const int64_t cell = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (cell >= ncells) return;  // whole wave
+    const int lo = start[cell], m = start[cell + 1] - lo;
+    for (int k0 = 0; k0 < m; k0 += 64) {
+        const int k = k0 + lane;
+        const int32_t v = k < m ? order[lo + k] : INT32_MAX;
+        int r = 0;  // entries of the cell with a smaller original index
+        for (int j0 = 0; j0 < m; j0 += 64) {
+            const int32_t vj = j0 + lane < m ? order[lo + j0 + lane] : INT32_MAX;
+            const int nj = min(64, m - j0);
+            for (int t = 0; t < nj; ++t) r += __shfl(vj, t) < v ? 1 : 0;
         }
-        order[b + 1] = v;
+        if (k < m) {
+            const int64_t p = lo + r;
+            const int32_t i = v;
+            perm[p] = i;
+            double w[3];
+            for (int a = 0; a < 3; ++a) {
+                w[a] = wpos[3 * (int64_t)i + a];
+                const double x = pos[3 * (int64_t)i + a];
+                const double kk = isfinite(x) ? rint((w[a] - x) / g.L[a]) : 0.0;
+                shift[3 * p + a] = (int32_t)kk;
+            }
+            xs[p] = make_double4(w[0], w[1], w[2], 0.0);
+            sp[p] = species[i];
+            cell_sorted[p] = (int32_t)cell;
+        }
     }
 }
 
-__global__ void k_gather_sorted(int64_t n, const int32_t* __restrict__ order, const double* __restrict__ wpos,
-                                const double* __restrict__ pos, const int32_t* __restrict__ species, GridArgs g,
-                                int32_t* __restrict__ perm, int32_t* __restrict__ shift, double4* __restrict__ xs,
-                                int32_t* __restrict__ sp, int32_t* __restrict__ cell_sorted,
-                                const int32_t* __restrict__ cell_of, int32_t* __restrict__ blkcnt) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = p < n;
-    int s = -1;
-    if (valid) {
-        const int32_t i = order[p];
-        perm[p] = i;
-        double w[3];
-        for (int a = 0; a < 3; ++a) {
-            w[a] = wpos[3 * i + a];
-            double x = pos[3 * i + a];
-            double k = isfinite(x) ? rint((w[a] - x) / g.L[a]) : 0.0;
-            shift[3 * p + a] = (int32_t)k;
-        }
-        xs[p] = make_double4(w[0], w[1], w[2], 0.0);
-        s = species[i];
-        sp[p] = s;
-        cell_sorted[p] = cell_of[i];
-    }
-    // per-block species counts (invalid species fail the build on the host and
-    // are not counted); scanned over blocks by k_species_scan
+// Per 256-atom block of the sorted order, the count of each species (invalid
+// species fail the build on the host and are not counted); scanned over
+// blocks by k_species_scan.
+__global__ void __launch_bounds__(256) k_species_blocks(int64_t n, const int32_t* __restrict__ sp,
+                                                        int32_t* __restrict__ blkcnt) {
     __shared__ int32_t wc[kBlock / 64][kMaxSpecies];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = p < n ? sp[p] : -1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int b = 0; b < kMaxSpecies; ++b) {
         const unsigned long long m = __ballot(s == b);
@@ -675,12 +682,13 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     }
     {
         ProfScope ps_(ctx, "nb_sort");
-        k_sort_cells<<<grid_for(ncells), kBlock, 0, st>>>(ncells, cellstart, order);
+        k_sort_gather<<<(unsigned)((ncells + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
+            ncells, cellstart, order, wpos, sys->pos, sys->species, g, nl->perm, nl->shift, nl->xs, nl->sp,
+            cell_sorted);
     }
     {
-        ProfScope ps_(ctx, "nb_gather");
-        k_gather_sorted<<<grid_for(n), kBlock, 0, st>>>(n, order, wpos, sys->pos, sys->species, g, nl->perm, nl->shift,
-                                                         nl->xs, nl->sp, cell_sorted, cell_of, blkcnt);
+        ProfScope ps_(ctx, "nb_species_blocks");
+        k_species_blocks<<<grid_for(n), kBlock, 0, st>>>(n, nl->sp, blkcnt);
     }
     {
         ProfScope ps_(ctx, "nb_species_scan");
