@@ -212,10 +212,24 @@ tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_sys
     tmd_status st = eval_buffers(ctx, m, nl, &b);
     if (st != TMD_OK) return st;
     if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
-    if ((st = launch_descriptors(ctx, m, nl, b.G, b.P)) != TMD_OK) return st;
+    // A list with a skin carries ~(1 + skin/rc)^3 - 1 more entries than the
+    // cutoff needs (60 % for 1 A on 6 A); the descriptor and adjoint loops
+    // then run over rows pruned to the cutoff at the current positions.
+    const tmd_nlist* use = nl;
+    tmd_nlist pruned;
+    if (nl->rlist > m->rcut * (1.0 + 1e-9)) {
+        tmd_nlist* mnl = const_cast<tmd_nlist*>(nl);  // the pruned rows are scratch owned by the list
+        if ((st = launch_prune(ctx, mnl, m->rcut)) != TMD_OK) return st;
+        pruned = *nl;  // a view: same atoms, cells and work order, pruned rows
+        pruned.nbr = nl->pnbr;
+        pruned.img = nl->pimg;
+        pruned.cnt = nl->pcnt;
+        use = &pruned;
+    }
+    if ((st = launch_descriptors(ctx, m, use, b.G, b.P)) != TMD_OK) return st;
     if ((st = launch_mlp(ctx, m, species_groups(nl), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
     int nvir = 0;
-    if ((st = launch_adjoint(ctx, m, nl, b.dG, b.P, b.Fs, b.vir, &nvir)) != TMD_OK) return st;
+    if ((st = launch_adjoint(ctx, m, use, b.dG, b.P, b.Fs, b.vir, &nvir)) != TMD_OK) return st;
     return launch_finalize(ctx, nl, b.Ei, b.Fs, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals);
 }
 
@@ -537,7 +551,7 @@ void tmd_nlist_destroy(tmd_nlist* nl) {
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)nl->perm, (void*)nl->shift, (void*)nl->xs, (void*)nl->sp, (void*)nl->nbr, (void*)nl->img,
                     (void*)nl->cnt, (void*)nl->sp_idx, (void*)nl->cellstart, (void*)nl->wperm, (void*)nl->wcell,
-                    (void*)nl->wbase})
+                    (void*)nl->wbase, (void*)nl->pnbr, (void*)nl->pimg, (void*)nl->pcnt})
         if (p) (void)hipFree(p);
     delete nl;
 }

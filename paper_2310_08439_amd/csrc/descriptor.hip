@@ -271,18 +271,6 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b
     }
 }
 
-// Workgroups are dispatched to the eight XCDs round-robin (workgroup b runs on
-// XCD b mod 8, each XCD with its own L2).  The logical block of a workgroup is
-// chosen so that each XCD walks one contiguous eighth of the blocks: sorted
-// atoms are cell-major, so an XCD's neighbour gathers stay in a compact slab
-// that its L2 holds.  The grid is rounded up to a multiple of 8; the padding
-// workgroups get -1.
-__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
-    const int64_t b = blockIdx.x, per = (nblocks + 7) / 8;
-    const int64_t l = (b % 8) * per + b / 8;
-    return l < nblocks ? l : -1;
-}
-
 template <int KC, int M, bool TAB, bool NT>
 __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D;
@@ -1016,7 +1004,7 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     const int64_t nblocks = (nl->n * (m->K / kcd) + kBlock - 1) / kBlock;
     {
         ProfScope ps_(ctx, "descriptor");
-        fn<<<(unsigned)((nblocks + 7) / 8 * 8), kBlock, 0, ctx->stream>>>(a, nblocks);
+        fn<<<xcd_grid(nblocks), kBlock, 0, ctx->stream>>>(a, nblocks);
     }
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;

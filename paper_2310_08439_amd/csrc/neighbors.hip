@@ -209,6 +209,108 @@ __global__ void __launch_bounds__(256) k_sort_gather(int64_t ncells, const int32
     }
 }
 
+// Rows of the list pruned to the cutoff at the current positions: each wave
+// takes kPruneRows consecutive rows (row t = p * S + b) and issues the loads of
+// all of them (counts, the first 64 entries and image words, then the
+// neighbour positions) before it compacts any, so that a wave waits for a few
+// memory round trips in total instead of a few per row; the rare entries past
+// the first 64 of a row follow one 64-entry chunk at a time.  Kept entries
+// keep their order.
+constexpr int kPruneRows = 4;
+
+// The full rows are read once and the pruned rows written once per step:
+// streamed past the caches, which keep the neighbour positions.
+__device__ __forceinline__ int32_t ld_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(int32_t* p, int32_t v) { __builtin_nontemporal_store(v, p); }
+
+__device__ __forceinline__ bool prune_keep(double xi, double yi, double zi, const double* xj, int32_t im, double L0,
+                                           double L1, double L2, double rc2) {
+    int nx, ny, nz;
+    unpack_img(im, nx, ny, nz);
+    const double dx = (xj[0] - xi) + (double)nx * L0;
+    const double dy = (xj[1] - yi) + (double)ny * L1;
+    const double dz = (xj[2] - zi) + (double)nz * L2;
+    return (dx * dx + dy * dy) + dz * dz < rc2;
+}
+
+__global__ void __launch_bounds__(256) k_prune(int64_t n, int S, int cap, double rc2, const double4* __restrict__ xs,
+                                               double L0, double L1, double L2, const int32_t* __restrict__ nbr,
+                                               const int32_t* __restrict__ img, const int32_t* __restrict__ cnt,
+                                               int32_t* __restrict__ pnbr, int32_t* __restrict__ pimg,
+                                               int32_t* __restrict__ pcnt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t rows = n * S;
+    // wave-uniform row range: counts and centre positions come in scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * kPruneRows;
+    if (t0 >= rows) return;  // whole wave
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int c[kPruneRows];
+    int64_t pr[kPruneRows];  // atom of each row (its species b = t - p * S)
+    int32_t q[kPruneRows], im[kPruneRows];
+    double xj[kPruneRows][3];
+    {
+        int64_t p = t0 / S;
+        int b = (int)(t0 - p * S);
+#pragma unroll
+        for (int r = 0; r < kPruneRows; ++r) {
+            const int64_t t = t0 + r;
+            const bool ok = t < rows;
+            pr[r] = ok ? p : 0;
+            c[r] = ok ? cnt[(int64_t)b * n + p] : 0;
+            if (++b == S) {
+                b = 0;
+                ++p;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kPruneRows; ++r) {
+        q[r] = lane < c[r] ? ld_stream(nbr + (t0 + r) * cap + lane) : 0;
+        im[r] = lane < c[r] ? ld_stream(img + (t0 + r) * cap + lane) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kPruneRows; ++r)
+        if (lane < c[r]) {
+            const double* x = reinterpret_cast<const double*>(xs + q[r]);
+            xj[r][0] = x[0];
+            xj[r][1] = x[1];
+            xj[r][2] = x[2];
+        }
+#pragma unroll
+    for (int r = 0; r < kPruneRows; ++r) {
+        const int64_t t = t0 + r;
+        const int64_t p = pr[r];
+        const double4 xi = xs[p];
+        const bool keep = lane < c[r] && prune_keep(xi.x, xi.y, xi.z, xj[r], im[r], L0, L1, L2, rc2);
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+            const int slot = (int)__popcll(m & below);
+            st_stream(pnbr + t * cap + slot, q[r]);
+            st_stream(pimg + t * cap + slot, im[r]);
+        }
+        int kept = (int)__popcll(m);
+        for (int k0 = 64; k0 < c[r]; k0 += 64) {  // c[r] is uniform: whole-wave loop
+            const int k = k0 + lane;
+            bool kk = false;
+            int32_t qq = 0, ii = 0;
+            if (k < c[r]) {
+                qq = nbr[t * cap + k];
+                ii = img[t * cap + k];
+                kk = prune_keep(xi.x, xi.y, xi.z, reinterpret_cast<const double*>(xs + qq), ii, L0, L1, L2, rc2);
+            }
+            const unsigned long long mm = __ballot(kk);
+            if (kk) {
+                const int slot = kept + (int)__popcll(mm & below);
+                pnbr[t * cap + slot] = qq;
+                pimg[t * cap + slot] = ii;
+            }
+            kept += (int)__popcll(mm);
+        }
+        if (lane == 0 && t < rows) pcnt[(t - p * S) * n + p] = kept;
+    }
+}
+
 // Per 256-atom block of the sorted order, the count of each species (invalid
 // species fail the build on the host and are not counted); scanned over
 // blocks by k_species_scan.
@@ -781,6 +883,33 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     }
     nl->built = true;
     return launch_work_order(ctx, nl);
+}
+
+tmd_status launch_prune(tmd_context* ctx, tmd_nlist* nl, double rcut) {
+    if (!nl->pnbr) {
+        const size_t lst = (size_t)nl->nmax * nl->S * nl->cap;
+        hipError_t e = hipMalloc((void**)&nl->pnbr, 4 * lst);
+        if (e == hipSuccess) e = hipMalloc((void**)&nl->pimg, 4 * lst);
+        if (e == hipSuccess) e = hipMalloc((void**)&nl->pcnt, 4 * (size_t)nl->nmax * nl->S);
+        if (e != hipSuccess) {
+            for (int32_t** q : {&nl->pnbr, &nl->pimg, &nl->pcnt}) {
+                if (*q) (void)hipFree(*q);
+                *q = nullptr;
+            }
+            return hip_fail(ctx, e, "pruned neighbour list allocation");
+        }
+    }
+    const double r = rcut * (1.0 + 1e-6);
+    const int64_t rows = nl->n * nl->S;
+    {
+        ProfScope ps_(ctx, "prune");
+        const int64_t waves = (rows + kPruneRows - 1) / kPruneRows;
+        k_prune<<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, ctx->stream>>>(
+            nl->n, nl->S, nl->cap, r * r, nl->xs, nl->box[0], nl->box[1], nl->box[2], nl->nbr, nl->img, nl->cnt,
+            nl->pnbr, nl->pimg, nl->pcnt);
+    }
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
 }
 
 tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl) {

@@ -104,8 +104,11 @@ int density_capacity(int64_t n, const double* box, double rlist, int S) {
     return std::max(16, (cap + 7) / 8 * 8);
 }
 
-size_t nlist_bytes(int64_t n, int S, int cap) {
-    return (size_t)n * 61 + (size_t)n * S * cap * 8 + (size_t)S * n * 4 + 8 * (size_t)(4 * n + 65);
+// Device bytes of a system's neighbour list; with a skin, evaluations also keep
+// the rows pruned to the cutoff (same size as the rows and counts).
+size_t nlist_bytes(int64_t n, int S, int cap, bool pruned) {
+    const size_t rows = (size_t)n * S * cap * 8 + (size_t)S * n * 4;
+    return (size_t)n * 61 + rows * (pruned ? 2 : 1) + 8 * (size_t)(4 * n + 65);
 }
 
 // Build (or rebuild) sys's list on ctx, growing it on overflow.
@@ -132,7 +135,7 @@ tmd_status build_list(tmd_server* sv, tmd_context* ctx, System* sys, int* rebuil
         if ((st = tmd_nlist_create(ctx, sys->n, m->S, cap, &nl)) != TMD_OK) return st;
         tmd_nlist_destroy(sys->nl);
         sys->nl = nl;
-        const size_t nb = nlist_bytes(sys->n, m->S, nl->cap);
+        const size_t nb = nlist_bytes(sys->n, m->S, nl->cap, sv->opts.skin > 0.0);
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             account(sv, (int64_t)nb - (int64_t)sys->nl_bytes);
@@ -248,7 +251,7 @@ bool pick(tmd_server* sv, Pending* out, System** sys_out, bool* rejected, Finish
             blocked.insert(sid);
             continue;
         }
-        int64_t need = sys->nl ? 0 : (int64_t)nlist_bytes(sys->n, sv->model->S, sys->cap);
+        int64_t need = sys->nl ? 0 : (int64_t)nlist_bytes(sys->n, sv->model->S, sys->cap, sv->opts.skin > 0.0);
         if (need > 0 && sv->mem_in_use + need > budget) {
             // evict idle lists, least recently used first
             std::vector<System*> idle;
@@ -324,7 +327,7 @@ void worker_main(tmd_server* sv, int slot) {
             st = tmd_nlist_create(ctx, sys->n, sv->model->S, sys->cap, &nl);
             if (st == TMD_OK) {
                 sys->nl = nl;
-                sys->nl_bytes = nlist_bytes(sys->n, sv->model->S, sys->cap);
+                sys->nl_bytes = nlist_bytes(sys->n, sv->model->S, sys->cap, sv->opts.skin > 0.0);
                 sys->nl_valid = false;
             }
         }
@@ -335,7 +338,8 @@ void worker_main(tmd_server* sv, int slot) {
             std::lock_guard<std::mutex> lk(sv->mu);
             if (st != TMD_OK) {
                 sv->last_error = ctx->last_error;
-                if (!sys->nl_bytes && sys->nl == nullptr) account(sv, -(int64_t)nlist_bytes(sys->n, sv->model->S, sys->cap));
+                if (!sys->nl_bytes && sys->nl == nullptr)
+                    account(sv, -(int64_t)nlist_bytes(sys->n, sv->model->S, sys->cap, sv->opts.skin > 0.0));
             }
             sys->busy = false;
             sys->last_use = ++sv->clock;
@@ -440,7 +444,8 @@ tmd_status tmd_serve_add_system(tmd_server* sv, int64_t n, const double* pos, co
     sys->state_bytes = (size_t)n * (24 * 3 + 12 + 4) + 16 * (size_t)S;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->mem_in_use + (int64_t)sys->state_bytes + (int64_t)nlist_bytes(n, S, sys->cap) > sv->opts.hbm_budget_bytes) {
+        const int64_t need = (int64_t)sys->state_bytes + (int64_t)nlist_bytes(n, S, sys->cap, sv->opts.skin > 0.0);
+        if (sv->mem_in_use + need > sv->opts.hbm_budget_bytes) {
             sv->last_error = "system state does not fit in the memory budget";
             return TMD_ERR_REJECTED;
         }

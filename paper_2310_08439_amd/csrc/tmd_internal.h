@@ -19,6 +19,19 @@ constexpr int kMaxSpecies = 8;
 constexpr int kBlockShape[3] = {4, 2, 2};
 constexpr int kBlock = 256;
 
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup b runs on
+// XCD b mod 8, each XCD with its own L2).  The logical block of a workgroup is
+// chosen so that each XCD walks one contiguous eighth of the blocks: sorted
+// atoms are cell-major, so an XCD's neighbour gathers stay in a compact slab
+// that its L2 holds.  The grid is rounded up to a multiple of 8; the padding
+// workgroups get -1.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+    const int64_t b = blockIdx.x, per = (nblocks + 7) / 8;
+    const int64_t l = (b % 8) * per + b / 8;
+    return l < nblocks ? l : -1;
+}
+inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)((nblocks + 7) / 8 * 8); }
+
 // Grow-only device buffers owned by a context, keyed by purpose.
 struct Workspace {
     std::unordered_map<std::string, std::pair<void*, size_t>> bufs;
@@ -159,6 +172,11 @@ struct tmd_nlist {
     uint8_t* wcell = nullptr;      // [nmax]
     int32_t* wbase = nullptr;      // [wbase_cap]
     int64_t wbase_cap = 0;
+    // Rows pruned to the model cutoff for lists built with a skin (same layout
+    // as nbr / img / cnt, allocated on first use, refilled at every evaluation).
+    int32_t* pnbr = nullptr;
+    int32_t* pimg = nullptr;
+    int32_t* pcnt = nullptr;
 };
 
 namespace tmd {
@@ -236,6 +254,11 @@ tmd_status launch_kick(tmd_context* ctx, int64_t n, double* v, const float* F, c
                        double dt);
 tmd_status launch_kinetic(tmd_context* ctx, int64_t n, const double* v, const int32_t* sp, const double* mass,
                           double* part, double* out4);
+
+// Copy of the list's rows keeping only the entries within rcut (times 1 + 1e-6)
+// at the current positions, into nl->pnbr / pimg / pcnt (allocated on first
+// use).  Every entry the kernels would use survives, in the same order.
+tmd_status launch_prune(tmd_context* ctx, tmd_nlist* nl, double rcut);
 
 // Work order for the descriptor and adjoint (see tmd_nlist::wo_valid); called
 // at the end of every successful list build.

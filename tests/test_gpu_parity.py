@@ -379,6 +379,28 @@ def test_list_reuse_after_small_moves(tmd, ctx, torch):
               E_TOL_FP32, F_TOL_FP32)
 
 
+@pytest.mark.parametrize("tab_dr", [0.0, 0.01])
+def test_pruned_rows_after_moves(tmd, ctx, torch, tab_dr):
+    """Skin lists are pruned to the cutoff at the current positions before the
+    descriptor and adjoint loops: two species, rows spanning several batches,
+    atoms moved by up to 0.3 A since the build, direct and tabulated radial
+    functions, against the oracle."""
+    import dataclasses
+    s = inputs.make_system("bcc", 3.16, (7, 7, 7), 0.06, 2, seed=96)
+    spec = dataclasses.replace(inputs.make_model(2, 16, 3, [64, 64], 5.5, seed=97), tab_dr=tab_dr)
+    _note(f"pruned rows n={s.n} tab_dr={tab_dr}")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, skin=1.2, ctx=ctx)
+    ev.build(pos, sp, s.box)
+    for it in range(2):
+        moved = s.pos + np.random.default_rng(98 + it).uniform(-0.3, 0.3, s.pos.shape)
+        pm = torch.tensor(moved, dtype=torch.float64, device="cuda")
+        E, Ea, F, W = ev.energy_forces(pm, sp, s.box, rebuild=False)
+        s2 = inputs.System(pos=moved, species=s.species, box=s.box, masses=s.masses)
+        _check_ef(E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, s2, spec,
+                  E_TOL_FP32, F_TOL_FP32)
+
+
 def test_forces_match_gpu_energy_differences(tmd, ctx, torch):
     s, spec, _ = inputs.workload("oracle32")
     _note("finite differences of the GPU energy")
