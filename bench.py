@@ -371,6 +371,31 @@ def time_precision(tmd, torch, ev, pos, sp, box, precision, steps, warmup):
     return (t1 - t0) / steps, prof, E
 
 
+def time_no_rebuild(tmd, torch, ev, pos, sp, box, precision, steps, warmup):
+    """E+F alone on the list built beforehand (no rebuild inside the timed region)."""
+    ev.model.set_precision(precision)
+    ev.build(pos, sp, box)
+    for _ in range(warmup):
+        ev.energy_forces(pos, sp, box, rebuild=False, atom_energy=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev.energy_forces(pos, sp, box, rebuild=False, atom_energy=False)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def whole_path_bound(spec, n_atoms: int, pairs: int) -> float:
+    """Seconds the E+F path needs at the published peaks: the contraction flops
+    of descriptor and adjoint (6*K*D per pair) on the FP32 vector units or the
+    minimum bytes per atom (positions 24, species 4, list 4 per pair, forces 12,
+    energy 4) from HBM, whichever is longer, plus the MLP flops on BF16 MFMA."""
+    f = algorithmic_flops(spec, n_atoms, pairs)
+    desc = (f["descriptor"] + f["adjoint"]) / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
+    hbm = n_atoms * (24 + 4 + 12 + 4 + 4 * pairs / n_atoms) / (PEAK_HBM_GBS * 1e9)
+    return max(desc, hbm) + f["mlp"] / (PEAK_BF16_MFMA_TFLOPS * 1e12)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,6 +446,11 @@ def main():
     for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
         sec, prof, E = time_precision(tmd, torch, ev, pos, sp, s.box, prec, args.steps, args.warmup)
         res[name] = {"sec": sec, "prof": prof, "E": E}
+
+    no_rebuild = {name: time_no_rebuild(tmd, torch, ev, pos, sp, s.box, prec, args.steps, args.warmup)
+                  for name, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32))}
+    ev.model.set_precision(tmd.BF16_MLP)
+    t_bound = whole_path_bound(spec, s.n, pairs)
 
     flops = algorithmic_flops(spec, s.n, pairs)
     prof = res["bf16"]["prof"]
@@ -486,6 +516,13 @@ def main():
                    "atoms": s.n, "pairs": pairs, "max_row": max_row, "parallelism": "single GPU"},
         "fp32": {"ns_per_step_atom": round(ns_fp32, 4), "ms_per_step": round(res["fp32"]["sec"] * 1e3, 4)},
         "bf16_speedup_vs_fp32": round(ns_fp32 / ns_bf16, 4),
+        "without_rebuild": {name: {"ns_per_step_atom": round(t / s.n * 1e9, 4), "ms_per_step": round(t * 1e3, 4)}
+                            for name, t in no_rebuild.items()},
+        "whole_path_bound": {"t_bound_ms": round(t_bound * 1e3, 4),
+                             "frac_with_rebuild": round(t_bound / res["bf16"]["sec"], 4),
+                             "frac_without_rebuild": round(t_bound / no_rebuild["bf16"], 4),
+                             "basis": f"max(6KD flops/pair on 157.3 TF FP32 vector, "
+                                      f"{44 + 4 * pairs / s.n:.0f} B/atom on 8 TB/s) + MLP flops on 2.5 PF BF16 MFMA"},
         "energy_per_atom": {"bf16": res["bf16"]["E"] / s.n, "fp32": res["fp32"]["E"] / s.n},
         "kernels_avg_ms": kernels,
         "accuracy_vs_oracle": acc,
