@@ -207,7 +207,7 @@ size_t eval_workspace_bytes(const tmd_model* m, int64_t n) {
 namespace {
 
 tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
-                             double* totals7_dev, float* atom_energy, float* forces) {
+                             double* totals7_dev, float* atom_energy, float* forces, const PruneGate* gate = nullptr) {
     EvalBuffers b;
     tmd_status st = eval_buffers(ctx, m, nl, &b);
     if (st != TMD_OK) return st;
@@ -219,7 +219,8 @@ tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_sys
     tmd_nlist pruned;
     if (nl->rlist > m->rcut * (1.0 + 1e-9)) {
         tmd_nlist* mnl = const_cast<tmd_nlist*>(nl);  // the pruned rows are scratch owned by the list
-        if ((st = launch_prune(ctx, mnl, m->rcut)) != TMD_OK) return st;
+        st = gate ? launch_prune_gated(ctx, mnl, m->rcut, *gate) : launch_prune(ctx, mnl, m->rcut);
+        if (st != TMD_OK) return st;
         pruned = *nl;  // a view: same atoms, cells and work order, pruned rows
         pruned.nbr = nl->pnbr;
         pruned.img = nl->pimg;
@@ -551,7 +552,7 @@ void tmd_nlist_destroy(tmd_nlist* nl) {
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)nl->perm, (void*)nl->shift, (void*)nl->xs, (void*)nl->sp, (void*)nl->nbr, (void*)nl->img,
                     (void*)nl->cnt, (void*)nl->sp_idx, (void*)nl->cellstart, (void*)nl->wperm, (void*)nl->wcell,
-                    (void*)nl->wbase, (void*)nl->pnbr, (void*)nl->pimg, (void*)nl->pcnt})
+                    (void*)nl->wbase, (void*)nl->pnbr, (void*)nl->pimg, (void*)nl->pcnt, (void*)nl->prune_state})
         if (p) (void)hipFree(p);
     delete nl;
 }
@@ -626,3 +627,16 @@ tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* m, const t
 }
 
 }  // extern "C"
+
+namespace tmd {
+
+tmd_status energy_forces_gated(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
+                               double* totals7, float* atom_energy, float* forces, const PruneGate* gate) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    tmd_status st = check_eval(ctx, m, sys, nl);
+    if (st != TMD_OK) return st;
+    if (!totals7 || !forces) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null totals or forces");
+    return run_energy_forces(ctx, m, sys, nl, totals7, atom_energy, forces, gate);
+}
+
+}  // namespace tmd

@@ -260,11 +260,27 @@ tmd_status md_thermo(tmd_md* md, tmd_thermo* out) {
     return TMD_OK;
 }
 
+// Skin lists are pruned to the cutoff plus a fifth of the skin and reused
+// while the displacements since the build allow (PruneGate); maxd2 holds the
+// largest squared displacement since the build for the current positions.
+PruneGate md_gate(const tmd_md* md) {
+    PruneGate g;
+    g.maxd2 = md->maxd2;
+    g.margin = 0.2 * md->opts.skin;
+    return g;
+}
+
+tmd_status md_energy_forces(tmd_md* md) {
+    tmd_system_view v = md_view(md);
+    const PruneGate g = md_gate(md);
+    return energy_forces_gated(md->ctx, md->model, &v, md->nl, md->tot7, nullptr, md->F,
+                               md->opts.skin > 0.0 ? &g : nullptr);
+}
+
 // Energy, forces and kinetic tensor at the current state.
 tmd_status md_evaluate(tmd_md* md) {
     tmd_context* ctx = md->ctx;
-    tmd_system_view v = md_view(md);
-    tmd_status st = tmd_energy_forces_async(ctx, md->model, &v, md->nl, md->tot7, nullptr, md->F);
+    tmd_status st = md_energy_forces(md);
     if (st != TMD_OK) return st;
     return launch_kinetic(ctx, md->n, md->v, md->sp, md->mass, md->part, md->ke4);
 }
@@ -339,6 +355,7 @@ tmd_status tmd_md_create(tmd_context* ctx, const tmd_model* model, const tmd_sys
     if (e == hipSuccess) e = hipMemcpyAsync(md->acc, acc.data(), 8 * (size_t)md->S, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(md->mass, masses, 8 * (size_t)md->S, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(md->state, st0, sizeof(st0), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(md->maxd2, 0, 8, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     tmd_status st = e == hipSuccess ? TMD_OK : hip_fail(ctx, e, "MD allocation");
     if (st == TMD_OK) {
@@ -380,9 +397,11 @@ tmd_status tmd_md_run(tmd_md* md, int64_t n_steps, int32_t thermo_every, tmd_the
     const bool by_distance = md->opts.rebuild_every == 0;
     for (int64_t s = 0; s < n_steps; ++s) {
         if ((st = md_thermostat(md)) != TMD_OK) return st;
-        if (by_distance) TMD_HIP(ctx, hipMemsetAsync(md->maxd2, 0, 8, ctx->stream));
-        if ((st = launch_kick_drift(ctx, md->n, md->x, md->v, md->F, md->sp, md->acc, dt, md->xref,
-                                    by_distance ? md->maxd2 : nullptr)) != TMD_OK)
+        // the displacement since the build decides rebuilds (by_distance) and
+        // whether the pruned rows can be reused
+        TMD_HIP(ctx, hipMemsetAsync(md->maxd2, 0, 8, ctx->stream));
+        if ((st = launch_kick_drift(ctx, md->n, md->x, md->v, md->F, md->sp, md->acc, dt, md->xref, md->maxd2)) !=
+            TMD_OK)
             return st;
         ++md->steps_since_build;
         bool rebuild = false;
@@ -396,8 +415,7 @@ tmd_status tmd_md_run(tmd_md* md, int64_t n_steps, int32_t thermo_every, tmd_the
             rebuild = md->steps_since_build >= md->opts.rebuild_every;
         }
         if (rebuild && (st = md_build(md)) != TMD_OK) return st;
-        tmd_system_view v = md_view(md);
-        if ((st = tmd_energy_forces_async(ctx, md->model, &v, md->nl, md->tot7, nullptr, md->F)) != TMD_OK) return st;
+        if ((st = md_energy_forces(md)) != TMD_OK) return st;
         if ((st = launch_kick(ctx, md->n, md->v, md->F, md->sp, md->acc, dt)) != TMD_OK) return st;
         if ((st = launch_kinetic(ctx, md->n, md->v, md->sp, md->mass, md->part, md->ke4)) != TMD_OK) return st;
         if ((st = md_thermostat(md)) != TMD_OK) return st;

@@ -237,7 +237,8 @@ __global__ void __launch_bounds__(256) k_prune(int64_t n, int S, int cap, double
                                                double L0, double L1, double L2, const int32_t* __restrict__ nbr,
                                                const int32_t* __restrict__ img, const int32_t* __restrict__ cnt,
                                                int32_t* __restrict__ pnbr, int32_t* __restrict__ pimg,
-                                               int32_t* __restrict__ pcnt) {
+                                               int32_t* __restrict__ pcnt, const int32_t* __restrict__ gate) {
+    if (gate && gate[0] == 0) return;  // uniform: the pruned rows are still valid
     const int lane = threadIdx.x & 63;
     const int64_t rows = n * S;
     // wave-uniform row range: counts and centre positions come in scalar loads
@@ -308,6 +309,19 @@ __global__ void __launch_bounds__(256) k_prune(int64_t n, int S, int cap, double
             kept += (int)__popcll(mm);
         }
         if (lane == 0 && t < rows) pcnt[(t - p * S) * n + p] = kept;
+    }
+}
+
+// One thread: does this evaluation need new pruned rows (see PruneGate)?
+__global__ void k_prune_gate(const unsigned long long* __restrict__ maxd2, double* __restrict__ state,
+                             int32_t* __restrict__ flag, int force, double half_margin) {
+    if (threadIdx.x != 0) return;
+    const double d = sqrt(__longlong_as_double((long long)maxd2[0]));
+    if (force || !(d + state[0] < half_margin)) {
+        flag[0] = 1;
+        state[0] = force ? 0.0 : d;  // a forced prune follows a build: no displacement yet
+    } else {
+        flag[0] = 0;
     }
 }
 
@@ -882,34 +896,62 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         nl->reach[a] = g.reach[a];
     }
     nl->built = true;
+    ++nl->build_id;
     return launch_work_order(ctx, nl);
 }
 
-tmd_status launch_prune(tmd_context* ctx, tmd_nlist* nl, double rcut) {
-    if (!nl->pnbr) {
-        const size_t lst = (size_t)nl->nmax * nl->S * nl->cap;
-        hipError_t e = hipMalloc((void**)&nl->pnbr, 4 * lst);
-        if (e == hipSuccess) e = hipMalloc((void**)&nl->pimg, 4 * lst);
-        if (e == hipSuccess) e = hipMalloc((void**)&nl->pcnt, 4 * (size_t)nl->nmax * nl->S);
-        if (e != hipSuccess) {
-            for (int32_t** q : {&nl->pnbr, &nl->pimg, &nl->pcnt}) {
-                if (*q) (void)hipFree(*q);
-                *q = nullptr;
-            }
-            return hip_fail(ctx, e, "pruned neighbour list allocation");
+namespace {
+
+tmd_status reserve_pruned(tmd_context* ctx, tmd_nlist* nl) {
+    if (nl->pnbr) return TMD_OK;
+    const size_t lst = (size_t)nl->nmax * nl->S * nl->cap;
+    hipError_t e = hipMalloc((void**)&nl->pnbr, 4 * lst);
+    if (e == hipSuccess) e = hipMalloc((void**)&nl->pimg, 4 * lst);
+    if (e == hipSuccess) e = hipMalloc((void**)&nl->pcnt, 4 * (size_t)nl->nmax * nl->S);
+    if (e == hipSuccess) e = hipMalloc((void**)&nl->prune_state, 16);
+    if (e != hipSuccess) {
+        for (void** q : {(void**)&nl->pnbr, (void**)&nl->pimg, (void**)&nl->pcnt, (void**)&nl->prune_state}) {
+            if (*q) (void)hipFree(*q);
+            *q = nullptr;
         }
+        return hip_fail(ctx, e, "pruned neighbour list allocation");
     }
-    const double r = rcut * (1.0 + 1e-6);
+    nl->prune_flag = reinterpret_cast<int32_t*>(nl->prune_state + 1);
+    return TMD_OK;
+}
+
+tmd_status prune_rows(tmd_context* ctx, tmd_nlist* nl, double r, const int32_t* gate) {
     const int64_t rows = nl->n * nl->S;
     {
         ProfScope ps_(ctx, "prune");
         const int64_t waves = (rows + kPruneRows - 1) / kPruneRows;
         k_prune<<<(unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, ctx->stream>>>(
             nl->n, nl->S, nl->cap, r * r, nl->xs, nl->box[0], nl->box[1], nl->box[2], nl->nbr, nl->img, nl->cnt,
-            nl->pnbr, nl->pimg, nl->pcnt);
+            nl->pnbr, nl->pimg, nl->pcnt, gate);
     }
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;
+}
+
+}  // namespace
+
+tmd_status launch_prune(tmd_context* ctx, tmd_nlist* nl, double rcut) {
+    tmd_status st = reserve_pruned(ctx, nl);
+    if (st != TMD_OK) return st;
+    nl->pruned_margin = -1.0;
+    return prune_rows(ctx, nl, rcut * (1.0 + 1e-6), nullptr);
+}
+
+tmd_status launch_prune_gated(tmd_context* ctx, tmd_nlist* nl, double rcut, const PruneGate& g) {
+    if (!g.maxd2 || !(g.margin > 0.0)) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "prune gate without displacements");
+    tmd_status st = reserve_pruned(ctx, nl);
+    if (st != TMD_OK) return st;
+    const int force = (nl->pruned_build_id != nl->build_id || nl->pruned_margin != g.margin) ? 1 : 0;
+    k_prune_gate<<<1, 64, 0, ctx->stream>>>(g.maxd2, nl->prune_state, nl->prune_flag, force, 0.5 * g.margin);
+    TMD_HIP(ctx, hipGetLastError());
+    nl->pruned_build_id = nl->build_id;
+    nl->pruned_margin = g.margin;
+    return prune_rows(ctx, nl, rcut + g.margin, nl->prune_flag);
 }
 
 tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl) {

@@ -172,11 +172,18 @@ struct tmd_nlist {
     uint8_t* wcell = nullptr;      // [nmax]
     int32_t* wbase = nullptr;      // [wbase_cap]
     int64_t wbase_cap = 0;
-    // Rows pruned to the model cutoff for lists built with a skin (same layout
-    // as nbr / img / cnt, allocated on first use, refilled at every evaluation).
+    // Rows pruned for lists built with a skin (same layout as nbr / img /
+    // cnt, allocated on first use): to the model cutoff at every evaluation,
+    // or, when the caller tracks displacements (PruneGate), to the cutoff plus
+    // a margin and only when the last such copy may have lost a pair.
     int32_t* pnbr = nullptr;
     int32_t* pimg = nullptr;
     int32_t* pcnt = nullptr;
+    double* prune_state = nullptr;  // device: displacement since the build at the last margin prune
+    int32_t* prune_flag = nullptr;  // device: 1 when this evaluation prunes
+    int64_t build_id = 0;           // count of builds
+    int64_t pruned_build_id = -1;   // build the pruned rows come from (margin prunes only)
+    double pruned_margin = -1.0;    // margin of the pruned rows (-1: pruned to the cutoff)
 };
 
 namespace tmd {
@@ -259,6 +266,24 @@ tmd_status launch_kinetic(tmd_context* ctx, int64_t n, const double* v, const in
 // at the current positions, into nl->pnbr / pimg / pcnt (allocated on first
 // use).  Every entry the kernels would use survives, in the same order.
 tmd_status launch_prune(tmd_context* ctx, tmd_nlist* nl, double rcut);
+
+// Displacement tracking that lets pruned rows be reused: maxd2 (device) holds
+// the bits of the largest squared displacement of any atom since the list was
+// built, for the positions being evaluated.  Rows pruned to rcut + margin when
+// the largest displacement since the build was d_p keep every pair within
+// rcut while d + d_p < margin / 2 (each of a pair's atoms moved by at most
+// d + d_p since the prune), so they are rebuilt only when that fails.
+struct PruneGate {
+    const unsigned long long* maxd2;
+    double margin;
+};
+// launch_prune with a gate: the decision is taken on the device (no host
+// synchronisation); a new build always prunes.
+tmd_status launch_prune_gated(tmd_context* ctx, tmd_nlist* nl, double rcut, const PruneGate& g);
+// E+F on the stream with device-resident totals (totals7: E, W[6]); gate may
+// be null (skin lists are then pruned to the cutoff at every call).
+tmd_status energy_forces_gated(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
+                               double* totals7, float* atom_energy, float* forces, const PruneGate* gate);
 
 // Work order for the descriptor and adjoint (see tmd_nlist::wo_valid); called
 // at the end of every successful list build.

@@ -131,6 +131,32 @@ def test_md_periodic_rebuild_equals_displacement_rule(tmd, ctx, torch):
     assert abs(out[0][1]["etotal"] - out[1][1]["etotal"]) <= 1e-6 * s.n
 
 
+@pytest.mark.parametrize("rebuild_every", [0, 30])
+def test_md_reused_pruned_rows_follow_a_fast_atom(tmd, ctx, torch, rebuild_every):
+    """The MD driver prunes a skin list to r_c + skin/5 and reuses those rows
+    until the displacement since the build could have brought a dropped pair
+    inside r_c.  One atom crosses 0.75 A in 15 steps (the threshold is 0.2 A,
+    and the list itself is rebuilt only after 1 A or 30 steps): the trajectory
+    must still follow the oracle's, which has no lists to reuse."""
+    _note(f"MD fast atom, pruned rows reused, rebuild_every={rebuild_every}")
+    s, spec, _ = inputs.workload("oracle32")
+    v0 = inputs.maxwell_boltzmann(np.full(s.n, CU), 300.0, seed=66)
+    v0[5] = [0.05, -0.01, 0.02]  # A/fs
+    model = tmd.Model(ctx, spec)
+    pos, sp, vel = _dev(torch, s, v0)
+    md = tmd.MD(ctx, model, pos, sp, s.box, s.masses, vel, dt_fs=1.0, ensemble=tmd.ENSEMBLE_NVE, skin=2.0,
+                rebuild_every=rebuild_every)
+    th = md.run(15, thermo_every=15)
+    x, v = (t.cpu().numpy() for t in md.state())
+    xr, vr, epot, ekin = oracle.nve(spec, s.pos, v0, s.species, s.masses, s.box, 1.0, 15)
+    print(f"  max |dx|={np.abs(x - xr).max():.3e}  rebuilds={th[-1]['rebuilds']}", flush=True)
+    assert th[-1]["rebuilds"] == 1  # the first build only: every other step reused the list
+    np.testing.assert_allclose(x, xr, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(v, vr, rtol=0, atol=1e-7)
+    assert abs(th[-1]["epot"] - epot[-1]) / s.n <= 1e-5
+    md.close()
+
+
 def test_md_nvt_long_run(tmd, ctx, torch):
     _note("MD NVT 2000 steps")
     s = inputs.make_system("fcc", 3.61, (3, 3, 3), 0.1, 1, seed=64, masses=[CU])
