@@ -204,7 +204,14 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
                 sys->nl_valid = false;
                 if ((st = build_list(sv, ctx, sys, &rebuilds)) != TMD_OK) return st;
             }
-            if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F)) != TMD_OK)
+            // b.maxd2 now holds this system's displacement since its build: the
+            // pruned rows are reused while it allows (the request's first
+            // evaluation pruned to the cutoff, so the first step here prunes)
+            PruneGate gate;
+            gate.maxd2 = b.maxd2;
+            gate.margin = 0.2 * sv->opts.skin;
+            if ((st = energy_forces_gated(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F,
+                                          sv->opts.skin > 0.0 ? &gate : nullptr)) != TMD_OK)
                 return st;
             if ((st = launch_kick(ctx, sys->n, sys->v, sys->F, sys->sp, sys->acc, dt)) != TMD_OK) return st;
             if ((st = kinetic(ctx, sys, b.part, b.ekin + 4 * s)) != TMD_OK) return st;
