@@ -191,6 +191,26 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
             raise RuntimeError(f"serving request failed: {r}")
         results.append(r)
         srv.release(tk)
+    # closed loop: a burst of requests drawn the same way, all queued at once,
+    # so that every slot stays busy; peak atom-steps/s over the burst
+    burst = []
+    for k in range(max(1, n_requests // 3)):
+        sid, n, m = systems[int(rng.integers(pool))]
+        md = rng.random() < 0.5
+        vel = inputs.maxwell_boltzmann(m, 300.0, seed=int(rng.integers(1 << 31))) if md else None
+        burst.append((sid, md, vel))
+    t0 = time.perf_counter()
+    btk = [srv.submit(sid, tmd.REQ_MD, 10, 1.0, vel) if md else srv.submit(sid) for (sid, md, vel) in burst]
+    bres = []
+    for tk in btk:
+        r = srv.wait(tk, 300.0)
+        if r is None or r["status"] != 0:
+            raise RuntimeError(f"serving request failed: {r}")
+        bres.append(r)
+        srv.release(tk)
+    bwall = time.perf_counter() - t0
+    saturation = {"requests": len(burst), "wall_s": round(bwall, 3),
+                  "atom_steps_per_s": round(sum(r["n_atoms"] * max(1, r["n_steps"]) for r in bres) / bwall, 1)}
     mem, peak = srv.memory()
     srv.close()
     meas = results[n_warmup:]
@@ -205,6 +225,7 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_latency_ms": round(float(lat.mean()), 3),
             "atom_steps_per_s": round(atom_steps / wall, 1),
+            "closed_loop_saturation": saturation,
             "device_bytes_peak": int(peak)}
 
 

@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
 
 // Atoms grouped by species in sorted order, without atomics: block offsets
 // from k_species_scan, wave offsets from the block's ballots, lane rank.
-__global__ void k_species_place(int64_t n, const int32_t* __restrict__ sp, const int64_t* __restrict__ sp_off,
+__global__ void k_species_place(int64_t n, int S, const int32_t* __restrict__ sp, const int32_t* __restrict__ spcount,
                                 const int32_t* __restrict__ blkoff, int32_t* __restrict__ sp_idx) {
     __shared__ int32_t wc[kBlock / 64][kMaxSpecies];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -648,10 +648,12 @@ __global__ void k_species_place(int64_t n, const int32_t* __restrict__ sp, const
         if (s == b) mine = m;
     }
     __syncthreads();
-    if (s >= 0 && s < kMaxSpecies) {
+    if (s >= 0 && s < S) {  // an invalid species fails the build on the host; it is not placed
         int32_t woff = 0;
         for (int w = 0; w < wv; ++w) woff += wc[w][s];
-        sp_idx[sp_off[s] + blkoff[(int64_t)blockIdx.x * kMaxSpecies + s] + woff + (int)__popcll(mine & below)] =
+        int64_t base = 0;  // atoms of the species before s
+        for (int b = 0; b < s; ++b) base += spcount[b];
+        sp_idx[base + blkoff[(int64_t)blockIdx.x * kMaxSpecies + s] + woff + (int)__popcll(mine & below)] =
             (int32_t)p;
     }
 }
@@ -695,17 +697,36 @@ __global__ void k_refresh(int64_t n, const double* __restrict__ pos, const int32
     xs[p] = make_double4(x, y, z, 0.0);
 }
 
-__global__ void k_count_stats(int64_t total, const int32_t* __restrict__ cnt, unsigned long long* __restrict__ sum,
-                              int32_t* __restrict__ mx) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = q < total ? cnt[q] : 0;
-    int s = v, m = v;
+// Sum and maximum of the row counts: grid-stride, one pair of atomics per
+// workgroup (a pair per wave made 2 M rows cost 0.75 ms of serialised atomics).
+constexpr int kStatsGroups = 256;
+__global__ void __launch_bounds__(256) k_count_stats(int64_t total, const int32_t* __restrict__ cnt,
+                                                     unsigned long long* __restrict__ sum, int32_t* __restrict__ mx) {
+    __shared__ unsigned long long ws[kBlock / 64];
+    __shared__ int32_t wm[kBlock / 64];
+    unsigned long long s = 0;
+    int m = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int v = cnt[q];
+        s += (unsigned long long)v;
+        m = max(m, v);
+    }
     for (int off = 32; off > 0; off >>= 1) {
         s += __shfl_xor(s, off);
         m = max(m, __shfl_xor(m, off));
     }
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(sum, (unsigned long long)s);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        ws[wv] = s;
+        wm[wv] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            s += ws[w];
+            m = max(m, wm[w]);
+        }
+        atomicAdd(sum, s);
         atomicMax(mx, m);
     }
 }
@@ -764,7 +785,6 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     int32_t* blkcnt = (int32_t*)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
     int32_t* blkoff = (int32_t*)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
     int32_t* flags = (int32_t*)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
-    int64_t* sp_off_d = (int64_t*)ctx->ws.get("nb.sp_off", sizeof(int64_t) * (kMaxSpecies + 1), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "neighbour workspace allocation");
     hipStream_t st = ctx->stream;
     int32_t* spcount = flags + 8;
@@ -809,6 +829,10 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     {
         ProfScope ps_(ctx, "nb_species_scan");
         k_species_scan<<<1, 1024, 0, st>>>(nblk, nl->S, blkcnt, blkoff, spcount);
+    }
+    {
+        ProfScope ps_(ctx, "nb_species");
+        k_species_place<<<grid_for(n), kBlock, 0, st>>>(n, nl->S, nl->sp, spcount, blkoff, nl->sp_idx);
     }
     FillArgs fa;
     fa.g = g;
@@ -877,13 +901,6 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         off += nl->sp_count[s];
     }
     nl->sp_off[nl->S] = off;
-    TMD_HIP(ctx, hipMemcpyAsync(sp_off_d, nl->sp_off, sizeof(int64_t) * (kMaxSpecies + 1), hipMemcpyHostToDevice, st));
-    {
-        ProfScope ps_(ctx, "nb_species");
-        k_species_place<<<grid_for(n), kBlock, 0, st>>>(n, nl->sp, sp_off_d, blkoff, nl->sp_idx);
-    }
-    TMD_HIP(ctx, hipGetLastError());
-    TMD_HIP(ctx, hipStreamSynchronize(st));
     nl->n = n;
     nl->rlist = rlist;
     nl->ncells = ncells;
@@ -980,7 +997,6 @@ tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S) {
     (void)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
     (void)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
     (void)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
-    (void)ctx->ws.get("nb.sp_off", sizeof(int64_t) * (kMaxSpecies + 1), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "neighbour workspace allocation");
     return TMD_OK;
 }
@@ -1001,7 +1017,8 @@ tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* to
     TMD_HIP(ctx, hipMemsetAsync(buf, 0, 16, ctx->stream));
     {
         ProfScope ps_(ctx, "nb_stats");
-        k_count_stats<<<grid_for(total), kBlock, 0, ctx->stream>>>(total, nl->cnt, sum, mx);
+        k_count_stats<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(kStatsGroups, grid_for(total))), kBlock, 0,
+                        ctx->stream>>>(total, nl->cnt, sum, mx);
     }
     TMD_HIP(ctx, hipGetLastError());
     TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, buf, 16, hipMemcpyDeviceToHost, ctx->stream));

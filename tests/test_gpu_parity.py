@@ -144,6 +144,8 @@ def test_neighbors_bitexact(tmd, ctx, torch, case):
     assert np.array_equal(gcnt, wcnt)
     assert got.shape == want.shape
     assert np.array_equal(got, want)
+    pairs, max_row = tmd.nlist_stats(ctx, nl)  # the on-device reduction of the row counts
+    assert pairs == int(wcnt.sum()) and max_row == int(wcnt.max())
 
 
 def test_capacity_overflow_reports_requirement(tmd, ctx, torch):
