@@ -198,7 +198,10 @@ tmd_status tmd_descriptors(tmd_context* ctx, const tmd_model* model, const tmd_s
 /* Energy, forces and virial (Sec. III.A).  energy: host FP64 total (Neumaier-
  * compensated sum of atomic energies); atom_energy: device [n] FP32 or NULL;
  * forces: device [n][3] FP32 (F = -dE/dx); virial6: host FP64 [6] or NULL.
- * Synchronises the stream. */
+ * With a list built with a skin, each call first copies the list's rows
+ * keeping the entries within rcut at the current positions (scratch owned by
+ * the list, as large as its rows, allocated at the first such call; an
+ * allocation failure returns TMD_ERR_OUT_OF_MEMORY).  Synchronises the stream. */
 tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
                              const tmd_nlist* nl, double* energy, float* atom_energy, float* forces,
                              double* virial6);
@@ -298,7 +301,9 @@ typedef enum { TMD_ENSEMBLE_NVE = 0, TMD_ENSEMBLE_NVT_NOSE_HOOVER = 1 } tmd_ense
  * rebuild_every > 0: rebuild the list every that many steps (the caller
  * guarantees that no atom moves more than skin/2 in between); 0: rebuild when
  * an atom has moved more than skin/2 since the last build (one host
- * synchronisation per step). */
+ * synchronisation per step).  With a skin, the force evaluations walk rows
+ * pruned to rcut + skin/5, rebuilt on the device whenever the displacement
+ * since the build could have brought a dropped pair inside rcut. */
 typedef struct {
     double dt_fs;
     double temperature_K;
