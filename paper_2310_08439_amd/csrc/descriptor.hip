@@ -155,6 +155,54 @@ __device__ __forceinline__ void load_pairs(const PathArgs& a, int64_t row, int c
     }
 }
 
+// The value of the neighbouring lane (lane ^ 1), by a DPP quad permutation
+// [1, 0, 3, 2] (no LDS crossbar).
+__device__ __forceinline__ float swap_pair(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// load_pairs for an atom whose list is walked by two adjacent lanes (its two
+// radial chunks; both lanes see the same row): each lane fetches every other
+// neighbour position and forms its displacement, and the two swap results, so
+// the row's position gathers and FP64 geometry are done once per atom rather
+// than once per lane.  The values are those of load_pairs bit for bit.
+template <int NB, class Pos>
+__device__ __forceinline__ void load_pairs_split2(const PathArgs& a, int64_t row, int c0, int nb, Pair (&pr)[NB],
+                                                  const Pos& pos, int odd) {
+    static_assert(NB % 2 == 0, "pairs are shared two at a time");
+    int q[NB], im[NB];
+    IntVec<NB>::split(*reinterpret_cast<const typename IntVec<NB>::T*>(a.nbr + row + c0), q);
+    IntVec<NB>::split(*reinterpret_cast<const typename IntVec<NB>::T*>(a.img + row + c0), im);
+#pragma unroll
+    for (int j = 1; j < NB; ++j)
+        if (c0 + j >= nb) {
+            q[j] = q[0];
+            im[j] = im[0];
+        }
+    decltype(pos.fetch(0, 0)) xj[NB / 2];  // entries 2t + odd
+#pragma unroll
+    for (int t = 0; t < NB / 2; ++t) xj[t] = pos.fetch(odd ? q[2 * t + 1] : q[2 * t], odd ? im[2 * t + 1] : im[2 * t]);
+#pragma unroll
+    for (int t = 0; t < NB / 2; ++t) {
+        const float3 mine = pos.disp(xj[t], odd ? im[2 * t + 1] : im[2 * t]);
+        const float3 other = make_float3(swap_pair(mine.x), swap_pair(mine.y), swap_pair(mine.z));
+        const float3 d0 = odd ? other : mine, d1 = odd ? mine : other;
+        pr[2 * t].dx = d0.x;
+        pr[2 * t].dy = d0.y;
+        pr[2 * t].dz = d0.z;
+        pr[2 * t + 1].dx = d1.x;
+        pr[2 * t + 1].dy = d1.y;
+        pr[2 * t + 1].dz = d1.z;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        pr[j].r2 = (c0 + j < nb) ? pr[j].dx * pr[j].dx + pr[j].dy * pr[j].dy + pr[j].dz * pr[j].dz
+                                 : __builtin_inff();
+        pr[j].q = q[j];
+        pr[j].code = img_ocode(im[j]);
+    }
+}
+
 constexpr int kBatchFwd = 4;
 constexpr int kBatchAdj = 2;
 
@@ -244,7 +292,10 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b
     const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
     for (int c0 = 0; c0 < nb; c0 += kBatchFwd) {
       Pair prs[kBatchFwd];
-      load_pairs<kBatchFwd>(a, base, c0, nb, prs, pos);
+      if (a.nch_log2 == 1)  // uniform: two chunk lanes per atom share the geometry
+          load_pairs_split2<kBatchFwd>(a, base, c0, nb, prs, pos, (k0 / KC) & 1);
+      else
+          load_pairs<kBatchFwd>(a, base, c0, nb, prs, pos);
 #pragma unroll
       for (int j = 0; j < kBatchFwd; ++j) {
         const Pair& pr = prs[j];
@@ -420,6 +471,8 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
                 float gx = s1 * ux + rinv * (Ax - ux * B);
                 float gy = s1 * uy + rinv * (Ay - uy * B);
                 float gz = s1 * uz + rinv * (Az - uz * B);
+                // shuffles (LDS crossbar) rather than DPP: this loop is VALU-bound and
+                // the LDS pipe has room (DPP measured 2.20 -> 2.44 ms at 1 M atoms)
                 for (int off = 1; off < nch; off <<= 1) {
                     gx += __shfl_xor(gx, off);
                     gy += __shfl_xor(gy, off);
