@@ -123,6 +123,9 @@ NB_CASES = {
     "fcc4_tiny_box_rc6": lambda: (inputs.make_system("fcc", 3.61, (1, 1, 1), 0.05, 1, seed=31), 6.0, 0.0),
     "hcp_ortho_rc5": lambda: (inputs.make_system("hcp", 2.553, (3, 2, 2), 0.1, 3, seed=32), 5.0, 0.5),
     "fcc32k_rc6": lambda: (inputs.workload("fcc32k")[0], 6.0, 0.0),
+    # cells of ~107 atoms: more than one wave tracks, so the build falls back
+    # to the per-atom fill
+    "fcc2916_rc10_crowded_cells": lambda: (inputs.make_system("fcc", 3.61, (9, 9, 9), 0.05, 2, seed=33), 10.0, 0.0),
 }
 
 
@@ -353,6 +356,16 @@ def test_energy_forces_cell_geometries(tmd, ctx, torch, case):
         s = inputs.make_system("bcc", 3.16, (6, 6, 6), 0.08, 2, seed=94)
         spec = inputs.make_model(2, 12, 3, [64, 64], 5.5, seed=95)
     _note(f"cell geometry {case} n={s.n} box={s.box}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
+    _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+
+
+def test_energy_forces_crowded_cells(tmd, ctx, torch):
+    """r_c = 10 A on fcc: ~107 atoms per cell (per-atom fill fallback) and
+    halos too large for the preferred cell block of the adjoint."""
+    s = inputs.make_system("fcc", 3.61, (9, 9, 9), 0.05, 2, seed=34)
+    spec = inputs.make_model(2, 8, 3, [32, 32], 10.0, seed=35)
+    _note(f"crowded cells n={s.n} rc=10")
     E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, tmd.FP32)
     _check_ef(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
 
