@@ -57,32 +57,25 @@ template <int M>
 __device__ __forceinline__ void moment_adjoint(float x, float y, float z, const float* V, const float* Mv,
                                                float& Ax, float& Ay, float& Az, float& B) {
     Ax = Ay = Az = 0.0f;
-    B = 0.0f;
     if constexpr (M >= 1) {
         Ax = V[1];
         Ay = V[2];
         Az = V[3];
-        B = V[1] * x + V[2] * y + V[3] * z;
     }
     if constexpr (M >= 2) {
         Ax += 2.0f * x * V[4] + y * V[5] + z * V[6];
         Ay += x * V[5] + 2.0f * y * V[7] + z * V[8];
         Az += x * V[6] + y * V[8] + 2.0f * z * V[9];
-        float b2 = 0.0f;
-#pragma unroll
-        for (int d = 4; d < 10; ++d) b2 += V[d] * Mv[d];
-        B += 2.0f * b2;
     }
     if constexpr (M >= 3) {
         const float xx = Mv[4], xy = Mv[5], xz = Mv[6], yy = Mv[7], yz = Mv[8], zz = Mv[9];
         Ax += 3.0f * xx * V[10] + 2.0f * xy * V[11] + 2.0f * xz * V[12] + yy * V[13] + yz * V[14] + zz * V[15];
         Ay += xx * V[11] + 2.0f * xy * V[13] + xz * V[14] + 3.0f * yy * V[16] + 2.0f * yz * V[17] + zz * V[18];
         Az += xx * V[12] + xy * V[14] + 2.0f * xz * V[15] + yy * V[17] + 2.0f * yz * V[18] + 3.0f * zz * V[19];
-        float b3 = 0.0f;
-#pragma unroll
-        for (int d = 10; d < 20; ++d) b3 += V[d] * Mv[d];
-        B += 3.0f * b3;
     }
+    // sum_d ord(d) V_d M_d = u . A: the monomials of order m are homogeneous of
+    // degree m, so u . grad M_d = m M_d (Euler)
+    B = x * Ax + y * Ay + z * Az;
 }
 
 // Directional derivative of the monomials along t: Mt_d = grad_u M_d . t.
