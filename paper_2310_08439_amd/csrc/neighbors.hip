@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 // No fused multiply-adds anywhere in this file: the predicate must round every
 // product and sum separately, like its FP64 definition.
@@ -526,6 +527,9 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         s_xi[wv][1][lane] = x.y;
         s_xi[wv][2][lane] = x.z;
     }
+    // every stencil cell inside the box (no periodic image): uniform
+    const bool interior = cx - rx >= 0 && cx + rx < g.nc[0] && cy - ry >= 0 && cy + ry < g.nc[1] &&
+                          cz - rz >= 0 && cz + rz < g.nc[2];
     // stencil cell of this lane (traversal order: z outer, x inner)
     int first = 0, count = 0;
     if (lane < ns) {
@@ -588,34 +592,50 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         }
         // this lane's entry offset inside a (atom, species) row block
         const int lane_row = okq ? bq * a.cap : 0;
-        for (int i = 0; i < natoms; ++i) {
-            const int p = a0 + i;
-            const double4 xi = make_double4(s_xi[wv][0][i], s_xi[wv][1][i], s_xi[wv][2][i], 0.0);
-            const double dx = (xj.x - xi.x) + sx;
-            const double dy = (xj.y - xi.y) + sy;
-            const double dz = (xj.z - xi.z) + sz;
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            const bool acc = okq && !(zero_img && q == p) && d2 < a.rl2;
-            if (acc && d2 == 0.0) coincident = true;
-            const unsigned long long m = __ballot(acc);
-            if (!m) continue;
-            // atom i's row lengths (held by lane i), this lane's species picked out
-            int base = 0;
+        const unsigned long long mine_below = mine & below;
+        // SHIFT: some candidate of the stencil lies in a periodic image.  A
+        // cell whose whole stencil is inside the box adds only +0.0 image
+        // shifts, which change no distance, so they are left out there.
+        auto test_atoms = [&](auto shift) {
+            constexpr bool SHIFT = decltype(shift)::value;
+            for (int i = 0; i < natoms; ++i) {
+                const int p = a0 + i;
+                const double4 xi = make_double4(s_xi[wv][0][i], s_xi[wv][1][i], s_xi[wv][2][i], 0.0);
+                double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+                if constexpr (SHIFT) {
+                    dx = dx + sx;
+                    dy = dy + sy;
+                    dz = dz + sz;
+                }
+                const double d2 = (dx * dx + dy * dy) + dz * dz;
+                const bool acc = okq && !((SHIFT ? zero_img : true) && q == p) && d2 < a.rl2;
+                if (acc && d2 == 0.0) coincident = true;
+                const unsigned long long m = __builtin_amdgcn_ballot_w64(acc);
+                if (!m) continue;
+                // atom i's row lengths (held by lane i), this lane's species picked out
+                int base = 0;
 #pragma unroll
-            for (int b = 0; b < SMAX; ++b) {
-                const int rb = __builtin_amdgcn_readlane(rowlen[b], i);
-                if (bq == b) base = rb;
-                if (lane == i) rowlen[b] = rb + (int)__popcll(m & spm[b]);
-            }
-            if (acc) {
-                const int c = base + (int)__popcll(m & mine & below);
-                if (c < a.cap) {
-                    const int64_t rows = (int64_t)p * a.S * a.cap;  // uniform
-                    a.nbr[rows + (lane_row + c)] = q;
-                    a.img[rows + (lane_row + c)] = word;
+                for (int b = 0; b < SMAX; ++b) {
+                    const int rb = __builtin_amdgcn_readlane(rowlen[b], i);
+                    if (bq == b) base = rb;
+                    if (lane == i) rowlen[b] = rb + (int)__popcll(m & spm[b]);
+                }
+                if (acc) {
+                    const int c = base + (int)__popcll(m & mine_below);
+                    if (c < a.cap) {
+                        const int64_t rows = (int64_t)p * a.S * a.cap;  // uniform: row block of atom p
+                        int32_t* nrow = a.nbr + rows;
+                        int32_t* irow = a.img + rows;
+                        nrow[lane_row + c] = q;
+                        irow[lane_row + c] = word;
+                    }
                 }
             }
-        }
+        };
+        if (interior)
+            test_atoms(std::false_type{});
+        else
+            test_atoms(std::true_type{});
     }
     int mx = 0;
     if (lane < natoms) {
