@@ -505,6 +505,7 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
     // per wave: stencil cell of every candidate, and the cell's own positions
     __shared__ uint8_t s_cell[kBlock / 64][kMaxCandidates];
     __shared__ double s_xi[kBlock / 64][3][kMaxCellAtoms];
+    __shared__ int32_t s_len[kBlock / 64][kMaxCellAtoms][SMAX];  // running row lengths
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t cell = (int64_t)blockIdx.x * (kBlock / 64) + wv;
     if (cell >= ncells) return;  // whole wave
@@ -553,13 +554,10 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
     }
     // candidate -> stencil cell table: stencil cell s owns candidates [pre_s, pre_s + count_s)
     for (int j = 0; j < count; ++j) s_cell[wv][pre + j] = (uint8_t)lane;
+    for (int t = lane; t < natoms * SMAX; t += 64) (&s_len[wv][0][0])[t] = 0;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // running row lengths: lane i holds atom i's count per species
-    int rowlen[SMAX];
-#pragma unroll
-    for (int b = 0; b < SMAX; ++b) rowlen[b] = 0;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool coincident = false;
     for (int k0 = 0; k0 < total; k0 += 64) {
@@ -593,6 +591,11 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         // this lane's entry offset inside a (atom, species) row block
         const int lane_row = okq ? bq * a.cap : 0;
         const unsigned long long mine_below = mine & below;
+        const unsigned long long mine_above = mine & ~below & ~(1ull << lane);
+        // row lengths of the cell's atoms for this lane's species, in LDS: each
+        // lane reads its species' length of atom i, and the last accepted lane
+        // of each species stores the new length
+        int32_t* len = &s_len[wv][0][okq ? bq : 0];
         // SHIFT: some candidate of the stencil lies in a periodic image.  A
         // cell whose whole stencil is inside the box adds only +0.0 image
         // shifts, which change no distance, so they are left out there.
@@ -612,23 +615,16 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
                 if (acc && d2 == 0.0) coincident = true;
                 const unsigned long long m = __builtin_amdgcn_ballot_w64(acc);
                 if (!m) continue;
-                // atom i's row lengths (held by lane i), this lane's species picked out
-                int base = 0;
-#pragma unroll
-                for (int b = 0; b < SMAX; ++b) {
-                    const int rb = __builtin_amdgcn_readlane(rowlen[b], i);
-                    if (bq == b) base = rb;
-                    if (lane == i) rowlen[b] = rb + (int)__popcll(m & spm[b]);
-                }
                 if (acc) {
-                    const int c = base + (int)__popcll(m & mine_below);
+                    const int c = len[i * SMAX] + (int)__popcll(m & mine_below);
                     if (c < a.cap) {
-                        const int64_t rows = (int64_t)p * a.S * a.cap;  // uniform: row block of atom p
-                        int32_t* nrow = a.nbr + rows;
-                        int32_t* irow = a.img + rows;
-                        nrow[lane_row + c] = q;
-                        irow[lane_row + c] = word;
+                        // uniform row block of atom p plus a 32-bit byte offset
+                        const int64_t rows = (int64_t)p * a.S * a.cap;
+                        const uint32_t boff = 4u * (uint32_t)(lane_row + c);
+                        *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(a.nbr + rows) + boff) = q;
+                        *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(a.img + rows) + boff) = word;
                     }
+                    if ((m & mine_above) == 0) len[i * SMAX] = c + 1;  // last of its species
                 }
             }
         };
@@ -643,7 +639,7 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
 #pragma unroll
         for (int b = 0; b < SMAX; ++b) {
             if (b >= a.S) break;
-            const int c = rowlen[b];
+            const int c = s_len[wv][lane][b];
             a.cnt[(int64_t)b * a.n + p] = min(c, a.cap);
             mx = max(mx, c);
         }
