@@ -601,7 +601,11 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         // shifts, which change no distance, so they are left out there.
         auto test_atoms = [&](auto shift) {
             constexpr bool SHIFT = decltype(shift)::value;
-            for (int i = 0; i < natoms; ++i) {
+            // row blocks of the cell's atoms, advanced by one atom's rows per step
+            const int64_t row_step = (int64_t)a.S * a.cap;
+            char* nrow = reinterpret_cast<char*>(a.nbr + (int64_t)a0 * row_step);
+            char* irow = reinterpret_cast<char*>(a.img + (int64_t)a0 * row_step);
+            for (int i = 0; i < natoms; ++i, nrow += 4 * row_step, irow += 4 * row_step) {
                 const int p = a0 + i;
                 const double4 xi = make_double4(s_xi[wv][0][i], s_xi[wv][1][i], s_xi[wv][2][i], 0.0);
                 double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
@@ -617,13 +621,11 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
                 if (!m) continue;
                 if (acc) {
                     const int c = len[i * SMAX] + (int)__popcll(m & mine_below);
-                    if (c < a.cap) {
-                        // uniform row block of atom p plus a 32-bit byte offset
-                        const int64_t rows = (int64_t)p * a.S * a.cap;
-                        const uint32_t boff = 4u * (uint32_t)(lane_row + c);
-                        *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(a.nbr + rows) + boff) = q;
-                        *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(a.img + rows) + boff) = word;
-                    }
+                    // past the capacity the build fails and is redone with a larger
+                    // one, so those entries only need to stay inside their row
+                    const uint32_t boff = 4u * (uint32_t)(lane_row + min(c, a.cap - 1));
+                    *reinterpret_cast<int32_t*>(nrow + boff) = q;
+                    *reinterpret_cast<int32_t*>(irow + boff) = word;
                     if ((m & mine_above) == 0) len[i * SMAX] = c + 1;  // last of its species
                 }
             }
