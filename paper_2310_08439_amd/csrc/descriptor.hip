@@ -323,7 +323,7 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b
 }
 
 template <int KC, int M, bool TAB, bool NT>
-__global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nblocks) {
+__global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D;
     constexpr int GW = KC * (M + 1);  // features of one thread's chunk
     // Per wave: its atoms' feature segments of two species, so that G's rows
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
     // cache line per lane) and, with two species, as whole rows (a row
     // written one species at a time leaves a cache line half written in
     // between), and the atoms' sorted indices.
-    __shared__ float sg[kBlock / 64][2 * 64 * GW];
+    __shared__ float sg[kBlock / 64][2 * 64 * GW + 64];  // rows padded to an odd stride (banks)
     __shared__ int32_t sp_row[kBlock / 64][64];
     const int64_t lb = xcd_block(nblocks);
     if (lb < 0) return;
@@ -355,11 +355,12 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
         const int b0 = b & ~1;                // species b0 and b0 + 1 are staged together
         const int nsp = min(2, a.S - b0);     // species in this pair
         const int RW = nsp * KM;              // staged floats per atom
+        const int RWp = RW | 1;               // their LDS stride
         if (active) {
             float P[KC][D];
             accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, P, pos);
             if (a.Pbuf) store_tile<KC, D, NT>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
-            float* seg = &sg[wv][(lane >> a.nch_log2) * RW + (b - b0) * KM + ch * GW];
+            float* seg = &sg[wv][(lane >> a.nch_log2) * RWp + (b - b0) * KM + ch * GW];
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
 #pragma unroll
@@ -377,10 +378,10 @@ __global__ void __launch_bounds__(256, 2) k_descriptor(PathArgs a, int64_t nbloc
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // the wave's (64 / chunks) atoms x RW features, 64 consecutive floats per
-        // store: staged float it * 64 + lane is feature e of atom al
+        // store: feature e of atom al is staged at al * RWp + e
         int al = lane / RW, e = lane - al * RW;
         for (int it = 0; it < nsp * GW; ++it) {
-            if (wave_w0 + al < a.n) a.G[(int64_t)sp_row[wv][al] * a.F + b0 * KM + e] = sg[wv][it * 64 + lane];
+            if (wave_w0 + al < a.n) a.G[(int64_t)sp_row[wv][al] * a.F + b0 * KM + e] = sg[wv][al * RWp + e];
             e += 64;
             while (e >= RW) {
                 e -= RW;
