@@ -1083,7 +1083,13 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
         BlockGeom bg = wo_geom(nl);
         bg.F = Fsorted;
         const unsigned grid = (unsigned)bg.nb[0] * bg.nb[1] * bg.nb[2];
-        auto fn = m->tab ? select_blocked<true>(m->kc, m->M) : select_blocked<false>(m->kc, m->M);
+        // P's layout does not depend on the chunk: for M = 3 and K >= 64 four
+        // radial functions per lane (two waves per SIMD) beat eight (one wave;
+        // measured at K = 128: 0.947 -> 0.908 ms; at K = 32 eight stay faster,
+        // 0.600 against 0.636 ms)
+        const int kca = (m->M == 3 && m->kc == 8 && m->K >= 64) ? 4 : m->kc;
+        a.nch_log2 = log2_int(m->K / kca);
+        auto fn = m->tab ? select_blocked<true>(kca, m->M) : select_blocked<false>(kca, m->M);
         {
             ProfScope ps_(ctx, "adjoint");
             fn<<<grid, kBlock, kHaloBytes * (size_t)bg.hmax, ctx->stream>>>(a, bg);
