@@ -49,7 +49,7 @@ def algorithmic_flops(spec, n_atoms: int, pairs: int) -> dict:
 KERNEL_OF_SCOPE = {
     "adjoint": ("k_adjoint", "paper_2310_08439_amd/csrc/descriptor.hip"),
     "descriptor": ("k_descriptor", "paper_2310_08439_amd/csrc/descriptor.hip"),
-    "mlp": ("k_mlp<true", "paper_2310_08439_amd/csrc/mlp.hip"),
+    "mlp": (("k_mlp_resident", "k_mlp<true"), "paper_2310_08439_amd/csrc/mlp.hip"),  # BF16: resident or staged
     "nb_fill": ("k_fill", "paper_2310_08439_amd/csrc/neighbors.hip"),
 }
 
@@ -71,12 +71,34 @@ def measured_traffic(workload: str, scope: str):
     cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
     if not m or m.group(1) != cur:
         return None
-    for line in text.splitlines():
-        f = line.split()
-        if len(f) == 6 and f[0] == "traffic" and f[1].startswith(prefix.replace(" ", "")):
-            fetch_kib, write_kib, ff, wf = map(float, f[2:])
-            return int(fetch_kib * 1024 * ff + write_kib * 1024 * wf)
+    prefixes = (prefix,) if isinstance(prefix, str) else prefix
+    for pre in prefixes:
+        for line in text.splitlines():
+            f = line.split()
+            if len(f) == 6 and f[0] == "traffic" and f[1].startswith(pre.replace(" ", "")):
+                fetch_kib, write_kib, ff, wf = map(float, f[2:])
+                return int(fetch_kib * 1024 * ff + write_kib * 1024 * wf)
     return None
+
+
+def kernel_rooflines(workload: str, flops: dict, avg_ms: dict) -> dict:
+    """Per kernel of the BF16 step: algorithmic TFLOP/s against its unit's peak
+    and, from the committed FETCH/WRITE summary (when it matches the source),
+    HBM GB/s against 8 TB/s."""
+    out = {}
+    for name, peak in (("adjoint", PEAK_FP32_VECTOR_TFLOPS), ("descriptor", PEAK_FP32_VECTOR_TFLOPS),
+                       ("mlp", PEAK_BF16_MFMA_TFLOPS)):
+        if name not in avg_ms:
+            continue
+        sec = avg_ms[name] * 1e-3
+        tf = flops[name] / sec / 1e12
+        row = {"ms": round(avg_ms[name], 4), "tflops": round(tf, 3), "peak_tflops": peak, "frac_compute": round(tf / peak, 4)}
+        traffic = measured_traffic(workload, name)
+        if traffic is not None:
+            gbs = traffic / sec / 1e9
+            row.update({"hbm_bytes": traffic, "gb_per_s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)})
+        out[name] = row
+    return out
 
 
 def cpu_baseline(seconds: float) -> dict:
@@ -548,6 +570,7 @@ def main():
         "kernels_avg_ms": kernels,
         "accuracy_vs_oracle": acc,
         "roofline": roof,
+        "kernels_roofline": kernel_rooflines(args.workload, flops, avg_ms),
         "cpu_baseline": cpu,
         "serving": serving,
         "training": training,
