@@ -50,7 +50,8 @@ struct GridArgs {
 
 __global__ void k_bin(int64_t n, const double* __restrict__ pos, const int32_t* __restrict__ species, int S,
                       GridArgs g, double* __restrict__ wpos, int32_t* __restrict__ cell_of,
-                      int32_t* __restrict__ cellcount, int32_t* __restrict__ flags) {
+                      int32_t* __restrict__ cell_rank, int32_t* __restrict__ cellcount,
+                      int32_t* __restrict__ flags) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c[3];
@@ -67,7 +68,7 @@ __global__ void k_bin(int64_t n, const double* __restrict__ pos, const int32_t* 
     if (s < 0 || s >= S) atomicOr(&flags[0], kErrSpecies);
     int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
     cell_of[i] = cell;
-    atomicAdd(&cellcount[cell], 1);
+    cell_rank[i] = atomicAdd(&cellcount[cell], 1);  // arrival order in the cell (k_sort_gather fixes the order)
 }
 
 // Exclusive scan by one block of 1024 threads over tiles of 1024 consecutive
@@ -159,13 +160,11 @@ __global__ void __launch_bounds__(1024) k_species_scan(int64_t nblk, int S, cons
     }
 }
 
-__global__ void k_place(int64_t n, const int32_t* __restrict__ cell_of, const int32_t* __restrict__ start,
-                        int32_t* __restrict__ fill, int32_t* __restrict__ order) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_place(int64_t n, const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_rank,
+                        const int32_t* __restrict__ start, int32_t* __restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int cell = cell_of[i];
-    int slot = start[cell] + atomicAdd(&fill[cell], 1);
-    order[slot] = (int32_t)i;
+    order[start[cell_of[i]] + cell_rank[i]] = (int32_t)i;
 }
 
 // One wave per cell: the cell's atoms (in the arbitrary order the atomic
@@ -799,7 +798,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     int32_t* order = (int32_t*)ctx->ws.get("nb.order", sizeof(int32_t) * n, &e);
     int32_t* cellcount = (int32_t*)ctx->ws.get("nb.cellcount", sizeof(int32_t) * (ncells + 1), &e);
     int32_t* tiles = (int32_t*)ctx->ws.get("nb.tiles", sizeof(int32_t) * ((ncells + 1023) / 1024 + 1), &e);
-    int32_t* cellfill = (int32_t*)ctx->ws.get("nb.cellfill", sizeof(int32_t) * (ncells + 1), &e);
+    int32_t* cell_rank = (int32_t*)ctx->ws.get("nb.cell_rank", sizeof(int32_t) * n, &e);
     int32_t* blkcnt = (int32_t*)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
     int32_t* blkoff = (int32_t*)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
     int32_t* flags = (int32_t*)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
@@ -807,12 +806,12 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     hipStream_t st = ctx->stream;
     int32_t* spcount = flags + 8;
     TMD_HIP(ctx, hipMemsetAsync(cellcount, 0, sizeof(int32_t) * (ncells + 1), st));
-    TMD_HIP(ctx, hipMemsetAsync(cellfill, 0, sizeof(int32_t) * (ncells + 1), st));
     TMD_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 64, st));
 
     {
         ProfScope ps_(ctx, "nb_bin");
-        k_bin<<<grid_for(n), kBlock, 0, st>>>(n, sys->pos, sys->species, nl->S, g, wpos, cell_of, cellcount, flags);
+        k_bin<<<grid_for(n), kBlock, 0, st>>>(n, sys->pos, sys->species, nl->S, g, wpos, cell_of, cell_rank,
+                                               cellcount, flags);
     }
     {
         ProfScope ps_(ctx, "nb_scan");
@@ -832,7 +831,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     }
     {
         ProfScope ps_(ctx, "nb_place");
-        k_place<<<grid_for(n), kBlock, 0, st>>>(n, cell_of, cellstart, cellfill, order);
+        k_place<<<grid_for(n), kBlock, 0, st>>>(n, cell_of, cell_rank, cellstart, order);
     }
     {
         ProfScope ps_(ctx, "nb_sort");
@@ -1011,7 +1010,7 @@ tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S) {
     (void)ctx->ws.get("nb.cellcount", sizeof(int32_t) * cells, &e);
     (void)ctx->ws.get("nb.tiles", sizeof(int32_t) * ((cells + 1023) / 1024 + 1), &e);
     (void)ctx->ws.get("wo.count", sizeof(int32_t) * cells, &e);
-    (void)ctx->ws.get("nb.cellfill", sizeof(int32_t) * cells, &e);
+    (void)ctx->ws.get("nb.cell_rank", sizeof(int32_t) * n, &e);
     (void)ctx->ws.get("nb.blkcnt", sizeof(int32_t) * kMaxSpecies * nblk, &e);
     (void)ctx->ws.get("nb.blkoff", sizeof(int32_t) * kMaxSpecies * (nblk + 1), &e);
     (void)ctx->ws.get("nb.flags", sizeof(int32_t) * 64, &e);
@@ -1022,7 +1021,7 @@ tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S) {
 size_t nlist_workspace_bytes(int64_t n) {
     const int64_t nblk = (n + kBlock - 1) / kBlock;
     const size_t cells = (size_t)std::max<int64_t>(64, 4 * n) + 1;
-    return (size_t)n * 36 + 12 * cells + 4 * (cells / 1024 + 2) + 8 * (size_t)kMaxSpecies * (nblk + 1) + 512;
+    return (size_t)n * 40 + 8 * cells + 4 * (cells / 1024 + 2) + 8 * (size_t)kMaxSpecies * (nblk + 1) + 512;
 }
 
 tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row) {
