@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double* __restric
     red[threadIdx.x] = d2;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(maxd2, (unsigned long long)__double_as_longlong(red[0]));
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_ke_partials(int64_t n, const double* __
     for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
         __syncthreads();
     }
