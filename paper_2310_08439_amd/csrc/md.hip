@@ -31,17 +31,18 @@ constexpr double kEvA3ToGPa = 160.21766208;
 
 // v += (dt/2) a; x += dt v; and (maxd2 non-null) the largest squared
 // displacement since the last list build, as the bits of a non-negative
-// double (ordered like the values).
+// double (ordered like the values).  Grid-stride over a few workgroups per CU,
+// so that few workgroups meet at the one atomicMax.
 __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double* __restrict__ x, double* __restrict__ v,
                                                     const float* __restrict__ F, const int32_t* __restrict__ sp,
                                                     const double* __restrict__ acc, double dt,
                                                     const double* __restrict__ xref,
                                                     unsigned long long* __restrict__ maxd2) {
     __shared__ double red[256];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double d2 = 0.0;
-    if (i < n) {
+    double d2 = 0.0;  // largest over this thread's atoms
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double a = acc[sp[i]];
+        double di = 0.0;
         for (int c = 0; c < 3; ++c) {
             const double vi = v[3 * i + c] + 0.5 * dt * a * (double)F[3 * i + c];
             const double xi = x[3 * i + c] + dt * vi;
@@ -49,9 +50,10 @@ __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double* __restric
             x[3 * i + c] = xi;
             if (maxd2) {
                 const double d = xi - xref[3 * i + c];
-                d2 += d * d;
+                di += d * d;
             }
         }
+        d2 = fmax(d2, di);
     }
     if (!maxd2) return;  // uniform over the grid
     red[threadIdx.x] = d2;
@@ -93,21 +95,35 @@ __global__ void __launch_bounds__(256) k_ke_partials(int64_t n, const double* __
     if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_ke_total(const double* __restrict__ part, int nb, double* __restrict__ out4) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double tot = 0.0;
+// Sum of the nb (<= 256) block partials per component: one workgroup, a fixed
+// pairwise tree of compensated (Neumaier) merges, so the result is the same
+// run to run.
+__global__ void __launch_bounds__(256) k_ke_total(const double* __restrict__ part, int nb, double* __restrict__ out4) {
+    __shared__ double rs[3][256], rc[3][256];
+    const int t = threadIdx.x;
     for (int c = 0; c < 3; ++c) {
-        double s = 0.0, comp = 0.0;
-        for (int b = 0; b < nb; ++b) {
-            const double x = part[3 * b + c], t = s + x;
-            if (fabs(s) >= fabs(x)) comp += (s - t) + x;
-            else comp += (x - t) + s;
-            s = t;
-        }
-        out4[c] = s + comp;
-        tot += out4[c];
+        rs[c][t] = t < nb ? part[3 * t + c] : 0.0;
+        rc[c][t] = 0.0;
     }
-    out4[3] = tot;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 3; ++c) {
+                const double x = rs[c][t], y = rs[c][t + w], s = x + y;
+                const double e = fabs(x) >= fabs(y) ? (x - s) + y : (y - s) + x;
+                rs[c][t] = s;
+                rc[c][t] += rc[c][t + w] + e;
+            }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double tot = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            out4[c] = rs[c][0] + rc[c][0];
+            tot += out4[c];
+        }
+        out4[3] = tot;
+    }
 }
 
 // Thermostat half step on the device: state = (xi, eta, scale); ke4 is the
@@ -140,7 +156,8 @@ unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 tmd_status launch_kick_drift(tmd_context* ctx, int64_t n, double* x, double* v, const float* F, const int32_t* sp,
                              const double* acc, double dt, const double* xref, unsigned long long* maxd2) {
-    k_kick_drift<<<blocks_of(n), kBlock, 0, ctx->stream>>>(n, x, v, F, sp, acc, dt, xref, maxd2);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_of(n), 4 * (int64_t)ctx->num_cus));
+    k_kick_drift<<<grid, kBlock, 0, ctx->stream>>>(n, x, v, F, sp, acc, dt, xref, maxd2);
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;
 }
@@ -155,7 +172,8 @@ tmd_status launch_kick(tmd_context* ctx, int64_t n, double* v, const float* F, c
 tmd_status launch_kinetic(tmd_context* ctx, int64_t n, const double* v, const int32_t* sp, const double* mass,
                           double* part, double* out4) {
     k_ke_partials<<<kKeBlocks, 256, 0, ctx->stream>>>(n, v, sp, mass, part);
-    k_ke_total<<<1, 64, 0, ctx->stream>>>(part, kKeBlocks, out4);
+    static_assert(kKeBlocks <= 256, "k_ke_total sums at most 256 partials");
+    k_ke_total<<<1, 256, 0, ctx->stream>>>(part, kKeBlocks, out4);
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;
 }
