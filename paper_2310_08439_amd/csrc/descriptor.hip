@@ -66,7 +66,7 @@ struct PathArgs {
 struct Pair {
     float dx, dy, dz, r2;
     int q;     // neighbour (sorted index)
-    int code;  // stencil cell offset code of the entry (0..26) or 255
+    int slot;  // where the entry's force goes: its LDS halo slot (LdsPos) or sorted index (GlobalPos)
 };
 
 template <int NB>
@@ -94,7 +94,10 @@ struct GlobalPos {
     const double4* xs;
     double L0, L1, L2;
     double4 xi;
-    __device__ double4 fetch(int q, int32_t) const { return xs[q]; }
+    __device__ double4 fetch(int q, int32_t, int& slot) const {
+        slot = q;
+        return xs[q];
+    }
     __device__ float3 disp(const double4& xj, int32_t im) const {
         int nx, ny, nz;
         unpack_img(im, nx, ny, nz);
@@ -111,8 +114,9 @@ struct LdsPos {
     int hp;
     float xi, yi, zi;  // centre atom, from its cell origin
     float wx, wy, wz;  // cell edges
-    __device__ float4 fetch(int q, int32_t im) const {
+    __device__ float4 fetch(int q, int32_t im, int& slot) const {
         const int i = hoff[hp + delta[img_ocode(im)]] + q;
+        slot = i;
         return make_float4(sx[i], sy[i], sz[i], 0.0f);
     }
     __device__ float3 disp(const float4& xj, int32_t im) const {
@@ -139,9 +143,10 @@ __device__ __forceinline__ void load_pairs(const PathArgs& a, int64_t row, int c
             q[j] = q[0];
             im[j] = im[0];
         }
-    decltype(pos.fetch(0, 0)) xj[NB];
+    int slot[NB];
+    decltype(pos.fetch(0, 0, slot[0])) xj[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) xj[j] = pos.fetch(q[j], im[j]);
+    for (int j = 0; j < NB; ++j) xj[j] = pos.fetch(q[j], im[j], slot[j]);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const float3 d = pos.disp(xj[j], im[j]);
@@ -151,7 +156,7 @@ __device__ __forceinline__ void load_pairs(const PathArgs& a, int64_t row, int c
         pr[j].r2 = (c0 + j < nb) ? pr[j].dx * pr[j].dx + pr[j].dy * pr[j].dy + pr[j].dz * pr[j].dz
                                  : __builtin_inff();
         pr[j].q = q[j];
-        pr[j].code = img_ocode(im[j]);
+        pr[j].slot = slot[j];
     }
 }
 
@@ -179,9 +184,11 @@ __device__ __forceinline__ void load_pairs_split2(const PathArgs& a, int64_t row
             q[j] = q[0];
             im[j] = im[0];
         }
-    decltype(pos.fetch(0, 0)) xj[NB / 2];  // entries 2t + odd
+    int slot_unused;
+    decltype(pos.fetch(0, 0, slot_unused)) xj[NB / 2];  // entries 2t + odd
 #pragma unroll
-    for (int t = 0; t < NB / 2; ++t) xj[t] = pos.fetch(odd ? q[2 * t + 1] : q[2 * t], odd ? im[2 * t + 1] : im[2 * t]);
+    for (int t = 0; t < NB / 2; ++t)
+        xj[t] = pos.fetch(odd ? q[2 * t + 1] : q[2 * t], odd ? im[2 * t + 1] : im[2 * t], slot_unused);
 #pragma unroll
     for (int t = 0; t < NB / 2; ++t) {
         const float3 mine = pos.disp(xj[t], odd ? im[2 * t + 1] : im[2 * t]);
@@ -199,7 +206,7 @@ __device__ __forceinline__ void load_pairs_split2(const PathArgs& a, int64_t row
         pr[j].r2 = (c0 + j < nb) ? pr[j].dx * pr[j].dx + pr[j].dy * pr[j].dy + pr[j].dz * pr[j].dz
                                  : __builtin_inff();
         pr[j].q = q[j];
-        pr[j].code = img_ocode(im[j]);
+        pr[j].slot = q[j];  // the descriptor has no force sink
     }
 }
 
@@ -396,8 +403,8 @@ __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a,
 
 // Per-atom adjoint for one (atom, radial chunk) thread: P' from dE/dG, then for
 // every pair U, V and g = dE/dD (summed over the atom's chunk lanes).  The
-// chunk-0 lane hands each pair's g to sink(q, code, gx, gy, gz) (code = the
-// pair's stencil-offset code), accumulates the
+// chunk-0 lane hands each pair's g to sink(slot, gx, gy, gz) (slot = where
+// the neighbour's force accumulates: Pair::slot), accumulates the
 // atom's own force sum in Fo and the virial in W6.
 template <int KC, int M, bool TAB, class Pos, class Sink>
 __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64_t w, int ch, int nch,
@@ -491,7 +498,7 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
                     Fo[0] += gx;
                     Fo[1] += gy;
                     Fo[2] += gz;
-                    sink(pr.q, pr.code, gx, gy, gz);
+                    sink(pr.slot, gx, gy, gz);
                     W6[0] -= pr.dx * gx;
                     W6[1] -= pr.dy * gy;
                     W6[2] -= pr.dz * gz;
@@ -535,7 +542,7 @@ __global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, float* F) {
         const int64_t p = a.wperm ? a.wperm[w] : w;
         float Fo[3] = {0.0f, 0.0f, 0.0f};
         adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, GlobalPos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]},
-                                 [&](int q, int, float gx, float gy, float gz) {
+                                 [&](int q, float gx, float gy, float gz) {
             unsafeAtomicAdd(&F[3 * (int64_t)q + 0], -gx);
             unsafeAtomicAdd(&F[3 * (int64_t)q + 1], -gy);
             unsafeAtomicAdd(&F[3 * (int64_t)q + 2], -gz);
@@ -688,8 +695,7 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         const LdsPos pos{sx, sy, sz, hoff, sdelta, hp, sx[ip], sy[ip], sz[ip], cw[0], cw[1], cw[2]};
         float Fo[3] = {0.0f, 0.0f, 0.0f};
         adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, pos,
-                                 [&](int q, int o, float gx, float gy, float gz) {
-            const int idx = hoff[hp + sdelta[o]] + q;
+                                 [&](int idx, float gx, float gy, float gz) {  // idx: the neighbour's halo slot
             atomicAdd(&sF[idx], -gx);
             atomicAdd(&sF[bg.hmax + idx], -gy);
             atomicAdd(&sF[2 * bg.hmax + idx], -gz);
