@@ -62,6 +62,7 @@ struct tmd_batch {
     float* grad = nullptr;       // [S][per_species]
     int32_t* flag = nullptr;     // [1] set when an entry has no mirror
     int tileT = 0;               // atoms per second-order tile
+    int tileQC = 0;              // weight columns per LDS block of the second-order pass
     int64_t tiles = 0;
     int64_t tile_off[tmd::kMaxSpecies + 1] = {0};
 };
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__(256) k_pt_tangent(PtArgs a) {
 // ---------------------------------------------------------------- second-order MLP pass
 
 struct MlpTrainArgs {
-    int S, F, L, H, act, T, P;
+    int S, F, L, H, act, T, QC, P;
     int64_t sp_off[kMaxSpecies + 1];
     int64_t tile_off[kMaxSpecies + 1];
     const int32_t* sp_idx;
@@ -506,15 +507,18 @@ __device__ __forceinline__ float d2sig(int act, float z) {
 }
 
 // One workgroup per tile of up to T atoms of one species; activations of the
-// tile live in LDS as [width][T].  Primal z_l = W_l a_{l-1} + b_l, a_l = s(z_l);
-// tangent zt_l = W_l at_{l-1}, at_l = s'(z_l) zt_l, from a_0 = G, at_0 = w.
-// Reverse mode of J = e E - w_out . at_L through both graphs:
+// tile live in LDS as [width][Tp] with the odd row stride Tp = T | 1, so that
+// lanes walking the width at a fixed atom hit distinct banks.  The weights of
+// a layer pass through LDS in blocks of QC input columns, [H][QC + 1].
+// Primal z_l = W_l a_{l-1} + b_l, a_l = s(z_l); tangent zt_l = W_l at_{l-1},
+// at_l = s'(z_l) zt_l, from a_0 = G, at_0 = w.  Reverse mode of
+// J = e E - w_out . at_L through both graphs:
 //   ztbar_l = s'(z_l) atbar_l,  zbar_l = s'(z_l) abar_l + s''(z_l) zt_l atbar_l,
 //   dW_l += zbar_l a_{l-1}^T + ztbar_l at_{l-1}^T,  db_l += zbar_l,
 //   abar_{l-1} = W_l^T zbar_l,  atbar_{l-1} = W_l^T ztbar_l.
 __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     extern __shared__ float lds[];
-    const int T = a.T, H = a.H, F = a.F, L = a.L;
+    const int T = a.T, Tp = a.T | 1, H = a.H, F = a.F, L = a.L, QC = a.QC;
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
     int s = 0;
@@ -522,18 +526,26 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         if (tile >= a.tile_off[q] && tile < a.tile_off[q + 1]) s = q;
     const int64_t first = a.sp_off[s] + (tile - a.tile_off[s]) * T;
     const int nt = (int)min((int64_t)T, a.sp_off[s + 1] - first);
-    float* X0 = lds;                      // [F][T]
-    float* X0t = X0 + F * T;              // [F][T]
-    float* Z = X0t + F * T;               // [L][H][T]
-    float* A = Z + L * H * T;
-    float* Zt = A + L * H * T;
-    float* At = Zt + L * H * T;
-    float* Ba = At + L * H * T;           // [H][T]
-    float* Bat = Ba + H * T;
-    float* Cz = Bat + H * T;
-    float* Czt = Cz + H * T;
+    float* X0 = lds;                      // [F][Tp]
+    float* X0t = X0 + F * Tp;             // [F][Tp]
+    float* Z = X0t + F * Tp;              // [L][H][Tp]
+    float* A = Z + L * H * Tp;
+    float* Zt = A + L * H * Tp;
+    float* At = Zt + L * H * Tp;
+    float* Ba = At + L * H * Tp;          // [H][Tp]
+    float* Bat = Ba + H * Tp;
+    float* Cz = Bat + H * Tp;
+    float* Czt = Cz + H * Tp;
+    float* Ws = Czt + H * Tp;             // [H][QC + 1]
     const float* p = a.params + (int64_t)s * a.P;
     float* gp = a.partial + tile * a.P;
+    // Ws[o][c] = W[o][q0 + c] for c < qn; the caller synchronises.
+    auto stage = [&](const float* W, int wi, int q0, int qn) {
+        for (int idx = tid; idx < H * qn; idx += blockDim.x) {
+            const int o = idx / qn, c = idx - o * qn;
+            Ws[o * (QC + 1) + c] = W[(int64_t)o * wi + q0 + c];
+        }
+    };
 
     for (int idx = tid; idx < F * T; idx += blockDim.x) {
         const int q = idx / T, t = idx - q * T;
@@ -543,11 +555,10 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
             g = a.G[atom * F + q];
             wt = a.w[atom * F + q];
         }
-        X0[idx] = g;
-        X0t[idx] = wt;
+        X0[q * Tp + t] = g;
+        X0t[q * Tp + t] = wt;
     }
-    __syncthreads();
-    // forward: primal and tangent
+    // forward: primal and tangent, accumulated over the weight blocks in Z, Zt
     int off = 0;
     int offW[TMD_MAX_HIDDEN], offb[TMD_MAX_HIDDEN];
     for (int l = 0; l < L; ++l) {
@@ -556,23 +567,36 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         off += H * wi;
         offb[l] = off;
         off += H;
-        const float* in = (l == 0) ? X0 : A + (l - 1) * H * T;
-        const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * T;
-        const float* W = p + offW[l];
-        for (int idx = tid; idx < H * T; idx += blockDim.x) {
-            const int o = idx / T, t = idx - o * T;
-            float z = p[offb[l] + o], zt = 0.0f;
-            for (int q = 0; q < wi; ++q) {
-                const float wv = W[o * wi + q];
-                z = fmaf(wv, in[q * T + t], z);
-                zt = fmaf(wv, int_[q * T + t], zt);
+        const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
+        const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
+        float* Zl = Z + l * H * Tp;
+        float* Ztl = Zt + l * H * Tp;
+        for (int q0 = 0; q0 < wi; q0 += QC) {
+            const int qn = min(QC, wi - q0);
+            const bool last = q0 + qn == wi;
+            stage(p + offW[l], wi, q0, qn);
+            __syncthreads();
+            for (int idx = tid; idx < H * T; idx += blockDim.x) {
+                const int o = idx / T, t = idx - o * T;
+                float z = q0 == 0 ? p[offb[l] + o] : Zl[o * Tp + t];
+                float zt = q0 == 0 ? 0.0f : Ztl[o * Tp + t];
+                const float* wrow = Ws + o * (QC + 1);
+                const float* ip = in + q0 * Tp + t;
+                const float* itp = int_ + q0 * Tp + t;
+                for (int c = 0; c < qn; ++c) {
+                    const float wv = wrow[c];
+                    z = fmaf(wv, ip[c * Tp], z);
+                    zt = fmaf(wv, itp[c * Tp], zt);
+                }
+                Zl[o * Tp + t] = z;
+                Ztl[o * Tp + t] = zt;
+                if (last) {
+                    A[(l * H + o) * Tp + t] = sig(a.act, z);
+                    At[(l * H + o) * Tp + t] = dsig(a.act, z) * zt;
+                }
             }
-            Z[(l * H + o) * T + t] = z;
-            A[(l * H + o) * T + t] = sig(a.act, z);
-            Zt[(l * H + o) * T + t] = zt;
-            At[(l * H + o) * T + t] = dsig(a.act, z) * zt;
+            __syncthreads();
         }
-        __syncthreads();
     }
     const int offWo = off, offbo = off + H;
     // output layer: E = w_out . a_L + b_out, q = w_out . at_L
@@ -580,14 +604,14 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         const int o = idx / T, t = idx - o * T;
         const bool live = t < nt;
         const float et = live ? a.e[a.sp_idx[first + t]] : 0.0f;
-        Ba[o * T + t] = live ? et * p[offWo + o] : 0.0f;
-        Bat[o * T + t] = live ? -p[offWo + o] : 0.0f;
+        Ba[o * Tp + t] = live ? et * p[offWo + o] : 0.0f;
+        Bat[o * Tp + t] = live ? -p[offWo + o] : 0.0f;
     }
     for (int o = tid; o < H; o += blockDim.x) {
         float gw = 0.0f;
         for (int t = 0; t < nt; ++t) {
             const float et = a.e[a.sp_idx[first + t]];
-            gw += et * A[((L - 1) * H + o) * T + t] - At[((L - 1) * H + o) * T + t];
+            gw += et * A[((L - 1) * H + o) * Tp + t] - At[((L - 1) * H + o) * Tp + t];
         }
         gp[offWo + o] = gw;
     }
@@ -600,52 +624,90 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     for (int l = L - 1; l >= 0; --l) {
         const int wi = (l == 0) ? F : H;
         for (int idx = tid; idx < H * T; idx += blockDim.x) {
-            const float z = Z[l * H * T + idx];
+            const int o = idx / T, t = idx - o * T;
+            const int at = o * Tp + t;
+            const float z = Z[l * H * Tp + at];
             const float d1 = dsig(a.act, z), d2 = d2sig(a.act, z);
-            Czt[idx] = d1 * Bat[idx];
-            Cz[idx] = d1 * Ba[idx] + d2 * Zt[l * H * T + idx] * Bat[idx];
+            Czt[at] = d1 * Bat[at];
+            Cz[at] = d1 * Ba[at] + d2 * Zt[l * H * Tp + at] * Bat[at];
         }
         __syncthreads();
-        const float* in = (l == 0) ? X0 : A + (l - 1) * H * T;
-        const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * T;
+        const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
+        const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
         for (int idx = tid; idx < H * wi; idx += blockDim.x) {
             const int o = idx / wi, q = idx - o * wi;
             float gw = 0.0f;
-            for (int t = 0; t < nt; ++t) gw += Cz[o * T + t] * in[q * T + t] + Czt[o * T + t] * int_[q * T + t];
+            for (int t = 0; t < nt; ++t)
+                gw += Cz[o * Tp + t] * in[q * Tp + t] + Czt[o * Tp + t] * int_[q * Tp + t];
             gp[offW[l] + idx] = gw;
         }
         for (int o = tid; o < H; o += blockDim.x) {
             float gb = 0.0f;
-            for (int t = 0; t < nt; ++t) gb += Cz[o * T + t];
+            for (int t = 0; t < nt; ++t) gb += Cz[o * Tp + t];
             gp[offb[l] + o] = gb;
         }
         if (l > 0) {
-            const float* W = p + offW[l];
-            for (int idx = tid; idx < H * T; idx += blockDim.x) {
-                const int q = idx / T, t = idx - q * T;
-                float sa = 0.0f, st = 0.0f;
-                for (int o = 0; o < H; ++o) {
-                    const float wv = W[o * wi + q];
-                    sa = fmaf(wv, Cz[o * T + t], sa);
-                    st = fmaf(wv, Czt[o * T + t], st);
+            // Ba, Bat = W_l^T (Cz, Czt), one block of input columns at a time
+            for (int q0 = 0; q0 < wi; q0 += QC) {
+                const int qn = min(QC, wi - q0);
+                stage(p + offW[l], wi, q0, qn);
+                __syncthreads();
+                for (int idx = tid; idx < qn * T; idx += blockDim.x) {
+                    const int c = idx / T, t = idx - c * T;
+                    float sa = 0.0f, st = 0.0f;
+                    for (int o = 0; o < H; ++o) {
+                        const float wv = Ws[o * (QC + 1) + c];
+                        sa = fmaf(wv, Cz[o * Tp + t], sa);
+                        st = fmaf(wv, Czt[o * Tp + t], st);
+                    }
+                    Ba[(q0 + c) * Tp + t] = sa;
+                    Bat[(q0 + c) * Tp + t] = st;
                 }
-                Ba[idx] = sa;
-                Bat[idx] = st;
+                __syncthreads();
             }
         }
         __syncthreads();
     }
 }
 
-// grad[s][p] = sum over the tiles of species s of partial[tile][p], in tile order.
-__global__ void k_grad_reduce(int S, int P, const int64_t* __restrict__ tile_off_dev, const float* __restrict__ partial,
-                              float* __restrict__ grad) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)S * P) return;
-    const int s = (int)(t / P), q = (int)(t - (int64_t)s * P);
+// Fixed-order reduction of the per-tile partials of each species, in two
+// passes so that it spreads over the chip: the tiles of species s form chunks
+// of kGradChunk consecutive tiles; pass one sums each chunk in tile order and
+// leaves the sum in the chunk's first row, pass two sums the chunks in order.
+constexpr int kGradChunk = 32;
+
+struct GradReduceArgs {
+    int S, P;
+    int64_t tile_off[kMaxSpecies + 1];   // tiles of species s: [tile_off[s], tile_off[s + 1])
+    int64_t chunk_off[kMaxSpecies + 1];  // chunks of species s: [chunk_off[s], chunk_off[s + 1])
+    float* partial;                      // [tiles][P]
+    float* grad;                         // [S][P]
+};
+
+// One thread per (chunk, parameter); workgroup x = chunk * pb + (parameter / 256)
+// with pb = ceil(P / 256).
+__global__ void __launch_bounds__(256) k_grad_chunks(GradReduceArgs a, int pb) {
+    const int64_t c = blockIdx.x / pb;
+    const int q = (int)(blockIdx.x - c * pb) * 256 + threadIdx.x;
+    if (q >= a.P) return;
+    int s = 0;
+    for (int k = 0; k < a.S; ++k)
+        if (c >= a.chunk_off[k] && c < a.chunk_off[k + 1]) s = k;
+    const int64_t lo = a.tile_off[s] + (c - a.chunk_off[s]) * kGradChunk;
+    const int64_t hi = min(lo + kGradChunk, a.tile_off[s + 1]);
     float acc = 0.0f;
-    for (int64_t tl = tile_off_dev[s]; tl < tile_off_dev[s + 1]; ++tl) acc += partial[tl * P + q];
-    grad[t] = acc;
+    for (int64_t tl = lo; tl < hi; ++tl) acc += a.partial[tl * a.P + q];
+    a.partial[lo * a.P + q] = acc;
+}
+
+// grad[s][q] = sum over the chunks of species s, in chunk order.
+__global__ void k_grad_reduce(GradReduceArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)a.S * a.P) return;
+    const int s = (int)(t / a.P), q = (int)(t - (int64_t)s * a.P);
+    float acc = 0.0f;
+    for (int64_t lo = a.tile_off[s]; lo < a.tile_off[s + 1]; lo += kGradChunk) acc += a.partial[lo * a.P + q];
+    a.grad[t] = acc;
 }
 
 // Adam (or SGD when beta1 < 0) on the master weights.
@@ -765,11 +827,24 @@ void batch_free(tmd_batch* b) {
     b->mirror = nullptr;
 }
 
-// Largest tile (atoms) whose LDS activations fit in 64 KB.
-int tile_atoms(int F, int H, int L) {
-    for (int T : {16, 8, 4, 2, 1})
-        if ((size_t)T * (2 * F + 4 * L * H + 4 * H) * sizeof(float) <= 64 * 1024) return T;
-    return 0;
+// LDS bytes of k_mlp_second: activations [width][T | 1] and a [H][QC + 1]
+// block of weights.
+size_t mlp2_lds(int F, int H, int L, int T, int QC) {
+    return sizeof(float) * ((size_t)(T | 1) * (2 * F + 4 * L * H + 4 * H) + (size_t)H * (QC + 1));
+}
+
+// Largest tile (atoms), then widest weight block (columns), that fit in 64 KB
+// of LDS; false when none does.
+bool mlp2_shape(int F, int H, int L, int* T, int* QC) {
+    for (int t : {16, 8, 4, 2, 1})
+        for (int q : {64, 32, 16, 8, 4, 2, 1}) {
+            if (mlp2_lds(F, H, L, t, q) <= 64 * 1024) {
+                *T = t;
+                *QC = q;
+                return true;
+            }
+        }
+    return false;
 }
 
 }  // namespace
@@ -801,7 +876,8 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
     }
     const int64_t N = sys_off[n_systems];
     if (N >= ((int64_t)1 << 31) / 8) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "batch too large");
-    if (m->F > 1024 || tile_atoms(m->F, m->H, m->L) == 0)
+    int tileT = 0, tileQC = 0;
+    if (m->F > 1024 || !mlp2_shape(m->F, m->H, m->L, &tileT, &tileQC))
         return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "model too wide for the training kernels");
 
     tmd_batch* b = new (std::nothrow) tmd_batch();
@@ -952,7 +1028,8 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
         if (flag) return bail(fail(ctx, TMD_ERR_NUMERICAL, "pair table inconsistent (an entry without its mirror)"));
     }
     // second-order tiles
-    b->tileT = tile_atoms(m->F, m->H, m->L);
+    b->tileT = tileT;
+    b->tileQC = tileQC;
     int64_t tiles = 0;
     for (int s = 0; s < m->S; ++s) {
         b->tile_off[s] = tiles;
@@ -1039,6 +1116,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     t.H = m->H;
     t.act = m->act;
     t.T = b->tileT;
+    t.QC = b->tileQC;
     t.P = (int)m->per_species;
     for (int s = 0; s <= m->S; ++s) {
         t.sp_off[s] = b->groups.off[s];
@@ -1050,7 +1128,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     t.e = b->e;
     t.params = m->params32;
     t.partial = b->partial;
-    const size_t lds = sizeof(float) * (size_t)t.T * (2 * t.F + 4 * t.L * t.H + 4 * t.H);
+    const size_t lds = mlp2_lds(t.F, t.H, t.L, t.T, t.QC);
     float* gdst = grad ? grad : b->grad;
     {
         ProfScope ps_(ctx, "train_mlp2");
@@ -1058,14 +1136,22 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     }
     TMD_HIP(ctx, hipGetLastError());
     {
-        // tile offsets per species (device copy, fixed order of the reduction)
-        hipError_t e = hipSuccess;
-        int64_t* toff = (int64_t*)ctx->ws.get("train.tile_off", 8 * (kMaxSpecies + 1), &e);
-        if (e != hipSuccess) return hip_fail(ctx, e, "training workspace");
-        TMD_HIP(ctx, hipMemcpyAsync(toff, b->tile_off, 8 * (size_t)(m->S + 1), hipMemcpyHostToDevice, ctx->stream));
+        GradReduceArgs g{};
+        g.S = m->S;
+        g.P = (int)m->per_species;
+        for (int q = 0; q <= m->S; ++q) {
+            g.tile_off[q] = b->tile_off[q];
+            g.chunk_off[q] = q == 0 ? 0
+                                    : g.chunk_off[q - 1] +
+                                          (b->tile_off[q] - b->tile_off[q - 1] + kGradChunk - 1) / kGradChunk;
+        }
+        g.partial = b->partial;
+        g.grad = gdst;
         ProfScope ps_(ctx, "train_grad_reduce");
-        k_grad_reduce<<<blocks_for((int64_t)m->S * m->per_species), kBlock, 0, ctx->stream>>>(
-            m->S, (int)m->per_species, toff, b->partial, gdst);
+        const int pb = (g.P + 255) / 256;
+        if (g.chunk_off[m->S] > 0)
+            k_grad_chunks<<<(unsigned)(g.chunk_off[m->S] * pb), 256, 0, ctx->stream>>>(g, pb);
+        k_grad_reduce<<<blocks_for((int64_t)m->S * m->per_species), kBlock, 0, ctx->stream>>>(g);
     }
     TMD_HIP(ctx, hipGetLastError());
     TMD_HIP(ctx, hipMemcpyAsync(ctx->h_totals, b->loss, sizeof(double) * 3, hipMemcpyDeviceToHost, ctx->stream));

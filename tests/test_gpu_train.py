@@ -120,6 +120,33 @@ def test_train_step_matches_oracle(tmd, ctx, torch, case):
     model.close()
 
 
+@pytest.mark.parametrize("shape", ["two_species", "hidden128"])
+def test_train_step_other_shapes(tmd, ctx, torch, shape):
+    """Two species (tiles and reduction chunks of each species apart), and
+    128-wide hidden layers (8-atom tiles, hidden weights in 16 LDS blocks)."""
+    _note(f"train step vs oracle: {shape}")
+    b = _small_batch()
+    if shape == "two_species":
+        b.species[:] = np.random.default_rng(7).integers(0, 2, b.n).astype(np.int32)
+        teacher = inputs.make_model(2, 8, 3, [64, 64], 5.0, seed=1013)
+        student = inputs.make_model(2, 8, 3, [64, 64], 5.0, seed=2013)
+    else:
+        teacher = inputs.make_model(1, 8, 3, [128, 128], 5.0, seed=1023)
+        student = inputs.make_model(1, 8, 3, [128, 128], 5.0, seed=2023)
+    E_l, F_l = _labels(teacher, b)
+    model = tmd.Model(ctx, student)
+    bt = _device_batch(tmd, ctx, torch, model, b, E_l, F_l)
+    grad = torch.empty(model.n_params, dtype=torch.float32, device="cuda")
+    loss, le, lf = tmd.train_step(ctx, model, bt, lam=0.1, lr=0.0, grad=grad)
+    lr_, le_r, lf_r, gr = oracle.train_loss_grad(student, b.sys_off, b.pos, b.species, b.boxes, E_l, F_l, 0.1)
+    print(f"  loss {loss:.8e} vs {lr_:.8e}", flush=True)
+    assert abs(le - le_r) <= 1e-3 * le_r + 1e-12
+    assert abs(lf - lf_r) <= 1e-3 * lf_r + 1e-12
+    _grad_close(grad.cpu().numpy().astype(np.float64), gr)
+    bt.close()
+    model.close()
+
+
 def test_train_step_full_batch_64_cells(tmd, ctx, torch):
     """The 64-cell fcc/bcc/hcp batch (about 18k atoms) against the oracle."""
     _note("train step 64-cell batch vs oracle")
