@@ -516,9 +516,11 @@ __device__ __forceinline__ float d2sig(int act, float z) {
 //   ztbar_l = s'(z_l) atbar_l,  zbar_l = s'(z_l) abar_l + s''(z_l) zt_l atbar_l,
 //   dW_l += zbar_l a_{l-1}^T + ztbar_l at_{l-1}^T,  db_l += zbar_l,
 //   abar_{l-1} = W_l^T zbar_l,  atbar_{l-1} = W_l^T ztbar_l.
+template <int T>
 __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     extern __shared__ float lds[];
-    const int T = a.T, Tp = a.T | 1, H = a.H, F = a.F, L = a.L, QC = a.QC;
+    constexpr int Tp = T | 1;
+    const int H = a.H, F = a.F, L = a.L, QC = a.QC;
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
     int s = 0;
@@ -537,6 +539,7 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     float* Cz = Bat + H * Tp;
     float* Czt = Cz + H * Tp;
     float* Ws = Czt + H * Tp;             // [H][QC + 1]
+    float* Es = Ws + H * (QC + 1);        // [T] energy seeds, 0 past the tile's last atom
     const float* p = a.params + (int64_t)s * a.P;
     float* gp = a.partial + tile * a.P;
     // Ws[o][c] = W[o][q0 + c] for c < qn; the caller synchronises.
@@ -547,6 +550,10 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         }
     };
 
+    // Past the tile's last atom the inputs, tangents and seeds are zero, so
+    // the cotangents Cz, Czt of those columns are exactly zero and the sums
+    // over the tile can run over all T columns.
+    if (tid < T) Es[tid] = tid < nt ? a.e[a.sp_idx[first + tid]] : 0.0f;
     for (int idx = tid; idx < F * T; idx += blockDim.x) {
         const int q = idx / T, t = idx - q * T;
         float g = 0.0f, wt = 0.0f;
@@ -583,6 +590,7 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
                 const float* wrow = Ws + o * (QC + 1);
                 const float* ip = in + q0 * Tp + t;
                 const float* itp = int_ + q0 * Tp + t;
+#pragma unroll 4
                 for (int c = 0; c < qn; ++c) {
                     const float wv = wrow[c];
                     z = fmaf(wv, ip[c * Tp], z);
@@ -603,21 +611,19 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     for (int idx = tid; idx < H * T; idx += blockDim.x) {
         const int o = idx / T, t = idx - o * T;
         const bool live = t < nt;
-        const float et = live ? a.e[a.sp_idx[first + t]] : 0.0f;
-        Ba[o * Tp + t] = live ? et * p[offWo + o] : 0.0f;
+        Ba[o * Tp + t] = live ? Es[t] * p[offWo + o] : 0.0f;
         Bat[o * Tp + t] = live ? -p[offWo + o] : 0.0f;
     }
     for (int o = tid; o < H; o += blockDim.x) {
         float gw = 0.0f;
-        for (int t = 0; t < nt; ++t) {
-            const float et = a.e[a.sp_idx[first + t]];
-            gw += et * A[((L - 1) * H + o) * Tp + t] - At[((L - 1) * H + o) * Tp + t];
-        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) gw += Es[t] * A[((L - 1) * H + o) * Tp + t] - At[((L - 1) * H + o) * Tp + t];
         gp[offWo + o] = gw;
     }
     if (tid == 0) {
         float gb = 0.0f;
-        for (int t = 0; t < nt; ++t) gb += a.e[a.sp_idx[first + t]];
+#pragma unroll
+        for (int t = 0; t < T; ++t) gb += Es[t];
         gp[offbo] = gb;
     }
     __syncthreads();
@@ -637,13 +643,15 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         for (int idx = tid; idx < H * wi; idx += blockDim.x) {
             const int o = idx / wi, q = idx - o * wi;
             float gw = 0.0f;
-            for (int t = 0; t < nt; ++t)
+#pragma unroll
+            for (int t = 0; t < T; ++t)
                 gw += Cz[o * Tp + t] * in[q * Tp + t] + Czt[o * Tp + t] * int_[q * Tp + t];
             gp[offW[l] + idx] = gw;
         }
         for (int o = tid; o < H; o += blockDim.x) {
             float gb = 0.0f;
-            for (int t = 0; t < nt; ++t) gb += Cz[o * Tp + t];
+#pragma unroll
+            for (int t = 0; t < T; ++t) gb += Cz[o * Tp + t];
             gp[offb[l] + o] = gb;
         }
         if (l > 0) {
@@ -655,6 +663,7 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
                 for (int idx = tid; idx < qn * T; idx += blockDim.x) {
                     const int c = idx / T, t = idx - c * T;
                     float sa = 0.0f, st = 0.0f;
+#pragma unroll 4
                     for (int o = 0; o < H; ++o) {
                         const float wv = Ws[o * (QC + 1) + c];
                         sa = fmaf(wv, Cz[o * Tp + t], sa);
@@ -827,10 +836,10 @@ void batch_free(tmd_batch* b) {
     b->mirror = nullptr;
 }
 
-// LDS bytes of k_mlp_second: activations [width][T | 1] and a [H][QC + 1]
-// block of weights.
+// LDS bytes of k_mlp_second: activations [width][T | 1], a [H][QC + 1]
+// block of weights and the tile's T energy seeds.
 size_t mlp2_lds(int F, int H, int L, int T, int QC) {
-    return sizeof(float) * ((size_t)(T | 1) * (2 * F + 4 * L * H + 4 * H) + (size_t)H * (QC + 1));
+    return sizeof(float) * ((size_t)(T | 1) * (2 * F + 4 * L * H + 4 * H) + (size_t)H * (QC + 1) + T);
 }
 
 // Largest tile (atoms), then widest weight block (columns), that fit in 64 KB
@@ -1132,7 +1141,12 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     float* gdst = grad ? grad : b->grad;
     {
         ProfScope ps_(ctx, "train_mlp2");
-        if (b->tiles > 0) k_mlp_second<<<(unsigned)b->tiles, 256, lds, ctx->stream>>>(t);
+        auto kern = t.T == 16 ? k_mlp_second<16>
+                    : t.T == 8 ? k_mlp_second<8>
+                    : t.T == 4 ? k_mlp_second<4>
+                    : t.T == 2 ? k_mlp_second<2>
+                               : k_mlp_second<1>;
+        if (b->tiles > 0) kern<<<(unsigned)b->tiles, 256, lds, ctx->stream>>>(t);
     }
     TMD_HIP(ctx, hipGetLastError());
     {
