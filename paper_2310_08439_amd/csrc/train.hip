@@ -318,25 +318,38 @@ __global__ void __launch_bounds__(256) k_pt_adjoint(PtArgs a) {
     }
 }
 
-// F_i = sum over i's entries of g_c - g_mirror(c), in entry order.
+// F_i = sum over i's entries of g_c - g_mirror(c).  Four adjacent lanes per
+// atom: lane l sums entries l, l + 4, ... of each row in order, then the
+// lanes combine in a fixed butterfly, so the result is reproducible.
+constexpr int kForceLanes = 4;
 __global__ void k_pt_forces(int64_t N, int S, int cap, const int32_t* __restrict__ tcnt,
                             const int32_t* __restrict__ mirror, const float4* __restrict__ g, float* __restrict__ F) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / kForceLanes;
+    const int l = (int)(t % kForceLanes);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    for (int b = 0; b < S; ++b) {
-        const int64_t row = (i * S + b) * cap;
-        const int nb = tcnt[i * S + b];
-        for (int c = 0; c < nb; ++c) {
-            const float4 u = g[row + c], v = g[mirror[row + c]];
-            fx += u.x - v.x;
-            fy += u.y - v.y;
-            fz += u.z - v.z;
+    if (i < N) {
+        for (int b = 0; b < S; ++b) {
+            const int64_t row = (i * S + b) * cap;
+            const int nb = tcnt[i * S + b];
+            for (int c = l; c < nb; c += kForceLanes) {
+                const float4 u = g[row + c], v = g[mirror[row + c]];
+                fx += u.x - v.x;
+                fy += u.y - v.y;
+                fz += u.z - v.z;
+            }
         }
     }
-    F[3 * i + 0] = fx;
-    F[3 * i + 1] = fy;
-    F[3 * i + 2] = fz;
+    for (int off = 1; off < kForceLanes; off <<= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    if (i < N && l == 0) {
+        F[3 * i + 0] = fx;
+        F[3 * i + 1] = fy;
+        F[3 * i + 2] = fz;
+    }
 }
 
 // Per system: E_s = sum of atomic energies and sum |F - Fhat|^2, FP64, fixed
@@ -372,10 +385,15 @@ __global__ void __launch_bounds__(256) k_loss_sys(const int64_t* __restrict__ sy
 }
 
 // Loss terms (Neumaier over systems in order) and the per-system energy seed.
-__global__ void k_loss_total(int B, int64_t N, double lambda, const int64_t* __restrict__ sys_off,
-                             const double* __restrict__ E_label, const double* __restrict__ sysE,
-                             const double* __restrict__ sysF, double* __restrict__ loss, double* __restrict__ eseed) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup of 256: the threads form the terms of 256 systems at a time,
+// thread 0 adds them in system order.
+__global__ void __launch_bounds__(256) k_loss_total(int B, int64_t N, double lambda,
+                                                    const int64_t* __restrict__ sys_off,
+                                                    const double* __restrict__ E_label, const double* __restrict__ sysE,
+                                                    const double* __restrict__ sysF, double* __restrict__ loss,
+                                                    double* __restrict__ eseed) {
+    __shared__ double te[256], tf[256];
+    const int tid = threadIdx.x;
     double le = 0.0, ce = 0.0, lf = 0.0, cf = 0.0;
     auto add = [](double& s, double& c, double x) {
         const double t = s + x;
@@ -383,16 +401,28 @@ __global__ void k_loss_total(int B, int64_t N, double lambda, const int64_t* __r
         else c += (x - t) + s;
         s = t;
     };
-    for (int s = 0; s < B; ++s) {
-        const double ns = (double)(sys_off[s + 1] - sys_off[s]);
-        const double de = (sysE[s] - E_label[s]) / ns;
-        add(le, ce, de * de / (double)B);
-        add(lf, cf, lambda * sysF[s] / (3.0 * (double)N));
-        eseed[s] = 2.0 / (double)B * (sysE[s] - E_label[s]) / (ns * ns);
+    for (int base = 0; base < B; base += 256) {
+        const int s = base + tid;
+        if (s < B) {
+            const double ns = (double)(sys_off[s + 1] - sys_off[s]);
+            const double de = (sysE[s] - E_label[s]) / ns;
+            te[tid] = de * de / (double)B;
+            tf[tid] = lambda * sysF[s] / (3.0 * (double)N);
+            eseed[s] = 2.0 / (double)B * (sysE[s] - E_label[s]) / (ns * ns);
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int k = 0; k < min(256, B - base); ++k) {
+                add(le, ce, te[k]);
+                add(lf, cf, tf[k]);
+            }
+        __syncthreads();
     }
-    loss[1] = le + ce;
-    loss[2] = lf + cf;
-    loss[0] = loss[1] + loss[2];
+    if (tid == 0) {
+        loss[1] = le + ce;
+        loss[2] = lf + cf;
+        loss[0] = loss[1] + loss[2];
+    }
 }
 
 // r_i = dL/dF_i = 2 lambda/(3N) (F_i - Fhat_i); e_i = seed of i's system.
@@ -785,6 +815,10 @@ using PtFn = void (*)(PtArgs);
 #define TMD_PICK(NAME, KERNEL)                                    \
     PtFn NAME(int kc, int M) {                                    \
         switch (kc * 10 + M) {                                    \
+            case 20: return KERNEL<2, 0>;                         \
+            case 21: return KERNEL<2, 1>;                         \
+            case 22: return KERNEL<2, 2>;                         \
+            case 23: return KERNEL<2, 3>;                         \
             case 40: return KERNEL<4, 0>;                         \
             case 41: return KERNEL<4, 1>;                         \
             case 42: return KERNEL<4, 2>;                         \
@@ -805,6 +839,14 @@ TMD_PICK(pick_tangent, k_pt_tangent)
 #undef TMD_PICK
 
 unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+// Radial functions per thread of the pair-table kernels: the model's chunk,
+// halved (8 -> 4 -> 2) while the batch would give fewer than 1024 threads per
+// compute unit.  P is stored by radial index, so any chunk reads it.
+int batch_kc(int K, int kc, int64_t N) {
+    while (kc % 4 == 0 && N * (K / kc) < (int64_t)256 * 1024 && 2 * K / kc <= 64) kc /= 2;
+    return kc;
+}
 
 PtArgs pt_args(const tmd_batch* bt) {
     PtArgs a{};
@@ -899,7 +941,7 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
     b->M = m->M;
     b->D = m->D;
     b->F = m->F;
-    b->kc = m->kc;
+    b->kc = batch_kc(m->K, m->kc, N);
     b->rcut = m->rcut;
     b->mu.resize(m->K);
     b->eta.resize(m->K);
@@ -1028,7 +1070,7 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
         a.eta = m->eta;
         a.G = b->G;
         a.P = b->P;
-        pick_forward(b->kc, b->M)<<<blocks_for(N * (m->K / m->kc)), kBlock, 0, ctx->stream>>>(a);
+        pick_forward(b->kc, b->M)<<<blocks_for(N * (b->K / b->kc)), kBlock, 0, ctx->stream>>>(a);
         e = hipGetLastError();
         int32_t flag = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&flag, b->flag, 4, hipMemcpyDeviceToHost, ctx->stream);
@@ -1064,7 +1106,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
     if (!m || !bc || !opts || !loss) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null argument");
     tmd_batch* b = const_cast<tmd_batch*>(bc);  // per-step scratch lives in the batch
-    if (m->S != b->S || m->K != b->K || m->M != b->M || m->rcut != b->rcut || m->kc != b->kc)
+    if (m->S != b->S || m->K != b->K || m->M != b->M || m->rcut != b->rcut)
         return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "model descriptor shape differs from the batch's");
     {
         std::vector<float> mu(m->mu_h.begin(), m->mu_h.end()), eta(m->eta_h.begin(), m->eta_h.end());
@@ -1093,21 +1135,21 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     a.g = b->g;
     a.r = b->r;
     a.w = b->w;
-    const unsigned pt_grid = blocks_for(N * (m->K / m->kc));
+    const unsigned pt_grid = blocks_for(N * (b->K / b->kc));
     {
         ProfScope ps_(ctx, "train_adjoint");
         pick_adjoint(b->kc, b->M)<<<pt_grid, kBlock, 0, ctx->stream>>>(a);
     }
     {
         ProfScope ps_(ctx, "train_forces");
-        k_pt_forces<<<blocks_for(N), kBlock, 0, ctx->stream>>>(N, b->S, b->cap, b->cnt, b->mirror, b->g, b->Fp);
+        k_pt_forces<<<blocks_for(N * kForceLanes), kBlock, 0, ctx->stream>>>(N, b->S, b->cap, b->cnt, b->mirror, b->g, b->Fp);
     }
     // 2. loss and seeds
     {
         ProfScope ps_(ctx, "train_loss");
         double* eseed = b->loss + 4;
         k_loss_sys<<<b->B, 256, 0, ctx->stream>>>(b->sys_off, b->Ei, b->Fp, b->F_label, b->sysE, b->sysF);
-        k_loss_total<<<1, 64, 0, ctx->stream>>>(b->B, N, opts->lambda, b->sys_off, b->E_label, b->sysE, b->sysF,
+        k_loss_total<<<1, 256, 0, ctx->stream>>>(b->B, N, opts->lambda, b->sys_off, b->E_label, b->sysE, b->sysF,
                                                 b->loss, eseed);
         k_residual<<<blocks_for(N), kBlock, 0, ctx->stream>>>(N, (float)(2.0 * opts->lambda / (3.0 * (double)N)),
                                                                b->sys_of, eseed, b->Fp, b->F_label, b->r, b->e);

@@ -166,6 +166,35 @@ def test_train_step_full_batch_64_cells(tmd, ctx, torch):
     model.close()
 
 
+def test_train_step_large_batch_repeated_cells(tmd, ctx, torch):
+    """The 64-cell batch repeated 15 times (276,420 atoms): at this size the
+    pair-table kernels keep the model's eight radial functions per thread.
+    Both loss terms are means over systems and atoms, so the repeated batch
+    has exactly the loss and gradient of the 64-cell batch, which the oracle
+    gives."""
+    _note("train step, 64-cell batch repeated 15 times")
+    rep = 15
+    _, teacher, _ = inputs.workload("train_teacher")
+    _, student, _ = inputs.workload("train_student")
+    b = inputs.train_batch()
+    E_l, F_l = _labels(teacher, b)
+    off = np.concatenate([[0]] + [b.sys_off[1:] + k * b.n for k in range(rep)]).astype(np.int64)
+    big = inputs.Batch(pos=np.tile(b.pos, (rep, 1)), species=np.tile(b.species, rep), sys_off=off,
+                       boxes=np.tile(b.boxes, (rep, 1)), kinds=list(b.kinds) * rep)
+    assert big.n >= 256 * 1024  # N * K / 8 threads with K = 8
+    model = tmd.Model(ctx, student)
+    bt = _device_batch(tmd, ctx, torch, model, big, np.tile(E_l, rep), np.tile(F_l, (rep, 1)))
+    grad = torch.empty(model.n_params, dtype=torch.float32, device="cuda")
+    loss, le, lf = tmd.train_step(ctx, model, bt, lam=0.1, lr=0.0, grad=grad)
+    lr_, le_r, lf_r, gr = oracle.train_loss_grad(student, b.sys_off, b.pos, b.species, b.boxes, E_l, F_l, 0.1)
+    print(f"  loss {loss:.8e} vs {lr_:.8e}", flush=True)
+    assert abs(le - le_r) <= 1e-3 * le_r + 1e-12
+    assert abs(lf - lf_r) <= 1e-3 * lf_r + 1e-12
+    _grad_close(grad.cpu().numpy().astype(np.float64), gr)
+    bt.close()
+    model.close()
+
+
 def test_train_step_is_deterministic(tmd, ctx, torch):
     _note("train step bitwise repeat")
     _, teacher, _ = inputs.workload("train_teacher")
