@@ -570,6 +570,8 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     float* Czt = Cz + H * Tp;
     float* Ws = Czt + H * Tp;             // [H][QC + 1]
     float* Es = Ws + H * (QC + 1);        // [T] energy seeds, 0 past the tile's last atom
+    constexpr int G = 256 / T;            // rows of a [width][T] array covered by one pass of the workgroup
+    const int tcol = tid % T, row0 = tid / T;  // this thread's column and first row
     const float* p = a.params + (int64_t)s * a.P;
     float* gp = a.partial + tile * a.P;
     // Ws[o][c] = W[o][q0 + c] for c < qn; the caller synchronises.
@@ -613,24 +615,39 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
             const bool last = q0 + qn == wi;
             stage(p + offW[l], wi, q0, qn);
             __syncthreads();
-            for (int idx = tid; idx < H * T; idx += blockDim.x) {
-                const int o = idx / T, t = idx - o * T;
-                float z = q0 == 0 ? p[offb[l] + o] : Zl[o * Tp + t];
-                float zt = q0 == 0 ? 0.0f : Ztl[o * Tp + t];
-                const float* wrow = Ws + o * (QC + 1);
-                const float* ip = in + q0 * Tp + t;
-                const float* itp = int_ + q0 * Tp + t;
-#pragma unroll 4
-                for (int c = 0; c < qn; ++c) {
-                    const float wv = wrow[c];
-                    z = fmaf(wv, ip[c * Tp], z);
-                    zt = fmaf(wv, itp[c * Tp], zt);
+            // thread (tcol, row0) owns rows row0, row0 + G, row0 + 2G, ... of column tcol;
+            // four rows at a time share the loads of the inputs
+            for (int ob = row0; ob < H; ob += 4 * G) {
+                float z[4], zt[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int o = min(ob + k * G, H - 1);
+                    z[k] = q0 == 0 ? p[offb[l] + o] : Zl[o * Tp + tcol];
+                    zt[k] = q0 == 0 ? 0.0f : Ztl[o * Tp + tcol];
                 }
-                Zl[o * Tp + t] = z;
-                Ztl[o * Tp + t] = zt;
-                if (last) {
-                    A[(l * H + o) * Tp + t] = sig(a.act, z);
-                    At[(l * H + o) * Tp + t] = dsig(a.act, z) * zt;
+                const float* ip = in + q0 * Tp + tcol;
+                const float* itp = int_ + q0 * Tp + tcol;
+#pragma unroll 2
+                for (int c = 0; c < qn; ++c) {
+                    const float x = ip[c * Tp], xt = itp[c * Tp];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float wv = Ws[min(ob + k * G, H - 1) * (QC + 1) + c];
+                        z[k] = fmaf(wv, x, z[k]);
+                        zt[k] = fmaf(wv, xt, zt[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int o = ob + k * G;
+                    if (o < H) {
+                        Zl[o * Tp + tcol] = z[k];
+                        Ztl[o * Tp + tcol] = zt[k];
+                        if (last) {
+                            A[(l * H + o) * Tp + tcol] = sig(a.act, z[k]);
+                            At[(l * H + o) * Tp + tcol] = dsig(a.act, z[k]) * zt[k];
+                        }
+                    }
                 }
             }
             __syncthreads();
@@ -670,13 +687,30 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         __syncthreads();
         const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
         const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
-        for (int idx = tid; idx < H * wi; idx += blockDim.x) {
-            const int o = idx / wi, q = idx - o * wi;
-            float gw = 0.0f;
+        if (256 % wi == 0) {
+            // each thread keeps one input row q for all its rows o
+            const int q = tid % wi;
+            float xi[T], xt[T];
 #pragma unroll
-            for (int t = 0; t < T; ++t)
-                gw += Cz[o * Tp + t] * in[q * Tp + t] + Czt[o * Tp + t] * int_[q * Tp + t];
-            gp[offW[l] + idx] = gw;
+            for (int u = 0; u < T; ++u) {
+                xi[u] = in[q * Tp + u];
+                xt[u] = int_[q * Tp + u];
+            }
+            for (int o = tid / wi; o < H; o += 256 / wi) {
+                float gw = 0.0f;
+#pragma unroll
+                for (int u = 0; u < T; ++u) gw += Cz[o * Tp + u] * xi[u] + Czt[o * Tp + u] * xt[u];
+                gp[offW[l] + o * wi + q] = gw;
+            }
+        } else {
+            for (int idx = tid; idx < H * wi; idx += blockDim.x) {
+                const int o = idx / wi, q = idx - o * wi;
+                float gw = 0.0f;
+#pragma unroll
+                for (int u = 0; u < T; ++u)
+                    gw += Cz[o * Tp + u] * in[q * Tp + u] + Czt[o * Tp + u] * int_[q * Tp + u];
+                gp[offW[l] + idx] = gw;
+            }
         }
         for (int o = tid; o < H; o += blockDim.x) {
             float gb = 0.0f;
@@ -690,17 +724,28 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
                 const int qn = min(QC, wi - q0);
                 stage(p + offW[l], wi, q0, qn);
                 __syncthreads();
-                for (int idx = tid; idx < qn * T; idx += blockDim.x) {
-                    const int c = idx / T, t = idx - c * T;
-                    float sa = 0.0f, st = 0.0f;
-#pragma unroll 4
+                // thread (tcol, row0) owns block columns row0, row0 + G, ... of atom tcol;
+                // four at a time share the loads of Cz, Czt
+                for (int cb = row0; cb < qn; cb += 4 * G) {
+                    float sa[4] = {0.0f, 0.0f, 0.0f, 0.0f}, st[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
                     for (int o = 0; o < H; ++o) {
-                        const float wv = Ws[o * (QC + 1) + c];
-                        sa = fmaf(wv, Cz[o * Tp + t], sa);
-                        st = fmaf(wv, Czt[o * Tp + t], st);
+                        const float cz = Cz[o * Tp + tcol], czt = Czt[o * Tp + tcol];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float wv = Ws[o * (QC + 1) + min(cb + k * G, qn - 1)];
+                            sa[k] = fmaf(wv, cz, sa[k]);
+                            st[k] = fmaf(wv, czt, st[k]);
+                        }
                     }
-                    Ba[(q0 + c) * Tp + t] = sa;
-                    Bat[(q0 + c) * Tp + t] = st;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int c = cb + k * G;
+                        if (c < qn) {
+                            Ba[(q0 + c) * Tp + tcol] = sa[k];
+                            Bat[(q0 + c) * Tp + tcol] = st[k];
+                        }
+                    }
                 }
                 __syncthreads();
             }
