@@ -63,6 +63,7 @@ struct tmd_batch {
     int32_t* flag = nullptr;     // [1] set when an entry has no mirror
     int tileT = 0;               // atoms per second-order tile
     int tileQC = 0;              // weight columns per LDS block of the second-order pass
+    int tileR = 0;               // sub-tiles of tileT atoms per second-order workgroup
     int64_t tiles = 0;
     int64_t tile_off[tmd::kMaxSpecies + 1] = {0};
 };
@@ -507,7 +508,7 @@ __global__ void __launch_bounds__(256) k_pt_tangent(PtArgs a) {
 // ---------------------------------------------------------------- second-order MLP pass
 
 struct MlpTrainArgs {
-    int S, F, L, H, act, T, QC, P;
+    int S, F, L, H, act, T, QC, R, P;
     int64_t sp_off[kMaxSpecies + 1];
     int64_t tile_off[kMaxSpecies + 1];
     const int32_t* sp_idx;
@@ -556,8 +557,7 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     int s = 0;
     for (int q = 0; q < a.S; ++q)
         if (tile >= a.tile_off[q] && tile < a.tile_off[q + 1]) s = q;
-    const int64_t first = a.sp_off[s] + (tile - a.tile_off[s]) * T;
-    const int nt = (int)min((int64_t)T, a.sp_off[s + 1] - first);
+    const int64_t first0 = a.sp_off[s] + (tile - a.tile_off[s]) * (int64_t)T * a.R;
     float* X0 = lds;                      // [F][Tp]
     float* X0t = X0 + F * Tp;             // [F][Tp]
     float* Z = X0t + F * Tp;              // [L][H][Tp]
@@ -582,175 +582,183 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
         }
     };
 
-    // Past the tile's last atom the inputs, tangents and seeds are zero, so
-    // the cotangents Cz, Czt of those columns are exactly zero and the sums
-    // over the tile can run over all T columns.
-    if (tid < T) Es[tid] = tid < nt ? a.e[a.sp_idx[first + tid]] : 0.0f;
-    for (int idx = tid; idx < F * T; idx += blockDim.x) {
-        const int q = idx / T, t = idx - q * T;
-        float g = 0.0f, wt = 0.0f;
-        if (t < nt) {
-            const int64_t atom = a.sp_idx[first + t];
-            g = a.G[atom * F + q];
-            wt = a.w[atom * F + q];
-        }
-        X0[q * Tp + t] = g;
-        X0t[q * Tp + t] = wt;
-    }
-    // forward: primal and tangent, accumulated over the weight blocks in Z, Zt
-    int off = 0;
-    int offW[TMD_MAX_HIDDEN], offb[TMD_MAX_HIDDEN];
-    for (int l = 0; l < L; ++l) {
-        const int wi = (l == 0) ? F : H;
-        offW[l] = off;
-        off += H * wi;
-        offb[l] = off;
-        off += H;
-        const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
-        const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
-        float* Zl = Z + l * H * Tp;
-        float* Ztl = Zt + l * H * Tp;
-        for (int q0 = 0; q0 < wi; q0 += QC) {
-            const int qn = min(QC, wi - q0);
-            const bool last = q0 + qn == wi;
-            stage(p + offW[l], wi, q0, qn);
-            __syncthreads();
-            // thread (tcol, row0) owns rows row0, row0 + G, row0 + 2G, ... of column tcol;
-            // four rows at a time share the loads of the inputs
-            for (int ob = row0; ob < H; ob += 4 * G) {
-                float z[4], zt[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int o = min(ob + k * G, H - 1);
-                    z[k] = q0 == 0 ? p[offb[l] + o] : Zl[o * Tp + tcol];
-                    zt[k] = q0 == 0 ? 0.0f : Ztl[o * Tp + tcol];
-                }
-                const float* ip = in + q0 * Tp + tcol;
-                const float* itp = int_ + q0 * Tp + tcol;
-#pragma unroll 2
-                for (int c = 0; c < qn; ++c) {
-                    const float x = ip[c * Tp], xt = itp[c * Tp];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float wv = Ws[min(ob + k * G, H - 1) * (QC + 1) + c];
-                        z[k] = fmaf(wv, x, z[k]);
-                        zt[k] = fmaf(wv, xt, zt[k]);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int o = ob + k * G;
-                    if (o < H) {
-                        Zl[o * Tp + tcol] = z[k];
-                        Ztl[o * Tp + tcol] = zt[k];
-                        if (last) {
-                            A[(l * H + o) * Tp + tcol] = sig(a.act, z[k]);
-                            At[(l * H + o) * Tp + tcol] = dsig(a.act, z[k]) * zt[k];
-                        }
-                    }
-                }
+    // The workgroup's tile is R sub-tiles of T atoms, taken in order; each
+    // adds its weight-gradient terms to the tile's partial row.
+    for (int r = 0; r < a.R; ++r) {
+        const int64_t first = first0 + (int64_t)r * T;
+        if (first >= a.sp_off[s + 1]) break;  // the same for the whole workgroup
+        const int nt = (int)min((int64_t)T, a.sp_off[s + 1] - first);
+        auto put = [&](int64_t k, float v) { gp[k] = r == 0 ? v : gp[k] + v; };
+        // Past the tile's last atom the inputs, tangents and seeds are zero, so
+        // the cotangents Cz, Czt of those columns are exactly zero and the sums
+        // over the tile can run over all T columns.
+        if (tid < T) Es[tid] = tid < nt ? a.e[a.sp_idx[first + tid]] : 0.0f;
+        for (int idx = tid; idx < F * T; idx += blockDim.x) {
+            const int q = idx / T, t = idx - q * T;
+            float g = 0.0f, wt = 0.0f;
+            if (t < nt) {
+                const int64_t atom = a.sp_idx[first + t];
+                g = a.G[atom * F + q];
+                wt = a.w[atom * F + q];
             }
-            __syncthreads();
+            X0[q * Tp + t] = g;
+            X0t[q * Tp + t] = wt;
         }
-    }
-    const int offWo = off, offbo = off + H;
-    // output layer: E = w_out . a_L + b_out, q = w_out . at_L
-    for (int idx = tid; idx < H * T; idx += blockDim.x) {
-        const int o = idx / T, t = idx - o * T;
-        const bool live = t < nt;
-        Ba[o * Tp + t] = live ? Es[t] * p[offWo + o] : 0.0f;
-        Bat[o * Tp + t] = live ? -p[offWo + o] : 0.0f;
-    }
-    for (int o = tid; o < H; o += blockDim.x) {
-        float gw = 0.0f;
-#pragma unroll
-        for (int t = 0; t < T; ++t) gw += Es[t] * A[((L - 1) * H + o) * Tp + t] - At[((L - 1) * H + o) * Tp + t];
-        gp[offWo + o] = gw;
-    }
-    if (tid == 0) {
-        float gb = 0.0f;
-#pragma unroll
-        for (int t = 0; t < T; ++t) gb += Es[t];
-        gp[offbo] = gb;
-    }
-    __syncthreads();
-    for (int l = L - 1; l >= 0; --l) {
-        const int wi = (l == 0) ? F : H;
-        for (int idx = tid; idx < H * T; idx += blockDim.x) {
-            const int o = idx / T, t = idx - o * T;
-            const int at = o * Tp + t;
-            const float z = Z[l * H * Tp + at];
-            const float d1 = dsig(a.act, z), d2 = d2sig(a.act, z);
-            Czt[at] = d1 * Bat[at];
-            Cz[at] = d1 * Ba[at] + d2 * Zt[l * H * Tp + at] * Bat[at];
-        }
-        __syncthreads();
-        const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
-        const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
-        if (256 % wi == 0) {
-            // each thread keeps one input row q for all its rows o
-            const int q = tid % wi;
-            float xi[T], xt[T];
-#pragma unroll
-            for (int u = 0; u < T; ++u) {
-                xi[u] = in[q * Tp + u];
-                xt[u] = int_[q * Tp + u];
-            }
-            for (int o = tid / wi; o < H; o += 256 / wi) {
-                float gw = 0.0f;
-#pragma unroll
-                for (int u = 0; u < T; ++u) gw += Cz[o * Tp + u] * xi[u] + Czt[o * Tp + u] * xt[u];
-                gp[offW[l] + o * wi + q] = gw;
-            }
-        } else {
-            for (int idx = tid; idx < H * wi; idx += blockDim.x) {
-                const int o = idx / wi, q = idx - o * wi;
-                float gw = 0.0f;
-#pragma unroll
-                for (int u = 0; u < T; ++u)
-                    gw += Cz[o * Tp + u] * in[q * Tp + u] + Czt[o * Tp + u] * int_[q * Tp + u];
-                gp[offW[l] + idx] = gw;
-            }
-        }
-        for (int o = tid; o < H; o += blockDim.x) {
-            float gb = 0.0f;
-#pragma unroll
-            for (int t = 0; t < T; ++t) gb += Cz[o * Tp + t];
-            gp[offb[l] + o] = gb;
-        }
-        if (l > 0) {
-            // Ba, Bat = W_l^T (Cz, Czt), one block of input columns at a time
+        // forward: primal and tangent, accumulated over the weight blocks in Z, Zt
+        int off = 0;
+        int offW[TMD_MAX_HIDDEN], offb[TMD_MAX_HIDDEN];
+        for (int l = 0; l < L; ++l) {
+            const int wi = (l == 0) ? F : H;
+            offW[l] = off;
+            off += H * wi;
+            offb[l] = off;
+            off += H;
+            const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
+            const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
+            float* Zl = Z + l * H * Tp;
+            float* Ztl = Zt + l * H * Tp;
             for (int q0 = 0; q0 < wi; q0 += QC) {
                 const int qn = min(QC, wi - q0);
+                const bool last = q0 + qn == wi;
                 stage(p + offW[l], wi, q0, qn);
                 __syncthreads();
-                // thread (tcol, row0) owns block columns row0, row0 + G, ... of atom tcol;
-                // four at a time share the loads of Cz, Czt
-                for (int cb = row0; cb < qn; cb += 4 * G) {
-                    float sa[4] = {0.0f, 0.0f, 0.0f, 0.0f}, st[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                // thread (tcol, row0) owns rows row0, row0 + G, row0 + 2G, ... of column tcol;
+                // four rows at a time share the loads of the inputs
+                for (int ob = row0; ob < H; ob += 4 * G) {
+                    float z[4], zt[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int o = min(ob + k * G, H - 1);
+                        z[k] = q0 == 0 ? p[offb[l] + o] : Zl[o * Tp + tcol];
+                        zt[k] = q0 == 0 ? 0.0f : Ztl[o * Tp + tcol];
+                    }
+                    const float* ip = in + q0 * Tp + tcol;
+                    const float* itp = int_ + q0 * Tp + tcol;
 #pragma unroll 2
-                    for (int o = 0; o < H; ++o) {
-                        const float cz = Cz[o * Tp + tcol], czt = Czt[o * Tp + tcol];
+                    for (int c = 0; c < qn; ++c) {
+                        const float x = ip[c * Tp], xt = itp[c * Tp];
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            const float wv = Ws[o * (QC + 1) + min(cb + k * G, qn - 1)];
-                            sa[k] = fmaf(wv, cz, sa[k]);
-                            st[k] = fmaf(wv, czt, st[k]);
+                            const float wv = Ws[min(ob + k * G, H - 1) * (QC + 1) + c];
+                            z[k] = fmaf(wv, x, z[k]);
+                            zt[k] = fmaf(wv, xt, zt[k]);
                         }
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const int c = cb + k * G;
-                        if (c < qn) {
-                            Ba[(q0 + c) * Tp + tcol] = sa[k];
-                            Bat[(q0 + c) * Tp + tcol] = st[k];
+                        const int o = ob + k * G;
+                        if (o < H) {
+                            Zl[o * Tp + tcol] = z[k];
+                            Ztl[o * Tp + tcol] = zt[k];
+                            if (last) {
+                                A[(l * H + o) * Tp + tcol] = sig(a.act, z[k]);
+                                At[(l * H + o) * Tp + tcol] = dsig(a.act, z[k]) * zt[k];
+                            }
                         }
                     }
                 }
                 __syncthreads();
             }
         }
+        const int offWo = off, offbo = off + H;
+        // output layer: E = w_out . a_L + b_out, q = w_out . at_L
+        for (int idx = tid; idx < H * T; idx += blockDim.x) {
+            const int o = idx / T, t = idx - o * T;
+            const bool live = t < nt;
+            Ba[o * Tp + t] = live ? Es[t] * p[offWo + o] : 0.0f;
+            Bat[o * Tp + t] = live ? -p[offWo + o] : 0.0f;
+        }
+        for (int o = tid; o < H; o += blockDim.x) {
+            float gw = 0.0f;
+#pragma unroll
+            for (int t = 0; t < T; ++t) gw += Es[t] * A[((L - 1) * H + o) * Tp + t] - At[((L - 1) * H + o) * Tp + t];
+            put(offWo + o, gw);
+        }
+        if (tid == 0) {
+            float gb = 0.0f;
+#pragma unroll
+            for (int t = 0; t < T; ++t) gb += Es[t];
+            put(offbo, gb);
+        }
         __syncthreads();
+        for (int l = L - 1; l >= 0; --l) {
+            const int wi = (l == 0) ? F : H;
+            for (int idx = tid; idx < H * T; idx += blockDim.x) {
+                const int o = idx / T, t = idx - o * T;
+                const int at = o * Tp + t;
+                const float z = Z[l * H * Tp + at];
+                const float d1 = dsig(a.act, z), d2 = d2sig(a.act, z);
+                Czt[at] = d1 * Bat[at];
+                Cz[at] = d1 * Ba[at] + d2 * Zt[l * H * Tp + at] * Bat[at];
+            }
+            __syncthreads();
+            const float* in = (l == 0) ? X0 : A + (l - 1) * H * Tp;
+            const float* int_ = (l == 0) ? X0t : At + (l - 1) * H * Tp;
+            if (256 % wi == 0) {
+                // each thread keeps one input row q for all its rows o
+                const int q = tid % wi;
+                float xi[T], xt[T];
+#pragma unroll
+                for (int u = 0; u < T; ++u) {
+                    xi[u] = in[q * Tp + u];
+                    xt[u] = int_[q * Tp + u];
+                }
+                for (int o = tid / wi; o < H; o += 256 / wi) {
+                    float gw = 0.0f;
+#pragma unroll
+                    for (int u = 0; u < T; ++u) gw += Cz[o * Tp + u] * xi[u] + Czt[o * Tp + u] * xt[u];
+                    put(offW[l] + o * wi + q, gw);
+                }
+            } else {
+                for (int idx = tid; idx < H * wi; idx += blockDim.x) {
+                    const int o = idx / wi, q = idx - o * wi;
+                    float gw = 0.0f;
+#pragma unroll
+                    for (int u = 0; u < T; ++u)
+                        gw += Cz[o * Tp + u] * in[q * Tp + u] + Czt[o * Tp + u] * int_[q * Tp + u];
+                    put(offW[l] + idx, gw);
+                }
+            }
+            for (int o = tid; o < H; o += blockDim.x) {
+                float gb = 0.0f;
+#pragma unroll
+                for (int t = 0; t < T; ++t) gb += Cz[o * Tp + t];
+                put(offb[l] + o, gb);
+            }
+            if (l > 0) {
+                // Ba, Bat = W_l^T (Cz, Czt), one block of input columns at a time
+                for (int q0 = 0; q0 < wi; q0 += QC) {
+                    const int qn = min(QC, wi - q0);
+                    stage(p + offW[l], wi, q0, qn);
+                    __syncthreads();
+                    // thread (tcol, row0) owns block columns row0, row0 + G, ... of atom tcol;
+                    // four at a time share the loads of Cz, Czt
+                    for (int cb = row0; cb < qn; cb += 4 * G) {
+                        float sa[4] = {0.0f, 0.0f, 0.0f, 0.0f}, st[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+                        for (int o = 0; o < H; ++o) {
+                            const float cz = Cz[o * Tp + tcol], czt = Czt[o * Tp + tcol];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const float wv = Ws[o * (QC + 1) + min(cb + k * G, qn - 1)];
+                                sa[k] = fmaf(wv, cz, sa[k]);
+                                st[k] = fmaf(wv, czt, st[k]);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int c = cb + k * G;
+                            if (c < qn) {
+                                Ba[(q0 + c) * Tp + tcol] = sa[k];
+                                Bat[(q0 + c) * Tp + tcol] = st[k];
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -929,10 +937,11 @@ size_t mlp2_lds(int F, int H, int L, int T, int QC) {
     return sizeof(float) * ((size_t)(T | 1) * (2 * F + 4 * L * H + 4 * H) + (size_t)H * (QC + 1) + T);
 }
 
-// Largest tile (atoms), then widest weight block (columns), that fit in 64 KB
-// of LDS; false when none does.
+// Largest sub-tile of at most 8 atoms, then widest weight block (columns),
+// that fit in 64 KB of LDS; false when none does.  (16-atom sub-tiles were
+// slower for the 32-64-64-1 network: two workgroups per CU instead of three.)
 bool mlp2_shape(int F, int H, int L, int* T, int* QC) {
-    for (int t : {16, 8, 4, 2, 1})
+    for (int t : {8, 4, 2, 1})
         for (int q : {64, 32, 16, 8, 4, 2, 1}) {
             if (mlp2_lds(F, H, L, t, q) <= 64 * 1024) {
                 *T = t;
@@ -1126,10 +1135,21 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
     // second-order tiles
     b->tileT = tileT;
     b->tileQC = tileQC;
+    {
+        // sub-tiles per workgroup: enough that the grid fills the workgroup
+        // slots the LDS allows about once
+        const size_t lds = mlp2_lds(m->F, m->H, m->L, tileT, tileQC);
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024 / lds)));
+        const int64_t slots = (int64_t)ctx->num_cus * per_cu;
+        int64_t sub = 0;
+        for (int s = 0; s < m->S; ++s) sub += (b->groups.off[s + 1] - b->groups.off[s] + tileT - 1) / tileT;
+        b->tileR = (int)std::max<int64_t>(1, (sub + slots - 1) / slots);
+    }
+    const int64_t tile_atoms_n = (int64_t)b->tileT * b->tileR;
     int64_t tiles = 0;
     for (int s = 0; s < m->S; ++s) {
         b->tile_off[s] = tiles;
-        tiles += (b->groups.off[s + 1] - b->groups.off[s] + b->tileT - 1) / b->tileT;
+        tiles += (b->groups.off[s + 1] - b->groups.off[s] + tile_atoms_n - 1) / tile_atoms_n;
     }
     b->tile_off[m->S] = tiles;
     b->tiles = tiles;
@@ -1213,6 +1233,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     t.act = m->act;
     t.T = b->tileT;
     t.QC = b->tileQC;
+    t.R = b->tileR;
     t.P = (int)m->per_species;
     for (int s = 0; s <= m->S; ++s) {
         t.sp_off[s] = b->groups.off[s];

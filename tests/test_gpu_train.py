@@ -123,14 +123,17 @@ def test_train_step_matches_oracle(tmd, ctx, torch, case):
 @pytest.mark.parametrize("shape", ["two_species", "hidden128"])
 def test_train_step_other_shapes(tmd, ctx, torch, shape):
     """Two species (tiles and reduction chunks of each species apart), and
-    128-wide hidden layers (8-atom tiles, hidden weights in 16 LDS blocks)."""
+    128-wide hidden layers (8-atom sub-tiles, hidden weights in 16 LDS blocks)."""
     _note(f"train step vs oracle: {shape}")
-    b = _small_batch()
     if shape == "two_species":
+        # the 64-cell batch: several sub-tiles per workgroup on each side of
+        # the species boundary
+        b = inputs.train_batch()
         b.species[:] = np.random.default_rng(7).integers(0, 2, b.n).astype(np.int32)
         teacher = inputs.make_model(2, 8, 3, [64, 64], 5.0, seed=1013)
         student = inputs.make_model(2, 8, 3, [64, 64], 5.0, seed=2013)
     else:
+        b = _small_batch()
         teacher = inputs.make_model(1, 8, 3, [128, 128], 5.0, seed=1023)
         student = inputs.make_model(1, 8, 3, [128, 128], 5.0, seed=2023)
     E_l, F_l = _labels(teacher, b)
