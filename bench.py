@@ -296,13 +296,14 @@ def md_leg(tmd, torch, ctx, s, spec, steps: int) -> dict:
     th = md.run(steps, thermo_every=10)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
-    last = th[-1]
+    last = th[-1] if th else None  # no record when steps < 10
     md.close()
     model.close()
     return {"workload": f"{s.n} atoms, NVT Nose-Hoover 300 K tau 100 fs, dt 1 fs, skin 1 A rebuilt every 5 steps, "
                         f"thermo every 10 steps, BF16 MLP, {steps} steps",
             "ns_per_step_atom": round(sec / s.n * 1e9, 4), "ms_per_step": round(sec * 1e3, 4),
-            "last_thermo": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in last.items()}}
+            "last_thermo": None if last is None else
+            {k: (round(v, 6) if isinstance(v, float) else v) for k, v in last.items()}}
 
 
 def interpolation_leg(tmd, torch, ev, pos, sp, s, spec, steps: int, warmup: int) -> dict:
