@@ -547,7 +547,7 @@ __device__ __forceinline__ float d2sig(int act, float z) {
 //   ztbar_l = s'(z_l) atbar_l,  zbar_l = s'(z_l) abar_l + s''(z_l) zt_l atbar_l,
 //   dW_l += zbar_l a_{l-1}^T + ztbar_l at_{l-1}^T,  db_l += zbar_l,
 //   abar_{l-1} = W_l^T zbar_l,  atbar_{l-1} = W_l^T ztbar_l.
-template <int T>
+template <int T, int NR>
 __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
     extern __shared__ float lds[];
     constexpr int Tp = T | 1;
@@ -623,11 +623,11 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
                 stage(p + offW[l], wi, q0, qn);
                 __syncthreads();
                 // thread (tcol, row0) owns rows row0, row0 + G, row0 + 2G, ... of column tcol;
-                // four rows at a time share the loads of the inputs
-                for (int ob = row0; ob < H; ob += 4 * G) {
-                    float z[4], zt[4];
+                // NR rows at a time share the loads of the inputs
+                for (int ob = row0; ob < H; ob += NR * G) {
+                    float z[NR], zt[NR];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < NR; ++k) {
                         const int o = min(ob + k * G, H - 1);
                         z[k] = q0 == 0 ? p[offb[l] + o] : Zl[o * Tp + tcol];
                         zt[k] = q0 == 0 ? 0.0f : Ztl[o * Tp + tcol];
@@ -638,14 +638,14 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
                     for (int c = 0; c < qn; ++c) {
                         const float x = ip[c * Tp], xt = itp[c * Tp];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
+                        for (int k = 0; k < NR; ++k) {
                             const float wv = Ws[min(ob + k * G, H - 1) * (QC + 1) + c];
                             z[k] = fmaf(wv, x, z[k]);
                             zt[k] = fmaf(wv, xt, zt[k]);
                         }
                     }
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < NR; ++k) {
                         const int o = ob + k * G;
                         if (o < H) {
                             Zl[o * Tp + tcol] = z[k];
@@ -732,21 +732,21 @@ __global__ void __launch_bounds__(256) k_mlp_second(MlpTrainArgs a) {
                     stage(p + offW[l], wi, q0, qn);
                     __syncthreads();
                     // thread (tcol, row0) owns block columns row0, row0 + G, ... of atom tcol;
-                    // four at a time share the loads of Cz, Czt
-                    for (int cb = row0; cb < qn; cb += 4 * G) {
-                        float sa[4] = {0.0f, 0.0f, 0.0f, 0.0f}, st[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    // NR at a time share the loads of Cz, Czt
+                    for (int cb = row0; cb < qn; cb += NR * G) {
+                        float sa[NR] = {}, st[NR] = {};
 #pragma unroll 2
                         for (int o = 0; o < H; ++o) {
                             const float cz = Cz[o * Tp + tcol], czt = Czt[o * Tp + tcol];
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
+                            for (int k = 0; k < NR; ++k) {
                                 const float wv = Ws[o * (QC + 1) + min(cb + k * G, qn - 1)];
                                 sa[k] = fmaf(wv, cz, sa[k]);
                                 st[k] = fmaf(wv, czt, st[k]);
                             }
                         }
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
+                        for (int k = 0; k < NR; ++k) {
                             const int c = cb + k * G;
                             if (c < qn) {
                                 Ba[(q0 + c) * Tp + tcol] = sa[k];
@@ -1249,11 +1249,18 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     float* gdst = grad ? grad : b->grad;
     {
         ProfScope ps_(ctx, "train_mlp2");
-        auto kern = t.T == 16 ? k_mlp_second<16>
-                    : t.T == 8 ? k_mlp_second<8>
-                    : t.T == 4 ? k_mlp_second<4>
-                    : t.T == 2 ? k_mlp_second<2>
-                               : k_mlp_second<1>;
+        // rows per thread and pass: H T / 256 (H and T powers of two), 1 to 4
+        const int nr = std::max(1, std::min(4, t.H * t.T / 256));
+        using Mlp2 = void (*)(MlpTrainArgs);
+        Mlp2 kern = nullptr;
+#define TMD_MLP2(TT) \
+    if (t.T == TT) kern = nr == 4 ? k_mlp_second<TT, 4> : nr == 2 ? k_mlp_second<TT, 2> : k_mlp_second<TT, 1>;
+        TMD_MLP2(8)
+        TMD_MLP2(4)
+        TMD_MLP2(2)
+        TMD_MLP2(1)
+#undef TMD_MLP2
+        if (!kern) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "no second-order kernel for this tile");
         if (b->tiles > 0) kern<<<(unsigned)b->tiles, 256, lds, ctx->stream>>>(t);
     }
     TMD_HIP(ctx, hipGetLastError());
