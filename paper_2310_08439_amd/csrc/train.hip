@@ -788,6 +788,7 @@ __global__ void __launch_bounds__(256) k_grad_chunks(GradReduceArgs a, int pb) {
     const int64_t lo = a.tile_off[s] + (c - a.chunk_off[s]) * kGradChunk;
     const int64_t hi = min(lo + kGradChunk, a.tile_off[s + 1]);
     float acc = 0.0f;
+#pragma unroll 8
     for (int64_t tl = lo; tl < hi; ++tl) acc += a.partial[tl * a.P + q];
     a.partial[lo * a.P + q] = acc;
 }
@@ -798,6 +799,7 @@ __global__ void k_grad_reduce(GradReduceArgs a) {
     if (t >= (int64_t)a.S * a.P) return;
     const int s = (int)(t / a.P), q = (int)(t - (int64_t)s * a.P);
     float acc = 0.0f;
+#pragma unroll 8
     for (int64_t lo = a.tile_off[s]; lo < a.tile_off[s + 1]; lo += kGradChunk) acc += a.partial[lo * a.P + q];
     a.grad[t] = acc;
 }
