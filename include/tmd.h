@@ -81,12 +81,16 @@ typedef struct {
 
 /* Shape of a model (Sec. III.A and the tensor ranges of Table I).
  *   n_species   S, 1..8 (the neighbour-species index b and the MLP selector)
- *   n_radial    K, 4..128; K must be 4, 6 or 8 times a power of two
+ *   n_radial    K, 1..128
  *   max_moment  M, 0..3 (D = 1, 4, 10, 20 moment components)
- *   n_hidden    1..4 hidden layers, all of the same width hidden[0] in {32, 64, 128}
+ *   n_hidden    1..4 hidden layers of widths hidden[0..n_hidden-1], each 1..128
  *   activation  tmd_activation of the hidden layers; the output layer is linear
  *   rcut        cutoff radius (A), > 0
- *   mu, eta     host, [K] FP64: Gaussian centres and widths of h_k. */
+ *   mu, eta     host, [K] FP64: Gaussian centres (finite) and widths (finite, >= 0) of h_k.
+ * Internally the kernels run K rounded up to 4, 6 or 8 times a power of two
+ * and every hidden layer at the widest width rounded up to 32, 64 or 128; the
+ * extra radial functions and hidden units meet zero weights and change no
+ * result, but cost their share of the work (K = 10 runs 12 radial functions). */
 typedef struct {
     int32_t n_species;
     int32_t n_radial;
@@ -189,9 +193,12 @@ tmd_status tmd_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total
 
 /* ---------------------------------------------------------------- evaluation */
 
-/* Descriptors G (device, [n][S*K*(M+1)] FP32, original atom order) for the
+/* Descriptors G_abkm (Sec. III.A, eqns tensor_formalism and sigma_function:
+ * P = sum_c H M, S = T P^2, G = sqrt(S) for m = 0 and S otherwise) for the
  * positions in sys, using a list built by tmd_build_neighbors for the same
- * atoms (positions may have moved by less than skin/2 since). */
+ * atoms (positions may have moved by less than skin/2 since).
+ * G: device, [n][S*K*(M+1)] FP32, original atom order, feature index
+ * ((b*K + k)*(M+1) + m).  Errors as tmd_energy_forces.  Does not synchronise. */
 tmd_status tmd_descriptors(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
                            const tmd_nlist* nl, float* G);
 

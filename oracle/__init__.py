@@ -27,7 +27,7 @@ class OrcModel(ctypes.Structure):
         ("n_hidden", ctypes.c_int32),
         ("hidden", ctypes.c_int32 * MAXL),
         ("activation", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("mlp_bf16", ctypes.c_int32),
         ("rcut", ctypes.c_double),
         ("tab_dr", ctypes.c_double),
         ("mu", ctypes.c_void_p),
@@ -78,6 +78,10 @@ def lib():
         L.orc_params_per_species.restype = i32
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = None
+        L.orc_round_bf16.argtypes = [i64, vp, vp]
+        L.orc_round_bf16.restype = None
         _lib = L
     return _lib
 
@@ -87,9 +91,10 @@ def _p(a: np.ndarray) -> int:
 
 
 class _ModelRef:
-    """Keeps the numpy arrays a C model struct points at alive."""
+    """Keeps the numpy arrays a C model struct points at alive.  bf16: the
+    model's BF16 form (MLP matrix-product operands rounded to BF16)."""
 
-    def __init__(self, spec):
+    def __init__(self, spec, bf16: bool = False):
         self.mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
         self.eta = np.ascontiguousarray(spec.eta, dtype=np.float64)
         self.params = np.ascontiguousarray(spec.params, dtype=np.float64)
@@ -101,6 +106,7 @@ class _ModelRef:
         for q, h in enumerate(spec.hidden):
             m.hidden[q] = h
         m.activation = spec.activation
+        m.mlp_bf16 = 1 if bf16 else 0
         m.rcut = spec.rcut
         m.tab_dr = float(getattr(spec, "tab_dr", 0.0))
         m.mu = _p(self.mu)
@@ -180,10 +186,11 @@ def descriptors(spec, pos, species, box, sel: Optional[np.ndarray] = None) -> np
     return G
 
 
-def energy_forces(spec, pos, species, box):
-    """(E, E_atoms [n], F [n,3], W [3,3]) for the whole system."""
+def energy_forces(spec, pos, species, box, bf16: bool = False):
+    """(E, E_atoms [n], F [n,3], W [3,3]) for the whole system (bf16: the
+    BF16 form of the MLP)."""
     pos, species, box = _sys_arrays(pos, species, box)
-    mref = _ModelRef(spec)
+    mref = _ModelRef(spec, bf16)
     n = pos.shape[0]
     E = np.zeros(1, dtype=np.float64)
     Ea = np.empty(n, dtype=np.float64)
@@ -195,10 +202,10 @@ def energy_forces(spec, pos, species, box):
     return float(E[0]), Ea, F, W.reshape(3, 3)
 
 
-def forces_subset(spec, pos, species, box, sel):
+def forces_subset(spec, pos, species, box, sel, bf16: bool = False):
     """(E_atoms [k], F [k,3]) for the selected atoms of a large system."""
     pos, species, box = _sys_arrays(pos, species, box)
-    mref = _ModelRef(spec)
+    mref = _ModelRef(spec, bf16)
     sel = np.ascontiguousarray(sel, dtype=np.int64)
     Ea = np.empty(sel.shape[0], dtype=np.float64)
     F = np.empty((sel.shape[0], 3), dtype=np.float64)
@@ -209,11 +216,11 @@ def forces_subset(spec, pos, species, box, sel):
     return Ea, F
 
 
-def mlp(spec, species, G):
+def mlp(spec, species, G, bf16: bool = False):
     """(E [n], dE/dG [n,F]) of the per-element MLPs on given descriptors."""
     species = np.ascontiguousarray(species, dtype=np.int32)
     G = np.ascontiguousarray(G, dtype=np.float64)
-    mref = _ModelRef(spec)
+    mref = _ModelRef(spec, bf16)
     n = G.shape[0]
     E = np.empty(n, dtype=np.float64)
     dG = np.empty_like(G)
@@ -230,6 +237,19 @@ def neumaier_sum(x) -> float:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().orc_set_num_threads(int(n))
+
+
+def round_bf16(x) -> np.ndarray:
+    """The oracle's BF16 rounding (FP32 first, then 8 significant bits, ties to even)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_round_bf16(x.size, _p(x), _p(out))
+    return out
 
 
 def descriptor_jvp(spec, pos, species, box, r) -> np.ndarray:

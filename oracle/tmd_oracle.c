@@ -60,7 +60,7 @@ typedef struct {
     int32_t n_hidden;      /* number of hidden layers */
     int32_t hidden[MAXL];  /* hidden widths */
     int32_t activation;    /* 0 tanh, 1 squareplus */
-    int32_t pad_;
+    int32_t mlp_bf16;      /* 1: MLP matrix-product operands rounded to BF16 (see mlp_eval) */
     double rcut;
     double tab_dr;         /* > 0: radial functions from a table of this spacing (at most) */
     const double* mu;      /* [K] */
@@ -316,6 +316,33 @@ static double act_df(int act, double z) {
     return 1.0 - t * t;
 }
 
+/* BF16 rounding of an FP32 operand: the value is first rounded to FP32 (the
+ * precision the GPU path holds it in), then to the nearest number with an
+ * 8-bit significand, ties to even (the IEEE rule; FE_TONEAREST is the default
+ * rounding mode, under which nearbyint rounds halfway cases to even).
+ * frexp gives x = f 2^e with 0.5 <= |f| < 1, so x 2^(8-e) has its 8
+ * significant bits in the integer part.  Below 2^-126 BF16, like FP32, is
+ * subnormal: a fixed spacing of 2^-133. */
+static double round_bf16(double x) {
+    const double xf = (double)(float)x;
+    if (xf == 0.0 || !isfinite(xf)) return xf;
+    int e;
+    (void)frexp(xf, &e);
+    if (e < -125) e = -125;
+    return ldexp(nearbyint(ldexp(xf, 8 - e)), e - 8);
+}
+
+void orc_round_bf16(int64_t n, const double* in, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = round_bf16(in[i]);
+}
+
+/* Operand of an MLP matrix product: exact, or rounded to BF16 when the model
+ * asks for the BF16 form (reading of the precision form: every operand of a
+ * matrix product -- weights, descriptors, hidden activations, back-propagated
+ * deltas -- is rounded to BF16 and products are accumulated exactly; biases,
+ * activation functions, their derivatives and the output layer stay exact). */
+static double opnd(const orc_model* m, double x) { return m->mlp_bf16 ? round_bf16(x) : x; }
+
 /* Forward and input-gradient of the MLP of one species.
  * z_l = W_l a_{l-1} + b_l, a_l = act(z_l), E = w_out . a_L + b_out,
  * dE/dG by back-propagation. */
@@ -335,7 +362,7 @@ static double mlp_eval(const orc_model* m, int species, const double* G, double*
         bp[l] = p; p += wo;
         for (int o = 0; o < wo; ++o) {
             double s = bp[l][o];
-            for (int q = 0; q < wi; ++q) s += Wp[l][(size_t)o * wi + q] * a[l][q];
+            for (int q = 0; q < wi; ++q) s += opnd(m, Wp[l][(size_t)o * wi + q]) * opnd(m, a[l][q]);
             z[l][o] = s;
             a[l + 1][o] = act_f(m->activation, s);
         }
@@ -352,7 +379,7 @@ static double mlp_eval(const orc_model* m, int species, const double* G, double*
             for (int o = 0; o < wo; ++o) delta[o] *= act_df(m->activation, z[l][o]);
             for (int q = 0; q < wi; ++q) {
                 double s = 0.0;
-                for (int o = 0; o < wo; ++o) s += Wp[l][(size_t)o * wi + q] * delta[o];
+                for (int o = 0; o < wo; ++o) s += opnd(m, Wp[l][(size_t)o * wi + q]) * opnd(m, delta[o]);
                 tmp[q] = s;
             }
             for (int q = 0; q < wi; ++q) delta[q] = tmp[q];
@@ -613,6 +640,14 @@ int orc_forces_subset(const orc_model* m, int64_t n, const double* pos, const in
     }
     free(w);
     return ORC_OK;
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
 }
 
 int orc_num_threads(void) {

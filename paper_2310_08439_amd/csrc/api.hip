@@ -102,30 +102,54 @@ int choose_kc(int K) {
     return 0;
 }
 
+// Radial functions the kernels run for a model of K: the smallest 4, 6 or 8
+// times a power of two that is at least K (so that K/kc chunks of kc radial
+// functions cover them; at most 128).
+int padded_k(int K) {
+    for (int k = std::max(K, 4); k <= 128; ++k)
+        if (choose_kc(k)) return k;
+    return 0;
+}
+
+// Hidden width the kernels run: the widest layer rounded up to 32, 64 or 128.
+int padded_h(const int* hid, int L) {
+    int w = 0;
+    for (int l = 0; l < L; ++l) w = std::max(w, hid[l]);
+    for (int h : {32, 64, 128})
+        if (w <= h) return h;
+    return 0;
+}
+
+// The operand copies of every species (W, W^T in FP32 and BF16 at the padded
+// sizes, biases, output layer) and the padded master copy, from ABI-layout
+// parameters; every padded entry is zero.
 tmd_status upload_params(tmd_model* m, const float* params) {
     tmd_context* ctx = m->ctx;
-    const int S = m->S, L = m->L, H = m->H, F = m->F, Fpad = m->Fpad;
+    const int S = m->S, L = m->L, H = m->H, Fpad = m->Fpad;
+    const ParamMap pm = param_map(m);
     std::vector<float> w32((size_t)S * m->w_species_stride, 0.0f);
     std::vector<float> bias((size_t)S * L * H, 0.0f), wout((size_t)S * H, 0.0f), bout(S, 0.0f);
+    std::vector<float> pint(m->padded ? (size_t)S * m->per_species_int : 0, 0.0f);
     for (int s = 0; s < S; ++s) {
         const float* p = params + (size_t)s * m->per_species;
         float* ws = w32.data() + (size_t)s * m->w_species_stride;
-        int in = F;
-        for (int l = 0; l < L; ++l) {
-            const int in_pad = (l == 0) ? Fpad : H;
-            for (int o = 0; o < H; ++o)
-                for (int q = 0; q < in; ++q) {
-                    const float v = p[(size_t)o * in + q];
-                    ws[m->w_off[l] + (size_t)o * in_pad + q] = v;
-                    ws[m->wt_off[l] + (size_t)q * H + o] = v;
-                }
-            p += (size_t)H * in;
-            for (int o = 0; o < H; ++o) bias[((size_t)s * L + l) * H + o] = p[o];
-            p += H;
-            in = H;
+        for (int64_t q = 0; q < m->per_species; ++q) {
+            int l, o, c, kind;
+            const int64_t qi = pm.map(q, l, o, c, kind);
+            const float v = p[q];
+            if (m->padded) pint[(size_t)s * m->per_species_int + qi] = v;
+            if (kind == 0) {
+                const int in_pad = (l == 0) ? Fpad : H;
+                ws[m->w_off[l] + (size_t)o * in_pad + c] = v;
+                ws[m->wt_off[l] + (size_t)c * H + o] = v;
+            } else if (kind == 1) {
+                bias[((size_t)s * L + l) * H + o] = v;
+            } else if (kind == 2) {
+                wout[(size_t)s * H + o] = v;
+            } else {
+                bout[s] = v;
+            }
         }
-        for (int o = 0; o < H; ++o) wout[(size_t)s * H + o] = p[o];
-        bout[s] = p[H];
     }
     std::vector<uint16_t> wbf(w32.size());
     for (size_t q = 0; q < w32.size(); ++q) wbf[q] = float_to_bf16_rne(w32[q]);
@@ -135,6 +159,7 @@ tmd_status upload_params(tmd_model* m, const float* params) {
     TMD_HIP(ctx, hipMemcpy(m->wout, wout.data(), wout.size() * 4, hipMemcpyHostToDevice));
     TMD_HIP(ctx, hipMemcpy(m->bout, bout.data(), bout.size() * 4, hipMemcpyHostToDevice));
     TMD_HIP(ctx, hipMemcpy(m->params32, params, (size_t)S * m->per_species * 4, hipMemcpyHostToDevice));
+    if (m->padded) TMD_HIP(ctx, hipMemcpy(m->params_int, pint.data(), pint.size() * 4, hipMemcpyHostToDevice));
     return TMD_OK;
 }
 
@@ -315,45 +340,54 @@ int32_t tmd_profile_read(tmd_context* ctx, int32_t max_kernels, char* names, dou
 tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const float* params, tmd_model** out) {
     if (!ctx || !spec || !params || !out) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null argument");
     *out = nullptr;
-    const int S = spec->n_species, K = spec->n_radial, M = spec->max_moment, L = spec->n_hidden;
+    const int S = spec->n_species, Kabi = spec->n_radial, M = spec->max_moment, L = spec->n_hidden;
     if (S < 1 || S > kMaxSpecies) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_species must be in 1..8");
-    if (K < 4 || K > 128) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_radial must be in 4..128");
-    const int kc = choose_kc(K);
-    if (!kc) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_radial must be 4, 6 or 8 times a power of two");
+    if (Kabi < 1 || Kabi > 128) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_radial must be in 1..128");
     if (M < 0 || M > 3) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "max_moment must be in 0..3");
     if (L < 1 || L > TMD_MAX_HIDDEN) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "n_hidden must be in 1..4");
-    const int H = spec->hidden[0];
-    if (H != 32 && H != 64 && H != 128) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "hidden width must be 32, 64 or 128");
-    for (int l = 1; l < L; ++l)
-        if (spec->hidden[l] != H) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "all hidden layers must have one width");
+    for (int l = 0; l < L; ++l)
+        if (spec->hidden[l] < 1 || spec->hidden[l] > 128)
+            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "hidden widths must be in 1..128");
     if (spec->activation != TMD_ACT_TANH && spec->activation != TMD_ACT_SQUAREPLUS)
         return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "unknown activation");
     if (!(spec->rcut > 0.0) || !std::isfinite(spec->rcut)) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "rcut must be positive");
     if (!spec->mu || !spec->eta) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null mu or eta");
-    for (int k = 0; k < K; ++k)
-        if (!std::isfinite(spec->mu[k]) || !(spec->eta[k] >= 0.0))
-            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "mu must be finite and eta non-negative");
+    for (int k = 0; k < Kabi; ++k)
+        if (!std::isfinite(spec->mu[k]) || !(spec->eta[k] >= 0.0) || !std::isfinite(spec->eta[k]))
+            return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "mu must be finite and eta finite and non-negative");
+    const int K = padded_k(Kabi), H = padded_h(spec->hidden, L);
+    const int kc = choose_kc(K);
     tmd_model* m = new (std::nothrow) tmd_model();
     if (!m) return fail(ctx, TMD_ERR_OUT_OF_MEMORY, "host allocation");
     m->ctx = ctx;
     m->S = S;
     m->K = K;
+    m->Kabi = Kabi;
     m->M = M;
     m->D = (M + 1) * (M + 2) * (M + 3) / 6;
     m->F = S * K * (M + 1);
+    m->Fabi = S * Kabi * (M + 1);
     m->Fpad = (m->F + 31) / 32 * 32;
     m->L = L;
     m->H = H;
+    for (int l = 0; l < L; ++l) m->hid[l] = spec->hidden[l];
     m->act = spec->activation;
     m->kc = kc;
     m->rcut = spec->rcut;
-    int64_t per = 0;
-    int in = m->F;
-    for (int l = 0; l < L; ++l) {
-        per += (int64_t)H * in + H;
-        in = H;
+    m->padded = K != Kabi;
+    for (int l = 0; l < L; ++l) m->padded = m->padded || m->hid[l] != H;
+    {
+        int64_t per = 0, per_int = 0;
+        int in = m->Fabi, in_int = m->F;
+        for (int l = 0; l < L; ++l) {
+            per += (int64_t)m->hid[l] * in + m->hid[l];
+            per_int += (int64_t)H * in_int + H;
+            in = m->hid[l];
+            in_int = H;
+        }
+        m->per_species = per + in + 1;
+        m->per_species_int = per_int + H + 1;
     }
-    m->per_species = per + H + 1;
     int64_t off = 0;
     m->w_off.resize(L);
     m->wt_off.resize(L);
@@ -365,22 +399,34 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
         off += (int64_t)H * in_pad;
     }
     m->w_species_stride = off;
-    std::vector<float> mu(K), eta(K);
-    m->mu_h.assign(spec->mu, spec->mu + K);
-    m->eta_h.assign(spec->eta, spec->eta + K);
+    // radial functions past the model's K continue its grid (uniform grids
+    // keep the two-exponential recurrence); their features meet zero weights
+    std::vector<double> mu_d(K), eta_d(K);
     for (int k = 0; k < K; ++k) {
-        mu[k] = (float)spec->mu[k];
-        eta[k] = (float)spec->eta[k];
+        if (k < Kabi) {
+            mu_d[k] = spec->mu[k];
+            eta_d[k] = spec->eta[k];
+        } else {
+            const double step = Kabi > 1 ? spec->mu[Kabi - 1] - spec->mu[Kabi - 2] : 0.0;
+            mu_d[k] = spec->mu[Kabi - 1] + (k - Kabi + 1) * step;
+            eta_d[k] = spec->eta[Kabi - 1];
+        }
+    }
+    std::vector<float> mu(K), eta(K);
+    m->mu_h = mu_d;
+    m->eta_h = eta_d;
+    for (int k = 0; k < K; ++k) {
+        mu[k] = (float)mu_d[k];
+        eta[k] = (float)eta_d[k];
     }
     {
         // recurrence for the Gaussians of a chunk on a uniform grid (see tmd_model)
-        const double d = spec->mu[1] - spec->mu[0], e0 = spec->eta[0];
+        const double d = K > 1 ? mu_d[1] - mu_d[0] : 0.0, e0 = eta_d[0];
         bool ok = d > 0.0 && e0 > 0.0;
         for (int k = 0; k < K && ok; ++k)
-            ok = std::fabs(spec->mu[k] - spec->mu[0] - k * d) <= 1e-9 * d &&
-                 std::fabs(spec->eta[k] - e0) <= 1e-12 * e0;
+            ok = std::fabs(mu_d[k] - mu_d[0] - k * d) <= 1e-9 * d && std::fabs(eta_d[k] - e0) <= 1e-12 * e0;
         for (int k0 = 0; k0 < K && ok; k0 += kc) {
-            const double tmax = std::max(std::fabs(spec->rcut - spec->mu[k0]), std::fabs(spec->mu[k0]));
+            const double tmax = std::max(std::fabs(spec->rcut - mu_d[k0]), std::fabs(mu_d[k0]));
             ok = e0 * tmax * tmax <= 80.0 && 2.0 * e0 * d * tmax <= 80.0;
         }
         if (ok) {
@@ -403,6 +449,8 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
     alloc((void**)&m->wout, 4 * (size_t)S * H);
     alloc((void**)&m->bout, 4 * (size_t)S);
     alloc((void**)&m->params32, 4 * (size_t)S * m->per_species);
+    if (m->padded) alloc((void**)&m->params_int, 4 * (size_t)S * m->per_species_int);
+    else m->params_int = m->params32;
     if (e == hipSuccess) e = hipMemcpy(m->mu, mu.data(), 4 * K, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->eta, eta.data(), 4 * K, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -500,13 +548,14 @@ tmd_status tmd_model_tabulate(tmd_model* m, double dr) {
 double tmd_model_tab_spacing(const tmd_model* m) { return m ? m->tab_delta : 0.0; }
 
 int64_t tmd_model_params_per_species(const tmd_model* m) { return m ? m->per_species : 0; }
-int32_t tmd_model_n_features(const tmd_model* m) { return m ? m->F : 0; }
+int32_t tmd_model_n_features(const tmd_model* m) { return m ? m->Fabi : 0; }
 
 void tmd_model_destroy(tmd_model* m) {
     if (!m) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)m->mu, (void*)m->eta, (void*)m->w32, (void*)m->wbf, (void*)m->bias, (void*)m->wout,
-                    (void*)m->bout, (void*)m->params32, (void*)m->opt_m, (void*)m->opt_v, (void*)m->tab})
+                    (void*)m->bout, (void*)m->params32, (void*)m->opt_m, (void*)m->opt_v, (void*)m->tab,
+                    (void*)(m->padded ? m->params_int : nullptr)})
         if (p) (void)hipFree(p);
     delete m;
 }
@@ -596,7 +645,7 @@ tmd_status tmd_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_syste
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor workspace");
     if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
     if ((st = launch_descriptors(ctx, m, nl, Gs, nullptr)) != TMD_OK) return st;
-    return launch_permute_rows(ctx, nl, Gs, m->F, G);
+    return launch_permute_rows(ctx, nl, Gs, m, G);
 }
 
 tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,

@@ -97,13 +97,17 @@ __global__ void __launch_bounds__(256) k_totals(const double* __restrict__ part,
     if (threadIdx.x < 7) totals[threadIdx.x] = res[threadIdx.x].s + res[threadIdx.x].c;
 }
 
-__global__ void k_permute_rows(int64_t n, int width, const int32_t* __restrict__ perm, const float* __restrict__ in,
-                               float* __restrict__ out) {
+// out[perm[p] or p][f] = in[p][column of f at the padded radial functions]
+// for the model's features f = (b Kabi + k)(M+1) + m.
+__global__ void k_permute_rows(int64_t n, int Fabi, int F, int Kabi, int K, int M1, const int32_t* __restrict__ perm,
+                               const float* __restrict__ in, float* __restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * width) return;
-    const int64_t p = idx / width;
-    const int c = (int)(idx - p * width);
-    out[(int64_t)perm[p] * width + c] = in[idx];
+    if (idx >= n * Fabi) return;
+    const int64_t p = idx / Fabi;
+    const int f = (int)(idx - p * Fabi);
+    const int per_b = Kabi * M1, b = f / per_b, r = f - b * per_b;
+    const int fi = (b * K + r / M1) * M1 + r % M1;
+    out[(perm ? (int64_t)perm[p] : p) * Fabi + f] = in[p * F + fi];
 }
 
 }  // namespace
@@ -131,13 +135,23 @@ tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* E
     return TMD_OK;
 }
 
-tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, int width, float* out) {
-    const int64_t total = nl->n * width;
+tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, const tmd_model* m, float* out) {
+    const int64_t total = nl->n * m->Fabi;
     {
         ProfScope ps_(ctx, "permute_rows");
-        k_permute_rows<<<(unsigned)((total + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(nl->n, width, nl->perm, in,
-                                                                                              out);
+        k_permute_rows<<<(unsigned)((total + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
+            nl->n, m->Fabi, m->F, m->Kabi, m->K, m->M + 1, nl->perm, in, out);
     }
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
+}
+
+tmd_status launch_compact_features(tmd_context* ctx, int64_t n, const float* in, int F, int Fabi, int K, int Kabi,
+                                   int M1, float* out) {
+    const int64_t total = n * Fabi;
+    if (total == 0) return TMD_OK;
+    k_permute_rows<<<(unsigned)((total + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, Fabi, F, Kabi, K, M1,
+                                                                                         nullptr, in, out);
     TMD_HIP(ctx, hipGetLastError());
     return TMD_OK;
 }

@@ -91,13 +91,25 @@ struct ProfScope {
 };
 }  // namespace tmd
 
+// The kernels run a padded copy of the model: K radial functions rounded up to
+// 4, 6 or 8 times a power of two (so that each thread takes a whole chunk of
+// them) and every hidden layer at one width H in {32, 64, 128}.  The padded
+// radial functions continue the model's grid and the padded hidden units sit
+// behind zero weights, so that neither reaches an atomic energy, a force or
+// the virial: the first layer's columns of padded features, and every row
+// and column of a padded unit, are zero.  K, F and H below are the padded
+// sizes; Kabi, Fabi and hid[] are the model's own.
 struct tmd_model {
     tmd_context* ctx = nullptr;
     int S = 0, K = 0, M = 0, D = 0, F = 0, Fpad = 0, L = 0, H = 0, act = 0;
+    int Kabi = 0, Fabi = 0;
+    int hid[TMD_MAX_HIDDEN] = {0, 0, 0, 0};
     int kc = 8;  // radial functions per thread in the descriptor / adjoint kernels
     double rcut = 0.0;
     tmd_precision prec = TMD_FP32;
-    int64_t per_species = 0;  // floats per species in the ABI parameter layout
+    int64_t per_species = 0;      // floats per species in the ABI parameter layout
+    int64_t per_species_int = 0;  // the same layout at the padded sizes
+    bool padded = false;          // the padded sizes differ from the model's
     // device parameters
     float* mu = nullptr;   // [K]
     float* eta = nullptr;  // [K]
@@ -123,12 +135,79 @@ struct tmd_model {
     float* bias = nullptr;   // [S][L][H]
     float* wout = nullptr;   // [S][H]
     float* bout = nullptr;   // [S]
-    // master copy in the ABI layout [S][per_species] and optimiser state
+    // master copy in the ABI layout [S][per_species] and optimiser state;
+    // params_int: the master copy in the padded layout [S][per_species_int]
+    // (zero at every padded entry; == params32 when nothing is padded)
     float* params32 = nullptr;
+    float* params_int = nullptr;
     float* opt_m = nullptr;
     float* opt_v = nullptr;
     int64_t opt_t = 0;
 };
+
+namespace tmd {
+// Position of an ABI-layout parameter in the padded layout.  Both layouts
+// hold, per species, W_l [out][in] then b_l [out] for each hidden layer, then
+// the output weights [width] and bias; the padded one at the padded sizes.
+// Returns the offset inside the species block and, for a weight, its row o
+// and padded column c (layer l; -1 for the output layer and biases).
+struct ParamMap {
+    int L, H, F, Fabi, K, Kabi, M1;
+    int hid[TMD_MAX_HIDDEN];
+    __host__ __device__ int64_t map(int64_t q, int& l, int& o, int& c, int& kind) const {
+        int64_t base = 0;
+        int in_abi = Fabi, in_int = F;
+        for (l = 0; l < L; ++l) {
+            const int out = hid[l];
+            if (q < (int64_t)out * in_abi) {
+                o = (int)(q / in_abi);
+                const int ca = (int)(q - (int64_t)o * in_abi);
+                if (l == 0) {
+                    const int per_b = Kabi * M1, b = ca / per_b, r = ca - b * per_b;
+                    c = (b * K + r / M1) * M1 + r % M1;
+                } else {
+                    c = ca;
+                }
+                kind = 0;
+                return base + (int64_t)o * in_int + c;
+            }
+            q -= (int64_t)out * in_abi;
+            base += (int64_t)H * in_int;
+            if (q < out) {
+                o = (int)q;
+                c = -1;
+                kind = 1;
+                return base + q;
+            }
+            q -= out;
+            base += H;
+            in_abi = out;
+            in_int = H;
+        }
+        c = -1;
+        if (q < in_abi) {
+            o = (int)q;
+            kind = 2;
+            return base + q;
+        }
+        o = 0;
+        kind = 3;
+        return base + H;
+    }
+};
+inline ParamMap param_map(const tmd_model* m) {
+    ParamMap pm{};
+    pm.L = m->L;
+    pm.H = m->H;
+    pm.F = m->F;
+    pm.Fabi = m->Fabi;
+    pm.K = m->K;
+    pm.Kabi = m->Kabi;
+    pm.M1 = m->M + 1;
+    for (int l = 0; l < TMD_MAX_HIDDEN; ++l) pm.hid[l] = m->hid[l];
+    return pm;
+}
+}  // namespace tmd
 
 struct tmd_nlist {
     tmd_context* ctx = nullptr;
@@ -235,7 +314,13 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
                           float* Fsorted, double* vir_partials, int* nvir_out);
 tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fsorted,
                            const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7);
-tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, int width, float* out);
+// Descriptor rows [n][F] (sorted order, padded radial functions) to the
+// caller's order and the model's own F columns.
+tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, const tmd_model* m, float* out);
+// Rows [n][F] at the padded radial functions (F features, K radial
+// functions) to the model's Fabi columns (Kabi radial functions), same rows.
+tmd_status launch_compact_features(tmd_context* ctx, int64_t n, const float* in, int F, int Fabi, int K, int Kabi,
+                                   int M1, float* out);
 tmd_status launch_export_nlist(tmd_context* ctx, const tmd_nlist* nl, int32_t* nbr, int32_t* img, int32_t* cnt);
 tmd_status launch_nlist_stats(tmd_context* ctx, const tmd_nlist* nl, int64_t* total_pairs, int32_t* max_row);
 

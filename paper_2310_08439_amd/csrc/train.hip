@@ -31,6 +31,10 @@ struct tmd_batch {
     int B = 0;
     int64_t N = 0;
     int S = 0, K = 0, M = 0, D = 0, F = 0, kc = 0, cap = 0;
+    // network shape the per-step buffers were sized for (padded widths) and
+    // the model's own radial count and feature count (batch reads)
+    int H = 0, L = 0, Kabi = 0, Fabi = 0;
+    int64_t P_int = 0;
     double rcut = 0.0;
     std::vector<float> mu, eta;  // descriptor parameters the batch was prepared with
     std::vector<int64_t> sys_off_h;
@@ -58,8 +62,8 @@ struct tmd_batch {
     double* sysE = nullptr;      // [B]
     double* sysF = nullptr;      // [B]
     double* loss = nullptr;      // [4]
-    float* partial = nullptr;    // [tiles][per_species]
-    float* grad = nullptr;       // [S][per_species]
+    float* partial = nullptr;    // [tiles][P_int]
+    float* grad = nullptr;       // [S][P_int], the gradient in the padded layout
     int32_t* flag = nullptr;     // [1] set when an entry has no mirror
     int tileT = 0;               // atoms per second-order tile
     int tileQC = 0;              // weight columns per LDS block of the second-order pass
@@ -822,10 +826,12 @@ __global__ void k_optimizer(int64_t n, int adam, float lr, float b1, float b2, f
 }
 
 struct UnpackArgs {
-    int S, L, H, F, Fpad;
-    int64_t P, wstride;
+    int S, L, H, Fpad;
+    int64_t P, P_int, wstride;
     int64_t w_off[TMD_MAX_HIDDEN], wt_off[TMD_MAX_HIDDEN];
+    ParamMap pm;
     const float* params;
+    float* params_int;  // null when the model is not padded
     float* w32;
     __hip_bfloat16* wbf;
     float* bias;
@@ -833,36 +839,44 @@ struct UnpackArgs {
     float* bout;
 };
 
-// One thread per master parameter: write it to every operand copy.
+// One thread per master parameter (ABI layout): write it to every operand
+// copy and to the padded master copy.  Padded entries are never written and
+// stay zero.
 __global__ void k_unpack(UnpackArgs u) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)u.S * u.P) return;
     const int s = (int)(t / u.P);
-    int64_t q = t - (int64_t)s * u.P;
+    const int64_t q = t - (int64_t)s * u.P;
     const float v = u.params[t];
-    float* ws = u.w32 + s * u.wstride;
-    __hip_bfloat16* wb = u.wbf + s * u.wstride;
-    int in = u.F;
-    for (int l = 0; l < u.L; ++l) {
+    int l, o, c, kind;
+    const int64_t qi = u.pm.map(q, l, o, c, kind);
+    if (u.params_int) u.params_int[(int64_t)s * u.P_int + qi] = v;
+    if (kind == 0) {
+        float* ws = u.w32 + s * u.wstride;
+        __hip_bfloat16* wb = u.wbf + s * u.wstride;
         const int in_pad = (l == 0) ? u.Fpad : u.H;
-        if (q < (int64_t)u.H * in) {
-            const int o = (int)(q / in), c = (int)(q - (int64_t)o * in);
-            ws[u.w_off[l] + (int64_t)o * in_pad + c] = v;
-            ws[u.wt_off[l] + (int64_t)c * u.H + o] = v;
-            wb[u.w_off[l] + (int64_t)o * in_pad + c] = __float2bfloat16(v);
-            wb[u.wt_off[l] + (int64_t)c * u.H + o] = __float2bfloat16(v);
-            return;
-        }
-        q -= (int64_t)u.H * in;
-        if (q < u.H) {
-            u.bias[((int64_t)s * u.L + l) * u.H + q] = v;
-            return;
-        }
-        q -= u.H;
-        in = u.H;
+        ws[u.w_off[l] + (int64_t)o * in_pad + c] = v;
+        ws[u.wt_off[l] + (int64_t)c * u.H + o] = v;
+        wb[u.w_off[l] + (int64_t)o * in_pad + c] = __float2bfloat16(v);
+        wb[u.wt_off[l] + (int64_t)c * u.H + o] = __float2bfloat16(v);
+    } else if (kind == 1) {
+        u.bias[((int64_t)s * u.L + l) * u.H + o] = v;
+    } else if (kind == 2) {
+        u.wout[(int64_t)s * u.H + o] = v;
+    } else {
+        u.bout[s] = v;
     }
-    if (q < u.H) u.wout[(int64_t)s * u.H + q] = v;
-    else u.bout[s] = v;
+}
+
+// Gradient of a padded model back to the ABI layout: out[s][q] = in[s][map(q)].
+__global__ void k_grad_compact(int S, int64_t P, int64_t P_int, ParamMap pm, const float* __restrict__ in,
+                               float* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)S * P) return;
+    const int s = (int)(t / P);
+    int l, o, c, kind;
+    const int64_t qi = pm.map(t - (int64_t)s * P, l, o, c, kind);
+    out[t] = in[(int64_t)s * P_int + qi];
 }
 
 using PtFn = void (*)(PtArgs);
@@ -997,6 +1011,11 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
     b->M = m->M;
     b->D = m->D;
     b->F = m->F;
+    b->H = m->H;
+    b->L = m->L;
+    b->Kabi = m->Kabi;
+    b->Fabi = m->Fabi;
+    b->P_int = m->per_species_int;
     b->kc = batch_kc(m->K, m->kc, N);
     b->rcut = m->rcut;
     b->mu.resize(m->K);
@@ -1051,7 +1070,7 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
     alloc((void**)&b->sysE, 8 * (size_t)n_systems);
     alloc((void**)&b->sysF, 8 * (size_t)n_systems);
     alloc((void**)&b->loss, 8 * 4 + 8 * (size_t)n_systems);
-    alloc((void**)&b->grad, 4 * (size_t)m->S * m->per_species);
+    alloc((void**)&b->grad, 4 * (size_t)m->S * m->per_species_int);
     alloc((void**)&b->flag, 4);
     if (e == hipSuccess) e = hipMemcpy(b->sys_off, sys_off, 8 * (size_t)(n_systems + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->sys_of, sys_of_h.data(), 4 * (size_t)N, hipMemcpyHostToDevice);
@@ -1155,7 +1174,7 @@ tmd_status tmd_batch_create(tmd_context* ctx, const tmd_model* m, int32_t n_syst
     }
     b->tile_off[m->S] = tiles;
     b->tiles = tiles;
-    alloc((void**)&b->partial, 4 * (size_t)std::max<int64_t>(tiles, 1) * m->per_species);
+    alloc((void**)&b->partial, 4 * (size_t)std::max<int64_t>(tiles, 1) * m->per_species_int);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "training workspace"));
     *out = b;
     return TMD_OK;
@@ -1175,6 +1194,11 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     tmd_batch* b = const_cast<tmd_batch*>(bc);  // per-step scratch lives in the batch
     if (m->S != b->S || m->K != b->K || m->M != b->M || m->rcut != b->rcut)
         return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "model descriptor shape differs from the batch's");
+    // the per-step buffers (second-order tiles, partial and gradient rows) are
+    // sized for the network shape of the model the batch was created with
+    if (m->H != b->H || m->L != b->L || m->per_species_int != b->P_int)
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT,
+                    "network shape differs from the one the batch was created for (create a batch for this model)");
     {
         std::vector<float> mu(m->mu_h.begin(), m->mu_h.end()), eta(m->eta_h.begin(), m->eta_h.end());
         if (mu != b->mu || eta != b->eta)
@@ -1236,7 +1260,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     t.T = b->tileT;
     t.QC = b->tileQC;
     t.R = b->tileR;
-    t.P = (int)m->per_species;
+    t.P = (int)m->per_species_int;
     for (int s = 0; s <= m->S; ++s) {
         t.sp_off[s] = b->groups.off[s];
         t.tile_off[s] = b->tile_off[s];
@@ -1245,10 +1269,18 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     t.G = b->G;
     t.w = b->w;
     t.e = b->e;
-    t.params = m->params32;
+    t.params = m->params_int;
     t.partial = b->partial;
     const size_t lds = mlp2_lds(t.F, t.H, t.L, t.T, t.QC);
+    // gradient in the ABI layout: reduced straight into it, or for a padded
+    // model reduced in the padded layout and compacted
     float* gdst = grad ? grad : b->grad;
+    if (!grad && m->padded) {
+        hipError_t e = hipSuccess;
+        gdst = (float*)ctx->ws.get("train.grad_abi", sizeof(float) * (size_t)m->S * m->per_species, &e);
+        if (e != hipSuccess) return hip_fail(ctx, e, "gradient workspace");
+    }
+    float* gred = m->padded ? b->grad : gdst;
     {
         ProfScope ps_(ctx, "train_mlp2");
         // rows per thread and pass: H T / 256 (H and T powers of two), 1 to 4
@@ -1269,7 +1301,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     {
         GradReduceArgs g{};
         g.S = m->S;
-        g.P = (int)m->per_species;
+        g.P = (int)m->per_species_int;
         for (int q = 0; q <= m->S; ++q) {
             g.tile_off[q] = b->tile_off[q];
             g.chunk_off[q] = q == 0 ? 0
@@ -1277,12 +1309,15 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
                                           (b->tile_off[q] - b->tile_off[q - 1] + kGradChunk - 1) / kGradChunk;
         }
         g.partial = b->partial;
-        g.grad = gdst;
+        g.grad = gred;
         ProfScope ps_(ctx, "train_grad_reduce");
         const int pb = (g.P + 255) / 256;
         if (g.chunk_off[m->S] > 0)
             k_grad_chunks<<<(unsigned)(g.chunk_off[m->S] * pb), 256, 0, ctx->stream>>>(g, pb);
-        k_grad_reduce<<<blocks_for((int64_t)m->S * m->per_species), kBlock, 0, ctx->stream>>>(g);
+        k_grad_reduce<<<blocks_for((int64_t)m->S * m->per_species_int), kBlock, 0, ctx->stream>>>(g);
+        if (m->padded)
+            k_grad_compact<<<blocks_for((int64_t)m->S * m->per_species), kBlock, 0, ctx->stream>>>(
+                m->S, m->per_species, m->per_species_int, param_map(m), gred, gdst);
     }
     TMD_HIP(ctx, hipGetLastError());
     TMD_HIP(ctx, hipMemcpyAsync(ctx->h_totals, b->loss, sizeof(double) * 3, hipMemcpyDeviceToHost, ctx->stream));
@@ -1323,15 +1358,21 @@ tmd_status tmd_batch_read(tmd_context* ctx, const tmd_batch* b, int32_t field, f
     if (!b || !out) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null argument");
     const float* src = nullptr;
     size_t n = 0;
+    bool rows = false;  // [N][F] rows: the model's own features
     switch (field) {
-        case TMD_BATCH_G: src = b->G, n = (size_t)b->N * b->F; break;
+        case TMD_BATCH_G: src = b->G, rows = true; break;
         case TMD_BATCH_ENERGY: src = b->Ei, n = (size_t)b->N; break;
         case TMD_BATCH_FORCES: src = b->Fp, n = (size_t)b->N * 3; break;
         case TMD_BATCH_RESIDUAL: src = b->r, n = (size_t)b->N * 3; break;
-        case TMD_BATCH_TANGENT: src = b->w, n = (size_t)b->N * b->F; break;
+        case TMD_BATCH_TANGENT: src = b->w, rows = true; break;
         default: return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "unknown batch field");
     }
-    TMD_HIP(ctx, hipMemcpyAsync(out, src, 4 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    if (rows) {
+        tmd_status st = launch_compact_features(ctx, b->N, src, b->F, b->Fabi, b->K, b->Kabi, b->M + 1, out);
+        if (st != TMD_OK) return st;
+    } else {
+        TMD_HIP(ctx, hipMemcpyAsync(out, src, 4 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    }
     TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return TMD_OK;
 }
@@ -1345,15 +1386,17 @@ tmd_status launch_unpack_params(tmd_context* ctx, tmd_model* m) {
     u.S = m->S;
     u.L = m->L;
     u.H = m->H;
-    u.F = m->F;
     u.Fpad = m->Fpad;
     u.P = m->per_species;
+    u.P_int = m->per_species_int;
     u.wstride = m->w_species_stride;
     for (int l = 0; l < m->L; ++l) {
         u.w_off[l] = m->w_off[l];
         u.wt_off[l] = m->wt_off[l];
     }
+    u.pm = param_map(m);
     u.params = m->params32;
+    u.params_int = m->padded ? m->params_int : nullptr;
     u.w32 = m->w32;
     u.wbf = m->wbf;
     u.bias = m->bias;

@@ -273,3 +273,31 @@ def train_batch(n_cells: int = 64, seed: int = 3, sigma: float = 0.15,
         kinds.append(f"{kind}{cl[0]}x{cl[1]}x{cl[2]}")
     return Batch(pos=np.ascontiguousarray(np.concatenate(pos)), species=np.concatenate(sps).astype(np.int32),
                  sys_off=np.asarray(offs, dtype=np.int64), boxes=np.asarray(boxes, dtype=np.float64), kinds=kinds)
+
+
+def cluster_cut(s: System, centre: int, n_sample: int, reach: float):
+    """A non-periodic piece of a periodic system for sampled comparisons.
+
+    The `n_sample` atoms nearest to atom `centre` (minimum image) form the
+    sample; every atom within `reach` of the centre's sample sphere (so within
+    `reach` of each sampled atom) is kept, unwrapped around the centre, in a box
+    wide enough that no periodic image of the piece comes within reach of it.
+    With reach >= 2 rcut the atomic energies and forces of the sampled atoms are
+    those of the periodic system.  Returns (piece, sample indices in s, sample
+    indices in the piece).  Requires the box edges to exceed twice the piece's
+    radius (the minimum-image step)."""
+    d = s.pos - s.pos[centre]
+    d -= s.box[None, :] * np.round(d / s.box[None, :])
+    r = np.sqrt((d * d).sum(1))
+    order = np.argsort(r, kind="stable")
+    sample = np.sort(order[:n_sample])
+    r_s = float(r[sample].max())
+    radius = r_s + reach
+    if np.any(2.0 * radius >= s.box):
+        raise ValueError("piece wider than half the box")
+    keep = np.nonzero(r <= radius)[0]
+    L = 2.0 * radius + reach + 1.0
+    piece = System(pos=d[keep] + L / 2.0, species=s.species[keep].copy(), box=np.array([L, L, L]),
+                   masses=s.masses)
+    where = np.searchsorted(keep, sample)
+    return piece, sample, where

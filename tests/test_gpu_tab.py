@@ -1,9 +1,8 @@
 """Tabulated radial functions (tmd_model_tabulate) on the GPU.
 
 Parity: the GPU with a table against the oracle with the same table (same
-spacing rule, cubic Hermite nodes) at the direct path's bars: FP32
-|E - E_ref|/N <= 1e-5 eV, force RMS error <= 1e-4 eV/A, virial per atom
-<= rcut * 1e-4; BF16 MLP <= 1e-3 eV and 5e-3 eV/A.  Static accuracy (the
+spacing rule, cubic Hermite nodes) at the direct path's bars (tests/parity.py:
+FP32 bars, and BF16 against the oracle and its BF16 form).  Static accuracy (the
 paper's static test): GPU tabulated against GPU direct forces, RMS error
 falling with the spacing down to the FP32 floor.  Dynamics: an NVE run with
 the table conserves energy as well as the direct one.
@@ -16,12 +15,11 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from paper_2310_08439_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-E_TOL_FP32, F_TOL_FP32 = 1e-5, 1e-4
-E_TOL_BF16, F_TOL_BF16 = 1e-3, 5e-3
 CU = 63.546
 
 
@@ -60,23 +58,6 @@ def _eval(tmd, ctx, torch, spec, s, prec=0):
     return E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, ev
 
 
-def _check(E, Ea, F, W, s, spec, etol, ftol, sel=None):
-    if sel is None:
-        Er, Ear, Fr, Wr = oracle.energy_forces(spec, s.pos, s.species, s.box)
-        dE = abs(E - Er) / s.n
-        frms = math.sqrt(np.mean((F - Fr) ** 2))
-        Wm = np.array([[W[0], W[3], W[4]], [W[3], W[1], W[5]], [W[4], W[5], W[2]]])
-        dW = np.abs(Wm - Wr).max() / s.n
-        print(f"  |dE|/N={dE:.3e}  F rms err={frms:.3e}  |dW|/N={dW:.3e}", flush=True)
-        assert dE <= etol and frms <= ftol and dW <= spec.rcut * ftol
-        np.testing.assert_allclose(Ea, Ear, atol=20 * etol)
-    else:
-        Ear, Fr = oracle.forces_subset(spec, s.pos, s.species, s.box, sel)
-        frms = math.sqrt(np.mean((F[sel] - Fr) ** 2))
-        print(f"  sampled {len(sel)}: F rms err={frms:.3e}", flush=True)
-        assert frms <= ftol and np.abs(Ea[sel] - Ear).max() <= 20 * etol
-
-
 @pytest.mark.parametrize("name,dr", [("oracle32", 0.05), ("oracle32", 0.0625), ("bcc4k", 0.01), ("fcc32k", 0.003)])
 def test_tabulated_matches_oracle_table(tmd, ctx, torch, name, dr):
     s, spec, _ = inputs.workload(name)
@@ -84,7 +65,7 @@ def test_tabulated_matches_oracle_table(tmd, ctx, torch, name, dr):
     _note(f"tabulated {name} dr={dr} n={s.n}")
     E, Ea, F, W, ev = _eval(tmd, ctx, torch, tab, s)
     assert ev.model.tab_spacing == spec.rcut / math.ceil(spec.rcut / dr)
-    _check(E, Ea, F, W, s, tab, E_TOL_FP32, F_TOL_FP32)
+    parity.check_fp32(E, Ea, F, W, s, tab)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -96,10 +77,9 @@ def test_tabulated_model_shapes(tmd, ctx, torch, prec):
         _note(f"tabulated K={K} M={M} prec={prec}")
         E, Ea, F, W, _ = _eval(tmd, ctx, torch, spec, s, prec)
         if prec == 0:
-            _check(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+            parity.check_fp32(E, Ea, F, W, s, spec)
         else:
-            scale = max(1.0, math.sqrt(spec.n_features / 96.0))
-            _check(E, Ea, F, W, s, spec, E_TOL_BF16 * scale, F_TOL_BF16 * scale)
+            parity.check_bf16(E, Ea, F, W, s, spec)
 
 
 def test_tabulated_non_uniform_grid_and_wide_stencil(tmd, ctx, torch):
@@ -111,7 +91,7 @@ def test_tabulated_non_uniform_grid_and_wide_stencil(tmd, ctx, torch):
     spec = dataclasses.replace(spec, mu=spec.mu + rng.uniform(-0.05, 0.05, size=spec.mu.shape), tab_dr=0.01)
     _note("tabulated, jittered mu, wide stencil")
     E, Ea, F, W, _ = _eval(tmd, ctx, torch, spec, s)
-    _check(E, Ea, F, W, s, spec, E_TOL_FP32, F_TOL_FP32)
+    parity.check_fp32(E, Ea, F, W, s, spec)
 
 
 def test_static_error_against_direct(tmd, ctx, torch):
@@ -143,8 +123,7 @@ def test_bcc1m_tabulated_sampled(tmd, ctx, torch):
     tab = dataclasses.replace(spec, tab_dr=0.01)
     _note(f"bcc1m tabulated n={s.n}")
     E, Ea, F, W, _ = _eval(tmd, ctx, torch, tab, s)
-    sel = np.random.default_rng(156).choice(s.n, 16, replace=False)
-    _check(E, Ea, F, W, s, tab, E_TOL_FP32, F_TOL_FP32, sel=sel)
+    parity.check_sampled(Ea, F, s, tab, False, n_sample=1000, seeds=(156,))
 
 
 def test_tabulated_md_conserves_energy(tmd, ctx, torch):

@@ -82,6 +82,51 @@ def _grad_close(g, gr, bar=2e-3):
     assert err <= bar and rel <= bar
 
 
+def test_train_step_any_k_and_widths(tmd, ctx, torch):
+    """A model whose K (10) and hidden widths (40, 24) are padded inside the
+    kernels: loss and gradient (ABI layout, padded entries dropped) against the
+    oracle, and an SGD step that leaves the model's own parameters consistent."""
+    _note("train step, padded model K=10 hidden [40, 24]")
+    teacher = inputs.make_model(1, 10, 3, [40, 24], 5.0, seed=1005)
+    student = inputs.make_model(1, 10, 3, [40, 24], 5.0, seed=2005)
+    b = _small_batch()
+    E_l, F_l = _labels(teacher, b)
+    model = tmd.Model(ctx, student)
+    assert model.n_params == student.params.shape[0]
+    bt = _device_batch(tmd, ctx, torch, model, b, E_l, F_l)
+    grad = torch.empty(model.n_params, dtype=torch.float32, device="cuda")
+    loss, le, lf = tmd.train_step(ctx, model, bt, lam=0.1, lr=0.0, grad=grad)
+    lr_, le_r, lf_r, gr = oracle.train_loss_grad(student, b.sys_off, b.pos, b.species, b.boxes, E_l, F_l, 0.1)
+    print(f"  loss {loss:.8e} vs {lr_:.8e}", flush=True)
+    assert abs(loss - lr_) <= 1e-3 * lr_
+    _grad_close(grad.cpu().numpy().astype(np.float64), gr)
+    G = bt.read(tmd.BATCH_G).cpu().numpy().astype(np.float64)
+    x, sp, box = b.system(0)
+    Gr = oracle.descriptors(student, x, sp, box)
+    assert G.shape[1] == student.n_features
+    assert (np.abs(G[:b.sys_off[1]] - Gr) / (np.abs(Gr) + 1.0)).max() <= 2e-5
+    # one SGD step: the model's parameters move by -lr * grad exactly (FP32)
+    p0 = model.get_params()
+    tmd.train_step(ctx, model, bt, lam=0.1, lr=1e-2, optimizer=tmd.OPT_SGD)
+    p1 = model.get_params()
+    g = grad.cpu().numpy()
+    np.testing.assert_allclose(p1, (p0 - np.float32(1e-2) * g).astype(np.float32), rtol=0, atol=1e-6)
+    # and the updated model evaluates as the oracle does with those parameters
+    import dataclasses
+    upd = dataclasses.replace(student, params=p1.astype(np.float64))
+    ev_pos = torch.tensor(x, dtype=torch.float64, device="cuda")
+    ev_sp = torch.tensor(sp, dtype=torch.int32, device="cuda")
+    nl = tmd.NeighborList(ctx, len(x), 1, 96)
+    tmd.build_neighbors(ctx, ev_pos, ev_sp, box, student.rcut, 0.0, nl)
+    E, _, F, _ = tmd.energy_forces(ctx, model, ev_pos, ev_sp, box, nl)
+    Er, _, Fr, _ = oracle.energy_forces(upd, x, sp, box)
+    assert abs(E - Er) / len(x) <= 1e-5
+    assert math.sqrt(np.mean((F.cpu().numpy() - Fr) ** 2)) <= 1e-4
+    nl.close()
+    bt.close()
+    model.close()
+
+
 @pytest.mark.parametrize("case", ["cell32", "three_cells"])
 def test_train_step_matches_oracle(tmd, ctx, torch, case):
     _note(f"train step vs oracle: {case}")
@@ -292,6 +337,14 @@ def test_batch_input_errors(tmd, ctx, torch):
     with pytest.raises(tmd.TMDError) as ei:
         tmd.train_step(ctx, other, bt)
     assert ei.value.status == 1
+    # same descriptor shape, wider or deeper network than the batch was sized for:
+    # rejected on the host (its per-step buffers are sized by the creation model)
+    for hidden in ([128, 128], [64, 64, 64]):
+        wider = tmd.Model(ctx, inputs.make_model(1, 8, 3, hidden, student.rcut, seed=2004))
+        with pytest.raises(tmd.TMDError) as ei:
+            tmd.train_step(ctx, wider, bt)
+        assert ei.value.status == 1
+        wider.close()
     with pytest.raises(tmd.TMDError):
         tmd.train_step(ctx, model, bt, lr=-1.0)
 

@@ -387,3 +387,109 @@ def test_subset_forces_match_full_evaluation():
     Ea2, F2 = oracle.forces_subset(spec, s.pos, s.species, s.box, sel)
     np.testing.assert_allclose(Ea2, Ea[sel], rtol=1e-13)
     np.testing.assert_allclose(F2, F[sel], atol=1e-12)
+
+
+# ---------------------------------------------------------------- BF16 form of the MLP
+
+def test_bf16_rounding_matches_torch():
+    """The oracle's BF16 rounding (FP64 -> FP32 -> nearest 8-bit significand,
+    ties to even) against torch's FP32 -> bfloat16 conversion, including exact
+    halfway cases, subnormal-range FP32 values and signed zeros."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=20000) * np.exp(rng.uniform(-30.0, 30.0, 20000))
+    ties = []
+    for e in range(-20, 21):
+        for m in range(128, 256):
+            base = m * 2.0 ** (e - 7)
+            ties += [base + 2.0 ** (e - 8), -(base + 2.0 ** (e - 8))]  # exactly halfway to the next bf16
+    x = np.concatenate([x, np.array(ties), [0.0, -0.0, 1e-40, -3e-39, 1.0 + 2.0 ** -30]])
+    want = torch.tensor(x, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = oracle.round_bf16(x)
+    assert np.array_equal(got, want)
+    # halfway cases go to the even neighbour: 1 + 2^-8 -> 1, 1 + 3 * 2^-8 -> 1 + 2^-6
+    assert oracle.round_bf16(np.array([1 + 2.0 ** -8]))[0] == 1.0
+    assert oracle.round_bf16(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6
+
+
+def _bf16_exact(rng, shape, scale):
+    return oracle.round_bf16(rng.normal(0, scale, size=shape))
+
+
+def test_bf16_form_is_exact_on_bf16_operands():
+    """One hidden layer whose weights and inputs are already BF16 numbers: the
+    forward pass of the BF16 form rounds nothing, so its energies equal the
+    exact network's bit for bit (the input gradient still rounds the deltas)."""
+    spec = inputs.make_model(1, 4, 3, [24], 5.0, seed=12)
+    rng = np.random.default_rng(13)
+    spec.params[:] = oracle.round_bf16(spec.params)
+    G = _bf16_exact(rng, (16, spec.n_features), 1.5)
+    sp = np.zeros(16, dtype=np.int32)
+    E64, dG64 = oracle.mlp(spec, sp, G)
+    E16, dG16 = oracle.mlp(spec, sp, G, bf16=True)
+    assert np.array_equal(E16, E64)
+    assert not np.array_equal(dG16, dG64)
+    # the deltas' rounding moves dG_q by at most u sum_o |W_oq delta_o| with
+    # |delta_o| <= |w_out,o| (tanh' <= 1) and u = 2^-8 (1 + 2^-15)
+    F = spec.n_features
+    W1 = spec.params[:24 * F].reshape(24, F)
+    wout = spec.params[24 * F + 24:24 * F + 48]
+    bound = 2.0 ** -8 * (1 + 2.0 ** -15) * (np.abs(W1) * np.abs(wout)[:, None]).sum(0)
+    assert np.all(np.abs(dG16 - dG64) <= bound[None, :])
+
+
+def _first_order_bound(spec, s, G):
+    """First-order bound on |E_bf16 - E| for one atom: each rounded operand x
+    carries a relative error of at most u = 2^-8 (1 + 2^-15) (FP32, then BF16),
+    a product of two rounded operands at most 2u, and the activations are
+    1-Lipschitz (tanh, squareplus)."""
+    u = 2.0 ** -8 * (1 + 2.0 ** -15)
+    per = inputs.params_per_species(spec.n_features, spec.hidden)
+    p = spec.params[s * per:(s + 1) * per]
+    off, a, err = 0, np.asarray(G, dtype=np.float64), np.zeros(len(G))
+    win = spec.n_features
+    for h in spec.hidden:
+        W = p[off:off + h * win].reshape(h, win)
+        off += h * win
+        b = p[off:off + h]
+        off += h
+        z = W @ a + b
+        err = np.abs(W) @ err + 2 * u * (np.abs(W) @ np.abs(a))
+        a = np.tanh(z) if spec.activation == inputs.ACT_TANH else 0.5 * (z + np.sqrt(z * z + 4.0))
+        win = h
+    wout = p[off:off + win]
+    return float(np.abs(wout) @ err)
+
+
+def test_bf16_form_error_within_rounding_bound():
+    """Two hidden layers on random descriptors: the BF16 form differs from the
+    exact network by no more than the first-order rounding bound, and on every
+    atom by something (so the rounding is applied)."""
+    spec = inputs.make_model(2, 6, 3, [32, 24], 5.0, seed=14)
+    rng = np.random.default_rng(15)
+    G = rng.uniform(0.0, 3.0, size=(40, spec.n_features))
+    sp = rng.integers(0, 2, size=40).astype(np.int32)
+    E64, _ = oracle.mlp(spec, sp, G)
+    E16, _ = oracle.mlp(spec, sp, G, bf16=True)
+    bound = np.array([_first_order_bound(spec, int(sp[a]), G[a]) for a in range(40)])
+    err = np.abs(E16 - E64)
+    assert np.all(err <= 1.01 * bound)
+    assert np.all(err > 0.0)
+
+
+def test_cluster_cut_reproduces_periodic_atoms():
+    """A piece cut out of a periodic system with reach 2 rcut (+ margin) gives the
+    sampled atoms' energies and forces of the whole periodic system: an atom's
+    energy depends on neighbours within rcut, its force on their energies."""
+    s = inputs.make_system("bcc", 3.16, (10, 10, 10), 0.1, 2, seed=24)
+    spec = inputs.make_model(2, 6, 3, [16, 16], 4.0, seed=25)
+    _, Ea, F, _ = oracle.energy_forces(spec, s.pos, s.species, s.box)
+    piece, sample, where = inputs.cluster_cut(s, 123, 60, 2 * spec.rcut + 0.5)
+    assert piece.n < s.n
+    _, Ea_p, F_p, _ = oracle.energy_forces(spec, piece.pos, piece.species, piece.box)
+    np.testing.assert_allclose(Ea_p[where], Ea[sample], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(F_p[where], F[sample], rtol=0, atol=1e-11)
+    # too small a reach changes the forces of the outer sampled atoms
+    piece2, sample2, where2 = inputs.cluster_cut(s, 123, 60, spec.rcut)
+    _, _, F2, _ = oracle.energy_forces(spec, piece2.pos, piece2.species, piece2.box)
+    assert np.abs(F2[where2] - F[sample2]).max() > 1e-6
