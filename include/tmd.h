@@ -218,6 +218,29 @@ tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* model, const tmd
 tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
                                    const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation as tmd_energy_forces_async, with every intermediate (descriptors,
+ * their gradient, the P tensors, atomic energies, force accumulators, virial
+ * and energy partials) in one scratch array that the library holds in device
+ * memory, tmd_noalloc_scratch_bytes() = 64 MiB per device, for the life of the
+ * process.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine) and does not synchronise; the caller still passes the
+ * outputs: totals7 device FP64 [7] = (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz),
+ * atom_energy device [n] FP32 or NULL, forces device [n][3] FP32.
+ * The list must be built with rlist = rcut (no skin; a skin list needs
+ * pruned-row memory); per-kernel timing is suspended during the call.
+ * Errors: as tmd_energy_forces_async; a system whose intermediates need more
+ * than the scratch (about 2.7 KB per atom for 96 features, K = 12, two
+ * species: roughly 24,000 atoms) -> TMD_ERR_INVALID_ARGUMENT with the size
+ * it needs.  All calls on one device share its scratch and its contents
+ * persist between calls: calls that overlap on one device (other streams,
+ * other host threads, other contexts) race and must not be issued. */
+tmd_status tmd_energy_forces_noalloc(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
+                                     const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces);
+/* Size of the per-device scratch array of tmd_energy_forces_noalloc, in bytes. */
+int64_t tmd_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- training (force matching) */
 
 /* Force matching is not part of the paper's method (its potentials were

@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
+#include <unordered_map>
 
 namespace tmd {
 
@@ -189,7 +192,7 @@ tmd_status check_eval(tmd_context* ctx, const tmd_model* m, const tmd_system_vie
 
 struct EvalBuffers {
     float *G, *dG, *Ei, *Fs, *P;
-    double *vir, *totals;
+    double *vir, *totals, *part;
 };
 
 tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, EvalBuffers* b) {
@@ -202,8 +205,58 @@ tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* n
     b->P = (float*)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->D, &e);
     b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * 6 * (size_t)adjoint_max_partials(m, nl), &e);
     b->totals = (double*)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
+    b->part = (double*)ctx->ws.get("ev.part", sizeof(double) * finalize_part_doubles(), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "evaluation workspace allocation");
     return TMD_OK;
+}
+
+// Scratch of tmd_energy_forces_noalloc: one array per device (each device
+// that loads the library holds its own copy until the process ends).  In host
+// code `scratch` names a host-side stand-in, not device memory: host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, unsigned char*> g_scratch_addr;
+
+// Device address of `scratch` on `device` (current), looked up once per
+// device; nullptr when the lookup fails.
+unsigned char* scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) return it->second;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) ptr = nullptr;
+    g_scratch_addr[device] = (unsigned char*)ptr;
+    return (unsigned char*)ptr;
+}
+
+// Evaluation buffers carved from the scratch array, 256-byte aligned; the
+// bytes they need in *need (more than kScratchBytes: nothing is carved).
+void scratch_buffers(unsigned char* base, const tmd_model* m, const tmd_nlist* nl, EvalBuffers* b, size_t* need) {
+    const int64_t n = nl->n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t oG = take(sizeof(float) * n * m->F), odG = take(sizeof(float) * n * m->F);
+    const size_t oEi = take(sizeof(float) * n), oFs = take(sizeof(float) * 3 * n);
+    const size_t oP = take(sizeof(float) * (size_t)n * m->S * m->K * m->D);
+    const size_t ovir = take(sizeof(double) * 6 * (size_t)adjoint_max_partials(m, nl));
+    const size_t opart = take(sizeof(double) * finalize_part_doubles());
+    *need = off;
+    if (off > kScratchBytes) return;
+    b->G = (float*)(base + oG);
+    b->dG = (float*)(base + odG);
+    b->Ei = (float*)(base + oEi);
+    b->Fs = (float*)(base + oFs);
+    b->P = (float*)(base + oP);
+    b->vir = (double*)(base + ovir);
+    b->part = (double*)(base + opart);
+    b->totals = nullptr;
 }
 
 }  // namespace
@@ -231,11 +284,10 @@ size_t eval_workspace_bytes(const tmd_model* m, int64_t n) {
 
 namespace {
 
-tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
-                             double* totals7_dev, float* atom_energy, float* forces, const PruneGate* gate = nullptr) {
-    EvalBuffers b;
-    tmd_status st = eval_buffers(ctx, m, nl, &b);
-    if (st != TMD_OK) return st;
+tmd_status run_energy_forces_in(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys,
+                                const tmd_nlist* nl, const EvalBuffers& b, double* totals7_dev, float* atom_energy,
+                                float* forces, const PruneGate* gate) {
+    tmd_status st;
     if ((st = launch_refresh_positions(ctx, sys, nl)) != TMD_OK) return st;
     // A list with a skin carries ~(1 + skin/rc)^3 - 1 more entries than the
     // cutoff needs (60 % for 1 A on 6 A); the descriptor and adjoint loops
@@ -256,7 +308,16 @@ tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_sys
     if ((st = launch_mlp(ctx, m, species_groups(nl), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
     int nvir = 0;
     if ((st = launch_adjoint(ctx, m, use, b.dG, b.P, b.Fs, b.vir, &nvir)) != TMD_OK) return st;
-    return launch_finalize(ctx, nl, b.Ei, b.Fs, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals);
+    return launch_finalize(ctx, nl, b.Ei, b.Fs, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals,
+                           b.part);
+}
+
+tmd_status run_energy_forces(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys, const tmd_nlist* nl,
+                             double* totals7_dev, float* atom_energy, float* forces, const PruneGate* gate = nullptr) {
+    EvalBuffers b;
+    tmd_status st = eval_buffers(ctx, m, nl, &b);
+    if (st != TMD_OK) return st;
+    return run_energy_forces_in(ctx, m, sys, nl, b, totals7_dev, atom_energy, forces, gate);
 }
 
 }  // namespace
@@ -279,6 +340,7 @@ tmd_status tmd_context_create(int device, void* hip_stream, tmd_context** out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->num_cus = cus;
+    ctx->scratch = scratch_address(device);  // with `device` current
     if (hipHostMalloc((void**)&ctx->h_totals, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_flags, sizeof(int32_t) * 64, hipHostMallocDefault) != hipSuccess) {
         delete ctx;
@@ -674,6 +736,34 @@ tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* m, const t
     if (!totals7 || !forces) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null totals or forces");
     return run_energy_forces(ctx, m, sys, nl, totals7, atom_energy, forces);
 }
+
+tmd_status tmd_energy_forces_noalloc(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys,
+                                     const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    tmd_status st = check_eval(ctx, m, sys, nl);
+    if (st != TMD_OK) return st;
+    if (!totals7 || !forces) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null totals or forces");
+    if (nl->rlist > m->rcut * (1.0 + 1e-9))
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT,
+                    "tmd_energy_forces_noalloc takes lists built with rlist = rcut (a skin list needs pruned-row "
+                    "memory)");
+    if (!ctx->scratch) return fail(ctx, TMD_ERR_DEVICE, "the scratch array's device address is unavailable");
+    EvalBuffers b{};
+    size_t need = 0;
+    scratch_buffers(ctx->scratch, m, nl, &b, &need);
+    if (need > kScratchBytes)
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT,
+                    "system too large for tmd_energy_forces_noalloc: needs " + std::to_string(need) +
+                        " bytes of scratch, the limit is " + std::to_string(kScratchBytes));
+    // per-kernel timing would create events; it is suspended for this call
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    st = run_energy_forces_in(ctx, m, sys, nl, b, totals7, atom_energy, forces, nullptr);
+    ctx->prof.on = prof;
+    return st;
+}
+
+int64_t tmd_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
 
 }  // extern "C"
 

@@ -848,6 +848,11 @@ __global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, int cap, const int
     }
 }
 
+__global__ void k_zero(float* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
 using PathFn = void (*)(PathArgs, int64_t);
 using AtomicFn = void (*)(PathArgs, float*);
 using BlockedFn = void (*)(PathArgs, BlockGeom);
@@ -1084,7 +1089,9 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
     a.dG = dG;
     a.Pbuf = Pbuf;
     a.vir = vir_partials;
-    TMD_HIP(ctx, hipMemsetAsync(Fsorted, 0, sizeof(float) * 3 * nl->n, ctx->stream));
+    // zeroed by a kernel rather than a memset, so that the sequence can be
+    // captured into a graph and replayed
+    k_zero<<<(unsigned)((3 * nl->n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(Fsorted, 3 * nl->n);
     if (nl->wo_valid) {
         BlockGeom bg = wo_geom(nl);
         bg.F = Fsorted;

@@ -113,16 +113,15 @@ __global__ void k_permute_rows(int64_t n, int Fabi, int F, int Kabi, int K, int 
 }  // namespace
 
 tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fs,
-                           const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7) {
+                           const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7,
+                           double* part) {
+    static_assert(finalize_part_doubles() == kPartBlocks * 14, "partials of the two-stage reduction");
     const int64_t n = nl->n;
     {
         ProfScope ps_(ctx, "scatter_out");
         k_scatter_out<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, nl->perm, Ei, Fs,
                                                                                          atom_energy, forces);
     }
-    hipError_t e = hipSuccess;
-    double* part = (double*)ctx->ws.get("ev.part", sizeof(double) * kPartBlocks * 14, &e);
-    if (e != hipSuccess) return hip_fail(ctx, e, "partials workspace");
     {
         ProfScope ps_(ctx, "partials");
         k_partials<<<kPartBlocks, 256, 0, ctx->stream>>>(n, Ei, nvir, vir_partials, part);

@@ -69,6 +69,9 @@ struct tmd_context {
     tmd::Profiler prof;
     double* h_totals = nullptr;  // pinned host [8]
     int32_t* h_flags = nullptr;  // pinned host [64]
+    // device address of the library's static scratch array on this context's
+    // device (tmd_energy_forces_noalloc), looked up once per device at creation
+    unsigned char* scratch = nullptr;
 };
 
 namespace tmd {
@@ -312,8 +315,11 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups&
 // virial block partials into vir_partials (count returned in *nvir_out).
 tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Pbuf,
                           float* Fsorted, double* vir_partials, int* nvir_out);
+// part: device scratch of finalize_part_doubles() doubles.
+constexpr int64_t finalize_part_doubles() { return 256 * 14; }
 tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fsorted,
-                           const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7);
+                           const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7,
+                           double* part);
 // Descriptor rows [n][F] (sorted order, padded radial functions) to the
 // caller's order and the model's own F columns.
 tmd_status launch_permute_rows(tmd_context* ctx, const tmd_nlist* nl, const float* in, const tmd_model* m, float* out);

@@ -33,7 +33,8 @@ EXPORTS = (
     "tmd_model_n_features", "tmd_model_destroy",
     "tmd_nlist_create", "tmd_nlist_destroy", "tmd_build_neighbors", "tmd_nlist_export", "tmd_nlist_capacity",
     "tmd_nlist_stats",
-    "tmd_descriptors", "tmd_energy_forces", "tmd_energy_forces_async",
+    "tmd_descriptors", "tmd_energy_forces", "tmd_energy_forces_async", "tmd_energy_forces_noalloc",
+    "tmd_noalloc_scratch_bytes",
     "tmd_profile_enable", "tmd_profile_reset", "tmd_profile_read",
     "tmd_model_get_params", "tmd_batch_create", "tmd_batch_destroy", "tmd_train_step", "tmd_batch_read",
     "tmd_serve_create", "tmd_serve_add_system", "tmd_serve_submit", "tmd_serve_poll", "tmd_serve_wait",
@@ -160,6 +161,9 @@ def load_library(path: str = LIB_PATH):
     L.tmd_descriptors.argtypes = [vp, vp, P(SystemView), vp, vp]
     L.tmd_energy_forces.argtypes = [vp, vp, P(SystemView), vp, P(dbl), vp, vp, vp]
     L.tmd_energy_forces_async.argtypes = [vp, vp, P(SystemView), vp, vp, vp, vp]
+    L.tmd_energy_forces_noalloc.argtypes = [vp, vp, P(SystemView), vp, vp, vp, vp]
+    L.tmd_noalloc_scratch_bytes.argtypes = []
+    L.tmd_noalloc_scratch_bytes.restype = i64
     L.tmd_profile_enable.argtypes = [vp, ctypes.c_int]
     L.tmd_profile_reset.argtypes = [vp]
     L.tmd_profile_read.argtypes = [vp, i32, vp, vp, vp]
@@ -437,6 +441,14 @@ def energy_forces_async(ctx: Context, model: Model, pos, species, box, nl: Neigh
     v = system_view(pos, species, box)
     ctx.check(ctx.lib.tmd_energy_forces_async(ctx.h, model.h, ctypes.byref(v), nl.h, _ptr(totals7), _ptr(atom_energy),
                                               _ptr(forces)), "tmd_energy_forces_async")
+
+
+def energy_forces_noalloc(ctx: Context, model: Model, pos, species, box, nl: NeighborList, totals7, forces,
+                          atom_energy=None):
+    """tmd_energy_forces_noalloc: the evaluation in the library's static scratch (no allocation)."""
+    v = system_view(pos, species, box)
+    ctx.check(ctx.lib.tmd_energy_forces_noalloc(ctx.h, model.h, ctypes.byref(v), nl.h, _ptr(totals7),
+                                                _ptr(atom_energy), _ptr(forces)), "tmd_energy_forces_noalloc")
 
 
 def virial_matrix(w6) -> np.ndarray:

@@ -1,0 +1,107 @@
+"""tmd_energy_forces_noalloc (the evaluation in the library's static scratch)
+against tmd_energy_forces_async on the same inputs, through the C ABI: two
+calls in a row, the second on a smaller system, each compared with the
+allocating entry point (energy and virial bit for bit: the same kernels and
+fixed-order sums; forces to the FP32 bar, since the force scatter adds in an
+order that may vary between launches), plus the size and skin-list errors."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_08439_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def tmd(torch):
+    from paper_2310_08439_amd import tmd as _tmd
+    _tmd.load_library()
+    return _tmd
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _run(tmd, torch, ctx, model, s, rc, prec):
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    S = int(s.species.max()) + 1
+    nl = tmd.NeighborList(ctx, s.n, S, tmd.default_capacity(s.n, s.box, rc, S))
+    tmd.build_neighbors(ctx, pos, sp, s.box, rc, 0.0, nl)
+    model.set_precision(prec)
+    out = {}
+    for kind in ("async", "noalloc"):
+        tot = torch.full((7,), float("nan"), dtype=torch.float64, device="cuda")
+        F = torch.full((s.n, 3), float("nan"), dtype=torch.float32, device="cuda")
+        Ea = torch.full((s.n,), float("nan"), dtype=torch.float32, device="cuda")
+        fn = tmd.energy_forces_async if kind == "async" else tmd.energy_forces_noalloc
+        fn(ctx, model, pos, sp, s.box, nl, tot, F, Ea)
+        torch.cuda.synchronize()
+        out[kind] = (tot.cpu().numpy(), F.cpu().numpy(), Ea.cpu().numpy())
+    a, b = out["async"], out["noalloc"]
+    print(f"  E {a[0][0]:.10f} vs {b[0][0]:.10f}; max|dF|={np.abs(a[1] - b[1]).max():.3e}", flush=True)
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[2], b[2])
+    assert np.all(np.isfinite(b[1]))
+    assert np.abs(a[1] - b[1]).max() <= 1e-5
+    return nl
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_noalloc_matches_allocating_entry_point(tmd, torch, prec):
+    ctx = tmd.Context(0)
+    spec = inputs.make_model(2, 12, 3, [128, 128], 6.0, seed=102)
+    model = tmd.Model(ctx, spec)
+    big = inputs.make_system("bcc", 3.16, (16, 16, 16), 0.08, 2, seed=20)    # 8,192 atoms
+    small = inputs.make_system("bcc", 3.16, (7, 7, 7), 0.08, 2, seed=21)     # 686 atoms
+    _note(f"noalloc prec={prec}: {big.n} atoms, then {small.n}")
+    nls = [_run(tmd, torch, ctx, model, big, spec.rcut, prec), _run(tmd, torch, ctx, model, small, spec.rcut, prec)]
+    assert tmd.load_library().tmd_noalloc_scratch_bytes() == 64 << 20
+    for nl in nls:
+        nl.close()
+    model.close()
+    ctx.close()
+
+
+def test_noalloc_rejects_what_does_not_fit(tmd, torch):
+    ctx = tmd.Context(0)
+    spec = inputs.make_model(2, 12, 3, [128, 128], 6.0, seed=102)
+    model = tmd.Model(ctx, spec)
+    _note("noalloc errors")
+    # 31,250 atoms x ~2.7 KB of intermediates exceed the 64 MiB scratch
+    s = inputs.make_system("bcc", 3.16, (25, 25, 25), 0.08, 2, seed=22)
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    nl = tmd.NeighborList(ctx, s.n, 2, tmd.default_capacity(s.n, s.box, spec.rcut, 2))
+    tmd.build_neighbors(ctx, pos, sp, s.box, spec.rcut, 0.0, nl)
+    tot = torch.zeros(7, dtype=torch.float64, device="cuda")
+    F = torch.zeros((s.n, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(tmd.TMDError) as ei:
+        tmd.energy_forces_noalloc(ctx, model, pos, sp, s.box, nl, tot, F)
+    assert ei.value.status == 1 and "scratch" in str(ei.value)
+    # a list with a skin is refused (its pruned rows would need memory)
+    small = inputs.make_system("bcc", 3.16, (6, 6, 6), 0.08, 2, seed=23)
+    p2 = torch.tensor(small.pos, dtype=torch.float64, device="cuda")
+    s2 = torch.tensor(small.species, dtype=torch.int32, device="cuda")
+    nl2 = tmd.NeighborList(ctx, small.n, 2, tmd.default_capacity(small.n, small.box, spec.rcut + 1.0, 2))
+    tmd.build_neighbors(ctx, p2, s2, small.box, spec.rcut, 1.0, nl2)
+    F2 = torch.zeros((small.n, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(tmd.TMDError) as ei:
+        tmd.energy_forces_noalloc(ctx, model, p2, s2, small.box, nl2, tot, F2)
+    assert ei.value.status == 1
+    nl.close()
+    nl2.close()
+    model.close()
+    ctx.close()
