@@ -191,7 +191,8 @@ tmd_status check_eval(tmd_context* ctx, const tmd_model* m, const tmd_system_vie
 }
 
 struct EvalBuffers {
-    float *G, *dG, *Ei, *Fs, *P;
+    float *G, *dG, *Ei, *P;
+    unsigned long long* Fq;  // fixed-point force accumulators [n][3]
     double *vir, *totals, *part;
 };
 
@@ -201,9 +202,9 @@ tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* n
     b->G = (float*)ctx->ws.get("ev.G", sizeof(float) * n * m->F, &e);
     b->dG = (float*)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
     b->Ei = (float*)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
-    b->Fs = (float*)ctx->ws.get("ev.Fs", sizeof(float) * 3 * n, &e);
+    b->Fq = (unsigned long long*)ctx->ws.get("ev.Fq", sizeof(unsigned long long) * 3 * n, &e);
     b->P = (float*)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->D, &e);
-    b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * 6 * (size_t)adjoint_max_partials(m, nl), &e);
+    b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * kVirDoubles * (size_t)adjoint_max_partials(m, nl), &e);
     b->totals = (double*)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
     b->part = (double*)ctx->ws.get("ev.part", sizeof(double) * finalize_part_doubles(), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "evaluation workspace allocation");
@@ -243,16 +244,16 @@ void scratch_buffers(unsigned char* base, const tmd_model* m, const tmd_nlist* n
         return at;
     };
     const size_t oG = take(sizeof(float) * n * m->F), odG = take(sizeof(float) * n * m->F);
-    const size_t oEi = take(sizeof(float) * n), oFs = take(sizeof(float) * 3 * n);
+    const size_t oEi = take(sizeof(float) * n), oFq = take(sizeof(unsigned long long) * 3 * n);
     const size_t oP = take(sizeof(float) * (size_t)n * m->S * m->K * m->D);
-    const size_t ovir = take(sizeof(double) * 6 * (size_t)adjoint_max_partials(m, nl));
+    const size_t ovir = take(sizeof(double) * kVirDoubles * (size_t)adjoint_max_partials(m, nl));
     const size_t opart = take(sizeof(double) * finalize_part_doubles());
     *need = off;
     if (off > kScratchBytes) return;
     b->G = (float*)(base + oG);
     b->dG = (float*)(base + odG);
     b->Ei = (float*)(base + oEi);
-    b->Fs = (float*)(base + oFs);
+    b->Fq = (unsigned long long*)(base + oFq);
     b->P = (float*)(base + oP);
     b->vir = (double*)(base + ovir);
     b->part = (double*)(base + opart);
@@ -267,19 +268,22 @@ tmd_status reserve_eval_workspace(tmd_context* ctx, const tmd_model* m, int64_t 
     (void)ctx->ws.get("ev.G", sizeof(float) * n * m->F, &e);
     (void)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
     (void)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
-    (void)ctx->ws.get("ev.Fs", sizeof(float) * 3 * n, &e);
+    (void)ctx->ws.get("ev.Fq", sizeof(unsigned long long) * 3 * n, &e);
     (void)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->D, &e);
     (void)ctx->ws.get("ev.vir",
-                      sizeof(double) * 6 * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock), &e);
+                      sizeof(double) * kVirDoubles * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock),
+                      &e);
     (void)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
+    (void)ctx->ws.get("ev.part", sizeof(double) * finalize_part_doubles(), &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "evaluation workspace allocation");
     return TMD_OK;
 }
 
 size_t eval_workspace_bytes(const tmd_model* m, int64_t n) {
     const int64_t nch = m->K / m->kc;
-    return (size_t)n * (8 * m->F + 4 + 12 + 4 * (size_t)m->S * m->K * m->D) +
-           48 * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock) + 64;
+    return (size_t)n * (8 * m->F + 4 + 24 + 4 * (size_t)m->S * m->K * m->D) +
+           8 * kVirDoubles * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock) +
+           8 * finalize_part_doubles() + 64;
 }
 
 namespace {
@@ -307,8 +311,8 @@ tmd_status run_energy_forces_in(tmd_context* ctx, const tmd_model* m, const tmd_
     if ((st = launch_descriptors(ctx, m, use, b.G, b.P)) != TMD_OK) return st;
     if ((st = launch_mlp(ctx, m, species_groups(nl), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
     int nvir = 0;
-    if ((st = launch_adjoint(ctx, m, use, b.dG, b.P, b.Fs, b.vir, &nvir)) != TMD_OK) return st;
-    return launch_finalize(ctx, nl, b.Ei, b.Fs, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals,
+    if ((st = launch_adjoint(ctx, m, use, b.dG, b.P, b.Fq, b.vir, &nvir)) != TMD_OK) return st;
+    return launch_finalize(ctx, nl, b.Ei, b.Fq, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals,
                            b.part);
 }
 

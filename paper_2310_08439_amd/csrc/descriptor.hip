@@ -41,6 +41,7 @@ struct PathArgs {
     float rc2, half_inv_rc, pi_over_rc;
     int rec;
     float rec_a, rec_b, rec_c;
+    float rec_m2eta, rec_delta;  // uniform grid: -2 eta and the centre spacing Delta
     // radial table (TAB kernels): [(tab_n + 1)][K] cubic coefficients, spacing 1/tab_inv
     const float4* tab;
     float tab_inv;
@@ -86,10 +87,11 @@ struct IntVec<4> {
 // reads the sorted FP64 positions from HBM and forms D = (x_q - x_i) + n L in
 // FP64.  LdsPos reads a workgroup's LDS copy of its cell block and one-cell
 // halo, held as FP32 offsets from each atom's own cell origin: the entry's
-// stencil code names the halo slot (slot = centre's slot + delta[code]; atom
-// q of slot h sits at hoff[h] + q) and the cell offset o, and
-// D = (x_q - x_i) + o w with w the cell edge.  Both hand D to the caller in
-// FP32 (the LDS form carries about 3e-7 A more rounding on |D| < 8 A).
+// stencil offset (ox, oy, oz), stored as the bit fields ox+1, oy+1, oz+1 of
+// its image word, names the halo slot (slot = centre's slot +
+// (oz HY + oy) HX + ox; atom q of slot h sits at hoff[h] + q) and the cell
+// offset, and D = (x_q - x_i) + o w with w the cell edge.  Both hand D to the
+// caller in FP32 (the LDS form carries about 3e-7 A more rounding on |D| < 8 A).
 struct GlobalPos {
     const double4* xs;
     double L0, L1, L2;
@@ -110,19 +112,19 @@ struct LdsPos {
     const float* sy;
     const float* sz;
     const int32_t* hoff;
-    const int32_t* delta;
-    int hp;
-    float xi, yi, zi;  // centre atom, from its cell origin
+    int hp0;           // centre's halo slot minus (HX HY + HX + 1), the slot offset of the bit fields (0, 0, 0)
+    int HX, HXY;       // halo cells along x, and per z layer
+    float xi, yi, zi;  // centre atom from its cell origin, plus one cell edge
     float wx, wy, wz;  // cell edges
     __device__ float4 fetch(int q, int32_t im, int& slot) const {
-        const int i = hoff[hp + delta[img_ocode(im)]] + q;
+        const int i = hoff[hp0 + img_sz(im) * HXY + img_sy(im) * HX + img_sx(im)] + q;
         slot = i;
         return make_float4(sx[i], sy[i], sz[i], 0.0f);
     }
+    // (x_q - x_i) + (b - 1) w = x_q - (x_i + w) + b w for the field b = o + 1
     __device__ float3 disp(const float4& xj, int32_t im) const {
-        const int o = img_ocode(im);
-        return make_float3((xj.x - xi) + (float)(o % 3 - 1) * wx, (xj.y - yi) + (float)((o / 3) % 3 - 1) * wy,
-                           (xj.z - zi) + (float)(o / 9 - 1) * wz);
+        return make_float3(fmaf((float)img_sx(im), wx, xj.x - xi), fmaf((float)img_sy(im), wy, xj.y - yi),
+                           fmaf((float)img_sz(im), wz, xj.z - zi));
     }
 };
 
@@ -244,26 +246,37 @@ __device__ __forceinline__ void load_tile(const float* src, int64_t n, float (&P
 // exponentials and a multiplicative recurrence replace the KC exponentials:
 // e_{k+1} = e_k r_k, r_k = exp2(rec_a (R - mu_k) + rec_b), r_{k+1} = r_k rec_c.
 template <int KC>
-__device__ __forceinline__ void gaussians(const PathArgs& a, float R, const float* mu, const float* nef,
-                                          float (&e)[KC]) {
-    if (a.rec) {
-        const float t0 = R - mu[0];
-        float ek = __builtin_amdgcn_exp2f(nef[0] * t0 * t0);
-        float rk = __builtin_amdgcn_exp2f(fmaf(a.rec_a, t0, a.rec_b));
+__device__ __forceinline__ void gaussians_rec(const PathArgs& a, float R, const float* mu, const float* nef,
+                                              float (&e)[KC]) {
+    const float t0 = R - mu[0];
+    float ek = __builtin_amdgcn_exp2f(nef[0] * t0 * t0);
+    float rk = __builtin_amdgcn_exp2f(fmaf(a.rec_a, t0, a.rec_b));
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            e[kk] = ek;
-            ek *= rk;
-            rk *= a.rec_c;
-        }
-    } else {
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const float t = R - mu[kk];
-            e[kk] = __builtin_amdgcn_exp2f(nef[kk] * t * t);
-        }
+    for (int kk = 0; kk < KC; ++kk) {
+        e[kk] = ek;
+        ek *= rk;
+        rk *= a.rec_c;
     }
 }
+template <int KC>
+__device__ __forceinline__ void gaussians_direct(float R, const float* mu, const float* nef, float (&e)[KC]) {
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const float t = R - mu[kk];
+        e[kk] = __builtin_amdgcn_exp2f(nef[kk] * t * t);
+    }
+}
+template <int KC>
+__device__ __forceinline__ void gaussians(const PathArgs& a, float R, const float* mu, const float* nef,
+                                          float (&e)[KC]) {
+    if (a.rec) gaussians_rec<KC>(a, R, mu, nef, e);
+    else gaussians_direct<KC>(R, mu, nef, e);
+}
+
+// How the adjoint kernels evaluate the radial functions (a template
+// parameter, so that each instantiation keeps only its own registers):
+// directly, by the uniform-grid recurrence, or from the table.
+constexpr int kRadDirect = 0, kRadRec = 1, kRadTab = 2;
 
 // Chunk k0 .. k0+KC-1 of the tabulated radial functions at distance R (the
 // caller has R < rc): interval j = floor(R / delta), clamped to the zero row
@@ -401,45 +414,171 @@ __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a,
     }
 }
 
-// Per-atom adjoint for one (atom, radial chunk) thread: P' from dE/dG, then for
-// every pair U, V and g = dE/dD (summed over the atom's chunk lanes).  The
-// chunk-0 lane hands each pair's g to sink(slot, gx, gy, gz) (slot = where
-// the neighbour's force accumulates: Pair::slot), accumulates the
-// atom's own force sum in Fo and the virial in W6.
-template <int KC, int M, bool TAB, class Pos, class Sink>
-__device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64_t w, int ch, int nch,
-                                             float (&W6)[6], float (&Fo)[3], const Pos& pos, Sink&& sink) {
-    constexpr int D = Moments<M>::D;
-    float mu[KC], nef[KC], m2eta[KC];
+// ---- adjoint ---------------------------------------------------------------
+//
+// Force sums.  Each pair's g is added to the neighbour's force (F_j -= g) by
+// an atomic add, first into the workgroup's LDS accumulators and then into
+// the global ones.  The adds are made on 64-bit fixed-point integers with 32
+// fractional bits: integer addition is associative, so the result does not
+// depend on the order in which the atomics land and the forces are the same
+// bit for bit on every run (float atomics would round in arrival order).
+// A contribution g is split as g = hi + fr with hi = floor(g) (an integer,
+// exact in FP32 for |g| < 2^31) and fr in [0, 1) (exact); fr 2^32 is exact
+// too and converts to the low word (truncating only bits below 2^-32), hi to
+// the high word, which together are the two's-complement integer g 2^32.
+__device__ __forceinline__ unsigned long long to_fixed(float g) {
+    const float hi = floorf(g);
+    const unsigned lo = (unsigned)((g - hi) * 4294967296.0f);
+    return ((unsigned long long)(unsigned)(int)hi << 32) | lo;
+}
+
+// P' = 2 T sigma' P in place for one species' KC x D tile (sigma' = dE/dS
+// from dE/dG): for m = 0, G = sqrt(P_k0^2) = |P_k0|, so P'_k0 = G' sign(P_k0)
+// (0 where P_k0 = 0; no reciprocal square root of a possibly denormal S).
+template <int KC, int M>
+__device__ __forceinline__ void tile_adjoint(const float* dGp, float (&P)[KC][Moments<M>::D]) {
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-        mu[kk] = a.mu[ch * KC + kk];
-        nef[kk] = -a.eta[ch * KC + kk] * kLog2e;
-        m2eta[kk] = -2.0f * a.eta[ch * KC + kk];
+#pragma unroll
+        for (int m = 0; m <= M; ++m) {
+            const float gbar = dGp[kk * (M + 1) + m];
+            if (m == 0) {
+                const float pk = P[kk][0];
+                P[kk][0] = pk > 0.0f ? gbar : (pk < 0.0f ? -gbar : 0.0f);
+            } else {
+#pragma unroll
+                for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * gbar;
+            }
+        }
     }
+}
+
+// This chunk's share of g = dE/dD for one pair within the cutoff:
+// U_k = sum_d P'_kd M_d, V_d = sum_k P'_kd h_k,
+// g = (sum_k U_k h'_k) u + (1/R)(sum_d V_d grad_u M_d - u sum_d ord(d) V_d M_d).
+template <int KC, int M, int RAD>
+__device__ __forceinline__ void pair_grad(const PathArgs& a, float dx, float dy, float dz, float r2, int k0,
+                                          const float* mu, const float* nef, const float* m2eta,
+                                          const float (&P)[KC][Moments<M>::D], float& gx, float& gy, float& gz) {
+    constexpr int D = Moments<M>::D;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float R = r2 * rinv;
+    const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+    float Mv[D];
+    monomials<M>(ux, uy, uz, Mv);
+    float V[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) V[d] = 0.0f;
+    if constexpr (RAD == kRadRec) {
+        // Uniform grid (mu_k = mu_0 + k Delta, one eta): with e_k the bare
+        // Gaussians, h_k = e_k f_c and h'_k = e_k (-2 eta (t0 - k Delta) f_c + f_c'),
+        // t0 = R - mu_0, so sum_k U_k h'_k = -2 eta f_c (t0 S0 - Delta S1) + f_c' S0
+        // with S0 = sum_k U_k e_k and S1 = sum_k k U_k e_k, and f_c, being common
+        // to every V_d, factors out of the moment adjoint.
+        const float ang = R * a.half_inv_rc;
+        const float fc = 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f;
+        const float dfc = -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang);
+        float e[KC];
+        gaussians_rec<KC>(a, R, mu, nef, e);
+        float S0 = 0.0f, S1 = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            float U = 0.0f;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                U = fmaf(P[kk][d], Mv[d], U);
+                V[d] = fmaf(P[kk][d], e[kk], V[d]);
+            }
+            const float Ue = U * e[kk];
+            S0 += Ue;
+            S1 = fmaf((float)kk, Ue, S1);
+        }
+        const float t0 = R - mu[0];
+        const float s1 = fmaf(a.rec_m2eta * fc, fmaf(-a.rec_delta, S1, t0 * S0), dfc * S0);
+        float Ax, Ay, Az, B;
+        moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
+        const float rf = rinv * fc;
+        gx = s1 * ux + rf * (Ax - ux * B);
+        gy = s1 * uy + rf * (Ay - uy * B);
+        gz = s1 * uz + rf * (Az - uz * B);
+        return;
+    }
+    float s1 = 0.0f, hv[KC], dhv[KC];
+    if constexpr (RAD == kRadTab) {
+        tabulated<KC, true>(a, R, k0, hv, dhv);
+    } else {
+        const float ang = R * a.half_inv_rc;
+        const float fc = 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f;
+        const float dfc = -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang);
+        gaussians_direct<KC>(R, mu, nef, hv);
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const float e = hv[kk];
+            hv[kk] = e * fc;
+            dhv[kk] = e * fmaf(m2eta[kk] * (R - mu[kk]), fc, dfc);
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const float h = hv[kk];
+        const float dh = dhv[kk];
+        float U = 0.0f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            U = fmaf(P[kk][d], Mv[d], U);
+            V[d] = fmaf(P[kk][d], h, V[d]);
+        }
+        s1 = fmaf(U, dh, s1);
+    }
+    float Ax, Ay, Az, B;
+    moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
+    gx = s1 * ux + rinv * (Ax - ux * B);
+    gy = s1 * uy + rinv * (Ay - uy * B);
+    gz = s1 * uz + rinv * (Az - uz * B);
+}
+
+// Virial of one pair: w6 -= D (x) g, off-diagonals symmetrised.
+__device__ __forceinline__ void virial_add(float (&w6)[6], float dx, float dy, float dz, float gx, float gy, float gz) {
+    w6[0] -= dx * gx;
+    w6[1] -= dy * gy;
+    w6[2] -= dz * gz;
+    w6[3] -= 0.5f * (dx * gy + dy * gx);
+    w6[4] -= 0.5f * (dx * gz + dz * gx);
+    w6[5] -= 0.5f * (dy * gz + dz * gy);
+}
+
+// Radial parameters of this thread's chunk k0 .. k0+KC-1.
+template <int KC>
+__device__ __forceinline__ void chunk_params(const PathArgs& a, int k0, float (&mu)[KC], float (&nef)[KC],
+                                             float (&m2eta)[KC]) {
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        mu[kk] = a.mu[k0 + kk];
+        nef[kk] = -a.eta[k0 + kk] * kLog2e;
+        m2eta[kk] = -2.0f * a.eta[k0 + kk];
+    }
+}
+
+// Per-atom adjoint for one (atom, radial chunk) thread with any number nch of
+// chunk lanes per atom: P' from dE/dG, then for every pair U, V and g = dE/dD
+// (summed over the atom's chunk lanes by shuffles).  The chunk-0 lane hands
+// each pair's g to sink(slot, gx, gy, gz) (slot = where the neighbour's force
+// accumulates: Pair::slot), accumulates the atom's own force sum in Fo and
+// the virial: per species row in FP32 (like an atomic energy), added to the
+// FP64 per-thread sums Wd after each row.
+template <int KC, int M, int RAD, class Pos, class Sink>
+__device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64_t w, int ch, int nch,
+                                             double (&Wd)[6], float (&Fo)[3], const Pos& pos, Sink&& sink) {
+    constexpr int D = Moments<M>::D;
+    float mu[KC], nef[KC], m2eta[KC];
+    chunk_params<KC>(a, ch * KC, mu, nef, m2eta);
     for (int b = 0; b < a.S; ++b) {
         float P[KC][D];
         load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
-        // P' = 2 T sigma' P in place (sigma' = dE/dS from dE/dG).
-        const float* dGp = a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1);
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-#pragma unroll
-            for (int m = 0; m <= M; ++m) {
-                const float gbar = dGp[kk * (M + 1) + m];
-                if (m == 0) {
-                    // G = sqrt(P_k0^2) = |P_k0|, so P'_k0 = G' sign(P_k0) (0 where P_k0 = 0);
-                    // no reciprocal square root of a possibly denormal S
-                    const float pk = P[kk][0];
-                    P[kk][0] = pk > 0.0f ? gbar : (pk < 0.0f ? -gbar : 0.0f);
-                } else {
-#pragma unroll
-                    for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) P[kk][d] *= 2.0f * kMult[d] * gbar;
-                }
-            }
-        }
+        tile_adjoint<KC, M>(a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1), P);
         const int nb = a.cnt[(int64_t)b * a.n + p];
         const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
+        float w6[6] = {0, 0, 0, 0, 0, 0};
         for (int c0 = 0; c0 < nb; c0 += kBatchAdj) {
             Pair prs[kBatchAdj];
             load_pairs<kBatchAdj>(a, base, c0, nb, prs, pos);
@@ -447,48 +586,8 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
             for (int j = 0; j < kBatchAdj; ++j) {
                 const Pair& pr = prs[j];
                 if (pr.r2 >= a.rc2) continue;  // skin entries and padding carry no force
-                const float rinv = __builtin_amdgcn_rsqf(pr.r2);
-                const float R = pr.r2 * rinv;
-                const float ux = pr.dx * rinv, uy = pr.dy * rinv, uz = pr.dz * rinv;
-                float Mv[D];
-                monomials<M>(ux, uy, uz, Mv);
-                float V[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) V[d] = 0.0f;
-                float s1 = 0.0f, hv[KC], dhv[KC];
-                if (TAB) {
-                    tabulated<KC, true>(a, R, ch * KC, hv, dhv);
-                } else {
-                    const float ang = R * a.half_inv_rc;
-                    const float fc = 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f;
-                    const float dfc = -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang);
-                    gaussians<KC>(a, R, mu, nef, hv);
-#pragma unroll
-                    for (int kk = 0; kk < KC; ++kk) {
-                        const float e = hv[kk];
-                        hv[kk] = e * fc;
-                        dhv[kk] = e * fmaf(m2eta[kk] * (R - mu[kk]), fc, dfc);
-                    }
-                }
-#pragma unroll
-                for (int kk = 0; kk < KC; ++kk) {
-                    const float h = hv[kk];
-                    const float dh = dhv[kk];
-                    float U = 0.0f;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        U = fmaf(P[kk][d], Mv[d], U);
-                        V[d] = fmaf(P[kk][d], h, V[d]);
-                    }
-                    s1 = fmaf(U, dh, s1);
-                }
-                float Ax, Ay, Az, B;
-                moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
-                float gx = s1 * ux + rinv * (Ax - ux * B);
-                float gy = s1 * uy + rinv * (Ay - uy * B);
-                float gz = s1 * uz + rinv * (Az - uz * B);
-                // shuffles (LDS crossbar) rather than DPP: this loop is VALU-bound and
-                // the LDS pipe has room (DPP measured 2.20 -> 2.44 ms at 1 M atoms)
+                float gx, gy, gz;
+                pair_grad<KC, M, RAD>(a, pr.dx, pr.dy, pr.dz, pr.r2, ch * KC, mu, nef, m2eta, P, gx, gy, gz);
                 for (int off = 1; off < nch; off <<= 1) {
                     gx += __shfl_xor(gx, off);
                     gy += __shfl_xor(gy, off);
@@ -499,61 +598,142 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
                     Fo[1] += gy;
                     Fo[2] += gz;
                     sink(pr.slot, gx, gy, gz);
-                    W6[0] -= pr.dx * gx;
-                    W6[1] -= pr.dy * gy;
-                    W6[2] -= pr.dz * gz;
-                    W6[3] -= 0.5f * (pr.dx * gy + pr.dy * gx);
-                    W6[4] -= 0.5f * (pr.dx * gz + pr.dz * gx);
-                    W6[5] -= 0.5f * (pr.dy * gz + pr.dz * gy);
+                    virial_add(w6, pr.dx, pr.dy, pr.dz, gx, gy, gz);
                 }
             }
         }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) Wd[j] += (double)w6[j];
     }
 }
 
-// Block reduction of the virial partials in FP64 (256 threads) into out[0..5].
-__device__ __forceinline__ void block_virial(const float (&W6)[6], double (*red)[kBlock / 64], double* out) {
+// The same for exactly two chunk lanes per atom (K = 2 KC), the lanes t and
+// t ^ 1 of a wave.  The pairs go two at a time, and the work of a pair that
+// does not depend on the chunk is split between the lanes: lane `odd` fetches
+// entry c0 + odd (its halo slot and position) and forms its displacement, and
+// the lanes swap displacements by a DPP lane permutation; both lanes then run
+// their chunk's share of both pairs, sum the two shares by the same
+// permutation, and lane `odd` adds pair c0 + odd to the force sums and the
+// virial.  Every value is the one the generic form computes; the two lanes of
+// an atom always run together (same row, same r2 for each pair), so the lane
+// permutations always find their partner active.
+template <int KC, int M, int RAD, class Sink>
+__device__ __forceinline__ void adjoint_atom_pair2(const PathArgs& a, int64_t p, int64_t w, int ch, double (&Wd)[6],
+                                                   float (&Fo)[3], const LdsPos& pos, Sink&& sink) {
+    constexpr int D = Moments<M>::D;
+    const int odd = ch & 1;
+    float mu[KC], nef[KC], m2eta[KC];
+    chunk_params<KC>(a, ch * KC, mu, nef, m2eta);
+    for (int b = 0; b < a.S; ++b) {
+        float P[KC][D];
+        load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
+        tile_adjoint<KC, M>(a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1), P);
+        const int nb = a.cnt[(int64_t)b * a.n + p];
+        const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species), 16-byte aligned
+        float w6[6] = {0, 0, 0, 0, 0, 0};
+        for (int c0 = 0; c0 < nb; c0 += 2) {
+            const int2 qv = *reinterpret_cast<const int2*>(a.nbr + base + c0);
+            const int2 iv = *reinterpret_cast<const int2*>(a.img + base + c0);
+            const bool v1 = c0 + 1 < nb;  // past the row's end entry c0 + 1 repeats entry c0, marked out of range
+            const int q = (odd && v1) ? qv.y : qv.x;
+            const int im = (odd && v1) ? iv.y : iv.x;
+            int slot;
+            const float4 xj = pos.fetch(q, im, slot);
+            const float3 dm = pos.disp(xj, im);
+            const float ox = swap_pair(dm.x), oy = swap_pair(dm.y), oz = swap_pair(dm.z);
+            const float d0x = odd ? ox : dm.x, d0y = odd ? oy : dm.y, d0z = odd ? oz : dm.z;
+            const float d1x = odd ? dm.x : ox, d1y = odd ? dm.y : oy, d1z = odd ? dm.z : oz;
+            const float r20 = d0x * d0x + d0y * d0y + d0z * d0z;
+            const float r21 = v1 ? d1x * d1x + d1y * d1y + d1z * d1z : __builtin_inff();
+            float g0x = 0.0f, g0y = 0.0f, g0z = 0.0f, g1x = 0.0f, g1y = 0.0f, g1z = 0.0f;
+            if (r20 < a.rc2)  // skin entries and padding carry no force
+                pair_grad<KC, M, RAD>(a, d0x, d0y, d0z, r20, ch * KC, mu, nef, m2eta, P, g0x, g0y, g0z);
+            if (r21 < a.rc2)
+                pair_grad<KC, M, RAD>(a, d1x, d1y, d1z, r21, ch * KC, mu, nef, m2eta, P, g1x, g1y, g1z);
+            g0x += swap_pair(g0x);
+            g0y += swap_pair(g0y);
+            g0z += swap_pair(g0z);
+            g1x += swap_pair(g1x);
+            g1y += swap_pair(g1y);
+            g1z += swap_pair(g1z);
+            if ((odd ? r21 : r20) < a.rc2) {
+                const float gx = odd ? g1x : g0x, gy = odd ? g1y : g0y, gz = odd ? g1z : g0z;
+                Fo[0] += gx;
+                Fo[1] += gy;
+                Fo[2] += gz;
+                sink(slot, gx, gy, gz);
+                virial_add(w6, dm.x, dm.y, dm.z, gx, gy, gz);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) Wd[j] += (double)w6[j];
+    }
+}
+
+struct CompD {
+    double s, c;
+};
+__device__ __forceinline__ CompD comp_merge_d(CompD a, CompD b) {
+    const double t = a.s + b.s;
+    if (fabs(a.s) >= fabs(b.s)) a.c += (a.s - t) + b.s;
+    else a.c += (b.s - t) + a.s;
+    a.s = t;
+    a.c += b.c;
+    return a;
+}
+
+// Block reduction of the per-thread FP64 virial sums (256 threads) into
+// out[12] = six Neumaier-compensated sums (value, compensation), in a fixed
+// order: a butterfly inside each wave, then the four waves in turn.
+__device__ __forceinline__ void block_virial(const double (&Wd)[6], double (*red)[kBlock / 64][2], double* out) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        double v = (double)W6[j];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[j][wv] = v;
+        CompD v{Wd[j], 0.0};
+        for (int off = 32; off > 0; off >>= 1) {
+            const CompD o{__shfl_xor(v.s, off), __shfl_xor(v.c, off)};
+            v = (lane & off) ? comp_merge_d(o, v) : comp_merge_d(v, o);
+        }
+        if (lane == 0) {
+            red[j][wv][0] = v.s;
+            red[j][wv][1] = v.c;
+        }
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[threadIdx.x][w];
-        out[threadIdx.x] = s;
+        CompD r{0.0, 0.0};
+        for (int w = 0; w < kBlock / 64; ++w) r = comp_merge_d(r, CompD{red[threadIdx.x][w][0], red[threadIdx.x][w][1]});
+        out[2 * threadIdx.x] = r.s;
+        out[2 * threadIdx.x + 1] = r.c;
     }
 }
 
 // Adjoint with the force scatter done by device-scope atomics: used only when
 // the stencil is wider than 3x3x3 (a box edge shorter than two list cutoffs).
-template <int KC, int M, bool TAB>
-__global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, float* F) {
-    __shared__ double red[6][kBlock / 64];
+template <int KC, int M, int RAD>
+__global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, unsigned long long* F) {
+    __shared__ double red[6][kBlock / 64][2];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w = t >> a.nch_log2;
     const int nch = 1 << a.nch_log2;
     const int ch = (int)(t & (nch - 1));
-    float W6[6] = {0, 0, 0, 0, 0, 0};
+    double Wd[6] = {0, 0, 0, 0, 0, 0};
     if (w < a.n) {
         const int64_t p = a.wperm ? a.wperm[w] : w;
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, GlobalPos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]},
+        adjoint_atom<KC, M, RAD>(a, p, w, ch, nch, Wd, Fo, GlobalPos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]},
                                  [&](int q, float gx, float gy, float gz) {
-            unsafeAtomicAdd(&F[3 * (int64_t)q + 0], -gx);
-            unsafeAtomicAdd(&F[3 * (int64_t)q + 1], -gy);
-            unsafeAtomicAdd(&F[3 * (int64_t)q + 2], -gz);
+            atomicAdd(&F[3 * (int64_t)q + 0], to_fixed(-gx));
+            atomicAdd(&F[3 * (int64_t)q + 1], to_fixed(-gy));
+            atomicAdd(&F[3 * (int64_t)q + 2], to_fixed(-gz));
         });
         if (ch == 0) {
-            unsafeAtomicAdd(&F[3 * p + 0], Fo[0]);
-            unsafeAtomicAdd(&F[3 * p + 1], Fo[1]);
-            unsafeAtomicAdd(&F[3 * p + 2], Fo[2]);
+            atomicAdd(&F[3 * p + 0], to_fixed(Fo[0]));
+            atomicAdd(&F[3 * p + 1], to_fixed(Fo[1]));
+            atomicAdd(&F[3 * p + 2], to_fixed(Fo[2]));
         }
     }
-    block_virial(W6, red, a.vir + (int64_t)blockIdx.x * 6);
+    block_virial(Wd, red, a.vir + (int64_t)blockIdx.x * kVirDoubles);
 }
 
 struct BlockGeom {
@@ -562,7 +742,7 @@ struct BlockGeom {
     int nb[3];   // blocks per dimension
     int hmax;    // capacity of the LDS force accumulators (atoms)
     const int32_t* cellstart;
-    float* F;
+    unsigned long long* F;  // fixed-point forces [n][3]
     const int32_t* wbase;  // [blocks + 1] first work slot of each block
     const int32_t* wperm;  // work slot -> sorted atom
     const uint8_t* wcell;  // work slot -> cell inside its block
@@ -595,11 +775,9 @@ __device__ __forceinline__ void scan256(int v, int32_t* out, int32_t* wtmp) {
 
 // Halo slots of block lb: h_first[h] = first sorted atom of slot h's cell,
 // h_base = exclusive scan of the slot counts (h_base[nh] = halo atoms),
-// hoff[h] = h_base[h] - h_first[h]; sdelta[o] = slot offset of stencil code o.
-// Ends with a barrier.
+// hoff[h] = h_base[h] - h_first[h].  Ends with a barrier.
 __device__ __forceinline__ void halo_slots(const BlockGeom& bg, int64_t lb, int32_t* h_first, int32_t* h_base,
-                                           int32_t* hoff, int32_t* sdelta, int32_t* wtmp, int& x0, int& y0,
-                                           int& z0) {
+                                           int32_t* hoff, int32_t* wtmp, int& x0, int& y0, int& z0) {
     const int t = threadIdx.x;
     const int bx = (int)(lb % bg.nb[0]), by = (int)((lb / bg.nb[0]) % bg.nb[1]), bz = (int)(lb / (bg.nb[0] * bg.nb[1]));
     x0 = bx * bg.B[0];
@@ -615,7 +793,6 @@ __device__ __forceinline__ void halo_slots(const BlockGeom& bg, int64_t lb, int3
         h_first[t] = bg.cellstart[gc];
         hcount = bg.cellstart[gc + 1] - h_first[t];
     }
-    if (t < 27) sdelta[t] = ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * HX + (t % 3 - 1);
     scan256(hcount, h_base, wtmp);
     if (t < nh) hoff[t] = h_base[t] - h_first[t];
     __syncthreads();
@@ -648,33 +825,36 @@ __device__ __forceinline__ void halo_positions(const BlockGeom& bg, const PathAr
 // Adjoint over one block of B0 x B1 x B2 cells (ScatterSum, Sec. III.A, done
 // in two levels like the paper's partial-then-global reduction).  The
 // workgroup first copies the positions of the block and its one-cell halo
-// into LDS, each halo slot shifted by its periodic image, and its pair loops
+// into LDS (FP32 offsets from each atom's cell origin), and its pair loops
 // read neighbour positions there (LdsPos) instead of gathering them from HBM.
 // The forces on the block's atoms and on its halo accumulate in LDS with LDS
-// atomics, located through the stencil offset each list entry recorded; the
-// block then adds its accumulators to F with coalesced device atomics, one
-// range per halo cell.
-template <int KC, int M, bool TAB>
+// atomics (fixed point, so that the sums do not depend on their order),
+// located through the stencil offset each list entry recorded; the block then
+// adds its accumulators to F with device atomics, one range per halo cell.
+// PAIR2: two chunk lanes per atom (adjoint_atom_pair2).
+template <int KC, int M, int RAD, bool PAIR2>
 __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom bg) {
-    extern __shared__ float spos[];  // [3][hmax] halo positions, then sF[3][hmax] force accumulators
-    __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells], sdelta[27];
+    // [3][hmax] halo positions (floats), then [3][hmax] fixed-point force accumulators
+    extern __shared__ __attribute__((aligned(8))) unsigned char lds_dyn[];
+    __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
     __shared__ int32_t wtmp[kBlock / 64];
-    __shared__ double red[6][kBlock / 64];
+    __shared__ double red[6][kBlock / 64][2];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int blk = blockIdx.x;
     int x0, y0, z0;
-    halo_slots(bg, blk, h_first, h_base, hoff, sdelta, wtmp, x0, y0, z0);
+    halo_slots(bg, blk, h_first, h_base, hoff, wtmp, x0, y0, z0);
     const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
     const int nh = HX * HY * HZ;
-    float* sx = spos;
-    float* sy = spos + bg.hmax;
-    float* sz = spos + 2 * bg.hmax;
-    float* sF = spos + 3 * bg.hmax;
+    const int hpos = (3 * bg.hmax + 1) & ~1;  // floats of the positions, rounded to 8 bytes
+    float* sx = reinterpret_cast<float*>(lds_dyn);
+    float* sy = sx + bg.hmax;
+    float* sz = sx + 2 * bg.hmax;
+    unsigned long long* sF = reinterpret_cast<unsigned long long*>(sx + hpos);
     const int htot = h_base[nh];
     for (int i = t; i < htot; i += kBlock) {
-        sF[i] = 0.0f;
-        sF[bg.hmax + i] = 0.0f;
-        sF[2 * bg.hmax + i] = 0.0f;
+        sF[i] = 0ull;
+        sF[bg.hmax + i] = 0ull;
+        sF[2 * bg.hmax + i] = 0ull;
     }
     halo_positions(bg, a, x0, y0, z0, h_first, h_base, sx, sy, sz);  // ends with a barrier
     const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
@@ -682,7 +862,12 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
     const int nch = 1 << a.nch_log2;
     const int64_t w0 = bg.wbase[blk];
     const int items = (int)(bg.wbase[blk + 1] - w0) << a.nch_log2;
-    float W6[6] = {0, 0, 0, 0, 0, 0};
+    double Wd[6] = {0, 0, 0, 0, 0, 0};
+    auto sink = [&](int idx, float gx, float gy, float gz) {  // idx: the neighbour's halo slot
+        atomicAdd(&sF[idx], to_fixed(-gx));
+        atomicAdd(&sF[bg.hmax + idx], to_fixed(-gy));
+        atomicAdd(&sF[2 * bg.hmax + idx], to_fixed(-gz));
+    };
     for (int item = t; item < ((items + kBlock - 1) / kBlock) * kBlock; item += kBlock) {
         if (item >= items) continue;
         const int ch = item & (nch - 1);
@@ -692,19 +877,21 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
         const int hp = (iz * HY + iy) * HX + ix;
         const int ip = hoff[hp] + (int)p;
-        const LdsPos pos{sx, sy, sz, hoff, sdelta, hp, sx[ip], sy[ip], sz[ip], cw[0], cw[1], cw[2]};
+        const LdsPos pos{sx, sy, sz, hoff, hp - (HX * HY + HX + 1), HX, HX * HY,
+                         sx[ip] + cw[0], sy[ip] + cw[1], sz[ip] + cw[2], cw[0], cw[1], cw[2]};
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M, TAB>(a, p, w, ch, nch, W6, Fo, pos,
-                                 [&](int idx, float gx, float gy, float gz) {  // idx: the neighbour's halo slot
-            atomicAdd(&sF[idx], -gx);
-            atomicAdd(&sF[bg.hmax + idx], -gy);
-            atomicAdd(&sF[2 * bg.hmax + idx], -gz);
-        });
-        if (ch == 0) {
-            const int idx = ip;
-            atomicAdd(&sF[idx], Fo[0]);
-            atomicAdd(&sF[bg.hmax + idx], Fo[1]);
-            atomicAdd(&sF[2 * bg.hmax + idx], Fo[2]);
+        if constexpr (PAIR2) {
+            adjoint_atom_pair2<KC, M, RAD>(a, p, w, ch, Wd, Fo, pos, sink);
+            atomicAdd(&sF[ip], to_fixed(Fo[0]));
+            atomicAdd(&sF[bg.hmax + ip], to_fixed(Fo[1]));
+            atomicAdd(&sF[2 * bg.hmax + ip], to_fixed(Fo[2]));
+        } else {
+            adjoint_atom<KC, M, RAD>(a, p, w, ch, nch, Wd, Fo, pos, sink);
+            if (ch == 0) {
+                atomicAdd(&sF[ip], to_fixed(Fo[0]));
+                atomicAdd(&sF[bg.hmax + ip], to_fixed(Fo[1]));
+                atomicAdd(&sF[2 * bg.hmax + ip], to_fixed(Fo[2]));
+            }
         }
     }
     __syncthreads();
@@ -712,13 +899,13 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
         const int lo = h_base[hc], cnt = h_base[hc + 1] - lo;
         for (int k = lane; k < cnt; k += 64) {
             const int64_t q = h_first[hc] + k;
-            const float fx = sF[lo + k], fy = sF[bg.hmax + lo + k], fz = sF[2 * bg.hmax + lo + k];
-            if (fx != 0.0f) unsafeAtomicAdd(&bg.F[3 * q + 0], fx);
-            if (fy != 0.0f) unsafeAtomicAdd(&bg.F[3 * q + 1], fy);
-            if (fz != 0.0f) unsafeAtomicAdd(&bg.F[3 * q + 2], fz);
+            const unsigned long long fx = sF[lo + k], fy = sF[bg.hmax + lo + k], fz = sF[2 * bg.hmax + lo + k];
+            if (fx) atomicAdd(&bg.F[3 * q + 0], fx);
+            if (fy) atomicAdd(&bg.F[3 * q + 1], fy);
+            if (fz) atomicAdd(&bg.F[3 * q + 2], fz);
         }
     }
-    block_virial(W6, red, a.vir + (int64_t)blockIdx.x * 6);
+    block_virial(Wd, red, a.vir + (int64_t)blockIdx.x * kVirDoubles);
 }
 
 // ---- work order ----------------------------------------------------------
@@ -848,13 +1035,13 @@ __global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, int cap, const int
     }
 }
 
-__global__ void k_zero(float* __restrict__ p, int64_t n) {
+__global__ void k_zero(unsigned long long* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
+    if (i < n) p[i] = 0ull;
 }
 
 using PathFn = void (*)(PathArgs, int64_t);
-using AtomicFn = void (*)(PathArgs, float*);
+using AtomicFn = void (*)(PathArgs, unsigned long long*);
 using BlockedFn = void (*)(PathArgs, BlockGeom);
 
 template <int KC, bool TAB, bool NT>
@@ -870,23 +1057,30 @@ template <int KC, bool TAB>
 PathFn pick_desc(int M, bool nt) {
     return nt ? pick_desc_nt<KC, TAB, true>(M) : pick_desc_nt<KC, TAB, false>(M);
 }
-template <int KC, bool TAB>
+template <int KC, int RAD>
 AtomicFn pick_atomic(int M) {
     switch (M) {
-        case 0: return k_adjoint_atomic<KC, 0, TAB>;
-        case 1: return k_adjoint_atomic<KC, 1, TAB>;
-        case 2: return k_adjoint_atomic<KC, 2, TAB>;
-        default: return k_adjoint_atomic<KC, 3, TAB>;
+        case 0: return k_adjoint_atomic<KC, 0, RAD>;
+        case 1: return k_adjoint_atomic<KC, 1, RAD>;
+        case 2: return k_adjoint_atomic<KC, 2, RAD>;
+        default: return k_adjoint_atomic<KC, 3, RAD>;
     }
 }
-template <int KC, bool TAB>
-BlockedFn pick_blocked(int M) {
+template <int KC, int RAD, bool PAIR2>
+BlockedFn pick_blocked_p(int M) {
     switch (M) {
-        case 0: return k_adjoint_blocked<KC, 0, TAB>;
-        case 1: return k_adjoint_blocked<KC, 1, TAB>;
-        case 2: return k_adjoint_blocked<KC, 2, TAB>;
-        default: return k_adjoint_blocked<KC, 3, TAB>;
+        case 0: return k_adjoint_blocked<KC, 0, RAD, PAIR2>;
+        case 1: return k_adjoint_blocked<KC, 1, RAD, PAIR2>;
+        case 2: return k_adjoint_blocked<KC, 2, RAD, PAIR2>;
+        default: return k_adjoint_blocked<KC, 3, RAD, PAIR2>;
     }
+}
+// Two chunk lanes per atom happen only with chunks of 6 or 8 (K = 12, 16).
+template <int KC, int RAD>
+BlockedFn pick_blocked(int M, bool pair2) {
+    if constexpr (KC >= 6)
+        if (pair2) return pick_blocked_p<KC, RAD, true>(M);
+    return pick_blocked_p<KC, RAD, false>(M);
 }
 
 template <bool TAB>
@@ -898,21 +1092,30 @@ PathFn select_desc(int kc, int M, bool nt) {
         default: return pick_desc<8, TAB>(M, nt);
     }
 }
-template <bool TAB>
-AtomicFn select_atomic(int kc, int M) {
+template <int RAD>
+AtomicFn select_atomic_r(int kc, int M) {
     switch (kc) {
-        case 4: return pick_atomic<4, TAB>(M);
-        case 6: return pick_atomic<6, TAB>(M);
-        default: return pick_atomic<8, TAB>(M);
+        case 4: return pick_atomic<4, RAD>(M);
+        case 6: return pick_atomic<6, RAD>(M);
+        default: return pick_atomic<8, RAD>(M);
     }
 }
-template <bool TAB>
-BlockedFn select_blocked(int kc, int M) {
+AtomicFn select_atomic(int rad, int kc, int M) {
+    return rad == kRadTab ? select_atomic_r<kRadTab>(kc, M)
+                          : rad == kRadRec ? select_atomic_r<kRadRec>(kc, M) : select_atomic_r<kRadDirect>(kc, M);
+}
+template <int RAD>
+BlockedFn select_blocked_r(int kc, int M, bool pair2) {
     switch (kc) {
-        case 4: return pick_blocked<4, TAB>(M);
-        case 6: return pick_blocked<6, TAB>(M);
-        default: return pick_blocked<8, TAB>(M);
+        case 4: return pick_blocked<4, RAD>(M, pair2);
+        case 6: return pick_blocked<6, RAD>(M, pair2);
+        default: return pick_blocked<8, RAD>(M, pair2);
     }
+}
+BlockedFn select_blocked(int rad, int kc, int M, bool pair2) {
+    return rad == kRadTab ? select_blocked_r<kRadTab>(kc, M, pair2)
+                          : rad == kRadRec ? select_blocked_r<kRadRec>(kc, M, pair2)
+                                           : select_blocked_r<kRadDirect>(kc, M, pair2);
 }
 
 PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
@@ -933,6 +1136,8 @@ PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
     a.rec_a = m->rec_a;
     a.rec_b = m->rec_b;
     a.rec_c = m->rec_c;
+    a.rec_m2eta = m->rec ? (float)(-2.0 * m->eta_h[0]) : 0.0f;
+    a.rec_delta = m->rec ? (float)(m->mu_h[1] - m->mu_h[0]) : 0.0f;
     a.tab = m->tab;
     a.tab_inv = m->tab ? (float)(1.0 / m->tab_delta) : 0.0f;
     a.tab_n = m->tab_n;
@@ -963,10 +1168,12 @@ int log2_int(int v) {
     return lg;
 }
 
-// Per halo atom the blocked adjoint keeps its position and force accumulator
-// (3 + 3 floats) in LDS; capped so that two workgroups fit on a CU.
-constexpr size_t kHaloBytes = 6 * sizeof(float);
+// Per halo atom the blocked adjoint keeps its position (3 floats) and its
+// fixed-point force accumulators (3 x 8 bytes) in LDS; capped so that two
+// workgroups fit on a CU.
+constexpr size_t kHaloBytes = 3 * sizeof(float) + 3 * sizeof(unsigned long long);
 constexpr size_t kMaxDynLds = 76 * 1024;
+size_t blocked_lds_bytes(int hmax) { return sizeof(float) * (size_t)((3 * hmax + 1) & ~1) + 24 * (size_t)hmax; }
 
 // Block geometry of the work order of a built list.
 BlockGeom wo_geom(const tmd_nlist* nl) {
@@ -1005,7 +1212,7 @@ bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
         int64_t nblocks = 1;
         for (int d = 0; d < 3; ++d) nblocks *= (nl->nc[d] + B[d] - 1) / B[d];
         if (!last && nblocks < 2 * (int64_t)nl->ctx->num_cus) continue;
-        if (hmax * (int64_t)kHaloBytes > (int64_t)kMaxDynLds) continue;
+        if ((int64_t)blocked_lds_bytes((int)std::min<int64_t>(hmax, 1 << 20)) > (int64_t)kMaxDynLds) continue;
         for (int d = 0; d < 3; ++d) {
             bg->nc[d] = nl->nc[d];
             bg->B[d] = B[d];
@@ -1084,7 +1291,7 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
 }
 
 tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Pbuf,
-                          float* Fsorted, double* vir_partials, int* nvir_out) {
+                          unsigned long long* Fsorted, double* vir_partials, int* nvir_out) {
     PathArgs a = make_args(m, nl);
     a.dG = dG;
     a.Pbuf = Pbuf;
@@ -1102,15 +1309,18 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
         // 0.600 against 0.636 ms)
         const int kca = (m->M == 3 && m->kc == 8 && m->K >= 64) ? 4 : m->kc;
         a.nch_log2 = log2_int(m->K / kca);
-        auto fn = m->tab ? select_blocked<true>(kca, m->M) : select_blocked<false>(kca, m->M);
+        const bool pair2 = m->K / kca == 2;  // two chunk lanes per atom share the pair geometry
+        const int rad = m->tab ? kRadTab : (m->rec ? kRadRec : kRadDirect);
+        auto fn = select_blocked(rad, kca, m->M, pair2);
         {
             ProfScope ps_(ctx, "adjoint");
-            fn<<<grid, kBlock, kHaloBytes * (size_t)bg.hmax, ctx->stream>>>(a, bg);
+            fn<<<grid, kBlock, blocked_lds_bytes(bg.hmax), ctx->stream>>>(a, bg);
         }
         *nvir_out = (int)grid;
     } else {
         const unsigned grid = path_grid(m, nl);
-        auto fn = m->tab ? select_atomic<true>(m->kc, m->M) : select_atomic<false>(m->kc, m->M);
+        const int rad = m->tab ? kRadTab : (m->rec ? kRadRec : kRadDirect);
+        auto fn = select_atomic(rad, m->kc, m->M);
         {
             ProfScope ps_(ctx, "adjoint");
             fn<<<grid, kBlock, 0, ctx->stream>>>(a, Fsorted);

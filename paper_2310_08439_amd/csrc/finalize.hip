@@ -24,15 +24,18 @@ __device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
     return a;
 }
 
-// Forces and atomic energies back to the caller's atom order.
+// Forces (fixed point, 32 fractional bits) and atomic energies back to the
+// caller's atom order: F = q 2^-32, exact in FP64, then rounded to FP32.
 __global__ void k_scatter_out(int64_t n, const int32_t* __restrict__ perm, const float* __restrict__ Ei,
-                              const float* __restrict__ Fs, float* __restrict__ atom_energy, float* __restrict__ forces) {
+                              const unsigned long long* __restrict__ Fq, float* __restrict__ atom_energy,
+                              float* __restrict__ forces) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t i = perm[p];
-    forces[3 * i + 0] = Fs[3 * p + 0];
-    forces[3 * i + 1] = Fs[3 * p + 1];
-    forces[3 * i + 2] = Fs[3 * p + 2];
+    constexpr double inv = 1.0 / kForceFixedScale;
+    forces[3 * i + 0] = (float)((double)(long long)Fq[3 * p + 0] * inv);
+    forces[3 * i + 1] = (float)((double)(long long)Fq[3 * p + 1] * inv);
+    forces[3 * i + 2] = (float)((double)(long long)Fq[3 * p + 2] * inv);
     if (atom_energy) atom_energy[i] = Ei[p];
 }
 
@@ -77,7 +80,8 @@ __global__ void __launch_bounds__(256) k_partials(int64_t n, const float* __rest
     const int64_t vlo = blockIdx.x * pv, vhi = min<int64_t>(nvir, vlo + pv);
     for (int64_t b = vlo + threadIdx.x; b < vhi; b += 256)
 #pragma unroll
-        for (int j = 0; j < 6; ++j) comp_add(acc[1 + j], vir[b * 6 + j]);
+        for (int j = 0; j < 6; ++j)
+            acc[1 + j] = comp_merge(acc[1 + j], Comp{vir[b * kVirDoubles + 2 * j], vir[b * kVirDoubles + 2 * j + 1]});
     block_merge(acc, red_s, red_c, res);
     if (threadIdx.x < 7) {
         part[(blockIdx.x * 7 + threadIdx.x) * 2] = res[threadIdx.x].s;
@@ -112,7 +116,7 @@ __global__ void k_permute_rows(int64_t n, int Fabi, int F, int Kabi, int K, int 
 
 }  // namespace
 
-tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fs,
+tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const unsigned long long* Fs,
                            const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7,
                            double* part) {
     static_assert(finalize_part_doubles() == kPartBlocks * 14, "partials of the two-stage reduction");

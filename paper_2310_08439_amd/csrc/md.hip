@@ -464,7 +464,7 @@ tmd_status tmd_md_thermostat_state(tmd_md* md, double* xi_eta) {
 
 void tmd_md_destroy(tmd_md* md) {
     if (!md) return;
-    (void)hipStreamSynchronize(md->ctx->stream);
+    (void)hipDeviceSynchronize();  // (not the context's stream: the handle does not keep its context alive)
     md_free(md);
     delete md;
 }

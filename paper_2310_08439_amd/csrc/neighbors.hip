@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
                 const int lo = a.cellstart[c2], hi = a.cellstart[c2 + 1];
                 const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
                 // stencil offset code of this cell (0..26), stored with each entry when the stencil is 3x3x3
-                const int ocode = a.narrow ? o : 255;
+                const int ocode = a.narrow ? stencil_bits(o) : 255;
                 ++o;
                 // candidates in batches of 4: all position loads issued first
                 for (int q0 = lo; q0 < hi; q0 += 4) {
@@ -579,7 +579,7 @@ __global__ void __launch_bounds__(256) k_fill_cells(FillArgs a, int64_t ncells) 
         const int bq = valid ? a.sp[q] : -1;
         const bool okq = valid && bq >= 0 && bq < a.S;
         const bool zero_img = (nx == 0 && ny == 0 && nz == 0);
-        const int32_t word = pack_img(nx, ny, nz, a.narrow ? sk : 255);
+        const int32_t word = pack_img(nx, ny, nz, a.narrow ? stencil_bits(sk) : 255);
         // candidates of each species this round, and this lane's own species' mask
         unsigned long long spm[SMAX], mine = 0;
 #pragma unroll

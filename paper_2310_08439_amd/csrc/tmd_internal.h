@@ -281,12 +281,21 @@ tmd_status hip_fail(tmd_context* ctx, hipError_t e, const char* what);
     } while (0)
 
 // Image word of a list entry: three signed 8-bit image components and, in the
-// top byte, the entry's stencil cell offset code (0..26, or 255 when unused).
+// top byte, the entry's stencil cell offset (ox, oy, oz in -1..1 as the
+// two-bit fields ox+1, oy+1, oz+1 at bits 0, 2, 4 of the byte; 255 when
+// unused, i.e. when the stencil is wider than 3x3x3).
+__host__ __device__ inline int stencil_bits(int o) {  // o = (ox+1) + 3 (oy+1) + 9 (oz+1)
+    return (o % 3) | (((o / 3) % 3) << 2) | ((o / 9) << 4);
+}
 __host__ __device__ inline int32_t pack_img(int nx, int ny, int nz, int ocode = 255) {
     return (int32_t)((uint32_t)(nx & 0xff) | ((uint32_t)(ny & 0xff) << 8) | ((uint32_t)(nz & 0xff) << 16) |
                      ((uint32_t)(ocode & 0xff) << 24));
 }
 __host__ __device__ inline int img_ocode(int32_t c) { return (int)(((uint32_t)c >> 24) & 0xff); }
+// ox+1, oy+1, oz+1 of an entry's stencil offset (0..2 each).
+__device__ inline int img_sx(int32_t c) { return (int)__builtin_amdgcn_ubfe((uint32_t)c, 24, 2); }
+__device__ inline int img_sy(int32_t c) { return (int)__builtin_amdgcn_ubfe((uint32_t)c, 26, 2); }
+__device__ inline int img_sz(int32_t c) { return (int)__builtin_amdgcn_ubfe((uint32_t)c, 28, 2); }
 __host__ __device__ inline void unpack_img(int32_t c, int& nx, int& ny, int& nz) {
     nx = (int)(int8_t)(c & 0xff);
     ny = (int)(int8_t)((c >> 8) & 0xff);
@@ -311,13 +320,21 @@ SpeciesGroups species_groups(const tmd_nlist* nl);
 // Per-element MLP: E_i and dE/dG for every grouped atom, in precision prec.
 tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups& g, tmd_precision prec,
                       const float* G, float* Ei, float* dG);
-// Adjoint: forces accumulated into Fsorted [n][3] (zeroed by the launcher),
-// virial block partials into vir_partials (count returned in *nvir_out).
+// Forces are accumulated as 64-bit fixed-point integers with 32 fractional
+// bits (F = q 2^-32, |F| < 2^31 eV/A): integer additions are associative, so
+// the sums do not depend on the order of the scatter's atomic adds and the
+// forces are reproducible bit for bit.
+constexpr double kForceFixedScale = 4294967296.0;  // 2^32
+// Virial partials: per block, 6 compensated FP64 sums (value, compensation).
+constexpr int kVirDoubles = 12;
+// Adjoint: forces accumulated into Fq [n][3] (fixed point, zeroed by the
+// launcher), virial block partials [blocks][6][2] into vir_partials (count in
+// *nvir_out).
 tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, const float* dG, float* Pbuf,
-                          float* Fsorted, double* vir_partials, int* nvir_out);
+                          unsigned long long* Fq, double* vir_partials, int* nvir_out);
 // part: device scratch of finalize_part_doubles() doubles.
 constexpr int64_t finalize_part_doubles() { return 256 * 14; }
-tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const float* Fsorted,
+tmd_status launch_finalize(tmd_context* ctx, const tmd_nlist* nl, const float* Ei, const unsigned long long* Fq,
                            const double* vir_partials, int nvir, float* atom_energy, float* forces, double* totals7,
                            double* part);
 // Descriptor rows [n][F] (sorted order, padded radial functions) to the

@@ -9,6 +9,7 @@ anything else.
 from __future__ import annotations
 
 import ctypes
+import weakref
 import math
 import os
 from typing import Optional, Tuple
@@ -225,6 +226,12 @@ class Context:
         if st != TMD_OK:
             raise TMDError(st, "tmd_context_create failed")
         self.h = h
+        # handles made on this context (models, lists, batches, MD runs), closed
+        # before the context itself so that none outlives it
+        self._children = weakref.WeakSet()
+
+    def adopt(self, obj):
+        self._children.add(obj)
 
     def check(self, st: int, what: str = ""):
         if st != TMD_OK:
@@ -252,6 +259,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for child in list(getattr(self, "_children", ())):
+                child.close()
             self.lib.tmd_context_destroy(self.h)
             self.h = None
 
@@ -282,6 +291,7 @@ class Model:
 
     def __init__(self, ctx: Context, spec, precision: int = FP32):
         self.ctx = ctx
+        ctx.adopt(self)
         self.spec = spec
         c = ModelSpecC()
         c.n_species = spec.n_species
@@ -359,6 +369,7 @@ def default_capacity(n_atoms: int, box, rlist: float, n_species: int) -> int:
 class NeighborList:
     def __init__(self, ctx: Context, n_atoms: int, n_species: int, capacity: int):
         self.ctx = ctx
+        ctx.adopt(self)
         self.n_atoms = n_atoms
         self.n_species = n_species
         h = ctypes.c_void_p()
@@ -500,6 +511,7 @@ class Batch:
                  capacity: int = 0):
         torch = _torch()
         self.ctx = ctx
+        ctx.adopt(self)
         self.sys_off = np.ascontiguousarray(sys_off, dtype=np.int64)
         self.boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
         self.energy_labels = np.ascontiguousarray(energy_labels, dtype=np.float64)
@@ -717,6 +729,7 @@ class MD:
                  ensemble: int = ENSEMBLE_NVT_NOSE_HOOVER, temperature_K: float = 300.0, tau_fs: float = 100.0,
                  skin: float = 1.0, rebuild_every: int = 5):
         self.ctx = ctx
+        ctx.adopt(self)
         self.model = model  # must outlive the MD handle
         self.n = int(pos.shape[0])
         v = system_view(pos, species, box)

@@ -6,9 +6,9 @@ Bars: energies and forces as in the inference tests (FP32: |dE|/N <= 1e-5 eV,
 force RMS <= 1e-4 eV/A); MD trajectories of 10 steps of 1 fs against the FP64
 oracle's velocity Verlet: positions within 1e-6 A and velocities within
 1e-7 A/fs (a force error of 1e-4 eV/A moves a 63.5 amu atom by ~1e-7 A in
-10 fs); alone vs mix: the same request on the same state gives forces within
-1e-4 eV/A and energies within 1e-6 relative (the only difference is the
-order of the force scatter's floating-point atomics).
+10 fs); alone vs mix: the same request on the same state gives the same
+forces, energies, positions and kinetic energies bit for bit (forces are
+summed in fixed point, totals in a fixed order).
 """
 import math
 import sys
@@ -181,12 +181,14 @@ def test_serve_results_same_alone_and_in_the_mix(tmd, ctx):
         assert r["status"] == 0
         spans.append((r["t_start"], r["t_done"]))
     srv.close()
+    # forces are summed in fixed point and energies in a fixed order, so the
+    # same request on the same state gives the same bits alone and in the mix
     for (ra, oa), (rm, om) in zip(alone, mixed):
-        assert abs(ra["energy"] - rm["energy"]) <= 1e-6 * abs(ra["energy"])
-        assert np.abs(oa["forces"] - om["forces"]).max() <= 1e-4
+        assert ra["energy"] == rm["energy"]
+        assert np.array_equal(oa["forces"], om["forces"])
         if ra["kind"] == tmd.REQ_MD:
-            assert np.abs(oa["pos"] - om["pos"]).max() <= 1e-6
-            assert abs(ra["kinetic"] - rm["kinetic"]) <= 1e-6 * abs(ra["kinetic"])
+            assert np.array_equal(oa["pos"], om["pos"])
+            assert ra["kinetic"] == rm["kinetic"]
     # requests ran concurrently: some pair of execution intervals overlaps
     spans.sort()
     overlap = any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
