@@ -240,6 +240,20 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
     wall = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
     atom_steps = sum(r["n_atoms"] * max(1, r["n_steps"]) for r in meas)
     sizes = np.array([n for (_, n, _) in systems])
+    # latency per system-size bucket and request kind
+    buckets = {}
+    natoms = np.array([r["n_atoms"] for r in meas])
+    kinds = np.array([r["kind"] for r in meas])
+    for lo, hi in ((0, 1000), (1000, 10000), (10000, 100000), (100000, 1 << 40)):
+        for kname, kv in (("ef", tmd.REQ_ENERGY_FORCES), ("md10", tmd.REQ_MD)):
+            sel = (natoms >= lo) & (natoms < hi) & (kinds == kv)
+            if sel.sum() == 0:
+                continue
+            key = f"{lo}-{hi if hi < (1 << 40) else 'max'}_atoms_{kname}"
+            buckets[key] = {"requests": int(sel.sum()), "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat[sel], 99)), 3)}
+    bsteps = sum(r["n_atoms"] * max(1, r["n_steps"]) for r in bres)
+    saturation["ns_per_atom_step"] = round(bwall / bsteps * 1e9, 3)
     return {"workload": f"Poisson {rate:g} req/s, {n_requests} requests after {n_warmup} warm-up, pool of {pool} "
                         f"resident fcc/bcc systems of {sizes.min()}..{sizes.max()} atoms (mean {sizes.mean():.0f}), "
                         f"50% E+F / 50% 10 VV steps, {slots} slots, BF16 MLP",
@@ -248,6 +262,7 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
             "mean_latency_ms": round(float(lat.mean()), 3),
             "atom_steps_per_s": round(atom_steps / wall, 1),
             "closed_loop_saturation": saturation,
+            "latency_by_size": buckets,
             "device_bytes_peak": int(peak)}
 
 

@@ -162,6 +162,32 @@ tmd_status launch_kick_drift(tmd_context* ctx, int64_t n, double* x, double* v, 
     return TMD_OK;
 }
 
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// flag |= (largest squared displacement > limit2); maxd2 holds the bits of a
+// non-negative double, whose order is that of the bits.
+__global__ void k_displacement_check(const unsigned long long* __restrict__ maxd2, double limit2,
+                                     unsigned long long* __restrict__ flag) {
+    if (threadIdx.x != 0) return;
+    if (__longlong_as_double((long long)*maxd2) > limit2) *flag = 1ull;
+}
+
+tmd_status launch_zero_u64(tmd_context* ctx, unsigned long long* p, int64_t n) {
+    if (n <= 0) return TMD_OK;
+    k_zero_u64<<<blocks_of(n), kBlock, 0, ctx->stream>>>(p, n);
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
+}
+
+tmd_status launch_displacement_check(tmd_context* ctx, const unsigned long long* maxd2, double limit2, unsigned long long* flag) {
+    k_displacement_check<<<1, 64, 0, ctx->stream>>>(maxd2, limit2, flag);
+    TMD_HIP(ctx, hipGetLastError());
+    return TMD_OK;
+}
+
 tmd_status launch_kick(tmd_context* ctx, int64_t n, double* v, const float* F, const int32_t* sp, const double* acc,
                        double dt) {
     k_kick<<<blocks_of(n), kBlock, 0, ctx->stream>>>(n, v, F, sp, acc, dt);

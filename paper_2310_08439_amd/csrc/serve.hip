@@ -150,15 +150,21 @@ struct SlotBuffers {
     double* tot = nullptr;                 // [7 (n_steps + 1)]
     double* ekin = nullptr;                // [4 (n_steps + 1)] kinetic tensor diagonal and total
     double* part = nullptr;                // [3 kKeBlocks]
-    unsigned long long* maxd2 = nullptr;   // [1]
+    unsigned long long* maxd2 = nullptr;   // [n_steps + 1] largest squared displacement since the build, per step
+    unsigned long long* flag = nullptr;    // [1] nonzero: some step moved an atom beyond skin/2
+    double* x0 = nullptr;                  // [n][3] positions and velocities at the start of an MD request
+    double* v0 = nullptr;
 };
 
-tmd_status slot_buffers(tmd_context* ctx, int n_steps, SlotBuffers* b) {
+tmd_status slot_buffers(tmd_context* ctx, int n_steps, int64_t n, SlotBuffers* b) {
     hipError_t e = hipSuccess;
     b->tot = (double*)ctx->ws.get("md.tot", sizeof(double) * 7 * (size_t)(n_steps + 1), &e);
     b->ekin = (double*)ctx->ws.get("md.ekin", sizeof(double) * 4 * (size_t)(n_steps + 1), &e);
     b->part = (double*)ctx->ws.get("md.part", sizeof(double) * 3 * kKeBlocks, &e);
-    b->maxd2 = (unsigned long long*)ctx->ws.get("md.maxd2", sizeof(unsigned long long), &e);
+    b->maxd2 = (unsigned long long*)ctx->ws.get("md.maxd2", sizeof(unsigned long long) * (size_t)(n_steps + 1), &e);
+    b->flag = (unsigned long long*)ctx->ws.get("md.flag", sizeof(unsigned long long), &e);
+    b->x0 = (double*)ctx->ws.get("md.x0", 24 * (size_t)n, &e);
+    b->v0 = (double*)ctx->ws.get("md.v0", 24 * (size_t)n, &e);
     if (e != hipSuccess) return hip_fail(ctx, e, "MD workspace");
     return TMD_OK;
 }
@@ -167,7 +173,75 @@ tmd_status kinetic(tmd_context* ctx, const System* sys, double* part, double* ou
     return launch_kinetic(ctx, sys->n, sys->v, sys->sp, sys->mass, part, out4);
 }
 
-// Run one request to completion on the worker's context.
+// The steps of an MD request with no host synchronisation between them: each
+// step's largest displacement since the list build (maxd2[s]) gates the
+// reuse of pruned rows on the device, and a sticky device flag records
+// whether any step moved an atom beyond skin/2, which would have made the
+// list incomplete.  The caller reads the flag with the results.
+tmd_status md_steps_device_gated(tmd_server* sv, tmd_context* ctx, System* sys, const tmd_system_view& view,
+                                 const SlotBuffers& b, int nsteps, double dt) {
+    const tmd_model* m = sv->model;
+    const double half_skin2 = 0.25 * sv->opts.skin * sv->opts.skin;
+    tmd_status st;
+    if ((st = launch_zero_u64(ctx, b.maxd2, nsteps + 1)) != TMD_OK) return st;
+    for (int s = 1; s <= nsteps; ++s) {
+        if ((st = launch_kick_drift(ctx, sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc, dt, sys->xref,
+                                    b.maxd2 + s)) != TMD_OK)
+            return st;
+        if ((st = launch_displacement_check(ctx, b.maxd2 + s, half_skin2, b.flag)) != TMD_OK) return st;
+        PruneGate gate;
+        gate.maxd2 = b.maxd2 + s;
+        gate.margin = 0.2 * sv->opts.skin;
+        if ((st = energy_forces_gated(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F, &gate)) != TMD_OK)
+            return st;
+        if ((st = launch_kick(ctx, sys->n, sys->v, sys->F, sys->sp, sys->acc, dt)) != TMD_OK) return st;
+        if ((st = kinetic(ctx, sys, b.part, b.ekin + 4 * s)) != TMD_OK) return st;
+    }
+    return TMD_OK;
+}
+
+// The same steps with a host synchronisation per step, rebuilding the list
+// whenever an atom has moved more than skin/2 since the last build.
+tmd_status md_steps_host_checked(tmd_server* sv, tmd_context* ctx, System* sys, const tmd_system_view& view,
+                                 const SlotBuffers& b, int nsteps, double dt, int* rebuilds) {
+    const tmd_model* m = sv->model;
+    const double half_skin2 = 0.25 * sv->opts.skin * sv->opts.skin;
+    tmd_status st;
+    for (int s = 1; s <= nsteps; ++s) {
+        if ((st = launch_zero_u64(ctx, b.maxd2 + s, 1)) != TMD_OK) return st;
+        if ((st = launch_kick_drift(ctx, sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc, dt, sys->xref,
+                                    b.maxd2 + s)) != TMD_OK)
+            return st;
+        unsigned long long bits = 0;
+        TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, b.maxd2 + s, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream));
+        TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        std::memcpy(&bits, ctx->h_flags, sizeof(bits));
+        double d2;
+        std::memcpy(&d2, &bits, sizeof(d2));
+        if (!(d2 <= half_skin2)) {
+            sys->nl_valid = false;
+            if ((st = build_list(sv, ctx, sys, rebuilds)) != TMD_OK) return st;
+        }
+        // b.maxd2[s] now holds this system's displacement since its build: the
+        // pruned rows are reused while it allows (the request's first
+        // evaluation pruned to the cutoff, so the first step here prunes)
+        PruneGate gate;
+        gate.maxd2 = b.maxd2 + s;
+        gate.margin = 0.2 * sv->opts.skin;
+        if ((st = energy_forces_gated(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F,
+                                      sv->opts.skin > 0.0 ? &gate : nullptr)) != TMD_OK)
+            return st;
+        if ((st = launch_kick(ctx, sys->n, sys->v, sys->F, sys->sp, sys->acc, dt)) != TMD_OK) return st;
+        if ((st = kinetic(ctx, sys, b.part, b.ekin + 4 * s)) != TMD_OK) return st;
+    }
+    return TMD_OK;
+}
+
+// Run one request to completion on the worker's context.  An MD request on a
+// list with a skin first runs all its steps without host synchronisation
+// (md_steps_device_gated); if the device flag shows that some step moved an
+// atom beyond skin/2 (so that a list rebuild was due), the request restarts
+// from its saved positions and velocities and runs with a check per step.
 tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pending& p, Finished* out) {
     const tmd_model* m = sv->model;
     tmd_result& r = out->res;
@@ -178,50 +252,46 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
     view.species = sys->sp;
     for (int a = 0; a < 3; ++a) view.box[a] = sys->box[a];
     int rebuilds = 0;
-    const int nsteps = (p.req.kind == TMD_REQ_MD) ? p.req.n_steps : 0;
+    const bool md = p.req.kind == TMD_REQ_MD;
+    const int nsteps = md ? p.req.n_steps : 0;
     SlotBuffers b;
-    if ((st = slot_buffers(ctx, nsteps, &b)) != TMD_OK) return st;
-    if (p.req.kind == TMD_REQ_MD && !p.vel.empty())
+    if ((st = slot_buffers(ctx, nsteps, sys->n, &b)) != TMD_OK) return st;
+    if (md && !p.vel.empty())
         TMD_HIP(ctx, hipMemcpyAsync(sys->v, p.vel.data(), 24 * (size_t)sys->n, hipMemcpyHostToDevice, ctx->stream));
     if (!sys->nl_valid && (st = build_list(sv, ctx, sys, &rebuilds)) != TMD_OK) return st;
+    const bool fast = md && nsteps > 0 && sv->opts.skin > 0.0;
+    if (fast) {
+        TMD_HIP(ctx, hipMemcpyAsync(b.x0, sys->x, 24 * (size_t)sys->n, hipMemcpyDeviceToDevice, ctx->stream));
+        TMD_HIP(ctx, hipMemcpyAsync(b.v0, sys->v, 24 * (size_t)sys->n, hipMemcpyDeviceToDevice, ctx->stream));
+        if ((st = launch_zero_u64(ctx, b.flag, 1)) != TMD_OK) return st;
+    }
     if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot, nullptr, sys->F)) != TMD_OK) return st;
-    if (p.req.kind == TMD_REQ_MD) {
+    if (md) {
         if ((st = kinetic(ctx, sys, b.part, b.ekin)) != TMD_OK) return st;  // slot 0
         const double dt = p.req.dt_fs;
-        const double half_skin2 = 0.25 * sv->opts.skin * sv->opts.skin;
-        for (int s = 1; s <= nsteps; ++s) {
-            TMD_HIP(ctx, hipMemsetAsync(b.maxd2, 0, sizeof(unsigned long long), ctx->stream));
-            if ((st = launch_kick_drift(ctx, sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc, dt, sys->xref,
-                                        b.maxd2)) != TMD_OK)
-                return st;
-            unsigned long long bits = 0;
-            TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, b.maxd2, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream));
+        bool done = false;
+        if (fast) {
+            if ((st = md_steps_device_gated(sv, ctx, sys, view, b, nsteps, dt)) != TMD_OK) return st;
+            TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, b.flag, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                        ctx->stream));
             TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            std::memcpy(&bits, ctx->h_flags, sizeof(bits));
-            double d2;
-            std::memcpy(&d2, &bits, sizeof(d2));
-            if (!(d2 <= half_skin2)) {
-                sys->nl_valid = false;
-                if ((st = build_list(sv, ctx, sys, &rebuilds)) != TMD_OK) return st;
+            done = ctx->h_flags[0] == 0 && ctx->h_flags[1] == 0;
+            if (!done) {  // restart with a check per step
+                TMD_HIP(ctx, hipMemcpyAsync(sys->x, b.x0, 24 * (size_t)sys->n, hipMemcpyDeviceToDevice, ctx->stream));
+                TMD_HIP(ctx, hipMemcpyAsync(sys->v, b.v0, 24 * (size_t)sys->n, hipMemcpyDeviceToDevice, ctx->stream));
+                if ((st = tmd_energy_forces_async(ctx, m, &view, sys->nl, b.tot, nullptr, sys->F)) != TMD_OK)
+                    return st;
+                if ((st = kinetic(ctx, sys, b.part, b.ekin)) != TMD_OK) return st;
             }
-            // b.maxd2 now holds this system's displacement since its build: the
-            // pruned rows are reused while it allows (the request's first
-            // evaluation pruned to the cutoff, so the first step here prunes)
-            PruneGate gate;
-            gate.maxd2 = b.maxd2;
-            gate.margin = 0.2 * sv->opts.skin;
-            if ((st = energy_forces_gated(ctx, m, &view, sys->nl, b.tot + 7 * s, nullptr, sys->F,
-                                          sv->opts.skin > 0.0 ? &gate : nullptr)) != TMD_OK)
-                return st;
-            if ((st = launch_kick(ctx, sys->n, sys->v, sys->F, sys->sp, sys->acc, dt)) != TMD_OK) return st;
-            if ((st = kinetic(ctx, sys, b.part, b.ekin + 4 * s)) != TMD_OK) return st;
         }
+        if (!done && (st = md_steps_host_checked(sv, ctx, sys, view, b, nsteps, dt, &rebuilds)) != TMD_OK)
+            return st;
     }
     std::vector<double> tot(7 * (size_t)(nsteps + 1));
     out->F.resize(3 * (size_t)sys->n);
     TMD_HIP(ctx, hipMemcpyAsync(tot.data(), b.tot, sizeof(double) * tot.size(), hipMemcpyDeviceToHost, ctx->stream));
     TMD_HIP(ctx, hipMemcpyAsync(out->F.data(), sys->F, 12 * (size_t)sys->n, hipMemcpyDeviceToHost, ctx->stream));
-    if (p.req.kind == TMD_REQ_MD) {
+    if (md) {
         out->ekin.resize(4 * (size_t)(nsteps + 1));
         out->x.resize(3 * (size_t)sys->n);
         out->v.resize(3 * (size_t)sys->n);
@@ -235,12 +305,12 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
     for (int s = 0; s <= nsteps; ++s) out->epot[s] = tot[7 * s];
     r.energy = tot[7 * nsteps];
     for (int j = 0; j < 6; ++j) r.virial[j] = tot[7 * nsteps + 1 + j];
-    if (p.req.kind == TMD_REQ_MD) {
+    if (md) {
         // keep the totals only
         for (int s = 0; s <= nsteps; ++s) out->ekin[s] = out->ekin[4 * (size_t)s + 3];
         out->ekin.resize(nsteps + 1);
     }
-    r.kinetic = p.req.kind == TMD_REQ_MD ? out->ekin[nsteps] : 0.0;
+    r.kinetic = md ? out->ekin[nsteps] : 0.0;
     r.rebuilds = rebuilds;
     return TMD_OK;
 }

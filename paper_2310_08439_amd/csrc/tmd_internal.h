@@ -369,6 +369,11 @@ tmd_status launch_kick(tmd_context* ctx, int64_t n, double* v, const float* F, c
                        double dt);
 tmd_status launch_kinetic(tmd_context* ctx, int64_t n, const double* v, const int32_t* sp, const double* mass,
                           double* part, double* out4);
+// p[0 .. n) = 0 (a kernel, not a memset).
+tmd_status launch_zero_u64(tmd_context* ctx, unsigned long long* p, int64_t n);
+// *flag = 1 when the squared displacement whose bits maxd2 holds exceeds
+// limit2 (flag is sticky: never cleared here).
+tmd_status launch_displacement_check(tmd_context* ctx, const unsigned long long* maxd2, double limit2, unsigned long long* flag);
 
 // Copy of the list's rows keeping only the entries within rcut (times 1 + 1e-6)
 // at the current positions, into nl->pnbr / pimg / pcnt (allocated on first

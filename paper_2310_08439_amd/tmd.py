@@ -130,6 +130,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: run paper_2310_08439_amd/build.py (hipcc, gfx950)")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (one runtime per process; loading ours first leaves torch a second one)
+    _torch()
     L = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
