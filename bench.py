@@ -93,7 +93,7 @@ def kernel_rooflines(workload: str, flops: dict, avg_ms: dict) -> dict:
         sec = avg_ms[name] * 1e-3
         tf = flops[name] / sec / 1e12
         row = {"ms": round(avg_ms[name], 4), "tflops": round(tf, 3), "peak_tflops": peak, "frac_compute": round(tf / peak, 4)}
-        traffic = measured_traffic(workload, name)
+        traffic = measured_traffic(workload, name) if workload else None
         if traffic is not None:
             gbs = traffic / sec / 1e9
             row.update({"hbm_bytes": traffic, "gb_per_s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)})
@@ -101,13 +101,11 @@ def kernel_rooflines(workload: str, flops: dict, avg_ms: dict) -> dict:
     return out
 
 
-def cpu_baseline(seconds: float) -> dict:
-    """The FP64 oracle (full E+F incl. its brute-force neighbour search) on the
-    4,096-atom sub-cell of the same alloy and model, repeated for ~`seconds`."""
+def _oracle_rate(spec, s, threads: int, seconds: float):
+    """(ns/step/atom of the oracle's full E+F, share of it in its brute-force
+    neighbour search, repetitions) with `threads` OpenMP threads."""
     import oracle
-    from paper_2310_08439_amd import inputs
-    s, spec, _ = inputs.workload("bcc4k")
-    oracle.lib()
+    oracle.set_num_threads(threads)
     reps, t0 = 0, time.perf_counter()
     while True:
         oracle.energy_forces(spec, s.pos, s.species, s.box)
@@ -115,10 +113,45 @@ def cpu_baseline(seconds: float) -> dict:
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": el / (reps * s.n) * 1e9, "unit": "ns/step/atom", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    t1 = time.perf_counter()
+    oracle.neighbors(s.pos, s.species, s.box, spec.rcut)
+    tn = time.perf_counter() - t1
+    return el / (reps * s.n) * 1e9, tn / (el / reps), reps
+
+
+def cpu_baseline(seconds: float) -> dict:
+    """The FP64 oracle (full E+F incl. its brute-force O(N^2) neighbour search)
+    on the 4,096-atom sub-cell of the same alloy and model, on every host core
+    (value), plus one thread and the other sizes: the 32-atom cell, the
+    4,096-atom sub-cell and the 32,000-atom fcc cell (all cores only)."""
+    import oracle
+    from paper_2310_08439_amd import inputs
+    oracle.lib()
+    cores = len(os.sched_getaffinity(0))
+    s, spec, _ = inputs.workload("bcc4k")
+    value, nshare, reps = _oracle_rate(spec, s, cores, seconds)
+    runs = []
+    for name, thr, secs in (("oracle32", 1, 1.0), ("oracle32", cores, 1.0), ("bcc4k", 1, 2.0), ("fcc32k", cores, 0.0)):
+        sx, specx, _ = inputs.workload(name)
+        v, sh, r = _oracle_rate(specx, sx, thr, secs)
+        runs.append({"workload": name, "atoms": sx.n, "threads": thr, "ns_per_step_atom": round(v, 1),
+                     "neighbour_search_share": round(sh, 3), "repetitions": r})
+    runs.append({"workload": "bcc4k", "atoms": s.n, "threads": cores, "ns_per_step_atom": round(value, 1),
+                 "neighbour_search_share": round(nshare, 3), "repetitions": reps})
+    oracle.set_num_threads(cores)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": value, "unit": "ns/step/atom", "cores": cores, "kind": "oracle",
             "sample": f"full FP64 E+F (brute-force neighbours included) of the 4,096-atom bcc sub-cell with the "
-                      f"1M-atom workload's model, {reps} repetitions in {el:.1f} s"}
+                      f"1M-atom workload's model on {cores} threads, {reps} repetitions in about {seconds:.0f} s; "
+                      f"host CPU {cpu}",
+            "runs": runs}
 
 
 def train_leg(tmd, torch, ctx, steps: int, warmup: int) -> dict:
@@ -282,9 +315,13 @@ def paper_shapes_leg(tmd, torch, ctx, steps: int, warmup: int) -> dict:
         row = {"atoms": s.n, "a_A": round(float(s.box[0] / 35 if s.n == 85750 else s.box[0] / 24), 4),
                "K": spec.n_radial, "mlp": f"{spec.n_features}-{'-'.join(map(str, spec.hidden))}-1 squareplus",
                "pairs_per_atom": round(pairs / s.n, 2)}
+        flops = algorithmic_flops(spec, s.n, pairs)
         for pname, prec in (("bf16", tmd.BF16_MLP), ("fp32", tmd.FP32)):
-            sec, _, _ = time_precision(tmd, torch, ev, pos, sp, s.box, prec, steps, warmup)
+            sec, prof, _ = time_precision(tmd, torch, ev, pos, sp, s.box, prec, steps, warmup)
             row[f"ns_per_step_atom_{pname}"] = round(sec / s.n * 1e9, 3)
+            if pname == "bf16":
+                avg = {k: v[0] / v[1] for k, v in prof.items()}
+                row["kernels_roofline_bf16"] = kernel_rooflines(None, flops, avg)
         out[name] = row
         ev.model.close()
         ev.nl.close()
@@ -396,18 +433,37 @@ def interpolation_leg(tmd, torch, ev, pos, sp, s, spec, steps: int, warmup: int)
 
 
 def accuracy(tmd, ev, pos, sp, s, spec, n_sample: int, precision: int) -> dict:
-    """Sampled per-atom energy and force errors against the FP64 oracle."""
+    """Per-atom energy and force errors against the FP64 oracle on n_sample
+    atoms: a compact sample cut out of the system with every atom within
+    2 rcut + 0.5 A of it (inputs.cluster_cut), so that the oracle evaluates the
+    piece exactly as it would the whole periodic system for those atoms.
+    Reports the mean signed error of E_i (the energy bias per atom at full
+    size, sampled) and, for BF16, the oracle's BF16 form beside it."""
     import numpy as np
     import oracle
+    from paper_2310_08439_amd import inputs
     ev.model.set_precision(precision)
     E, Ea, F, _ = ev.energy_forces(pos, sp, s.box)
-    sel = np.random.default_rng(1234).choice(s.n, n_sample, replace=False)
-    Ear, Fr = oracle.forces_subset(spec, s.pos, s.species, s.box, sel)
-    Ea = Ea.cpu().numpy().astype(np.float64)[sel]
-    Fg = F.cpu().numpy().astype(np.float64)[sel]
-    return {"sampled_atoms": int(n_sample), "max_abs_dE_atom_eV": float(np.abs(Ea - Ear).max()),
-            "force_rms_err_eV_per_A": float(math.sqrt(np.mean((Fg - Fr) ** 2))),
-            "force_rms_eV_per_A": float(math.sqrt(np.mean(Fr ** 2)))}
+    Ea = Ea.cpu().numpy().astype(np.float64)
+    F = F.cpu().numpy().astype(np.float64)
+    centre = int(np.random.default_rng(1234).integers(s.n))
+    t0 = time.perf_counter()
+    piece, sample, where = inputs.cluster_cut(s, centre, n_sample, 2.0 * spec.rcut + 0.5)
+    _, Ear, Fr, _ = oracle.energy_forces(spec, piece.pos, piece.species, piece.box)
+    Ear, Fr = Ear[where], Fr[where]
+    dE = Ea[sample] - Ear
+    dF = F[sample] - Fr
+    out = {"sampled_atoms": int(len(sample)), "piece_atoms": int(piece.n),
+           "mean_signed_dE_atom_eV": float(dE.mean()), "max_abs_dE_atom_eV": float(np.abs(dE).max()),
+           "force_rms_err_eV_per_A": float(math.sqrt(np.mean(dF ** 2))),
+           "force_max_abs_err_eV_per_A": float(np.abs(dF).max()),
+           "force_rms_eV_per_A": float(math.sqrt(np.mean(Fr ** 2)))}
+    if precision == tmd.BF16_MLP:
+        _, Ea16, F16, _ = oracle.energy_forces(spec, piece.pos, piece.species, piece.box, bf16=True)
+        out["oracle_bf16_form_mean_signed_dE_atom_eV"] = float((Ea16[where] - Ear).mean())
+        out["vs_bf16_form_median_abs_dE_atom_eV"] = float(np.median(np.abs(Ea[sample] - Ea16[where])))
+    out["oracle_seconds"] = round(time.perf_counter() - t0, 2)
+    return out
 
 
 def time_precision(tmd, torch, ev, pos, sp, box, precision, steps, warmup):
@@ -463,7 +519,7 @@ def main():
     ap.add_argument("--workload", default="bcc1m", choices=["bcc1m", "fcc32k", "bcc4k"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--accuracy-samples", type=int, default=8)
+    ap.add_argument("--accuracy-samples", type=int, default=2000)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--md-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=600)

@@ -183,7 +183,7 @@ def workload(name: str):
     oracle32   : 32-atom fcc (2x2x2, a=3.61), sigma 0.1, rc 5.0, K 8, M 3, MLP 64-64.
     fcc32k     : 32,000-atom fcc (20^3, a=3.61), sigma 0.05, rc 6.0, K 8, M 3, MLP 64-64.
     bcc1m      : 1,024,000-atom bcc alloy (80^3, a=3.16, 50/50), sigma 0.08, rc 6.0, K 12, M 3, 128-128.
-    bcc4k      : 4,096-atom sub-cell of the bcc alloy workload (16^3), own seed.
+    bcc4k      : 4,096-atom sub-cell of the bcc alloy workload (8 x 16 x 16 cells, 25.3 x 50.6 x 50.6 A), own seed.
     w_k32[_hp] : bcc W 35^3 (N 85,750), a 3.1887 (2.8 for _hp), rc 6, K 32, M 3, SquarePlus 128-128-128.
     w_k128[_hp]: bcc W 24x24x20 (N 23,040), a 3.1887 (2.8), rc 6, K 128, M 3, SquarePlus 128x4.
     """
@@ -200,7 +200,7 @@ def workload(name: str):
         model = make_model(2, 12, 3, [128, 128], 6.0, seed=102)
         return sysm, model, 0.0
     if name == "bcc4k":
-        sysm = make_system("bcc", 3.16, (16, 16, 16), 0.08, 2, seed=20, masses=[183.84, 95.95])
+        sysm = make_system("bcc", 3.16, (8, 16, 16), 0.08, 2, seed=20, masses=[183.84, 95.95])
         model = make_model(2, 12, 3, [128, 128], 6.0, seed=102)
         return sysm, model, 0.0
     # Shapes of the paper's own tungsten potentials (Sec. IV: bcc W, one species,
