@@ -215,8 +215,9 @@ __device__ __forceinline__ void load_pairs_split2(const PathArgs& a, int64_t row
 constexpr int kBatchFwd = 4;
 constexpr int kBatchAdj = 2;
 
-// A thread's KC x D tile of P in the element-major buffer [S][K][D][n]: element
-// (k, d) of work slot w lives at ((b*K + k)*D + d)*n + w, so for a fixed
+// A thread's KC x DR tile of P (its kept components) in the element-major
+// buffer [S][K][DR][n]: element (k, r) of work slot w lives at
+// ((b*K + k)*DR + r)*n + w, so for a fixed
 // element the lanes of a wave (consecutive slots, two chunks) write and read
 // whole contiguous cache lines.  P (2 GB at 1 M atoms) is written once and
 // read once by the adjoint, far more than the L2 holds.  With at most two
@@ -302,8 +303,8 @@ __device__ __forceinline__ void tabulated(const PathArgs& a, float R, int k0, fl
 // P tile of one species for this thread's radial chunk.
 template <int KC, int M, bool TAB, class Pos>
 __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b, int k0, const float* mu,
-                                             const float* nef, float (&P)[KC][Moments<M>::D], const Pos& pos) {
-    constexpr int D = Moments<M>::D;
+                                             const float* nef, float (&P)[KC][Moments<M>::DR], const Pos& pos) {
+    constexpr int D = Moments<M>::DR;  // the kept components (reduced_monomials)
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
@@ -324,7 +325,7 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b
         const float R = pr.r2 * rinv;
         const float ux = pr.dx * rinv, uy = pr.dy * rinv, uz = pr.dz * rinv;
         float Mv[D], hv[KC];
-        monomials<M>(ux, uy, uz, Mv);
+        reduced_monomials<M>(ux, uy, uz, Mv);
         if (TAB) {
             tabulated<KC, false>(a, R, k0, hv, hv);
         } else {
@@ -344,7 +345,7 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b
 
 template <int KC, int M, bool TAB, bool NT>
 __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a, int64_t nblocks) {
-    constexpr int D = Moments<M>::D;
+    constexpr int D = Moments<M>::D, DR = Moments<M>::DR;
     constexpr int GW = KC * (M + 1);  // features of one thread's chunk
     // Per wave: its atoms' feature segments of two species, so that G's rows
     // go out as consecutive floats (a lane-per-atom store would touch one
@@ -377,9 +378,10 @@ __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a,
         const int RW = nsp * KM;              // staged floats per atom
         const int RWp = RW | 1;               // their LDS stride
         if (active) {
-            float P[KC][D];
-            accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, P, pos);
-            if (a.Pbuf) store_tile<KC, D, NT>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
+            float Pr[KC][DR], P[KC][D];
+            accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, Pr, pos);
+            if (a.Pbuf) store_tile<KC, DR, NT>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * DR) * a.n + w, a.n, Pr);
+            expand_P<M, KC>(Pr, P);
             float* seg = &sg[wv][(lane >> a.nch_log2) * RWp + (b - b0) * KM + ch * GW];
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
@@ -453,19 +455,32 @@ __device__ __forceinline__ void tile_adjoint(const float* dGp, float (&P)[KC][Mo
     }
 }
 
+// This thread's P' tile of species b in the kept basis: the stored kept
+// components of P, expanded, turned into P' and folded back.
+template <int KC, int M>
+__device__ __forceinline__ void adjoint_tile(const PathArgs& a, int64_t p, int64_t w, int b, int ch,
+                                             float (&Pr)[KC][Moments<M>::DR]) {
+    constexpr int D = Moments<M>::D, DR = Moments<M>::DR;
+    float P[KC][D];
+    load_tile<KC, DR>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * DR) * a.n + w, a.n, Pr);
+    expand_P<M, KC>(Pr, P);
+    tile_adjoint<KC, M>(a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1), P);
+    fold_Pbar<M, KC>(P, Pr);
+}
+
 // This chunk's share of g = dE/dD for one pair within the cutoff:
 // U_k = sum_d P'_kd M_d, V_d = sum_k P'_kd h_k,
 // g = (sum_k U_k h'_k) u + (1/R)(sum_d V_d grad_u M_d - u sum_d ord(d) V_d M_d).
 template <int KC, int M, int RAD>
 __device__ __forceinline__ void pair_grad(const PathArgs& a, float dx, float dy, float dz, float r2, int k0,
                                           const float* mu, const float* nef, const float* m2eta,
-                                          const float (&P)[KC][Moments<M>::D], float& gx, float& gy, float& gz) {
-    constexpr int D = Moments<M>::D;
+                                          const float (&P)[KC][Moments<M>::DR], float& gx, float& gy, float& gz) {
+    constexpr int D = Moments<M>::DR;  // P' folded onto the kept basis (fold_Pbar)
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float R = r2 * rinv;
     const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
     float Mv[D];
-    monomials<M>(ux, uy, uz, Mv);
+    reduced_monomials<M>(ux, uy, uz, Mv);
     float V[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) V[d] = 0.0f;
@@ -496,7 +511,7 @@ __device__ __forceinline__ void pair_grad(const PathArgs& a, float dx, float dy,
         const float t0 = R - mu[0];
         const float s1 = fmaf(a.rec_m2eta * fc, fmaf(-a.rec_delta, S1, t0 * S0), dfc * S0);
         float Ax, Ay, Az, B;
-        moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
+        reduced_moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
         const float rf = rinv * fc;
         gx = s1 * ux + rf * (Ax - ux * B);
         gy = s1 * uy + rf * (Ay - uy * B);
@@ -531,7 +546,7 @@ __device__ __forceinline__ void pair_grad(const PathArgs& a, float dx, float dy,
         s1 = fmaf(U, dh, s1);
     }
     float Ax, Ay, Az, B;
-    moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
+    reduced_moment_adjoint<M>(ux, uy, uz, V, Mv, Ax, Ay, Az, B);
     gx = s1 * ux + rinv * (Ax - ux * B);
     gy = s1 * uy + rinv * (Ay - uy * B);
     gz = s1 * uz + rinv * (Az - uz * B);
@@ -569,13 +584,12 @@ __device__ __forceinline__ void chunk_params(const PathArgs& a, int k0, float (&
 template <int KC, int M, int RAD, class Pos, class Sink>
 __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64_t w, int ch, int nch,
                                              double (&Wd)[6], float (&Fo)[3], const Pos& pos, Sink&& sink) {
-    constexpr int D = Moments<M>::D;
+    constexpr int DR = Moments<M>::DR;
     float mu[KC], nef[KC], m2eta[KC];
     chunk_params<KC>(a, ch * KC, mu, nef, m2eta);
     for (int b = 0; b < a.S; ++b) {
-        float P[KC][D];
-        load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
-        tile_adjoint<KC, M>(a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1), P);
+        float P[KC][DR];
+        adjoint_tile<KC, M>(a, p, w, b, ch, P);
         const int nb = a.cnt[(int64_t)b * a.n + p];
         const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species)
         float w6[6] = {0, 0, 0, 0, 0, 0};
@@ -620,14 +634,13 @@ __device__ __forceinline__ void adjoint_atom(const PathArgs& a, int64_t p, int64
 template <int KC, int M, int RAD, class Sink>
 __device__ __forceinline__ void adjoint_atom_pair2(const PathArgs& a, int64_t p, int64_t w, int ch, double (&Wd)[6],
                                                    float (&Fo)[3], const LdsPos& pos, Sink&& sink) {
-    constexpr int D = Moments<M>::D;
+    constexpr int DR = Moments<M>::DR;
     const int odd = ch & 1;
     float mu[KC], nef[KC], m2eta[KC];
     chunk_params<KC>(a, ch * KC, mu, nef, m2eta);
     for (int b = 0; b < a.S; ++b) {
-        float P[KC][D];
-        load_tile<KC, D>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * D) * a.n + w, a.n, P);
-        tile_adjoint<KC, M>(a.dG + p * a.F + (b * a.K + ch * KC) * (M + 1), P);
+        float P[KC][DR];
+        adjoint_tile<KC, M>(a, p, w, b, ch, P);
         const int nb = a.cnt[(int64_t)b * a.n + p];
         const int64_t base = (p * a.S + b) * a.cap;  // row of (atom, species), 16-byte aligned
         float w6[6] = {0, 0, 0, 0, 0, 0};

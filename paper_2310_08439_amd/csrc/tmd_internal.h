@@ -105,6 +105,7 @@ struct ProfScope {
 struct tmd_model {
     tmd_context* ctx = nullptr;
     int S = 0, K = 0, M = 0, D = 0, F = 0, Fpad = 0, L = 0, H = 0, act = 0;
+    int Dr = 0;  // moment components of P the evaluation path stores (the unit-norm identity drops the rest)
     int Kabi = 0, Fabi = 0;
     int hid[TMD_MAX_HIDDEN] = {0, 0, 0, 0};
     int kc = 8;  // radial functions per thread in the descriptor / adjoint kernels
