@@ -921,6 +921,298 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
     block_virial(Wd, red, a.vir + (int64_t)blockIdx.x * kVirDoubles);
 }
 
+// ---- adjoint on the matrix cores (M = 3, K a multiple of 4) ---------------
+//
+// For one (atom, neighbour species) the two contractions of the adjoint are
+// small dense products over the radial index k, for every pair c:
+//   V1_d(c) = sum_k P'_kd B1_k(c),   V2_d(c) = sum_k P'_kd B2_k(c),
+// with (B1, B2) = (h_k, h'_k), or on a uniform grid (e_k, k e_k) for the bare
+// Gaussians e_k (the fold of pair_grad).  The rest of a pair's g needs only
+// these: sum_k U_k h'_k = sum_d M_d V2_d (or the fold's S0 = M.V1, S1 = M.V2)
+// and A = sum_d V1_d grad_u M_d.  v_mfma_f32_4x4x1f32 makes 16 independent
+// 4x4 outer-product updates per instruction: block i of the wave (lanes
+// 4i .. 4i+3) is one atom; lane 4i+n holds pair n of the atom's current
+// four; the A operand (one value per lane) is a 4-entry slice of the atom's
+// P' column k, the B operand the lane's own B_k; the 4x4 result keeps column
+// n in lane 4i+n.  After K accumulation steps on four slices every lane holds
+// all 16 entries of V1 and V2 for its own pair, and forms its pair's g alone.
+//
+// Lane n of a block supplies P' entries of the kept basis in the slices
+// (q = 0..3) {n, rb, rc, rf}: with n = 0: (1, xx, yy, xy), 1: (x, xxx, xyy, xz),
+// 2: (y, xxy, yyy, yz), 3: (z, xxz, yyz, xyz).  Each lane's first three are
+// exactly the kept components that the unit-norm identity ties to one
+// dropped component (zz, xzz, yzz, zzz), so the fold of P' onto the kept
+// basis stays inside the lane, and a lane computes its P' entries from its
+// own four P components and dE/dG alone.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Reduced-basis index of result entry i of slice q (the slices above).
+// Image word of the centre atom's own cell (stencil offset 0, 0, 0).
+constexpr int32_t kCentreWord = (int32_t)(0x15u << 24);
+
+__device__ constexpr int kMfmaRow[4][4] = {{0, 1, 2, 3}, {4, 9, 10, 11}, {7, 12, 14, 15}, {5, 6, 8, 13}};
+
+template <int KQ, int RAD>
+__global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom bg) {
+    constexpr int K = 4 * KQ, DR = Moments<3>::DR;
+    extern __shared__ __attribute__((aligned(8))) unsigned char lds_dyn[];
+    __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
+    __shared__ int32_t wtmp[kBlock / 64];
+    __shared__ double red[6][kBlock / 64][2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int quad = lane >> 2, j = lane & 3;
+    const int blk = blockIdx.x;
+    int x0, y0, z0;
+    halo_slots(bg, blk, h_first, h_base, hoff, wtmp, x0, y0, z0);
+    const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
+    const int nh = HX * HY * HZ;
+    const int hpos = (3 * bg.hmax + 1) & ~1;
+    float* sx = reinterpret_cast<float*>(lds_dyn);
+    float* sy = sx + bg.hmax;
+    float* sz = sx + 2 * bg.hmax;
+    unsigned long long* sF = reinterpret_cast<unsigned long long*>(sx + hpos);
+    const int htot = h_base[nh];
+    for (int i = t; i < htot; i += kBlock) {
+        sF[i] = 0ull;
+        sF[bg.hmax + i] = 0ull;
+        sF[2 * bg.hmax + i] = 0ull;
+    }
+    halo_positions(bg, a, x0, y0, z0, h_first, h_base, sx, sy, sz);  // ends with a barrier
+    const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
+    auto sink = [&](int idx, float gx, float gy, float gz) {
+        atomicAdd(&sF[idx], to_fixed(-gx));
+        atomicAdd(&sF[bg.hmax + idx], to_fixed(-gy));
+        atomicAdd(&sF[2 * bg.hmax + idx], to_fixed(-gz));
+    };
+    // this lane's kept components (reduced index) and 2 x their multiplicities
+    // (full T_dm row order: xx 1, xy 2, yy 1, zz 1; x 1, xz 2, xxx 1, xyy 3, xzz 3;
+    // y 1, yz 2, xxy 3, yyy 1, yzz 3; z 1, xxz 3, yyz 3, xyz 6, zzz 1)
+    const int rb = kMfmaRow[1][j], rc = kMfmaRow[2][j], rf = kMfmaRow[3][j];
+    const float c2b = j <= 1 ? 2.0f : 6.0f;
+    const float c2c = (j & 1) ? 6.0f : 2.0f;
+    const float c2f = j == 3 ? 12.0f : 4.0f;
+    const float c2d = (j == 0 || j == 3) ? 2.0f : 6.0f;
+    const float sel0 = j == 0 ? 1.0f : 0.0f, sel1 = 1.0f - sel0, sel3 = j == 3 ? 1.0f : 0.0f, sel3c = 1.0f - sel3;
+    float mu0 = 0.0f, nef0 = 0.0f;
+    if constexpr (RAD == kRadRec) {
+        mu0 = a.mu[0];
+        nef0 = -a.eta[0] * kLog2e;
+    }
+    const int64_t w0 = bg.wbase[blk];
+    const int natoms = (int)(bg.wbase[blk + 1] - w0);
+    double Wd[6] = {0, 0, 0, 0, 0, 0};
+    // each wave takes 16 atoms at a time (one per block of four lanes)
+    for (int base = wv * 16; base < natoms; base += kBlock / 4) {
+        const int ia = base + quad;
+        const bool aval = ia < natoms;
+        const int64_t w = w0 + (aval ? ia : natoms - 1);
+        const int64_t p = bg.wperm[w];
+        const int ic = bg.wcell[w];
+        const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
+        const int hp = (iz * HY + iy) * HX + ix;
+        const int ip = hoff[hp] + (int)p;
+        const LdsPos pos{sx, sy, sz, hoff, hp - (HX * HY + HX + 1), HX, HX * HY,
+                         sx[ip] + cw[0], sy[ip] + cw[1], sz[ip] + cw[2], cw[0], cw[1], cw[2]};
+        float Fo[3] = {0.0f, 0.0f, 0.0f};
+        for (int b = 0; b < a.S; ++b) {
+            // this lane's slices of P' (= 2 T sigma' P, folded onto the kept basis)
+            float Ap[K][4];
+            const float* Pb = a.Pbuf + (int64_t)b * K * DR * a.n + w;
+            const float4* g4 = reinterpret_cast<const float4*>(a.dG + p * a.F + (int64_t)b * K * 4);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float* Pk = Pb + (int64_t)k * DR * a.n;
+                const float pa = Pk[(int64_t)j * a.n], pb = Pk[(int64_t)rb * a.n], pc = Pk[(int64_t)rc * a.n],
+                            pf = Pk[(int64_t)rf * a.n];
+                const float4 g = g4[k];
+                // the lane's orders picked arithmetically (0/1 weights), so that
+                // every lane loads the whole dE/dG quadruple with one instruction
+                const float ga = fmaf(sel0, g.x, sel1 * g.y), gbc = fmaf(sel0, g.z, sel1 * g.w),
+                            gf = fmaf(sel3, g.w, sel3c * g.z);
+                // the dropped component (zz, xzz, yzz or zzz) = pa - pb - pc
+                const float pd = c2d * gbc * (pa - pb - pc);
+                // order 0: G = |P_k0|, so P'_k0 = G' sign(P_k0)
+                const float sg = (pa > 0.0f ? 1.0f : 0.0f) - (pa < 0.0f ? 1.0f : 0.0f);
+                const float pa1 = ga * fmaf(sel0, sg, sel1 * 2.0f * pa);
+                Ap[k][0] = pa1 + pd;
+                Ap[k][1] = fmaf(c2b * gbc, pb, -pd);
+                Ap[k][2] = fmaf(c2c * gbc, pc, -pd);
+                Ap[k][3] = c2f * gf * pf;
+            }
+            const int nb = aval ? a.cnt[(int64_t)b * a.n + p] : 0;
+            int nbmax = nb;
+            for (int off = 4; off < 64; off <<= 1) nbmax = max(nbmax, __shfl_xor(nbmax, off));
+            const int64_t row = (p * a.S + b) * a.cap;
+            float w6[6] = {0, 0, 0, 0, 0, 0};
+            // Software pipeline over batches of four pairs: while batch c0 runs,
+            // the displacements of batch c0 + 4 are formed (LDS) and the list
+            // entries of batch c0 + 12 are loaded.  Entry indices are clamped
+            // into the row's slots; lanes past the row's length read the centre
+            // atom (slot ip) and are inactive: unit displacement, zero B.
+            const int cl = a.cap - 1;
+            auto entry = [&](int c, int& q, int& im) {
+                const int cc = min(c, cl);
+                q = a.nbr[row + cc];
+                im = a.img[row + cc];
+            };
+            auto geom = [&](int c, int q, int im, float& gdx, float& gdy, float& gdz, int& gslot, bool& gact) {
+                const bool valid = c < nb;
+                const int qq = valid ? q : (int)p;
+                const int ii = valid ? im : kCentreWord;
+                const float4 xj = pos.fetch(qq, ii, gslot);
+                const float3 dm = pos.disp(xj, ii);
+                gact = valid && dm.x * dm.x + dm.y * dm.y + dm.z * dm.z < a.rc2;  // skin entries carry no force
+                gdx = gact ? dm.x : 1.0f;
+                gdy = gact ? dm.y : 0.0f;
+                gdz = gact ? dm.z : 0.0f;
+            };
+            float dx, dy, dz;
+            int slot;
+            bool act;
+            int qA, iA, qB, iB;
+            entry(j, qA, iA);
+            geom(j, qA, iA, dx, dy, dz, slot, act);
+            entry(4 + j, qA, iA);
+            entry(8 + j, qB, iB);
+            // one batch; (qx, ix) hold the entries of batch c0 + 4 and are
+            // reloaded with those of batch c0 + 12
+            auto batch = [&](int c0, int& qx, int& ix) {
+                float ndx, ndy, ndz;
+                int nslot;
+                bool nact;
+                geom(c0 + 4 + j, qx, ix, ndx, ndy, ndz, nslot, nact);
+                entry(c0 + 12 + j, qx, ix);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float R = r2 * rinv;
+                const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+                float fc = 0.0f, dfc = 0.0f;
+                if constexpr (RAD != kRadTab) {
+                    const float ang = R * a.half_inv_rc;
+                    fc = act ? 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f : 0.0f;
+                    dfc = act ? -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang) : 0.0f;
+                }
+                float B1[K], B2[K];
+                if constexpr (RAD == kRadRec) {
+                    const float t0 = R - mu0;
+                    float ek = act ? __builtin_amdgcn_exp2f(nef0 * t0 * t0) : 0.0f;
+                    float rk = __builtin_amdgcn_exp2f(fmaf(a.rec_a, t0, a.rec_b));
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        B1[k] = ek;
+                        B2[k] = (float)k * ek;
+                        ek *= rk;
+                        rk *= a.rec_c;
+                    }
+                } else if constexpr (RAD == kRadTab) {
+                    tabulated<K, true>(a, R, 0, B1, B2);
+                    const float msk = act ? 1.0f : 0.0f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        B1[k] *= msk;
+                        B2[k] *= msk;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const float tk = R - a.mu[k];
+                        const float e = __builtin_amdgcn_exp2f(-a.eta[k] * kLog2e * tk * tk);
+                        B1[k] = e * fc;
+                        B2[k] = e * fmaf(-2.0f * a.eta[k] * tk, fc, dfc);
+                    }
+                }
+                f32x4 acc1[4], acc2[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc1[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                    acc2[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc1[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ap[k][q], B1[k], acc1[q], 0, 0, 0);
+                        acc2[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ap[k][q], B2[k], acc2[q], 0, 0, 0);
+                    }
+                }
+                float V1[DR], V2[DR];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        V1[kMfmaRow[q][i]] = acc1[q][i];
+                        V2[kMfmaRow[q][i]] = acc2[q][i];
+                    }
+                float Mv[DR];
+                reduced_monomials<3>(ux, uy, uz, Mv);
+                float S0 = 0.0f, S1 = 0.0f;
+#pragma unroll
+                for (int d = 0; d < DR; ++d) {
+                    S0 = fmaf(Mv[d], V1[d], S0);
+                    S1 = fmaf(Mv[d], V2[d], S1);
+                }
+                float Ax, Ay, Az, Bu;
+                reduced_moment_adjoint<3>(ux, uy, uz, V1, Mv, Ax, Ay, Az, Bu);
+                float sr, rf;
+                if constexpr (RAD == kRadRec) {
+                    sr = fmaf(a.rec_m2eta * fc, fmaf(-a.rec_delta, S1, (R - mu0) * S0), dfc * S0);
+                    rf = rinv * fc;
+                } else {
+                    sr = S1;
+                    rf = rinv;
+                }
+                if (act) {
+                    const float gx = sr * ux + rf * (Ax - ux * Bu);
+                    const float gy = sr * uy + rf * (Ay - uy * Bu);
+                    const float gz = sr * uz + rf * (Az - uz * Bu);
+                    Fo[0] += gx;
+                    Fo[1] += gy;
+                    Fo[2] += gz;
+                    sink(slot, gx, gy, gz);
+                    virial_add(w6, dx, dy, dz, gx, gy, gz);
+                }
+                dx = ndx;
+                dy = ndy;
+                dz = ndz;
+                slot = nslot;
+                act = nact;
+            };
+            int c0 = 0;
+            for (; c0 + 8 <= nbmax; c0 += 8) {
+                batch(c0, qA, iA);
+                batch(c0 + 4, qB, iB);
+            }
+            if (c0 < nbmax) batch(c0, qA, iA);
+            if (c0 + 4 < nbmax) batch(c0 + 4, qB, iB);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Wd[i] += (double)w6[i];
+        }
+        // the atom's own force: its four lanes' sums, added in a fixed order
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            Fo[i] += __shfl_xor(Fo[i], 1);
+            Fo[i] += __shfl_xor(Fo[i], 2);
+        }
+        if (aval && j == 0) {
+            atomicAdd(&sF[ip], to_fixed(Fo[0]));
+            atomicAdd(&sF[bg.hmax + ip], to_fixed(Fo[1]));
+            atomicAdd(&sF[2 * bg.hmax + ip], to_fixed(Fo[2]));
+        }
+    }
+    __syncthreads();
+    for (int hc = wv; hc < nh; hc += kBlock / 64) {
+        const int lo = h_base[hc], cnt = h_base[hc + 1] - lo;
+        for (int k = lane; k < cnt; k += 64) {
+            const int64_t q = h_first[hc] + k;
+            const unsigned long long fx = sF[lo + k], fy = sF[bg.hmax + lo + k], fz = sF[2 * bg.hmax + lo + k];
+            if (fx) atomicAdd(&bg.F[3 * q + 0], fx);
+            if (fy) atomicAdd(&bg.F[3 * q + 1], fy);
+            if (fz) atomicAdd(&bg.F[3 * q + 2], fz);
+        }
+    }
+    block_virial(Wd, red, a.vir + (int64_t)blockIdx.x * kVirDoubles);
+}
+
 // ---- work order ----------------------------------------------------------
 //
 // Rows of one wave run in lockstep, so a wave costs the longest of its rows.
@@ -1125,6 +1417,22 @@ BlockedFn select_blocked_r(int kc, int M, bool pair2) {
         default: return pick_blocked<8, RAD>(M, pair2);
     }
 }
+template <int RAD>
+BlockedFn select_mfma_r(int kq) {
+    switch (kq) {
+        case 2: return k_adjoint_mfma<2, RAD>;
+        case 3: return k_adjoint_mfma<3, RAD>;
+        default: return k_adjoint_mfma<4, RAD>;
+    }
+}
+BlockedFn select_mfma(int rad, int kq) {
+    return rad == kRadTab ? select_mfma_r<kRadTab>(kq)
+                          : rad == kRadRec ? select_mfma_r<kRadRec>(kq) : select_mfma_r<kRadDirect>(kq);
+}
+// The matrix-core adjoint takes M = 3 and K = 8, 12 or 16 (K / 4 slices of
+// P' per lane stay in registers).
+bool mfma_adjoint(const tmd_model* m) { return m->M == 3 && m->K % 4 == 0 && m->K >= 8 && m->K <= 16; }
+
 BlockedFn select_blocked(int rad, int kc, int M, bool pair2) {
     return rad == kRadTab ? select_blocked_r<kRadTab>(kc, M, pair2)
                           : rad == kRadRec ? select_blocked_r<kRadRec>(kc, M, pair2)
@@ -1324,7 +1632,7 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
         a.nch_log2 = log2_int(m->K / kca);
         const bool pair2 = m->K / kca == 2;  // two chunk lanes per atom share the pair geometry
         const int rad = m->tab ? kRadTab : (m->rec ? kRadRec : kRadDirect);
-        auto fn = select_blocked(rad, kca, m->M, pair2);
+        auto fn = mfma_adjoint(m) ? select_mfma(rad, m->K / 4) : select_blocked(rad, kca, m->M, pair2);
         {
             ProfScope ps_(ctx, "adjoint");
             fn<<<grid, kBlock, blocked_lds_bytes(bg.hmax), ctx->stream>>>(a, bg);
