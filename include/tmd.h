@@ -218,6 +218,25 @@ tmd_status tmd_energy_forces(tmd_context* ctx, const tmd_model* model, const tmd
 tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* model, const tmd_system_view* sys,
                                    const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces);
 
+/* Energy, forces and virial of several systems in one launch chain (the
+ * continuous batching of many small systems a server sees; same quantities as
+ * tmd_energy_forces_async, Sec. III.A).  systems[s] and lists[s] as for
+ * tmd_energy_forces_async (each list built for its system, positions moved by
+ * less than skin/2 since; the lists are only read); 1..4096 systems.  The
+ * lists are merged into one over the concatenated atoms (each system padded to
+ * a multiple of 256 atoms; a pair's image shift uses its system's box) and the
+ * descriptor, MLP and adjoint run once over all of them, with the adjoint's
+ * force scatter by device atomics (fixed point, so each system's forces do
+ * not depend on what it was batched with).  Outputs: totals7 device FP64
+ * [n_systems][7] = (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz) per system, summed in
+ * FP64 with compensation; forces[s] device [n_s][3] FP32, system s's atom
+ * order.  Errors: as tmd_energy_forces_async for each system; a null array or
+ * a count outside 1..4096 -> TMD_ERR_INVALID_ARGUMENT.  Does not synchronise
+ * (the host table of systems is copied before the call returns). */
+tmd_status tmd_energy_forces_batch(tmd_context* ctx, const tmd_model* model, int32_t n_systems,
+                                   const tmd_system_view* systems, const tmd_nlist* const* lists, double* totals7,
+                                   float* const* forces);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * evaluation as tmd_energy_forces_async, with every intermediate (descriptors,

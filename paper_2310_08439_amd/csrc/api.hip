@@ -742,6 +742,86 @@ tmd_status tmd_energy_forces_async(tmd_context* ctx, const tmd_model* m, const t
     return run_energy_forces(ctx, m, sys, nl, totals7, atom_energy, forces);
 }
 
+tmd_status tmd_energy_forces_batch(tmd_context* ctx, const tmd_model* m, int32_t n_systems,
+                                   const tmd_system_view* systems, const tmd_nlist* const* lists, double* totals7,
+                                   float* const* forces) {
+    if (!ctx) return TMD_ERR_INVALID_ARGUMENT;
+    if (n_systems <= 0 || n_systems > kMaxBatchSystems || !systems || !lists || !totals7 || !forces)
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT,
+                    "tmd_energy_forces_batch: 1.." + std::to_string(kMaxBatchSystems) +
+                        " systems with non-null views, lists, totals and force arrays");
+    std::vector<BatchSeg> segs((size_t)n_systems);
+    int64_t N = 0, counts[kMaxSpecies] = {0};
+    int cap = 4;
+    for (int s = 0; s < n_systems; ++s) {
+        tmd_status st = check_eval(ctx, m, &systems[s], lists[s]);
+        if (st != TMD_OK) return st;
+        if (!forces[s]) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "null force array");
+        const tmd_nlist* nl = lists[s];
+        BatchSeg& g = segs[s];
+        g.off = N;
+        g.n = nl->n;
+        g.npad = (nl->n + kBlock - 1) / kBlock * kBlock;
+        N += g.npad;
+        g.cap = nl->cap;
+        cap = std::max(cap, nl->cap);
+        for (int a = 0; a < 3; ++a) g.L[a] = systems[s].box[a];
+        g.pos = systems[s].pos;
+        g.perm = nl->perm;
+        g.shift = nl->shift;
+        g.nbr = nl->nbr;
+        g.img = nl->img;
+        g.cnt = nl->cnt;
+        g.sp_idx = nl->sp_idx;
+        for (int b = 0; b <= m->S; ++b) g.sp_off[b] = nl->sp_off[b];
+        for (int b = 0; b < m->S; ++b) counts[b] += nl->sp_off[b + 1] - nl->sp_off[b];
+        g.forces = forces[s];
+    }
+    if (N >= (int64_t)1 << 31) return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "batch of more than 2^31-1 atoms");
+    tmd_nlist v;  // the merged list: a view over workspace arrays
+    v.ctx = ctx;
+    v.nmax = v.n = N;
+    v.S = m->S;
+    v.cap = cap;
+    v.built = true;
+    v.rlist = m->rcut;
+    v.sp_off[0] = 0;
+    for (int b = 0; b < m->S; ++b) {
+        v.sp_count[b] = counts[b];
+        v.sp_off[b + 1] = v.sp_off[b] + counts[b];
+    }
+    for (int b = 0; b < m->S; ++b) {
+        int64_t at = v.sp_off[b];
+        for (auto& g : segs) {
+            g.dst_off[b] = at;
+            at += g.sp_off[b + 1] - g.sp_off[b];
+        }
+    }
+    const int nch = m->K / m->kc;  // chunk lanes per atom in the adjoint: 256 / nch atoms per virial partial
+    hipError_t e = hipSuccess;
+    BatchSeg* dsegs = (BatchSeg*)ctx->ws.get("batch.segs", sizeof(BatchSeg) * segs.size(), &e);
+    v.xs = (double4*)ctx->ws.get("batch.xs", sizeof(double4) * N, &e);
+    double4* boxes = (double4*)ctx->ws.get("batch.boxes", sizeof(double4) * N, &e);
+    v.boxes = boxes;
+    v.nbr = (int32_t*)ctx->ws.get("batch.nbr", sizeof(int32_t) * (size_t)N * m->S * cap, &e);
+    v.img = (int32_t*)ctx->ws.get("batch.img", sizeof(int32_t) * (size_t)N * m->S * cap, &e);
+    v.cnt = (int32_t*)ctx->ws.get("batch.cnt", sizeof(int32_t) * (size_t)N * m->S, &e);
+    v.sp_idx = (int32_t*)ctx->ws.get("batch.sp_idx", sizeof(int32_t) * (size_t)N, &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch workspace allocation");
+    EvalBuffers b;
+    tmd_status st = eval_buffers(ctx, m, &v, &b);
+    if (st != TMD_OK) return st;
+    // pageable source: the copy is staged before the call returns
+    TMD_HIP(ctx, hipMemcpyAsync(dsegs, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice,
+                                ctx->stream));
+    if ((st = launch_batch_merge(ctx, dsegs, n_systems, &v, boxes)) != TMD_OK) return st;
+    if ((st = launch_descriptors(ctx, m, &v, b.G, b.P)) != TMD_OK) return st;
+    if ((st = launch_mlp(ctx, m, species_groups(&v), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
+    int nvir = 0;
+    if ((st = launch_adjoint(ctx, m, &v, b.dG, b.P, b.Fq, b.vir, &nvir)) != TMD_OK) return st;
+    return launch_batch_finalize(ctx, dsegs, n_systems, N, b.Fq, b.Ei, b.vir, kBlock / nch, totals7);
+}
+
 tmd_status tmd_energy_forces_noalloc(tmd_context* ctx, const tmd_model* m, const tmd_system_view* sys,
                                      const tmd_nlist* nl, double* totals7, float* atom_energy, float* forces) {
     if (!ctx) return TMD_ERR_INVALID_ARGUMENT;

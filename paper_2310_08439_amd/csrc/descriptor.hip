@@ -47,6 +47,9 @@ struct PathArgs {
     float tab_inv;
     int tab_n;
     double L[3];
+    // per-atom box edges (x, y, z) when the atoms of several systems share one
+    // list (tmd_energy_forces_batch); nullptr: every atom's box is L
+    const double4* boxes;
     const double4* xs;
     const int32_t* nbr;
     const int32_t* img;
@@ -371,7 +374,8 @@ __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a,
         mu[kk] = a.mu[ch * KC + kk];
         nef[kk] = -a.eta[ch * KC + kk] * kLog2e;
     }
-    const GlobalPos pos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]};
+    const double4 Lp = a.boxes ? a.boxes[p] : make_double4(a.L[0], a.L[1], a.L[2], 0.0);
+    const GlobalPos pos{a.xs, Lp.x, Lp.y, Lp.z, a.xs[p]};
     for (int b = 0; b < a.S; ++b) {
         const int b0 = b & ~1;                // species b0 and b0 + 1 are staged together
         const int nsp = min(2, a.S - b0);     // species in this pair
@@ -734,7 +738,8 @@ __global__ void __launch_bounds__(256) k_adjoint_atomic(PathArgs a, unsigned lon
     if (w < a.n) {
         const int64_t p = a.wperm ? a.wperm[w] : w;
         float Fo[3] = {0.0f, 0.0f, 0.0f};
-        adjoint_atom<KC, M, RAD>(a, p, w, ch, nch, Wd, Fo, GlobalPos{a.xs, a.L[0], a.L[1], a.L[2], a.xs[p]},
+        const double4 Lp = a.boxes ? a.boxes[p] : make_double4(a.L[0], a.L[1], a.L[2], 0.0);
+        adjoint_atom<KC, M, RAD>(a, p, w, ch, nch, Wd, Fo, GlobalPos{a.xs, Lp.x, Lp.y, Lp.z, a.xs[p]},
                                  [&](int q, float gx, float gy, float gz) {
             atomicAdd(&F[3 * (int64_t)q + 0], to_fixed(-gx));
             atomicAdd(&F[3 * (int64_t)q + 1], to_fixed(-gy));
@@ -1463,6 +1468,7 @@ PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
     a.tab_inv = m->tab ? (float)(1.0 / m->tab_delta) : 0.0f;
     a.tab_n = m->tab_n;
     for (int q = 0; q < 3; ++q) a.L[q] = nl->box[q];
+    a.boxes = nl->boxes;
     a.xs = nl->xs;
     a.nbr = nl->nbr;
     a.img = nl->img;

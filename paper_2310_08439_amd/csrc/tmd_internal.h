@@ -231,6 +231,7 @@ struct tmd_nlist {
     int32_t* perm = nullptr;     // [n]   sorted -> original index
     int32_t* shift = nullptr;    // [n][3] wrap shift: x_wrapped = x + shift * L
     double4* xs = nullptr;       // [n]   positions used by the kernels
+    const double4* boxes = nullptr;  // [n] per-atom box edges of a merged multi-system list (else box)
     int32_t* sp = nullptr;       // [n]   species
     int32_t* nbr = nullptr;      // [n][S][cap] neighbour (sorted index), row-major per atom
     int32_t* img = nullptr;      // [n][S][cap] image word (pack_img)
@@ -402,6 +403,33 @@ tmd_status energy_forces_gated(tmd_context* ctx, const tmd_model* m, const tmd_s
 // Work order for the descriptor and adjoint (see tmd_nlist::wo_valid); called
 // at the end of every successful list build.
 tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl);
+
+constexpr int kMaxBatchSystems = 4096;
+// Several systems' lists merged into one (tmd_energy_forces_batch): segment s
+// covers combined atoms [off, off + n) followed by padding up to off + npad
+// (npad a multiple of 256).
+struct BatchSeg {
+    int64_t off = 0, n = 0, npad = 0;
+    int cap = 0;
+    double L[3] = {0, 0, 0};
+    const double* pos = nullptr;     // system positions [n][3], original order
+    const int32_t* perm = nullptr;   // the system list's sorted -> original index
+    const int32_t* shift = nullptr;  // and its wrap shifts
+    const int32_t* nbr = nullptr;    // its rows (unpruned; skin entries are skipped by the kernels)
+    const int32_t* img = nullptr;
+    const int32_t* cnt = nullptr;
+    const int32_t* sp_idx = nullptr;  // its species grouping
+    int64_t sp_off[kMaxSpecies + 1] = {0};
+    int64_t dst_off[kMaxSpecies] = {0};  // first slot of its species-b atoms in the merged grouping
+    float* forces = nullptr;          // output [n][3], original order
+};
+// Merged positions, per-atom boxes, rows and species grouping into vnl's arrays.
+tmd_status launch_batch_merge(tmd_context* ctx, const BatchSeg* segs, int nseg, tmd_nlist* vnl, double4* boxes);
+// Forces to each segment's output and per-segment totals [nseg][7]; the adjoint
+// wrote one virial partial per vir_atoms combined atoms.
+tmd_status launch_batch_finalize(tmd_context* ctx, const BatchSeg* segs, int nseg, int64_t N,
+                                 const unsigned long long* Fq, const float* Ei, const double* vir, int vir_atoms,
+                                 double* totals);
 
 // Upper bound on the virial partials the adjoint writes.
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl);

@@ -35,7 +35,7 @@ EXPORTS = (
     "tmd_nlist_create", "tmd_nlist_destroy", "tmd_build_neighbors", "tmd_nlist_export", "tmd_nlist_capacity",
     "tmd_nlist_stats",
     "tmd_descriptors", "tmd_energy_forces", "tmd_energy_forces_async", "tmd_energy_forces_noalloc",
-    "tmd_noalloc_scratch_bytes",
+    "tmd_noalloc_scratch_bytes", "tmd_energy_forces_batch",
     "tmd_profile_enable", "tmd_profile_reset", "tmd_profile_read",
     "tmd_model_get_params", "tmd_batch_create", "tmd_batch_destroy", "tmd_train_step", "tmd_batch_read",
     "tmd_serve_create", "tmd_serve_add_system", "tmd_serve_submit", "tmd_serve_poll", "tmd_serve_wait",
@@ -167,6 +167,7 @@ def load_library(path: str = LIB_PATH):
     L.tmd_energy_forces_async.argtypes = [vp, vp, P(SystemView), vp, vp, vp, vp]
     L.tmd_energy_forces_noalloc.argtypes = [vp, vp, P(SystemView), vp, vp, vp, vp]
     L.tmd_noalloc_scratch_bytes.argtypes = []
+    L.tmd_energy_forces_batch.argtypes = [vp, vp, i32, P(SystemView), P(vp), vp, P(vp)]
     L.tmd_noalloc_scratch_bytes.restype = i64
     L.tmd_profile_enable.argtypes = [vp, ctypes.c_int]
     L.tmd_profile_reset.argtypes = [vp]
@@ -463,6 +464,20 @@ def energy_forces_noalloc(ctx: Context, model: Model, pos, species, box, nl: Nei
     v = system_view(pos, species, box)
     ctx.check(ctx.lib.tmd_energy_forces_noalloc(ctx.h, model.h, ctypes.byref(v), nl.h, _ptr(totals7),
                                                 _ptr(atom_energy), _ptr(forces)), "tmd_energy_forces_noalloc")
+
+
+def energy_forces_batch(ctx: Context, model: Model, systems, lists, totals7, forces) -> None:
+    """tmd_energy_forces_batch: systems is a sequence of (pos, species, box),
+    lists the matching NeighborLists, totals7 a [n, 7] float64 device tensor,
+    forces a sequence of [n_s, 3] float32 device tensors."""
+    n = len(systems)
+    if len(lists) != n or len(forces) != n:
+        raise ValueError("systems, lists and forces must have the same length")
+    views = (SystemView * n)(*[system_view(p, s, b) for p, s, b in systems])
+    hl = (ctypes.c_void_p * n)(*[nl.h for nl in lists])
+    hf = (ctypes.c_void_p * n)(*[_ptr(f) for f in forces])
+    ctx.check(ctx.lib.tmd_energy_forces_batch(ctx.h, model.h, n, views, hl, _ptr(totals7), hf),
+              "tmd_energy_forces_batch")
 
 
 def virial_matrix(w6) -> np.ndarray:
