@@ -207,17 +207,19 @@ def train_leg(tmd, torch, ctx, steps: int, warmup: int) -> dict:
             "batch_setup_ms": round(t_create * 1e3, 2), "loss_after_warmup_and_steps": last[0]}
 
 
-def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: float, slots: int) -> dict:
+def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: float, slots: int,
+              batch_atoms: int = 4096) -> dict:
     """Open-loop Poisson stream against the serving loop: systems are fcc
     (species 0, a = 3.61) or 50/50 bcc alloy (a = 3.16) cells with atom counts
     log-uniform in 64..262,144 (nearest cubic supercell), a pool of `pool`
     resident systems; requests are 50/50 energy+forces or 10 velocity-Verlet
-    steps of 1 fs from Maxwell-Boltzmann velocities at 300 K; BF16 MLP."""
+    steps of 1 fs from Maxwell-Boltzmann velocities at 300 K; BF16 MLP.  The
+    same systems and request stream are served twice: with energy-and-force
+    requests on systems of at most batch_atoms atoms evaluated together
+    (reported) and without ("without_batching")."""
     import numpy as np
     from paper_2310_08439_amd import inputs
     rng = np.random.default_rng(4)
-    model = tmd.Model(ctx, spec, precision=tmd.BF16_MLP)
-    srv = tmd.Server(model, max_slots=slots, max_atoms=262144, skin=1.0)
     systems = []
     for q in range(pool):
         target = math.exp(rng.uniform(math.log(64), math.log(262144)))
@@ -229,27 +231,56 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
             c = min(50, max(2, int(round((target / 2) ** (1 / 3)))))
             s = inputs.make_system("bcc", 3.16, (c, c, c), 0.08, 2, seed=1000 + q, masses=[183.84, 95.95])
             masses = np.array([183.84, 95.95])
-        sid = srv.add_system(s.pos, s.species, s.box, masses)
-        systems.append((sid, s.n, np.where(s.species == 0, masses[0], masses[1])))
+        systems.append((s, masses, np.where(s.species == 0, masses[0], masses[1])))
     total = n_warmup + n_requests
     plan = []
     t = 0.0
     for k in range(total):
         t += rng.exponential(1.0 / rate)
-        sid, n, m = systems[int(rng.integers(pool))]
+        q = int(rng.integers(pool))
         md = rng.random() < 0.5
-        vel = inputs.maxwell_boltzmann(m, 300.0, seed=int(rng.integers(1 << 31))) if md else None
-        plan.append((t, sid, n, md, vel))
+        vel = inputs.maxwell_boltzmann(systems[q][2], 300.0, seed=int(rng.integers(1 << 31))) if md else None
+        plan.append((t, q, md, vel))
+    # closed loop: a burst of requests drawn the same way, all queued at once,
+    # so that every slot stays busy; peak atom-steps/s over the burst
+    burst = []
+    for k in range(max(1, n_requests // 3)):
+        q = int(rng.integers(pool))
+        md = rng.random() < 0.5
+        vel = inputs.maxwell_boltzmann(systems[q][2], 300.0, seed=int(rng.integers(1 << 31))) if md else None
+        burst.append((q, md, vel))
+    # small systems only: every system of at most batch_atoms atoms gets four
+    # energy-and-force requests, all queued at once (shuffled)
+    small = [q for q, (s, _, _) in enumerate(systems) if s.n <= batch_atoms]
+    small_burst = [small[k] for k in rng.permutation(np.repeat(np.arange(len(small)), 4))]
+    runs = {}
+    for ba in (batch_atoms, 0):
+        runs[ba] = _serve_run(tmd, ctx, spec, systems, plan, burst, small_burst, n_warmup, slots, ba)
+        print(f"[bench] serving batch_atoms={ba}: p50 {runs[ba]['p50_latency_ms']} ms, "
+              f"saturation {runs[ba]['closed_loop_saturation']['atom_steps_per_s']:.3g} atom-steps/s",
+              file=sys.stderr, flush=True)
+    sizes = np.array([s.n for (s, _, _) in systems])
+    out = {"workload": f"Poisson {rate:g} req/s, {n_requests} requests after {n_warmup} warm-up, pool of {pool} "
+                       f"resident fcc/bcc systems of {sizes.min()}..{sizes.max()} atoms (mean {sizes.mean():.0f}), "
+                       f"50% E+F / 50% 10 VV steps, {slots} slots, BF16 MLP, E+F on systems of <= {batch_atoms} "
+                       f"atoms batched"}
+    out.update(runs[batch_atoms])
+    out["without_batching"] = runs[0]
+    return out
+
+
+def _serve_run(tmd, ctx, spec, systems, plan, burst, small_burst, n_warmup, slots, batch_atoms) -> dict:
+    import numpy as np
+    model = tmd.Model(ctx, spec, precision=tmd.BF16_MLP)
+    srv = tmd.Server(model, max_slots=slots, max_atoms=262144, skin=1.0, batch_atoms=batch_atoms)
+    ids = [srv.add_system(s.pos, s.species, s.box, masses) for (s, masses, _) in systems]
     tickets = []
     start = time.perf_counter()
-    for (ta, sid, n, md, vel) in plan:
+    for (ta, q, md, vel) in plan:
         delay = start + ta - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        if md:
-            tickets.append(srv.submit(sid, tmd.REQ_MD, 10, 1.0, vel))
-        else:
-            tickets.append(srv.submit(sid))
+        tickets.append(srv.submit(ids[q], tmd.REQ_MD, 10, 1.0, vel) if md else srv.submit(ids[q]))
     results = []
     for tk in tickets:
         r = srv.wait(tk, 300.0)
@@ -257,16 +288,8 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
             raise RuntimeError(f"serving request failed: {r}")
         results.append(r)
         srv.release(tk)
-    # closed loop: a burst of requests drawn the same way, all queued at once,
-    # so that every slot stays busy; peak atom-steps/s over the burst
-    burst = []
-    for k in range(max(1, n_requests // 3)):
-        sid, n, m = systems[int(rng.integers(pool))]
-        md = rng.random() < 0.5
-        vel = inputs.maxwell_boltzmann(m, 300.0, seed=int(rng.integers(1 << 31))) if md else None
-        burst.append((sid, md, vel))
     t0 = time.perf_counter()
-    btk = [srv.submit(sid, tmd.REQ_MD, 10, 1.0, vel) if md else srv.submit(sid) for (sid, md, vel) in burst]
+    btk = [srv.submit(ids[q], tmd.REQ_MD, 10, 1.0, vel) if md else srv.submit(ids[q]) for (q, md, vel) in burst]
     bres = []
     for tk in btk:
         r = srv.wait(tk, 300.0)
@@ -277,13 +300,36 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
     bwall = time.perf_counter() - t0
     saturation = {"requests": len(burst), "wall_s": round(bwall, 3),
                   "atom_steps_per_s": round(sum(r["n_atoms"] * max(1, r["n_steps"]) for r in bres) / bwall, 1)}
+    t0 = time.perf_counter()
+    stk = [srv.submit(ids[q]) for q in small_burst]
+    sres = []
+    for tk in stk:
+        r = srv.wait(tk, 300.0)
+        if r is None or r["status"] != 0:
+            raise RuntimeError(f"serving request failed: {r}")
+        sres.append(r)
+        srv.release(tk)
+    swall = time.perf_counter() - t0
+    slat = np.array([r["t_done"] - r["t_submit"] for r in sres]) * 1e3
+    ssz = np.array([r["batch_size"] for r in sres])
+    small_systems = {"requests": len(sres), "wall_s": round(swall, 4),
+                     "requests_per_s": round(len(sres) / swall, 1),
+                     "atom_steps_per_s": round(sum(r["n_atoms"] for r in sres) / swall, 1),
+                     "p50_ms": round(float(np.percentile(slat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(slat, 99)), 3),
+                     "mean_batch_size": round(float(ssz.mean()), 2),
+                     # the server's own span (first start to last completion) and
+                     # service time per request; the client's submit and wait calls
+                     # (Python, ~30 us per request) bound requests_per_s here
+                     "server_span_s": round(max(r["t_done"] for r in sres) - min(r["t_start"] for r in sres), 4),
+                     "mean_service_ms": round(float(np.mean([r["t_done"] - r["t_start"] for r in sres])) * 1e3, 3)}
     mem, peak = srv.memory()
     srv.close()
+    model.close()
     meas = results[n_warmup:]
     lat = np.array([r["t_done"] - r["t_submit"] for r in meas]) * 1e3
     wall = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
     atom_steps = sum(r["n_atoms"] * max(1, r["n_steps"]) for r in meas)
-    sizes = np.array([n for (_, n, _) in systems])
     # latency per system-size bucket and request kind
     buckets = {}
     natoms = np.array([r["n_atoms"] for r in meas])
@@ -298,15 +344,16 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
                             "p99_ms": round(float(np.percentile(lat[sel], 99)), 3)}
     bsteps = sum(r["n_atoms"] * max(1, r["n_steps"]) for r in bres)
     saturation["ns_per_atom_step"] = round(bwall / bsteps * 1e9, 3)
-    return {"workload": f"Poisson {rate:g} req/s, {n_requests} requests after {n_warmup} warm-up, pool of {pool} "
-                        f"resident fcc/bcc systems of {sizes.min()}..{sizes.max()} atoms (mean {sizes.mean():.0f}), "
-                        f"50% E+F / 50% 10 VV steps, {slots} slots, BF16 MLP",
-            "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+    bsz = np.array([r["batch_size"] for r in meas + bres])
+    return {"p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_latency_ms": round(float(lat.mean()), 3),
             "atom_steps_per_s": round(atom_steps / wall, 1),
             "closed_loop_saturation": saturation,
+            "small_system_ef_burst": small_systems,
             "latency_by_size": buckets,
+            "requests_batched": round(float((bsz > 1).mean()), 3),
+            "mean_batch_size_of_batched": round(float(bsz[bsz > 1].mean()), 2) if (bsz > 1).any() else None,
             "device_bytes_peak": int(peak)}
 
 

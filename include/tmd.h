@@ -421,7 +421,12 @@ typedef struct tmd_server tmd_server;
  * largest system accepted, which sizes each slot's workspace (0: 262,144);
  * skin: neighbour-list skin of MD runs (A), lists are rebuilt when an atom has
  * moved more than skin/2 since the last build; capacity: initial per-species
- * list capacity (0: from the density). */
+ * list capacity (0: from the density); batch_atoms: energy-and-force
+ * requests on systems of at most this many atoms whose lists are resident are
+ * served together: a slot that takes one also takes the other such requests
+ * queued on idle systems (the first queued request of each system, up to 64
+ * systems and max_atoms atoms) and evaluates them with one
+ * tmd_energy_forces_batch call (0: off). */
 typedef struct {
     int64_t hbm_budget_bytes;
     int32_t max_slots;
@@ -429,7 +434,7 @@ typedef struct {
     int64_t max_atoms;
     double skin;
     int32_t capacity;
-    int32_t reserved;
+    int32_t batch_atoms;
 } tmd_serve_opts;
 
 typedef enum { TMD_REQ_ENERGY_FORCES = 0, TMD_REQ_MD = 1 } tmd_request_kind;
@@ -453,7 +458,8 @@ typedef struct {
  * final positions); kinetic: MD final kinetic energy (103.6427 * m v^2 / 2, eV);
  * virial: at the final positions; t_submit, t_start, t_done: seconds on the
  * host steady clock since the server was created; rebuilds: neighbour-list
- * builds the request made. */
+ * builds the request made; batch_size: requests evaluated in the same launch
+ * chain as this one (1: alone, 0: rejected; see batch_atoms). */
 typedef struct {
     int32_t status;
     int32_t kind;
@@ -467,6 +473,8 @@ typedef struct {
     double t_submit;
     double t_start;
     double t_done;
+    int32_t batch_size;
+    int32_t reserved;
 } tmd_result;
 
 /* The server keeps `model` (not copied: it must outlive the server and not

@@ -315,6 +315,88 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
     return TMD_OK;
 }
 
+// Energy-and-force requests of several small systems with resident lists in
+// one tmd_energy_forces_batch call (lists rebuilt first where positions have
+// moved beyond skin/2).  outs[i] gets request i's result.
+tmd_status run_batch(tmd_server* sv, tmd_context* ctx, const std::vector<System*>& systems,
+                     std::vector<Finished>& outs) {
+    const tmd_model* m = sv->model;
+    const int nb = (int)systems.size();
+    std::vector<tmd_system_view> views((size_t)nb);
+    std::vector<const tmd_nlist*> lists((size_t)nb);
+    std::vector<float*> forces((size_t)nb);
+    std::vector<int> rebuilds((size_t)nb, 0);
+    std::vector<size_t> foff((size_t)nb + 1, 0);  // each system's slice of one staging array
+    for (int i = 0; i < nb; ++i) foff[i + 1] = foff[i] + 3 * (size_t)systems[i]->n;
+    hipError_t e = hipSuccess;
+    // totals [nb][7], then the forces of every system (an MD request recomputes
+    // its starting forces, so the resident force arrays need not be written)
+    double* tot = (double*)ctx->ws.get("serve.batch_out", sizeof(double) * 7 * (size_t)nb + 4 * foff[nb], &e);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch outputs");
+    float* fst = reinterpret_cast<float*>(tot + 7 * (size_t)nb);
+    tmd_status st;
+    for (int i = 0; i < nb; ++i) {
+        System* sys = systems[i];
+        if (!sys->nl_valid && (st = build_list(sv, ctx, sys, &rebuilds[i])) != TMD_OK) return st;
+        tmd_system_view& v = views[i];
+        v.n_atoms = sys->n;
+        v.pos = sys->x;
+        v.species = sys->sp;
+        for (int a = 0; a < 3; ++a) v.box[a] = sys->box[a];
+        lists[i] = sys->nl;
+        forces[i] = fst + foff[i];
+    }
+    if ((st = tmd_energy_forces_batch(ctx, m, nb, views.data(), lists.data(), tot, forces.data())) != TMD_OK)
+        return st;
+    std::vector<double> h((size_t)7 * nb + (4 * foff[nb] + 7) / 8);
+    TMD_HIP(ctx, hipMemcpyAsync(h.data(), tot, sizeof(double) * 7 * (size_t)nb + 4 * foff[nb], hipMemcpyDeviceToHost,
+                                ctx->stream));
+    TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const float* hf = reinterpret_cast<const float*>(h.data() + 7 * (size_t)nb);
+    for (int i = 0; i < nb; ++i) outs[i].F.assign(hf + foff[i], hf + foff[i + 1]);
+    for (int i = 0; i < nb; ++i) {
+        tmd_result& r = outs[i].res;
+        r.energy = h[7 * (size_t)i];
+        for (int j = 0; j < 6; ++j) r.virial[j] = h[7 * (size_t)i + 1 + j];
+        r.kinetic = 0.0;
+        r.rebuilds = rebuilds[i];
+        outs[i].epot.assign(1, r.energy);
+    }
+    return TMD_OK;
+}
+
+// Systems of at most this many atoms (and padded batches of at most
+// kServeBatchAtoms atoms, kServeBatchSystems systems) are batched.
+constexpr int kServeBatchSystems = 64;
+constexpr int64_t kServeBatchAtoms = 65536;
+
+// With `first` (an energy-and-force request on a small system with a resident
+// list) admitted, also take the other such requests from the queue: the first
+// queued request of each idle system.  Caller holds sv->mu.
+void pick_batch(tmd_server* sv, System* first, std::vector<Pending>& reqs, std::vector<System*>& systems) {
+    const int64_t lim = std::min<int64_t>(sv->opts.max_atoms, kServeBatchAtoms);
+    int64_t atoms = (first->n + kBlock - 1) / kBlock * kBlock;
+    std::set<int64_t> seen{first->id};
+    for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)systems.size() < kServeBatchSystems;) {
+        const int64_t sid = it->req.system_id;
+        System* s2 = sv->systems.at(sid).get();
+        const int64_t padded = (s2->n + kBlock - 1) / kBlock * kBlock;
+        const bool take = !seen.count(sid) && it->req.kind == TMD_REQ_ENERGY_FORCES && !s2->busy && s2->nl &&
+                          s2->n <= sv->opts.batch_atoms && atoms + padded <= lim;
+        seen.insert(sid);  // later requests of this system wait for the first one
+        if (!take) {
+            ++it;
+            continue;
+        }
+        atoms += padded;
+        s2->busy = true;
+        sv->running.insert(it->ticket);
+        reqs.push_back(std::move(*it));
+        systems.push_back(s2);
+        it = sv->queue.erase(it);
+    }
+}
+
 // Next admissible request (queue order, one per system at a time, list memory
 // within budget after evicting idle lists).  Caller holds sv->mu.
 bool pick(tmd_server* sv, Pending* out, System** sys_out, bool* rejected, Finished* rej) {
@@ -372,6 +454,38 @@ bool pick(tmd_server* sv, Pending* out, System** sys_out, bool* rejected, Finish
     return false;
 }
 
+// Run a batch taken by pick_batch and publish each request's result.
+void serve_batch(tmd_server* sv, tmd_context* ctx, std::vector<Pending>& reqs, std::vector<System*>& systems) {
+    const double t_start = now_s(sv->t0);
+    std::vector<Finished> outs(reqs.size());
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        Finished& f = outs[i];
+        f.res.kind = reqs[i].req.kind;
+        f.res.system_id = systems[i]->id;
+        f.res.n_atoms = systems[i]->n;
+        f.res.n_steps = 0;
+        f.res.t_submit = reqs[i].t_submit;
+        f.res.t_start = t_start;
+        f.res.batch_size = (int32_t)reqs.size();
+    }
+    const tmd_status st = run_batch(sv, ctx, systems, outs);
+    const double t_done = now_s(sv->t0);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (st != TMD_OK) sv->last_error = ctx->last_error;
+        for (size_t i = 0; i < reqs.size(); ++i) {
+            outs[i].res.status = st;
+            outs[i].res.t_done = t_done;
+            systems[i]->busy = false;
+            systems[i]->last_use = ++sv->clock;
+            sv->running.erase(reqs[i].ticket);
+            sv->done[reqs[i].ticket] = std::move(outs[i]);
+        }
+    }
+    sv->cv_done.notify_all();
+    sv->cv_work.notify_all();
+}
+
 void worker_main(tmd_server* sv, int slot) {
     (void)hipSetDevice(sv->opts.device);
     tmd_context* ctx = sv->ctxs[slot];
@@ -390,6 +504,20 @@ void worker_main(tmd_server* sv, int slot) {
                 continue;
             }
             sv->running.insert(p.ticket);
+            if (sv->opts.batch_atoms > 0 && p.req.kind == TMD_REQ_ENERGY_FORCES && sys->nl &&
+                sys->n <= sv->opts.batch_atoms) {
+                std::vector<Pending> reqs;
+                std::vector<System*> systems;
+                reqs.push_back(std::move(p));
+                systems.push_back(sys);
+                pick_batch(sv, sys, reqs, systems);
+                if (systems.size() > 1) {
+                    lk.unlock();
+                    serve_batch(sv, ctx, reqs, systems);
+                    continue;
+                }
+                p = std::move(reqs[0]);
+            }
         }
         Finished f;
         f.res.kind = p.req.kind;
@@ -398,6 +526,7 @@ void worker_main(tmd_server* sv, int slot) {
         f.res.n_steps = p.req.kind == TMD_REQ_MD ? p.req.n_steps : 0;
         f.res.t_submit = p.t_submit;
         f.res.t_start = now_s(sv->t0);
+        f.res.batch_size = 1;
         tmd_status st = TMD_OK;
         if (!sys->nl) {
             tmd_nlist* nl = nullptr;
@@ -460,6 +589,7 @@ tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, 
     if (o.max_slots > 64) return TMD_ERR_INVALID_ARGUMENT;
     if (o.max_atoms <= 0) o.max_atoms = 262144;
     if (!(o.skin >= 0.0) || !std::isfinite(o.skin)) return TMD_ERR_INVALID_ARGUMENT;
+    if (o.batch_atoms < 0) return TMD_ERR_INVALID_ARGUMENT;
     tmd_server* sv = new (std::nothrow) tmd_server();
     if (!sv) return TMD_ERR_OUT_OF_MEMORY;
     sv->model = model;
@@ -472,6 +602,10 @@ tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, 
     }
     account(sv, (int64_t)o.max_slots *
                     (int64_t)(eval_workspace_bytes(model, o.max_atoms) + nlist_workspace_bytes(o.max_atoms)));
+    // merged lists of batched requests (rows estimated at 64 entries per species)
+    if (o.batch_atoms > 0)
+        account(sv, (int64_t)o.max_slots * std::min<int64_t>(o.max_atoms, kServeBatchAtoms) *
+                        (68 + (int64_t)model->S * (64 * 8 + 4)));
     if (sv->mem_in_use > o.hbm_budget_bytes) {
         delete sv;
         return TMD_ERR_REJECTED;

@@ -99,7 +99,7 @@ class Thermo(ctypes.Structure):
 class ServeOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("max_atoms", ctypes.c_int64), ("skin", ctypes.c_double), ("capacity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("batch_atoms", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -111,13 +111,14 @@ class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("system_id", ctypes.c_int64),
                 ("n_atoms", ctypes.c_int64), ("n_steps", ctypes.c_int32), ("rebuilds", ctypes.c_int32),
                 ("energy", ctypes.c_double), ("kinetic", ctypes.c_double), ("virial", ctypes.c_double * 6),
-                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("batch_size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "kind": self.kind, "system_id": self.system_id, "n_atoms": self.n_atoms,
                 "n_steps": self.n_steps, "rebuilds": self.rebuilds, "energy": self.energy, "kinetic": self.kinetic,
                 "virial": list(self.virial), "t_submit": self.t_submit, "t_start": self.t_start,
-                "t_done": self.t_done}
+                "t_done": self.t_done, "batch_size": self.batch_size}
 
 
 _lib = None
@@ -629,7 +630,7 @@ class Server:
     their own streams, admission by memory budget."""
 
     def __init__(self, model: Model, max_slots: int = 8, hbm_budget_bytes: int = 0, max_atoms: int = 0,
-                 skin: float = 1.0, device: int = 0):
+                 skin: float = 1.0, device: int = 0, batch_atoms: int = 0):
         self.lib = model.ctx.lib
         self.model = model  # must outlive the server
         o = ServeOpts()
@@ -638,6 +639,7 @@ class Server:
         o.device = int(device)
         o.max_atoms = int(max_atoms)
         o.skin = float(skin)
+        o.batch_atoms = int(batch_atoms)
         h = ctypes.c_void_p()
         st = self.lib.tmd_serve_create(model.h, ctypes.byref(o), ctypes.byref(h))
         if st != TMD_OK:

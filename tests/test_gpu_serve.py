@@ -271,3 +271,56 @@ def test_serve_input_errors(tmd, ctx):
         srv.add_system(s.pos, np.full(s.n, 5, dtype=np.int32), s.box, s.masses)
     assert ei.value.status == 1
     srv.close()
+
+
+def test_serve_batches_small_energy_force_requests(tmd, ctx):
+    """Energy-and-force requests on small resident systems are evaluated together
+    (batch_atoms): results against the oracle to the FP32 bars, and the same
+    bit for bit whatever they were batched with."""
+    _note("serve EF batching of small systems vs oracle")
+    _, spec, _ = inputs.workload("oracle32")
+    model = tmd.Model(ctx, spec)
+    srv = tmd.Server(model, max_slots=1, max_atoms=8192, skin=1.0, batch_atoms=1024)
+    systems = [_fcc108(), inputs.make_system("bcc", 3.16, (4, 4, 4), 0.1, 1, seed=73, masses=[CU_MASS]),
+               inputs.make_system("fcc", 3.61, (2, 2, 3), 0.1, 1, seed=74, masses=[CU_MASS]),
+               inputs.make_system("bcc", 3.16, (3, 3, 5), 0.1, 1, seed=75, masses=[CU_MASS]),
+               inputs.make_system("fcc", 3.61, (4, 4, 4), 0.05, 1, seed=76, masses=[CU_MASS])]
+    ids = [srv.add_system(s.pos, s.species, s.box, s.masses) for s in systems]
+    # a larger system whose MD runs keep the one slot busy while a wave queues
+    big = inputs.make_system("fcc", 3.61, (6, 6, 6), 0.05, 1, seed=77, masses=[CU_MASS])
+    big_id = srv.add_system(big.pos, big.species, big.box, big.masses)
+    v0 = inputs.maxwell_boltzmann(np.full(big.n, CU_MASS), 300.0, seed=78)
+    # first requests build the resident lists (not batched: no list yet)
+    for t in [srv.submit(i) for i in ids]:
+        assert srv.wait(t, 60.0)["status"] == 0
+    refs = [oracle.energy_forces(spec, s.pos, s.species, s.box) for s in systems]
+    seen = {}
+    sizes = []
+    for wave in range(3):
+        order = ids if wave != 1 else ids[::-1]
+        order = order if wave != 2 else order[1::2]
+        busy = srv.submit(big_id, tmd.REQ_MD, 100, 1.0, v0)
+        tickets = [(i, srv.submit(i)) for i in order]
+        assert srv.wait(busy, 60.0)["status"] == 0
+        for i, t in tickets:
+            r = srv.wait(t, 60.0)
+            assert r is not None and r["status"] == 0
+            sizes.append(r["batch_size"])
+            out = srv.fetch(t, r)
+            k = ids.index(i)
+            s = systems[k]
+            Er, _, Fr, Wr = refs[k]
+            assert abs(r["energy"] - Er) / s.n <= 1e-5
+            assert math.sqrt(np.mean((out["forces"] - Fr) ** 2)) <= 1e-4
+            W = np.array(r["virial"])
+            Wr6 = np.array([Wr[0, 0], Wr[1, 1], Wr[2, 2], Wr[0, 1], Wr[0, 2], Wr[1, 2]])
+            assert np.abs(W - Wr6).max() / s.n <= spec.rcut * 1e-4
+            if r["batch_size"] > 1:
+                key = (i, "batched")
+                if key in seen:
+                    assert seen[key][0] == r["energy"]
+                    assert np.array_equal(seen[key][1], out["forces"])
+                seen[key] = (r["energy"], out["forces"])
+    print(f"  batch sizes seen: {sorted(set(sizes))}", flush=True)
+    assert max(sizes) > 1
+    srv.close()
