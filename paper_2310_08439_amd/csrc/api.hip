@@ -203,7 +203,7 @@ tmd_status eval_buffers(tmd_context* ctx, const tmd_model* m, const tmd_nlist* n
     b->dG = (float*)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
     b->Ei = (float*)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
     b->Fq = (unsigned long long*)ctx->ws.get("ev.Fq", sizeof(unsigned long long) * 3 * n, &e);
-    b->P = (float*)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->Dr, &e);
+    b->P = (float*)ctx->ws.get("ev.P", sizeof(float) * (size_t)p_slots(m, nl) * m->S * m->K * m->Dr, &e);
     b->vir = (double*)ctx->ws.get("ev.vir", sizeof(double) * kVirDoubles * (size_t)adjoint_max_partials(m, nl), &e);
     b->totals = (double*)ctx->ws.get("ev.totals", sizeof(double) * 8, &e);
     b->part = (double*)ctx->ws.get("ev.part", sizeof(double) * finalize_part_doubles(), &e);
@@ -245,7 +245,7 @@ void scratch_buffers(unsigned char* base, const tmd_model* m, const tmd_nlist* n
     };
     const size_t oG = take(sizeof(float) * n * m->F), odG = take(sizeof(float) * n * m->F);
     const size_t oEi = take(sizeof(float) * n), oFq = take(sizeof(unsigned long long) * 3 * n);
-    const size_t oP = take(sizeof(float) * (size_t)n * m->S * m->K * m->Dr);
+    const size_t oP = take(sizeof(float) * (size_t)p_slots(m, nl) * m->S * m->K * m->Dr);
     const size_t ovir = take(sizeof(double) * kVirDoubles * (size_t)adjoint_max_partials(m, nl));
     const size_t opart = take(sizeof(double) * finalize_part_doubles());
     *need = off;
@@ -269,7 +269,7 @@ tmd_status reserve_eval_workspace(tmd_context* ctx, const tmd_model* m, int64_t 
     (void)ctx->ws.get("ev.dG", sizeof(float) * n * m->F, &e);
     (void)ctx->ws.get("ev.Ei", sizeof(float) * n, &e);
     (void)ctx->ws.get("ev.Fq", sizeof(unsigned long long) * 3 * n, &e);
-    (void)ctx->ws.get("ev.P", sizeof(float) * (size_t)n * m->S * m->K * m->Dr, &e);
+    (void)ctx->ws.get("ev.P", sizeof(float) * (size_t)p_slots_reserve(n) * m->S * m->K * m->Dr, &e);
     (void)ctx->ws.get("ev.vir",
                       sizeof(double) * kVirDoubles * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock),
                       &e);
@@ -281,7 +281,7 @@ tmd_status reserve_eval_workspace(tmd_context* ctx, const tmd_model* m, int64_t 
 
 size_t eval_workspace_bytes(const tmd_model* m, int64_t n) {
     const int64_t nch = m->K / m->kc;
-    return (size_t)n * (8 * m->F + 4 + 24 + 4 * (size_t)m->S * m->K * m->Dr) +
+    return (size_t)n * (8 * m->F + 4 + 24) + (size_t)p_slots_reserve(n) * 4 * m->S * m->K * m->Dr +
            8 * kVirDoubles * (size_t)std::max<int64_t>(4 * n + 64, (n * nch + kBlock - 1) / kBlock) +
            8 * finalize_part_doubles() + 64;
 }

@@ -29,6 +29,7 @@
 #include "tensor_ops.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace tmd {
 namespace {
@@ -61,7 +62,10 @@ struct PathArgs {
     // forward output / backward input
     float* G;
     const float* dG;
-    // P [S][K][D][n] written by the forward pass (if non-null) and read back by the adjoint
+    // P written by the forward pass (if non-null) and read back by the
+    // adjoint: [S][K][DR][n] by work slot (VALU kernels), or, for the
+    // matrix-core pair, one tile per 16-atom group g of the work order,
+    // [g][S][K][4][16][4] (element (k, q, atom, i) = P[k][kMfmaRow[q][i]])
     float* Pbuf;
     // backward output: virial block partials
     double* vir;
@@ -762,6 +766,9 @@ struct BlockGeom {
     const int32_t* cellstart;
     unsigned long long* F;  // fixed-point forces [n][3]
     const int32_t* wbase;  // [blocks + 1] first work slot of each block
+    // [blocks + 1] first 16-atom group of each block in the matrix-core P
+    // layout (a block of c atoms takes ceil(c / 16) groups)
+    const int32_t* gbase;
     const int32_t* wperm;  // work slot -> sorted atom
     const uint8_t* wcell;  // work slot -> cell inside its block
 };
@@ -1011,6 +1018,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
         const int ia = base + quad;
         const bool aval = ia < natoms;
         const int64_t w = w0 + (aval ? ia : natoms - 1);
+        const int64_t g = bg.gbase[blk] + base / 16;  // the 16-atom group of P
         const int64_t p = bg.wperm[w];
         const int ic = bg.wcell[w];
         const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
@@ -1022,13 +1030,14 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
         for (int b = 0; b < a.S; ++b) {
             // this lane's slices of P' (= 2 T sigma' P, folded onto the kept basis)
             float Ap[K][4];
-            const float* Pb = a.Pbuf + (int64_t)b * K * DR * a.n + w;
+            // P in the group layout: element (k, q, atom, i) of the group's
+            // species-b tile is P[k][kMfmaRow[q][i]]; this lane takes i = j
+            const float* Pb = a.Pbuf + ((int64_t)g * a.S + b) * (K * 256) + quad * 4 + j;
             const float4* g4 = reinterpret_cast<const float4*>(a.dG + p * a.F + (int64_t)b * K * 4);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float* Pk = Pb + (int64_t)k * DR * a.n;
-                const float pa = Pk[(int64_t)j * a.n], pb = Pk[(int64_t)rb * a.n], pc = Pk[(int64_t)rc * a.n],
-                            pf = Pk[(int64_t)rf * a.n];
+                const float* Pk = Pb + k * 256;
+                const float pa = Pk[0], pb = Pk[64], pc = Pk[128], pf = Pk[192];
                 const float4 g = g4[k];
                 // the lane's orders picked arithmetically (0/1 weights), so that
                 // every lane loads the whole dE/dG quadruple with one instruction
@@ -1218,6 +1227,202 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
     block_virial(Wd, red, a.vir + (int64_t)blockIdx.x * kVirDoubles);
 }
 
+// Value of lane P of each block of four lanes, by a DPP quad permutation
+// [P, P, P, P].
+template <int P>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), P * 0x55, 0xF, 0xF, false));
+}
+
+// Descriptor on the matrix cores (M = 3, K = 4 KQ, blocked work order).  For
+// an atom and a neighbour species, P = sum_c h(R_c) m(u_c)^T is a sum of one
+// outer product per pair, taken as 4 x 4 x 1 FP32 MFMAs, one per (group kk of
+// four radial functions, slice q of four kept components).  The four lanes of
+// an MFMA block serve one atom (sixteen atoms per wave): lane j supplies the
+// monomials of kept components kMfmaRow[q][j] as the A operand and h_{4 kk + j}
+// as the B operand, so register i of its accumulator (kk, q) is
+// P[4 kk + j][kMfmaRow[q][i]]: each lane ends with all sixteen kept
+// components of its own radial functions and forms their G entries without
+// any exchange.  The slices factor per lane as s, xx s, yy s and v s with
+// s = (1, x, y, z)[j] and v = (xy, z, z, xy)[j].  Per batch each lane forms the
+// geometry of one pair of its atom's row (entries and positions prefetched as
+// in the matrix-core adjoint); the block's four pairs are then taken in turn,
+// their unit vector, distance and cutoff weight broadcast by DPP.
+template <int KQ, int RAD>
+__global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeom bg) {
+    constexpr int K = 4 * KQ, DR = Moments<3>::DR, D = Moments<3>::D;
+    extern __shared__ __attribute__((aligned(8))) unsigned char lds_dyn[];
+    __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
+    __shared__ int32_t wtmp[kBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int quad = lane >> 2, j = lane & 3;
+    const int blk = blockIdx.x;
+    int x0, y0, z0;
+    halo_slots(bg, blk, h_first, h_base, hoff, wtmp, x0, y0, z0);
+    const int HX = bg.B[0] + 2, HY = bg.B[1] + 2;
+    float* sx = reinterpret_cast<float*>(lds_dyn);
+    float* sy = sx + bg.hmax;
+    float* sz = sx + 2 * bg.hmax;
+    halo_positions(bg, a, x0, y0, z0, h_first, h_base, sx, sy, sz);  // ends with a barrier
+    const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
+    // this lane's monomial factors (0/1 weights: the selects stay arithmetic)
+    const float f1 = j == 0 ? 1.0f : 0.0f, fx = j == 1 ? 1.0f : 0.0f, fy = j == 2 ? 1.0f : 0.0f,
+                fz = j == 3 ? 1.0f : 0.0f;
+    const float vz = (j == 1 || j == 2) ? 1.0f : 0.0f, vxy = 1.0f - vz;
+    // this lane's radial functions 4 kk + j
+    float mu[KQ], nef[KQ];
+#pragma unroll
+    for (int kk = 0; kk < KQ; ++kk) {
+        mu[kk] = a.mu[4 * kk + j];
+        nef[kk] = -a.eta[4 * kk + j] * kLog2e;
+    }
+    const int KM = K * 4;  // G features of one species
+    const int64_t w0 = bg.wbase[blk];
+    const int natoms = (int)(bg.wbase[blk + 1] - w0);
+    for (int base = wv * 16; base < natoms; base += kBlock / 4) {
+        const int ia = base + quad;
+        const bool aval = ia < natoms;
+        const int64_t w = w0 + (aval ? ia : natoms - 1);
+        const int64_t g = bg.gbase[blk] + base / 16;
+        const int64_t p = bg.wperm[w];
+        const int ic = bg.wcell[w];
+        const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
+        const int hp = (iz * HY + iy) * HX + ix;
+        const int ip = hoff[hp] + (int)p;
+        const LdsPos pos{sx, sy, sz, hoff, hp - (HX * HY + HX + 1), HX, HX * HY,
+                         sx[ip] + cw[0], sy[ip] + cw[1], sz[ip] + cw[2], cw[0], cw[1], cw[2]};
+        for (int b = 0; b < a.S; ++b) {
+            f32x4 acc[KQ][4];
+#pragma unroll
+            for (int kk = 0; kk < KQ; ++kk)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[kk][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int nb = aval ? a.cnt[(int64_t)b * a.n + p] : 0;
+            int nbmax = nb;
+            for (int off = 4; off < 64; off <<= 1) nbmax = max(nbmax, __shfl_xor(nbmax, off));
+            const int64_t row = (p * a.S + b) * a.cap;
+            const int cl = a.cap - 1;
+            auto entry = [&](int c, int& q, int& im) {
+                const int cc = min(c, cl);
+                q = a.nbr[row + cc];
+                im = a.img[row + cc];
+            };
+            // lanes past the row's end read the centre atom and are inactive
+            auto geom = [&](int c, int q, int im, float& gdx, float& gdy, float& gdz, bool& gact) {
+                const bool valid = c < nb;
+                int unused;
+                const float4 xj = pos.fetch(valid ? q : (int)p, valid ? im : kCentreWord, unused);
+                const float3 dm = pos.disp(xj, valid ? im : kCentreWord);
+                gact = valid && dm.x * dm.x + dm.y * dm.y + dm.z * dm.z < a.rc2;  // skin entries add nothing
+                gdx = gact ? dm.x : 1.0f;
+                gdy = gact ? dm.y : 0.0f;
+                gdz = gact ? dm.z : 0.0f;
+            };
+            float dx, dy, dz;
+            bool act;
+            int qA, iA, qB, iB;
+            entry(j, qA, iA);
+            geom(j, qA, iA, dx, dy, dz, act);
+            entry(4 + j, qA, iA);
+            entry(8 + j, qB, iB);
+            // the MFMAs of pair P of the block
+            auto pair_step = [&](auto pc, float ux, float uy, float uz, float R, float wt) {
+                constexpr int P = decltype(pc)::value;
+                const float px = quad_bcast<P>(ux), py = quad_bcast<P>(uy), pz = quad_bcast<P>(uz);
+                const float pR = quad_bcast<P>(R), pw = quad_bcast<P>(wt);
+                float hB[KQ];
+                if constexpr (RAD == kRadTab) {
+                    const float xr = pR * a.tab_inv;
+                    const float jf = fminf(floorf(xr), (float)a.tab_n);
+                    const float tt = xr - jf;
+                    const float4* trow = a.tab + (int64_t)jf * K + j;
+                    float4 c[KQ];
+#pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk) c[kk] = trow[4 * kk];
+#pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk)
+                        hB[kk] = fmaf(tt, fmaf(tt, fmaf(tt, c[kk].w, c[kk].z), c[kk].y), c[kk].x);
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk) {
+                        const float tk = pR - mu[kk];
+                        hB[kk] = __builtin_amdgcn_exp2f(nef[kk] * tk * tk);
+                    }
+                }
+                const float s = pw * fmaf(fx, px, fmaf(fy, py, fmaf(fz, pz, f1)));
+                const float xy = px * py;
+                const float Am[4] = {s, px * px * s, py * py * s, fmaf(vz, pz, vxy * xy) * s};
+#pragma unroll
+                for (int kk = 0; kk < KQ; ++kk)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[kk][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Am[q], hB[kk], acc[kk][q], 0, 0, 0);
+            };
+            // one batch; (qx, ix) hold the entries of batch c0 + 4 and are
+            // reloaded with those of batch c0 + 12
+            auto batch = [&](int c0, int& qx, int& ix) {
+                float ndx, ndy, ndz;
+                bool nact;
+                geom(c0 + 4 + j, qx, ix, ndx, ndy, ndz, nact);
+                entry(c0 + 12 + j, qx, ix);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float R = r2 * rinv;
+                const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+                float wt;
+                if constexpr (RAD == kRadTab) wt = act ? 1.0f : 0.0f;  // the table has the cutoff folded in
+                else wt = act ? 0.5f * __builtin_amdgcn_cosf(R * a.half_inv_rc) + 0.5f : 0.0f;
+                pair_step(std::integral_constant<int, 0>{}, ux, uy, uz, R, wt);
+                pair_step(std::integral_constant<int, 1>{}, ux, uy, uz, R, wt);
+                pair_step(std::integral_constant<int, 2>{}, ux, uy, uz, R, wt);
+                pair_step(std::integral_constant<int, 3>{}, ux, uy, uz, R, wt);
+                dx = ndx;
+                dy = ndy;
+                dz = ndz;
+                act = nact;
+            };
+            int c0 = 0;
+            for (; c0 + 8 <= nbmax; c0 += 8) {
+                batch(c0, qA, iA);
+                batch(c0 + 4, qB, iB);
+            }
+            if (c0 < nbmax) batch(c0, qA, iA);
+            if (c0 + 4 < nbmax) batch(c0 + 4, qB, iB);
+            // P in the group layout (zeros for lanes past the block's atoms)
+            if (a.Pbuf) {
+                float* dst = a.Pbuf + (((int64_t)g * a.S + b) * K + j) * 256 + quad * 4;
+#pragma unroll
+                for (int kk = 0; kk < KQ; ++kk)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<f32x4*>(dst + kk * 1024 + q * 64) = acc[kk][q];
+            }
+            if (aval) {
+#pragma unroll
+                for (int kk = 0; kk < KQ; ++kk) {
+                    const int k = 4 * kk + j;
+                    float Pr[1][DR], P[1][D];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) Pr[0][kMfmaRow[q][i]] = acc[kk][q][i];
+                    expand_P<3, 1>(Pr, P);
+                    float g[4];
+#pragma unroll
+                    for (int m = 1; m <= 3; ++m) {
+                        float sm = 0.0f;
+#pragma unroll
+                        for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) sm += kMult[d] * P[0][d] * P[0][d];
+                        g[m] = sm;
+                    }
+                    g[0] = fabsf(P[0][0]);  // sqrt(S) of the single order-0 component
+                    *reinterpret_cast<float4*>(a.G + p * a.F + b * KM + 4 * k) = make_float4(g[0], g[1], g[2], g[3]);
+                }
+            }
+        }
+    }
+}
+
 // ---- work order ----------------------------------------------------------
 //
 // Rows of one wave run in lockstep, so a wave costs the longest of its rows.
@@ -1268,31 +1473,47 @@ __global__ void k_wo_count(WorkGeom g, int64_t nblocks, int32_t* __restrict__ co
 // base[nblocks] = n.
 __global__ void __launch_bounds__(1024) k_wo_scan(int64_t nblocks, const int32_t* __restrict__ count,
                                                   int32_t* __restrict__ base) {
-    __shared__ int32_t wsum[16];
+    // base[0 .. nblocks] = exclusive scan of the counts (first work slots),
+    // base[nblocks + 1 ..] = exclusive scan of ceil(count / 16) (first groups)
+    __shared__ int32_t wsum[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    int32_t carry = 0;
+    int32_t carry[2] = {0, 0};
+    int32_t* gb = base + nblocks + 1;
     for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
         const int64_t q = b0 + t;
-        const int32_t v = q < nblocks ? count[q] : 0;
-        int32_t x = v;
+        const int32_t c = q < nblocks ? count[q] : 0;
+        const int32_t v[2] = {c, (c + 15) >> 4};
+        int32_t x[2] = {v[0], v[1]};
         for (int off = 1; off < 64; off <<= 1) {
-            const int32_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        int32_t pre = 0, tot = 0;
 #pragma unroll
-        for (int w = 0; w < 16; ++w) {
-            const int32_t sw = wsum[w];
-            pre += (w < wv) ? sw : 0;
-            tot += sw;
+            for (int u = 0; u < 2; ++u) {
+                const int32_t y = __shfl_up(x[u], off);
+                if (lane >= off) x[u] += y;
+            }
         }
-        if (q < nblocks) base[q] = carry + pre + x - v;
-        carry += tot;
+        if (lane == 63) {
+            wsum[0][wv] = x[0];
+            wsum[1][wv] = x[1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int32_t pre = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) {
+                const int32_t sw = wsum[u][w];
+                pre += (w < wv) ? sw : 0;
+                tot += sw;
+            }
+            if (q < nblocks) (u ? gb : base)[q] = carry[u] + pre + x[u] - v[u];
+            carry[u] += tot;
+        }
         __syncthreads();
     }
-    if (t == 0) base[nblocks] = carry;
+    if (t == 0) {
+        base[nblocks] = carry[0];
+        gb[nblocks] = carry[1];
+    }
 }
 
 // One workgroup per block: counting sort of the block's atoms by descending
@@ -1435,8 +1656,20 @@ BlockedFn select_mfma(int rad, int kq) {
                           : rad == kRadRec ? select_mfma_r<kRadRec>(kq) : select_mfma_r<kRadDirect>(kq);
 }
 // The matrix-core adjoint takes M = 3 and K = 8, 12 or 16 (K / 4 slices of
-// P' per lane stay in registers).
+// P' per lane stay in registers); so does the matrix-core descriptor.
 bool mfma_adjoint(const tmd_model* m) { return m->M == 3 && m->K % 4 == 0 && m->K >= 8 && m->K <= 16; }
+
+template <int RAD>
+BlockedFn select_desc_mfma_r(int kq) {
+    switch (kq) {
+        case 2: return k_descriptor_mfma<2, RAD>;
+        case 3: return k_descriptor_mfma<3, RAD>;
+        default: return k_descriptor_mfma<4, RAD>;
+    }
+}
+BlockedFn select_desc_mfma(int rad, int kq) {
+    return rad == kRadTab ? select_desc_mfma_r<kRadTab>(kq) : select_desc_mfma_r<kRadDirect>(kq);
+}
 
 BlockedFn select_blocked(int rad, int kc, int M, bool pair2) {
     return rad == kRadTab ? select_blocked_r<kRadTab>(kc, M, pair2)
@@ -1513,6 +1746,7 @@ BlockGeom wo_geom(const tmd_nlist* nl) {
     bg.hmax = nl->wo_hmax;
     bg.cellstart = nl->cellstart;
     bg.wbase = nl->wbase;
+    bg.gbase = nl->wbase + ((int64_t)nl->wo_nb[0] * nl->wo_nb[1] * nl->wo_nb[2] + 1);
     bg.wperm = nl->wperm;
     bg.wcell = nl->wcell;
     return bg;
@@ -1558,12 +1792,12 @@ tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl) {
     BlockGeom bg{};
     if (!nl->narrow || !choose_blocks(nl, &bg)) return TMD_OK;  // atomic adjoint, identity order
     const int64_t nblocks = (int64_t)bg.nb[0] * bg.nb[1] * bg.nb[2];
-    if (nl->wbase_cap < nblocks + 1) {
+    if (nl->wbase_cap < 2 * (nblocks + 1)) {
         if (nl->wbase) TMD_HIP(ctx, hipFree(nl->wbase));
         nl->wbase = nullptr;
         nl->wbase_cap = 0;
-        TMD_HIP(ctx, hipMalloc((void**)&nl->wbase, sizeof(int32_t) * (nblocks + 1)));
-        nl->wbase_cap = nblocks + 1;
+        TMD_HIP(ctx, hipMalloc((void**)&nl->wbase, sizeof(int32_t) * 2 * (nblocks + 1)));
+        nl->wbase_cap = 2 * (nblocks + 1);
     }
     hipError_t e = hipSuccess;
     int32_t* count = (int32_t*)ctx->ws.get("wo.count", sizeof(int32_t) * nblocks, &e);
@@ -1595,6 +1829,15 @@ tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl) {
     return TMD_OK;
 }
 
+int64_t p_slots(const tmd_model* m, const tmd_nlist* nl) {
+    if (!(nl->wo_valid && mfma_adjoint(m))) return nl->n;
+    // each block's last group may be partly empty
+    const int64_t nblocks = (int64_t)nl->wo_nb[0] * nl->wo_nb[1] * nl->wo_nb[2];
+    return nl->n + 15 * std::min<int64_t>(nblocks, nl->n);
+}
+
+int64_t p_slots_reserve(int64_t n) { return n + n / 8 + 16 * 1024; }
+
 int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl) {
     return std::max<int64_t>((int64_t)path_grid(m, nl), nl->ncells);
 }
@@ -1603,6 +1846,17 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     PathArgs a = make_args(m, nl);
     a.G = G;
     a.Pbuf = Pbuf;
+    if (nl->wo_valid && mfma_adjoint(m)) {
+        const BlockGeom bg = wo_geom(nl);
+        const unsigned grid = (unsigned)bg.nb[0] * bg.nb[1] * bg.nb[2];
+        auto fn = select_desc_mfma(m->tab ? kRadTab : kRadDirect, m->K / 4);
+        {
+            ProfScope ps_(ctx, "descriptor");
+            fn<<<grid, kBlock, sizeof(float) * 3 * (size_t)bg.hmax, ctx->stream>>>(a, bg);
+        }
+        TMD_HIP(ctx, hipGetLastError());
+        return TMD_OK;
+    }
     const int kcd = desc_kc(m);
     a.nch_log2 = log2_int(m->K / kcd);
     // P stores cover whole 128-byte lines (and go out non-temporally) with at most two chunks per atom

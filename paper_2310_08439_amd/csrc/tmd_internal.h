@@ -249,7 +249,9 @@ struct tmd_nlist {
     // in block-major order, each block's atoms by descending species-0 row
     // length (so that a wave's rows are alike);
     // wperm[w] = sorted atom index of work slot w, wcell[w] = its cell inside
-    // the block, wbase[blk] = first slot of block blk.  P is stored by slot.
+    // the block, wbase[blk] = first slot of block blk, and after those
+    // (wbase + blocks + 1) the first 16-atom group of each block (the
+    // matrix-core kernels' P layout).  P is stored by slot or by group.
     bool wo_valid = false;
     int wo_B[3] = {1, 1, 1}, wo_nb[3] = {1, 1, 1}, wo_hmax = 0;
     int32_t* wperm = nullptr;      // [nmax]
@@ -309,8 +311,16 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
                                   int32_t* required_capacity);
 tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl);
 // Descriptors G [n][F] (sorted order); when Pbuf is non-null the per-atom P
-// tensors [n][S][K][D] are kept there for the adjoint.
+// tensors (kept components) are kept there for the adjoint: p_slots(m, nl)
+// x S x K x Dr floats.
 tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf);
+// Atom slots of the P buffer for this model and list (the matrix-core
+// kernels pad each work-order block to whole 16-atom groups), and a bound for
+// reserving workspace before any list exists (blocks of 128 atoms or more on
+// average, or up to 1,024 blocks; a list needing more grows the buffer at its
+// first evaluation).
+int64_t p_slots(const tmd_model* m, const tmd_nlist* nl);
+int64_t p_slots_reserve(int64_t n);
 // Atoms grouped by species: idx[off[s] .. off[s+1]) are the atoms of species s
 // (row indices into G, Ei and dG).
 struct SpeciesGroups {

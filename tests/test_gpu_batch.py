@@ -3,9 +3,14 @@
 * Against the FP64 oracle, per system, to the FP32 bars of tests/parity.py
   (whole-system energy, per-atom energies, forces, virial), and in BF16 to the
   BF16 bars against the oracle and its BF16 form.
-* Against tmd_energy_forces_async run per system: forces within the FP32
-  force bar (the single-system path may take the blocked matrix-core adjoint,
-  which sums in another order), energies and virials within 1e-6 relative.
+* Against tmd_energy_forces_async run per system.  The single-system path
+  may take the blocked descriptor and adjoint, which form displacements from
+  FP32 offsets held in LDS (about 3e-7 A of rounding per coordinate) and sum in
+  another order, while the batch forms them from the FP64 positions: forces
+  within the FP32 force bars, energies within 1e-6 eV per atom and virials
+  within rcut x 1e-6 eV per atom (a tenth of the FP32 energy target and a
+  hundredth of the FP32 virial bar; FP32 rounding of the displacements moves a
+  bcc atom's energy by ~1e-7 eV).
 * A system's results do not depend on its batch mates: alone in a batch of
   one and in the full batch they agree bit for bit (fixed-point force sums,
   per-system totals over segments that no workgroup crosses).
@@ -144,9 +149,9 @@ def test_batch_matches_single_system_path(tmd, ctx, torch):
         f1 = f1.cpu().numpy().astype(np.float64)
         print(f"  n={s.n}: |dE|={abs(tot[i][0] - t1[0]):.3e}  max|dF|={np.abs(F[i] - f1).max():.3e}  "
               f"max|dW|={np.abs(tot[i][1:] - t1[1:]).max():.3e}", flush=True)
-        assert abs(tot[i][0] - t1[0]) <= 1e-6 * abs(t1[0]) + 1e-6
+        assert abs(tot[i][0] - t1[0]) / s.n <= 1e-6
         assert parity._rms(F[i] - f1) <= parity.F_FP32 and np.abs(F[i] - f1).max() <= parity.FMAX_FP32
-        assert np.abs(tot[i][1:] - t1[1:]).max() <= 1e-6 * np.abs(t1[1:]).max() + 1e-5
+        assert np.abs(tot[i][1:] - t1[1:]).max() / s.n <= spec.rcut * 1e-6
     model.close()
     for _, _, nl in lists:
         nl.close()
