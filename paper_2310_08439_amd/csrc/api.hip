@@ -502,6 +502,15 @@ tmd_status tmd_model_create(tmd_context* ctx, const tmd_model_spec* spec, const 
             m->rec_a = (float)(2.0 * e0 * d * log2e);
             m->rec_b = (float)(-e0 * d * d * log2e);
             m->rec_c = (float)std::exp(-2.0 * e0 * d * d);
+            bool ok4 = K % 4 == 0;
+            for (int k0 = 0; k0 < 4 && k0 < K && ok4; ++k0) {
+                const double tmax = std::max(std::fabs(spec->rcut - mu_d[k0]), std::fabs(mu_d[k0]));
+                ok4 = e0 * tmax * tmax <= 80.0 && 8.0 * e0 * d * tmax <= 80.0;
+            }
+            if (ok4) {
+                m->rec4 = true;
+                m->rec_c4 = (float)std::exp(-32.0 * e0 * d * d);
+            }
         }
     }
     hipError_t e = hipSuccess;

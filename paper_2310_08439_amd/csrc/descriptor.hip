@@ -43,6 +43,7 @@ struct PathArgs {
     int rec;
     float rec_a, rec_b, rec_c;
     float rec_m2eta, rec_delta;  // uniform grid: -2 eta and the centre spacing Delta
+    float rec_c4;                // rec_c^16, the step of four radial functions (when rec4)
     // radial table (TAB kernels): [(tab_n + 1)][K] cubic coefficients, spacing 1/tab_inv
     const float4* tab;
     float tab_inv;
@@ -958,10 +959,10 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
 // own four P components and dE/dG alone.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Reduced-basis index of result entry i of slice q (the slices above).
 // Image word of the centre atom's own cell (stencil offset 0, 0, 0).
 constexpr int32_t kCentreWord = (int32_t)(0x15u << 24);
 
+// Reduced-basis index of entry n of slice q (the slices above).
 __device__ constexpr int kMfmaRow[4][4] = {{0, 1, 2, 3}, {4, 9, 10, 11}, {7, 12, 14, 15}, {5, 6, 8, 13}};
 
 template <int KQ, int RAD>
@@ -971,7 +972,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
     __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
     __shared__ int32_t wtmp[kBlock / 64];
     __shared__ double red[6][kBlock / 64][2];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int quad = lane >> 2, j = lane & 3;
     const int blk = blockIdx.x;
     int x0, y0, z0;
@@ -996,10 +997,10 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
         atomicAdd(&sF[bg.hmax + idx], to_fixed(-gy));
         atomicAdd(&sF[2 * bg.hmax + idx], to_fixed(-gz));
     };
-    // this lane's kept components (reduced index) and 2 x their multiplicities
-    // (full T_dm row order: xx 1, xy 2, yy 1, zz 1; x 1, xz 2, xxx 1, xyy 3, xzz 3;
-    // y 1, yz 2, xxy 3, yyy 1, yzz 3; z 1, xxz 3, yyz 3, xyz 6, zzz 1)
-    const int rb = kMfmaRow[1][j], rc = kMfmaRow[2][j], rf = kMfmaRow[3][j];
+    // 2 x the multiplicities of this lane's kept components kMfmaRow[q][j] and
+    // of its dropped one (full T_dm row order: xx 1, xy 2, yy 1, zz 1; x 1,
+    // xz 2, xxx 1, xyy 3, xzz 3; y 1, yz 2, xxy 3, yyy 1, yzz 3; z 1, xxz 3,
+    // yyz 3, xyz 6, zzz 1)
     const float c2b = j <= 1 ? 2.0f : 6.0f;
     const float c2c = (j & 1) ? 6.0f : 2.0f;
     const float c2f = j == 3 ? 12.0f : 4.0f;
@@ -1056,6 +1057,9 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
             const int nb = aval ? a.cnt[(int64_t)b * a.n + p] : 0;
             int nbmax = nb;
             for (int off = 4; off < 64; off <<= 1) nbmax = max(nbmax, __shfl_xor(nbmax, off));
+            // the same in every lane: the batch loop runs under the full EXEC
+            // mask (the DPP broadcasts read every lane of a block)
+            nbmax = __builtin_amdgcn_readfirstlane(nbmax);
             const int64_t row = (p * a.S + b) * a.cap;
             float w6[6] = {0, 0, 0, 0, 0, 0};
             // Software pipeline over batches of four pairs: while batch c0 runs,
@@ -1231,7 +1235,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
 // [P, P, P, P].
 template <int P>
 __device__ __forceinline__ float quad_bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), P * 0x55, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), P * 0x55, 0xF, 0xF, true));
 }
 
 // Descriptor on the matrix cores (M = 3, K = 4 KQ, blocked work order).  For
@@ -1254,7 +1258,7 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
     extern __shared__ __attribute__((aligned(8))) unsigned char lds_dyn[];
     __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
     __shared__ int32_t wtmp[kBlock / 64];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int quad = lane >> 2, j = lane & 3;
     const int blk = blockIdx.x;
     int x0, y0, z0;
@@ -1265,7 +1269,8 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
     float* sz = sx + 2 * bg.hmax;
     halo_positions(bg, a, x0, y0, z0, h_first, h_base, sx, sy, sz);  // ends with a barrier
     const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
-    // this lane's monomial factors (0/1 weights: the selects stay arithmetic)
+    // this lane's monomial factors s = (1, x, y, z)[j] and v = (xy, z, z, xy)[j],
+    // as 0/1 weights
     const float f1 = j == 0 ? 1.0f : 0.0f, fx = j == 1 ? 1.0f : 0.0f, fy = j == 2 ? 1.0f : 0.0f,
                 fz = j == 3 ? 1.0f : 0.0f;
     const float vz = (j == 1 || j == 2) ? 1.0f : 0.0f, vxy = 1.0f - vz;
@@ -1276,6 +1281,7 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
         mu[kk] = a.mu[4 * kk + j];
         nef[kk] = -a.eta[4 * kk + j] * kLog2e;
     }
+    const float ra4 = 4.0f * a.rec_a, rb4 = 16.0f * a.rec_b, rc4 = a.rec_c4;
     const int KM = K * 4;  // G features of one species
     const int64_t w0 = bg.wbase[blk];
     const int natoms = (int)(bg.wbase[blk + 1] - w0);
@@ -1300,6 +1306,9 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
             const int nb = aval ? a.cnt[(int64_t)b * a.n + p] : 0;
             int nbmax = nb;
             for (int off = 4; off < 64; off <<= 1) nbmax = max(nbmax, __shfl_xor(nbmax, off));
+            // the same in every lane: the batch loop runs under the full EXEC
+            // mask (the DPP broadcasts read every lane of a block)
+            nbmax = __builtin_amdgcn_readfirstlane(nbmax);
             const int64_t row = (p * a.S + b) * a.cap;
             const int cl = a.cap - 1;
             auto entry = [&](int c, int& q, int& im) {
@@ -1325,11 +1334,16 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
             geom(j, qA, iA, dx, dy, dz, act);
             entry(4 + j, qA, iA);
             entry(8 + j, qB, iB);
-            // the MFMAs of pair P of the block
-            auto pair_step = [&](auto pc, float ux, float uy, float uz, float R, float wt) {
+            // The MFMAs of pair P of the block.  The pair's lane hands over its
+            // distance, weight and the products the slices share (each
+            // broadcast feeds one arithmetic instruction, which takes it as a
+            // DPP operand).
+            struct PairVals {
+                float R, wt, ux, uy, uz, xx, yy, xy;
+            };
+            auto pair_step = [&](auto pc, const PairVals& v) {
                 constexpr int P = decltype(pc)::value;
-                const float px = quad_bcast<P>(ux), py = quad_bcast<P>(uy), pz = quad_bcast<P>(uz);
-                const float pR = quad_bcast<P>(R), pw = quad_bcast<P>(wt);
+                const float pR = quad_bcast<P>(v.R);
                 float hB[KQ];
                 if constexpr (RAD == kRadTab) {
                     const float xr = pR * a.tab_inv;
@@ -1342,6 +1356,18 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
 #pragma unroll
                     for (int kk = 0; kk < KQ; ++kk)
                         hB[kk] = fmaf(tt, fmaf(tt, fmaf(tt, c[kk].w, c[kk].z), c[kk].y), c[kk].x);
+                } else if constexpr (RAD == kRadRec) {
+                    // uniform grid: h_{k+4} = h_k r, r = exp2(4 rec_a t_k + 16 rec_b),
+                    // and r gains the factor rec_c^16 per step of four
+                    const float t0 = pR - mu[0];
+                    float e = __builtin_amdgcn_exp2f(nef[0] * t0 * t0);
+                    float r = __builtin_amdgcn_exp2f(fmaf(ra4, t0, rb4));
+#pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk) {
+                        hB[kk] = e;
+                        e *= r;
+                        r *= rc4;
+                    }
                 } else {
 #pragma unroll
                     for (int kk = 0; kk < KQ; ++kk) {
@@ -1349,9 +1375,15 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
                         hB[kk] = __builtin_amdgcn_exp2f(nef[kk] * tk * tk);
                     }
                 }
-                const float s = pw * fmaf(fx, px, fmaf(fy, py, fmaf(fz, pz, f1)));
-                const float xy = px * py;
-                const float Am[4] = {s, px * px * s, py * py * s, fmaf(vz, pz, vxy * xy) * s};
+                // s = w (1, x, y, z)[j], then xx s, yy s and (z or xy) s.  The
+                // lane's choices are 0/1 weights multiplying the broadcasts: a
+                // select of a broadcast value may be compiled into a DPP move
+                // under a partial EXEC mask, which reads the masked-off source
+                // lane as zero.
+                const float c = (quad_bcast<P>(v.ux) * fx + quad_bcast<P>(v.uy) * fy) + (quad_bcast<P>(v.uz) * fz + f1);
+                const float sw = quad_bcast<P>(v.wt) * c;
+                const float t3 = quad_bcast<P>(v.xy) * vxy + quad_bcast<P>(v.uz) * vz;
+                const float Am[4] = {sw, quad_bcast<P>(v.xx) * sw, quad_bcast<P>(v.yy) * sw, t3 * sw};
 #pragma unroll
                 for (int kk = 0; kk < KQ; ++kk)
 #pragma unroll
@@ -1372,10 +1404,11 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
                 float wt;
                 if constexpr (RAD == kRadTab) wt = act ? 1.0f : 0.0f;  // the table has the cutoff folded in
                 else wt = act ? 0.5f * __builtin_amdgcn_cosf(R * a.half_inv_rc) + 0.5f : 0.0f;
-                pair_step(std::integral_constant<int, 0>{}, ux, uy, uz, R, wt);
-                pair_step(std::integral_constant<int, 1>{}, ux, uy, uz, R, wt);
-                pair_step(std::integral_constant<int, 2>{}, ux, uy, uz, R, wt);
-                pair_step(std::integral_constant<int, 3>{}, ux, uy, uz, R, wt);
+                const PairVals v{R, wt, ux, uy, uz, ux * ux, uy * uy, ux * uy};
+                pair_step(std::integral_constant<int, 0>{}, v);
+                pair_step(std::integral_constant<int, 1>{}, v);
+                pair_step(std::integral_constant<int, 2>{}, v);
+                pair_step(std::integral_constant<int, 3>{}, v);
                 dx = ndx;
                 dy = ndy;
                 dz = ndz;
@@ -1395,7 +1428,7 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
                 for (int kk = 0; kk < KQ; ++kk)
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        *reinterpret_cast<f32x4*>(dst + kk * 1024 + q * 64) = acc[kk][q];
+                        __builtin_nontemporal_store(acc[kk][q], reinterpret_cast<f32x4*>(dst + kk * 1024 + q * 64));
             }
             if (aval) {
 #pragma unroll
@@ -1407,16 +1440,16 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
 #pragma unroll
                         for (int i = 0; i < 4; ++i) Pr[0][kMfmaRow[q][i]] = acc[kk][q][i];
                     expand_P<3, 1>(Pr, P);
-                    float g[4];
+                    float gv[4];
 #pragma unroll
                     for (int m = 1; m <= 3; ++m) {
                         float sm = 0.0f;
 #pragma unroll
                         for (int d = kOrderStart[m]; d < kOrderStart[m + 1]; ++d) sm += kMult[d] * P[0][d] * P[0][d];
-                        g[m] = sm;
+                        gv[m] = sm;
                     }
-                    g[0] = fabsf(P[0][0]);  // sqrt(S) of the single order-0 component
-                    *reinterpret_cast<float4*>(a.G + p * a.F + b * KM + 4 * k) = make_float4(g[0], g[1], g[2], g[3]);
+                    gv[0] = fabsf(P[0][0]);  // sqrt(S) of the single order-0 component
+                    *reinterpret_cast<float4*>(a.G + p * a.F + b * KM + 4 * k) = make_float4(gv[0], gv[1], gv[2], gv[3]);
                 }
             }
         }
@@ -1668,7 +1701,8 @@ BlockedFn select_desc_mfma_r(int kq) {
     }
 }
 BlockedFn select_desc_mfma(int rad, int kq) {
-    return rad == kRadTab ? select_desc_mfma_r<kRadTab>(kq) : select_desc_mfma_r<kRadDirect>(kq);
+    return rad == kRadTab ? select_desc_mfma_r<kRadTab>(kq)
+                          : rad == kRadRec ? select_desc_mfma_r<kRadRec>(kq) : select_desc_mfma_r<kRadDirect>(kq);
 }
 
 BlockedFn select_blocked(int rad, int kc, int M, bool pair2) {
@@ -1695,6 +1729,7 @@ PathArgs make_args(const tmd_model* m, const tmd_nlist* nl) {
     a.rec_a = m->rec_a;
     a.rec_b = m->rec_b;
     a.rec_c = m->rec_c;
+    a.rec_c4 = m->rec_c4;
     a.rec_m2eta = m->rec ? (float)(-2.0 * m->eta_h[0]) : 0.0f;
     a.rec_delta = m->rec ? (float)(m->mu_h[1] - m->mu_h[0]) : 0.0f;
     a.tab = m->tab;
@@ -1849,10 +1884,11 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     if (nl->wo_valid && mfma_adjoint(m)) {
         const BlockGeom bg = wo_geom(nl);
         const unsigned grid = (unsigned)bg.nb[0] * bg.nb[1] * bg.nb[2];
-        auto fn = select_desc_mfma(m->tab ? kRadTab : kRadDirect, m->K / 4);
+        auto fn = select_desc_mfma(m->tab ? kRadTab : (m->rec4 ? kRadRec : kRadDirect), m->K / 4);
+        const size_t lds = sizeof(float) * 3 * (size_t)bg.hmax;  // halo positions
         {
             ProfScope ps_(ctx, "descriptor");
-            fn<<<grid, kBlock, sizeof(float) * 3 * (size_t)bg.hmax, ctx->stream>>>(a, bg);
+            fn<<<grid, kBlock, lds, ctx->stream>>>(a, bg);
         }
         TMD_HIP(ctx, hipGetLastError());
         return TMD_OK;

@@ -123,6 +123,12 @@ struct tmd_model {
     // when no value of a chunk can underflow before the chunk's last one.
     bool rec = false;
     float rec_a = 0.0f, rec_b = 0.0f, rec_c = 0.0f;
+    // The same in steps of four radial functions (ratio exp2(4 rec_a t_k +
+    // 16 rec_b), which gains rec_c4 = rec_c^16 per step), set when none of
+    // those ratios or the first Gaussian of a lane (k = 0..3) can leave the
+    // FP32 range.
+    bool rec4 = false;
+    float rec_c4 = 0.0f;
     std::vector<double> mu_h, eta_h;  // host FP64 copies (table construction)
     // Tabulated radial functions (cubic Hermite on nodes tab_delta apart):
     // tab [(tab_n + 1)][K] float4 = (c0, c1, c2, c3) of h_k = c0 + t(c1 + t(c2 + t c3))
