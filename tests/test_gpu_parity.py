@@ -295,6 +295,34 @@ def test_energy_forces_non_uniform_radial_grid(tmd, ctx, torch, grid):
     _check_ef(E, Ea, F, W, s, spec, 0)
 
 
+@pytest.mark.parametrize("K", [8, 12, 16])
+@pytest.mark.parametrize("radial", ["uniform", "jittered_mu", "table"])
+def test_matrix_core_shapes(tmd, ctx, torch, K, radial):
+    """M = 3 with K = 8, 12 and 16 on 6 x 6 x 6 bcc cells with r_c 6 A: three
+    list cells per edge, so the list has a work order and the descriptor and
+    adjoint run on the matrix cores (K / 4 groups of radial functions per lane).
+    Uniform grid (stride-four recurrence), jittered centres (direct Gaussians)
+    and the table; G element by element and E, F, virial against the oracle."""
+    import dataclasses
+    s = inputs.make_system("bcc", 3.16, (6, 6, 6), 0.1, 2, seed=60 + K)
+    spec = inputs.make_model(2, K, 3, [64, 64], 6.0, seed=61)
+    if radial == "jittered_mu":
+        rng = np.random.default_rng(62)
+        spec = dataclasses.replace(spec, mu=spec.mu + rng.uniform(-0.05, 0.05, size=spec.mu.shape))
+    elif radial == "table":
+        spec = dataclasses.replace(spec, tab_dr=0.01)
+    _note(f"matrix-core path K={K} M=3 radial={radial} n={s.n}")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx)
+    G = ev.descriptors(pos, sp, s.box).cpu().numpy().astype(np.float64)
+    Gr = oracle.descriptors(spec, s.pos, s.species, s.box)
+    err = np.abs(G - Gr) / (np.abs(Gr) + 1.0)
+    print(f"  max scaled G err {err.max():.3e}", flush=True)
+    assert err.max() <= 2e-5
+    E, Ea, F, W = ev.energy_forces(pos, sp, s.box)
+    _check_ef(E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, s, spec, 0)
+
+
 @pytest.mark.parametrize("K,hidden", [(32, [128, 128, 128]), (128, [128, 128, 128, 128])])
 @pytest.mark.parametrize("a", [3.1887, 2.8])
 @pytest.mark.parametrize("prec", [0, 1])
