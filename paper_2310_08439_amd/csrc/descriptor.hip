@@ -244,6 +244,19 @@ __device__ __forceinline__ void store_tile(float* dst, int64_t n, const float (&
     }
 }
 
+// The same tile in the atom-major layout [n][S][K][DR] (the large-K
+// matrix-core adjoint reads one atom's P at a time): KC x D consecutive
+// floats, stored as float4s.
+template <int KC, int D>
+__device__ __forceinline__ void store_tile_am(float* dst, const float (&P)[KC][D]) {
+    static_assert((KC * D) % 4 == 0, "whole float4s");
+#pragma unroll
+    for (int q = 0; q < KC * D; q += 4)
+        *reinterpret_cast<float4*>(dst + q) =
+            make_float4(P[q / D][q % D], P[(q + 1) / D][(q + 1) % D], P[(q + 2) / D][(q + 2) % D],
+                        P[(q + 3) / D][(q + 3) % D]);
+}
+
 template <int KC, int D>
 __device__ __forceinline__ void load_tile(const float* src, int64_t n, float (&P)[KC][D]) {
 #pragma unroll
@@ -351,7 +364,8 @@ __device__ __forceinline__ void accumulate_P(const PathArgs& a, int64_t p, int b
     }
 }
 
-template <int KC, int M, bool TAB, bool NT>
+// PL: where P goes (0 element-major, 1 element-major non-temporal, 2 atom-major).
+template <int KC, int M, bool TAB, int PL>
 __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a, int64_t nblocks) {
     constexpr int D = Moments<M>::D, DR = Moments<M>::DR;
     constexpr int GW = KC * (M + 1);  // features of one thread's chunk
@@ -389,7 +403,12 @@ __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a,
         if (active) {
             float Pr[KC][DR], P[KC][D];
             accumulate_P<KC, M, TAB>(a, p, b, ch * KC, mu, nef, Pr, pos);
-            if (a.Pbuf) store_tile<KC, DR, NT>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * DR) * a.n + w, a.n, Pr);
+            if (a.Pbuf) {
+                if constexpr (PL == 2)
+                    store_tile_am<KC, DR>(a.Pbuf + (((int64_t)w * a.S + b) * a.K + ch * KC) * DR, Pr);
+                else
+                    store_tile<KC, DR, PL == 1>(a.Pbuf + ((int64_t)(b * a.K + ch * KC) * DR) * a.n + w, a.n, Pr);
+            }
             expand_P<M, KC>(Pr, P);
             float* seg = &sg[wv][(lane >> a.nch_log2) * RWp + (b - b0) * KM + ch * GW];
 #pragma unroll
@@ -1456,6 +1475,267 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
     }
 }
 
+// Adjoint on the matrix cores for larger K (M = 3, K = 4 KS >= 24), one
+// atom per wave at a time, its pairs sixteen at a time.  With E the group's
+// radial functions (K x 16 pairs), V1 = P'^T E and V2 = (k P')^T E (on a
+// uniform grid; else P'^T H and P'^T H') are 16 x 16 products over K, taken as
+// v_mfma_f32_16x16x4f32 steps of four radial functions.  The A operand (row i
+// = kept component, column = radial function 4 s + g from lane group g =
+// lane / 16) stays in registers for the atom's whole row: K / 4 values of P'
+// and of k P' per lane, formed from the atom-major P and dE/dG.  The B
+// operand is the radial function 4 s + g of the lane's pair (pair = lane %
+// 16).  Lane l ends with rows 4 g .. 4 g + 3 of its pair's column; row 4 g + r
+// is kept component kMfmaRow[r][g], so a lane group holds the fold set
+// s_g (1, xx, yy, v_g) of the 4x4x1 kernels: each lane forms its share of
+// S0 = M.V1, S1 = M.V2 and A = sum_d V1_d grad M_d from its four rows, two
+// exchanges (lanes 16 and 32 apart) complete them, lane groups 0, 1, 2
+// scatter the force components x, y, z and group 3 adds the virial.
+template <int KS, int RAD>
+__global__ void __launch_bounds__(256, 2) k_adjoint_mfma16(PathArgs a, BlockGeom bg) {
+    constexpr int K = 4 * KS, DR = Moments<3>::DR;
+    extern __shared__ __attribute__((aligned(8))) unsigned char lds_dyn[];
+    __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
+    __shared__ int32_t wtmp[kBlock / 64];
+    __shared__ double red[6][kBlock / 64][2];
+    __shared__ float2 rad_mm[RAD == kRadDirect ? K : 1];  // (mu_k, -2 eta_k)
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int jp = lane & 15, gq = lane >> 4;
+    const int blk = blockIdx.x;
+    int x0, y0, z0;
+    halo_slots(bg, blk, h_first, h_base, hoff, wtmp, x0, y0, z0);
+    const int HX = bg.B[0] + 2, HY = bg.B[1] + 2, HZ = bg.B[2] + 2;
+    const int nh = HX * HY * HZ;
+    const int hpos = (3 * bg.hmax + 1) & ~1;
+    float* sx = reinterpret_cast<float*>(lds_dyn);
+    float* sy = sx + bg.hmax;
+    float* sz = sx + 2 * bg.hmax;
+    unsigned long long* sF = reinterpret_cast<unsigned long long*>(sx + hpos);
+    const int htot = h_base[nh];
+    for (int i = t; i < htot; i += kBlock) {
+        sF[i] = 0ull;
+        sF[bg.hmax + i] = 0ull;
+        sF[2 * bg.hmax + i] = 0ull;
+    }
+    if constexpr (RAD == kRadDirect)
+        for (int k = t; k < K; k += kBlock) rad_mm[k] = make_float2(a.mu[k], -2.0f * a.eta[k]);
+    halo_positions(bg, a, x0, y0, z0, h_first, h_base, sx, sy, sz);  // ends with a barrier
+    const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
+    // A side: this lane supplies row jp = 4 gi + ri, kept component kMfmaRow[ri][gi]
+    const int gi = jp >> 2, ri = jp & 3;
+    const int ia0 = kMfmaRow[0][gi], ia1 = kMfmaRow[1][gi], ia2 = kMfmaRow[2][gi], ia3 = kMfmaRow[3][gi];
+    // 2 x multiplicities in fold set gi (as in k_adjoint_mfma) and 0/1 weights
+    const float c2b = gi <= 1 ? 2.0f : 6.0f;
+    const float c2c = (gi & 1) ? 6.0f : 2.0f;
+    const float c2f = gi == 3 ? 12.0f : 4.0f;
+    const float c2d = (gi == 0 || gi == 3) ? 2.0f : 6.0f;
+    const float sel0 = gi == 0 ? 1.0f : 0.0f, sel1 = 1.0f - sel0, sel3 = gi == 3 ? 1.0f : 0.0f, sel3c = 1.0f - sel3;
+    const float wr0 = ri == 0 ? 1.0f : 0.0f, wr1 = ri == 1 ? 1.0f : 0.0f, wr2 = ri == 2 ? 1.0f : 0.0f,
+                wr3 = ri == 3 ? 1.0f : 0.0f;
+    // C side: this lane's rows are fold set gq, monomials s (1, xx, yy, v)
+    const float f1 = gq == 0 ? 1.0f : 0.0f, fx = gq == 1 ? 1.0f : 0.0f, fy = gq == 2 ? 1.0f : 0.0f,
+                fz = gq == 3 ? 1.0f : 0.0f;
+    const float vz = (gq == 1 || gq == 2) ? 1.0f : 0.0f, vxy = 1.0f - vz;
+    float mu_g = 0.0f, nef_g = 0.0f, mu0 = 0.0f;
+    if constexpr (RAD == kRadRec) {
+        mu_g = a.mu[gq];
+        nef_g = -a.eta[gq] * kLog2e;
+        mu0 = a.mu[0];
+    }
+    const float ra4 = 4.0f * a.rec_a, rb4 = 16.0f * a.rec_b, rc4 = a.rec_c4;
+    const int64_t w0 = bg.wbase[blk];
+    const int natoms = (int)(bg.wbase[blk + 1] - w0);
+    double Wd[6] = {0, 0, 0, 0, 0, 0};
+    for (int ia = wv; ia < natoms; ia += kBlock / 64) {
+        const int64_t w = w0 + ia;
+        const int64_t p = bg.wperm[w];
+        const int ic = bg.wcell[w];
+        const int ix = ic % bg.B[0] + 1, iy = (ic / bg.B[0]) % bg.B[1] + 1, iz = ic / (bg.B[0] * bg.B[1]) + 1;
+        const int hp = (iz * HY + iy) * HX + ix;
+        const int ip = hoff[hp] + (int)p;
+        const LdsPos pos{sx, sy, sz, hoff, hp - (HX * HY + HX + 1), HX, HX * HY,
+                         sx[ip] + cw[0], sy[ip] + cw[1], sz[ip] + cw[2], cw[0], cw[1], cw[2]};
+        float Fo = 0.0f;  // component gq (< 3) of the centre atom's force, this lane's pairs
+        for (int b = 0; b < a.S; ++b) {
+            // this lane's A operands: P' (folded onto the kept basis) and k P'
+            float A1[KS], A2[KS];
+            const float* Pa = a.Pbuf + ((int64_t)w * a.S + b) * (K * DR);
+            const float4* g4 = reinterpret_cast<const float4*>(a.dG + p * a.F + (int64_t)b * K * 4);
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                const int k = 4 * st + gq;
+                const float* Pk = Pa + k * DR;
+                const float pa = Pk[ia0], pb = Pk[ia1], pc = Pk[ia2], pf = Pk[ia3];
+                const float4 g = g4[k];
+                const float ga = fmaf(sel0, g.x, sel1 * g.y), gbc = fmaf(sel0, g.z, sel1 * g.w),
+                            gf = fmaf(sel3, g.w, sel3c * g.z);
+                const float pd = c2d * gbc * (pa - pb - pc);
+                const float sg = (pa > 0.0f ? 1.0f : 0.0f) - (pa < 0.0f ? 1.0f : 0.0f);
+                const float pa1 = ga * fmaf(sel0, sg, sel1 * 2.0f * pa);
+                const float v0 = pa1 + pd, v1 = fmaf(c2b * gbc, pb, -pd), v2 = fmaf(c2c * gbc, pc, -pd),
+                            v3 = c2f * gf * pf;
+                A1[st] = fmaf(wr0, v0, fmaf(wr1, v1, fmaf(wr2, v2, wr3 * v3)));
+                A2[st] = (float)k * A1[st];
+            }
+            const int nb = __builtin_amdgcn_readfirstlane(a.cnt[(int64_t)b * a.n + p]);
+            const int64_t row = (p * a.S + b) * a.cap;
+            float w6[6] = {0, 0, 0, 0, 0, 0};
+            // Pipeline over the groups of sixteen pairs: while group c0 runs,
+            // the displacements of group c0 + 16 are formed (LDS) and the list
+            // entries of group c0 + 32 are loaded.  Entry indices are clamped
+            // into the row's slots; columns past the row's end read the centre
+            // atom and are inactive (unit displacement, zero B).
+            const int cl = a.cap - 1;
+            auto entry = [&](int c, int& q, int& im) {
+                const int cc = min(c, cl);
+                q = a.nbr[row + cc];
+                im = a.img[row + cc];
+            };
+            auto geom = [&](int c, int q, int im, float& gdx, float& gdy, float& gdz, int& gslot, bool& gact) {
+                const bool valid = c < nb;
+                const int ii = valid ? im : kCentreWord;
+                const float4 xj = pos.fetch(valid ? q : (int)p, ii, gslot);
+                const float3 dm = pos.disp(xj, ii);
+                gact = valid && dm.x * dm.x + dm.y * dm.y + dm.z * dm.z < a.rc2;
+                gdx = gact ? dm.x : 1.0f;
+                gdy = gact ? dm.y : 0.0f;
+                gdz = gact ? dm.z : 0.0f;
+            };
+            float dx, dy, dz;
+            int slot, qe, ie;
+            bool act;
+            entry(jp, qe, ie);
+            geom(jp, qe, ie, dx, dy, dz, slot, act);
+            entry(16 + jp, qe, ie);
+            for (int c0 = 0; c0 < nb; c0 += 16) {
+                float ndx, ndy, ndz;
+                int nslot;
+                bool nact;
+                geom(c0 + 16 + jp, qe, ie, ndx, ndy, ndz, nslot, nact);
+                entry(c0 + 32 + jp, qe, ie);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float R = r2 * rinv;
+                const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+                float fc = 0.0f, dfc = 0.0f;
+                if constexpr (RAD != kRadTab) {
+                    const float ang = R * a.half_inv_rc;
+                    fc = act ? 0.5f * __builtin_amdgcn_cosf(ang) + 0.5f : 0.0f;
+                    dfc = act ? -0.5f * a.pi_over_rc * __builtin_amdgcn_sinf(ang) : 0.0f;
+                }
+                // two accumulation chains per product (even and odd steps)
+                f32x4 acc1 = {0.0f, 0.0f, 0.0f, 0.0f}, acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+                f32x4 acc1b = {0.0f, 0.0f, 0.0f, 0.0f}, acc2b = {0.0f, 0.0f, 0.0f, 0.0f};
+                auto step = [&](int st, float A1s, float A2s, float B1s, float B2s) {
+                    if (st & 1) {
+                        acc1b = __builtin_amdgcn_mfma_f32_16x16x4f32(A1s, B1s, acc1b, 0, 0, 0);
+                        acc2b = __builtin_amdgcn_mfma_f32_16x16x4f32(A2s, B2s, acc2b, 0, 0, 0);
+                    } else {
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A1s, B1s, acc1, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(A2s, B2s, acc2, 0, 0, 0);
+                    }
+                };
+                if constexpr (RAD == kRadRec) {
+                    // e_{4 s + g} by the stride-four recurrence, cutoff applied after
+                    const float t0 = R - mu_g;
+                    float e = act ? __builtin_amdgcn_exp2f(nef_g * t0 * t0) : 0.0f;
+                    float rr = __builtin_amdgcn_exp2f(fmaf(ra4, t0, rb4));
+#pragma unroll
+                    for (int st = 0; st < KS; ++st) {
+                        step(st, A1[st], A2[st], e, e);
+                        e *= rr;
+                        rr *= rc4;
+                    }
+                } else if constexpr (RAD == kRadTab) {
+                    const float xr = R * a.tab_inv;
+                    const float jf = fminf(floorf(xr), (float)a.tab_n);
+                    const float tt = xr - jf;
+                    const float4* trow = a.tab + (int64_t)jf * K + gq;
+                    const float msk = act ? 1.0f : 0.0f;
+#pragma unroll
+                    for (int st = 0; st < KS; ++st) {
+                        const float4 cf = trow[4 * st];
+                        const float h = msk * fmaf(tt, fmaf(tt, fmaf(tt, cf.w, cf.z), cf.y), cf.x);
+                        const float dh = msk * a.tab_inv * fmaf(tt, fmaf(3.0f * tt, cf.w, 2.0f * cf.z), cf.y);
+                        step(st, A1[st], A1[st], h, dh);
+                    }
+                } else {
+#pragma unroll
+                    for (int st = 0; st < KS; ++st) {
+                        const float2 mm = rad_mm[4 * st + gq];
+                        const float tk = R - mm.x;
+                        const float e = __builtin_amdgcn_exp2f(0.5f * kLog2e * mm.y * tk * tk);
+                        step(st, A1[st], A1[st], e * fc, e * fmaf(mm.y * tk, fc, dfc));
+                    }
+                }
+                acc1 += acc1b;
+                acc2 += acc2b;
+                // this lane's rows: V1, V2 at s (1, xx, yy, v) of fold set gq
+                const float sm = fmaf(fx, ux, fmaf(fy, uy, fmaf(fz, uz, f1)));
+                const float xx = ux * ux, yy = uy * uy, xy = ux * uy;
+                const float vv = fmaf(vxy, xy, vz * uz);
+                const float Q1 = fmaf(vv, acc1[3], fmaf(yy, acc1[2], fmaf(xx, acc1[1], acc1[0])));
+                const float Q2 = fmaf(vv, acc2[3], fmaf(yy, acc2[2], fmaf(xx, acc2[1], acc2[0])));
+                float S0 = sm * Q1, S1 = sm * Q2;
+                float Ax = fmaf(fx, Q1, sm * fmaf(2.0f * ux, acc1[1], vxy * uy * acc1[3]));
+                float Ay = fmaf(fy, Q1, sm * fmaf(2.0f * uy, acc1[2], vxy * ux * acc1[3]));
+                float Az = fmaf(fz, Q1, sm * vz * acc1[3]);
+#pragma unroll
+                for (int off = 16; off <= 32; off <<= 1) {
+                    S0 += __shfl_xor(S0, off);
+                    S1 += __shfl_xor(S1, off);
+                    Ax += __shfl_xor(Ax, off);
+                    Ay += __shfl_xor(Ay, off);
+                    Az += __shfl_xor(Az, off);
+                }
+                const float Bu = ux * Ax + uy * Ay + uz * Az;
+                float sr, rf;
+                if constexpr (RAD == kRadRec) {
+                    sr = fmaf(a.rec_m2eta * fc, fmaf(-a.rec_delta, S1, (R - mu0) * S0), dfc * S0);
+                    rf = rinv * fc;
+                } else {
+                    sr = S1;
+                    rf = rinv;
+                }
+                const float gx = sr * ux + rf * (Ax - ux * Bu);
+                const float gy = sr * uy + rf * (Ay - uy * Bu);
+                const float gz = sr * uz + rf * (Az - uz * Bu);
+                if (act) {
+                    if (gq < 3) {
+                        const float gc = gq == 0 ? gx : (gq == 1 ? gy : gz);
+                        atomicAdd(&sF[gq * bg.hmax + slot], to_fixed(-gc));
+                        Fo += gc;
+                    } else {
+                        virial_add(w6, dx, dy, dz, gx, gy, gz);
+                    }
+                }
+                dx = ndx;
+                dy = ndy;
+                dz = ndz;
+                slot = nslot;
+                act = nact;
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Wd[i] += (double)w6[i];
+        }
+        // the centre atom's force: each lane group's sixteen pair columns, fixed order
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) Fo += __shfl_xor(Fo, off);
+        if (jp == 0 && gq < 3) atomicAdd(&sF[gq * bg.hmax + ip], to_fixed(Fo));
+    }
+    __syncthreads();
+    for (int hc = wv; hc < nh; hc += kBlock / 64) {
+        const int lo = h_base[hc], cnt = h_base[hc + 1] - lo;
+        for (int k = lane; k < cnt; k += 64) {
+            const int64_t q = h_first[hc] + k;
+            const unsigned long long fx_ = sF[lo + k], fy_ = sF[bg.hmax + lo + k], fz_ = sF[2 * bg.hmax + lo + k];
+            if (fx_) atomicAdd(&bg.F[3 * q + 0], fx_);
+            if (fy_) atomicAdd(&bg.F[3 * q + 1], fy_);
+            if (fz_) atomicAdd(&bg.F[3 * q + 2], fz_);
+        }
+    }
+    block_virial(Wd, red, a.vir + (int64_t)blockIdx.x * kVirDoubles);
+}
+
 // ---- work order ----------------------------------------------------------
 //
 // Rows of one wave run in lockstep, so a wave costs the longest of its rows.
@@ -1608,18 +1888,21 @@ using PathFn = void (*)(PathArgs, int64_t);
 using AtomicFn = void (*)(PathArgs, unsigned long long*);
 using BlockedFn = void (*)(PathArgs, BlockGeom);
 
-template <int KC, bool TAB, bool NT>
+template <int KC, bool TAB, int PL>
 PathFn pick_desc_nt(int M) {
     switch (M) {
-        case 0: return k_descriptor<KC, 0, TAB, NT>;
-        case 1: return k_descriptor<KC, 1, TAB, NT>;
-        case 2: return k_descriptor<KC, 2, TAB, NT>;
-        default: return k_descriptor<KC, 3, TAB, NT>;
+        case 0: return k_descriptor<KC, 0, TAB, PL>;
+        case 1: return k_descriptor<KC, 1, TAB, PL>;
+        case 2: return k_descriptor<KC, 2, TAB, PL>;
+        default: return k_descriptor<KC, 3, TAB, PL>;
     }
 }
+// pl 2 (atom-major P) only for M = 3 with chunks of four or six
 template <int KC, bool TAB>
-PathFn pick_desc(int M, bool nt) {
-    return nt ? pick_desc_nt<KC, TAB, true>(M) : pick_desc_nt<KC, TAB, false>(M);
+PathFn pick_desc(int M, int pl) {
+    if constexpr (KC == 4 || KC == 6)
+        if (pl == 2) return k_descriptor<KC, 3, TAB, 2>;
+    return pl == 1 ? pick_desc_nt<KC, TAB, 1>(M) : pick_desc_nt<KC, TAB, 0>(M);
 }
 template <int KC, int RAD>
 AtomicFn pick_atomic(int M) {
@@ -1648,12 +1931,12 @@ BlockedFn pick_blocked(int M, bool pair2) {
 }
 
 template <bool TAB>
-PathFn select_desc(int kc, int M, bool nt) {
+PathFn select_desc(int kc, int M, int pl) {
     switch (kc) {
-        case 3: return pick_desc<3, TAB>(M, nt);
-        case 4: return pick_desc<4, TAB>(M, nt);
-        case 6: return pick_desc<6, TAB>(M, nt);
-        default: return pick_desc<8, TAB>(M, nt);
+        case 3: return pick_desc<3, TAB>(M, pl);
+        case 4: return pick_desc<4, TAB>(M, pl);
+        case 6: return pick_desc<6, TAB>(M, pl);
+        default: return pick_desc<8, TAB>(M, pl);
     }
 }
 template <int RAD>
@@ -1700,6 +1983,22 @@ BlockedFn select_desc_mfma_r(int kq) {
         default: return k_descriptor_mfma<4, RAD>;
     }
 }
+template <int RAD>
+BlockedFn select_mfma16_r(int ks) {
+    switch (ks) {
+        case 6: return k_adjoint_mfma16<6, RAD>;
+        case 8: return k_adjoint_mfma16<8, RAD>;
+        case 12: return k_adjoint_mfma16<12, RAD>;
+        case 16: return k_adjoint_mfma16<16, RAD>;
+        case 24: return k_adjoint_mfma16<24, RAD>;
+        default: return k_adjoint_mfma16<32, RAD>;
+    }
+}
+BlockedFn select_mfma16(int rad, int ks) {
+    return rad == kRadTab ? select_mfma16_r<kRadTab>(ks)
+                          : rad == kRadRec ? select_mfma16_r<kRadRec>(ks) : select_mfma16_r<kRadDirect>(ks);
+}
+
 BlockedFn select_desc_mfma(int rad, int kq) {
     return rad == kRadTab ? select_desc_mfma_r<kRadTab>(kq)
                           : rad == kRadRec ? select_desc_mfma_r<kRadRec>(kq) : select_desc_mfma_r<kRadDirect>(kq);
@@ -1756,6 +2055,14 @@ unsigned path_grid(const tmd_model* m, const tmd_nlist* nl) {
 // so the descriptor's chunking need not match the adjoint's (m->kc).
 // Measured: four per thread beat eight for K = 32 and 128 with M = 3.
 int desc_kc(const tmd_model* m) { return (m->M == 3 && m->kc == 8) ? 4 : m->kc; }
+
+// The 16x16x4 matrix-core adjoint takes M = 3 and K = 24 .. 128 (K / 4 steps
+// of four radial functions), reading P in the atom-major layout that the
+// descriptor writes with chunks of four or six.
+bool mfma16_adjoint(const tmd_model* m) {
+    const int kcd = desc_kc(m);
+    return m->M == 3 && m->K >= 24 && m->K <= 128 && m->K % 4 == 0 && (kcd == 4 || kcd == 6);
+}
 
 int log2_int(int v) {
     int lg = 0;
@@ -1896,8 +2203,10 @@ tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nl
     const int kcd = desc_kc(m);
     a.nch_log2 = log2_int(m->K / kcd);
     // P stores cover whole 128-byte lines (and go out non-temporally) with at most two chunks per atom
-    const bool nt = a.nch_log2 <= 1;
-    auto fn = m->tab ? select_desc<true>(kcd, m->M, nt) : select_desc<false>(kcd, m->M, nt);
+    // atom-major P for the 16x16x4 adjoint; else element-major, non-temporal
+    // when the stores cover whole lines
+    const int pl = (nl->wo_valid && mfma16_adjoint(m)) ? 2 : (a.nch_log2 <= 1 ? 1 : 0);
+    auto fn = m->tab ? select_desc<true>(kcd, m->M, pl) : select_desc<false>(kcd, m->M, pl);
     const int64_t nblocks = (nl->n * (m->K / kcd) + kBlock - 1) / kBlock;
     {
         ProfScope ps_(ctx, "descriptor");
@@ -1928,7 +2237,10 @@ tmd_status launch_adjoint(tmd_context* ctx, const tmd_model* m, const tmd_nlist*
         a.nch_log2 = log2_int(m->K / kca);
         const bool pair2 = m->K / kca == 2;  // two chunk lanes per atom share the pair geometry
         const int rad = m->tab ? kRadTab : (m->rec ? kRadRec : kRadDirect);
-        auto fn = mfma_adjoint(m) ? select_mfma(rad, m->K / 4) : select_blocked(rad, kca, m->M, pair2);
+        const int rad4 = m->tab ? kRadTab : (m->rec4 ? kRadRec : kRadDirect);  // stride-four recurrence
+        auto fn = mfma_adjoint(m)     ? select_mfma(rad, m->K / 4)
+                  : mfma16_adjoint(m) ? select_mfma16(rad4, m->K / 4)
+                                      : select_blocked(rad, kca, m->M, pair2);
         {
             ProfScope ps_(ctx, "adjoint");
             fn<<<grid, kBlock, blocked_lds_bytes(bg.hmax), ctx->stream>>>(a, bg);

@@ -323,6 +323,29 @@ def test_matrix_core_shapes(tmd, ctx, torch, K, radial):
     _check_ef(E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, s, spec, 0)
 
 
+@pytest.mark.parametrize("K", [24, 32, 64, 128])
+@pytest.mark.parametrize("radial", ["uniform_wide", "uniform", "jittered_mu", "table"])
+def test_matrix_core_large_k(tmd, ctx, torch, K, radial):
+    """M = 3 with K = 24 .. 128 on 6 x 6 x 6 bcc cells (two species, r_c 6 A,
+    three list cells per edge): the 16x16x4 matrix-core adjoint with the
+    atom-major P.  Radial functions: a uniform grid of wide Gaussians (eta 2,
+    where the stride-four recurrence holds), the default narrow uniform grid
+    (direct Gaussians), jittered centres and the table."""
+    import dataclasses
+    s = inputs.make_system("bcc", 3.1887, (6, 6, 6), 0.08, 2, seed=70 + K, masses=[183.84, 95.95])
+    spec = inputs.make_model(2, K, 3, [32], 6.0, seed=71, activation=inputs.ACT_SQUAREPLUS)
+    if radial == "uniform_wide":
+        spec = dataclasses.replace(spec, eta=np.full(K, 2.0))
+    elif radial == "jittered_mu":
+        rng = np.random.default_rng(72)
+        spec = dataclasses.replace(spec, mu=spec.mu + rng.uniform(-0.02, 0.02, size=spec.mu.shape))
+    elif radial == "table":
+        spec = dataclasses.replace(spec, tab_dr=0.01)
+    _note(f"matrix-core large K={K} radial={radial} n={s.n}")
+    E, Ea, F, W, _ = _gpu_eval(tmd, ctx, spec, s, 0)
+    _check_ef(E, Ea, F, W, s, spec, 0)
+
+
 @pytest.mark.parametrize("K,hidden", [(32, [128, 128, 128]), (128, [128, 128, 128, 128])])
 @pytest.mark.parametrize("a", [3.1887, 2.8])
 @pytest.mark.parametrize("prec", [0, 1])
