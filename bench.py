@@ -29,11 +29,28 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
+def padded_k(K: int) -> int:
+    """The radial functions the kernels run for a model of K: the smallest 4, 6
+    or 8 times a power of two (at most 64 chunks) that is at least K."""
+    def chunked(k):
+        return any(k % kc == 0 and (k // kc) & (k // kc - 1) == 0 and k // kc <= 64 for kc in (8, 6, 4))
+    return next(k for k in range(max(K, 4), 129) if chunked(k))
+
+
 def adjoint_unit(spec):
-    """The unit that sets the adjoint's pace: the library runs the contractions
-    on the FP32 matrix cores for M = 3 and K = 8, 12 or 16 (the model's K is
-    then not padded), else on the vector ALUs; both peaks are 157.3 TFLOP/s."""
-    if spec.max_moment == 3 and spec.n_radial in (8, 12, 16):
+    """The unit that sets the adjoint's pace on a list with a work order: the
+    library runs its contractions on the FP32 matrix cores for M = 3 and a
+    padded K of 8 or more (4x4x1 MFMAs up to K = 16, 16x16x4 beyond), else on
+    the vector ALUs; both peaks are 157.3 TFLOP/s."""
+    if spec.max_moment == 3 and padded_k(spec.n_radial) >= 8:
+        return "mfma", PEAK_FP32_MFMA_TFLOPS
+    return "alu", PEAK_FP32_VECTOR_TFLOPS
+
+
+def descriptor_unit(spec):
+    """The descriptor's contraction runs on the FP32 matrix cores (4x4x1
+    MFMAs) for M = 3 and a padded K of 8, 12 or 16, else on the vector ALUs."""
+    if spec.max_moment == 3 and padded_k(spec.n_radial) in (8, 12, 16):
         return "mfma", PEAK_FP32_MFMA_TFLOPS
     return "alu", PEAK_FP32_VECTOR_TFLOPS
 
@@ -96,7 +113,8 @@ def kernel_rooflines(workload: str, spec, flops: dict, avg_ms: dict) -> dict:
     HBM GB/s against 8 TB/s."""
     out = {}
     adj_unit, adj_peak = adjoint_unit(spec)
-    for name, unit, peak in (("adjoint", adj_unit, adj_peak), ("descriptor", "alu", PEAK_FP32_VECTOR_TFLOPS),
+    desc_unit, desc_peak = descriptor_unit(spec)
+    for name, unit, peak in (("adjoint", adj_unit, adj_peak), ("descriptor", desc_unit, desc_peak),
                              ("mlp", "mfma", PEAK_BF16_MFMA_TFLOPS)):
         if name not in avg_ms:
             continue
@@ -586,8 +604,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--no-extra", action="store_true", help="skip the training and serving legs")
-    ap.add_argument("--mode", default="step", choices=["step", "copy"],
-                    help="copy: 3 device copies of 1 GiB, to calibrate HBM byte counters")
+    ap.add_argument("--mode", default="step", choices=["step", "copy", "paper"],
+                    help="copy: 3 device copies of 1 GiB, to calibrate HBM byte counters; "
+                         "paper: only the paper-shaped workloads (for profiling their kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the multi-GPU (spatial decomposition) path is a design, "
@@ -606,6 +625,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_copy": src.numel() * 4,
                           "bytes_written_per_copy": dst.numel() * 4}), flush=True)
+        return
+    if args.mode == "paper":
+        ctx = tmd.Context(0)
+        print(json.dumps({"mode": "paper", "paper_shapes": paper_shapes_leg(tmd, torch, ctx, args.steps,
+                                                                             args.warmup)}), flush=True)
+        ctx.close()
         return
 
     s, spec, skin = inputs.workload(args.workload)
