@@ -244,17 +244,25 @@ __device__ __forceinline__ void store_tile(float* dst, int64_t n, const float (&
     }
 }
 
-// The same tile in the atom-major layout [n][S][K][DR] (the large-K
-// matrix-core adjoint reads one atom's P at a time): KC x D consecutive
-// floats, stored as float4s.
+// Kept components (reduced index) of the matrix-core kernels' slices:
+// entry n of slice q is kMfmaRow[q][n]; column n, (kMfmaRow[0..3][n]), is fold
+// set n: the three kept components tied by the unit-norm identity to one
+// dropped component, and one more.
+__device__ constexpr int kMfmaRow[4][4] = {{0, 1, 2, 3}, {4, 9, 10, 11}, {7, 12, 14, 15}, {5, 6, 8, 13}};
+
+// The same tile (M = 3) in the atom-major layout [n][S][K][4][4] read by the
+// large-K matrix-core adjoint, one atom at a time: per radial function the
+// four fold sets, each a float4 (kMfmaRow[0..3][g]), so that a lane loads its
+// fold set with one instruction.
 template <int KC, int D>
 __device__ __forceinline__ void store_tile_am(float* dst, const float (&P)[KC][D]) {
-    static_assert((KC * D) % 4 == 0, "whole float4s");
+    static_assert(D == 16, "the 16-component basis");
 #pragma unroll
-    for (int q = 0; q < KC * D; q += 4)
-        *reinterpret_cast<float4*>(dst + q) =
-            make_float4(P[q / D][q % D], P[(q + 1) / D][(q + 1) % D], P[(q + 2) / D][(q + 2) % D],
-                        P[(q + 3) / D][(q + 3) % D]);
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            *reinterpret_cast<float4*>(dst + kk * 16 + 4 * g) =
+                make_float4(P[kk][kMfmaRow[0][g]], P[kk][kMfmaRow[1][g]], P[kk][kMfmaRow[2][g]], P[kk][kMfmaRow[3][g]]);
 }
 
 template <int KC, int D>
@@ -981,8 +989,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Image word of the centre atom's own cell (stencil offset 0, 0, 0).
 constexpr int32_t kCentreWord = (int32_t)(0x15u << 24);
 
-// Reduced-basis index of entry n of slice q (the slices above).
-__device__ constexpr int kMfmaRow[4][4] = {{0, 1, 2, 3}, {4, 9, 10, 11}, {7, 12, 14, 15}, {5, 6, 8, 13}};
 
 template <int KQ, int RAD>
 __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom bg) {
@@ -1522,7 +1528,6 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma16(PathArgs a, BlockGeom
     const float cw[3] = {(float)(a.L[0] / bg.nc[0]), (float)(a.L[1] / bg.nc[1]), (float)(a.L[2] / bg.nc[2])};
     // A side: this lane supplies row jp = 4 gi + ri, kept component kMfmaRow[ri][gi]
     const int gi = jp >> 2, ri = jp & 3;
-    const int ia0 = kMfmaRow[0][gi], ia1 = kMfmaRow[1][gi], ia2 = kMfmaRow[2][gi], ia3 = kMfmaRow[3][gi];
     // 2 x multiplicities in fold set gi (as in k_adjoint_mfma) and 0/1 weights
     const float c2b = gi <= 1 ? 2.0f : 6.0f;
     const float c2c = (gi & 1) ? 6.0f : 2.0f;
@@ -1563,8 +1568,8 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma16(PathArgs a, BlockGeom
 #pragma unroll
             for (int st = 0; st < KS; ++st) {
                 const int k = 4 * st + gq;
-                const float* Pk = Pa + k * DR;
-                const float pa = Pk[ia0], pb = Pk[ia1], pc = Pk[ia2], pf = Pk[ia3];
+                const float4 pv = *reinterpret_cast<const float4*>(Pa + k * DR + 4 * gi);  // fold set gi
+                const float pa = pv.x, pb = pv.y, pc = pv.z, pf = pv.w;
                 const float4 g = g4[k];
                 const float ga = fmaf(sel0, g.x, sel1 * g.y), gbc = fmaf(sel0, g.z, sel1 * g.w),
                             gf = fmaf(sel3, g.w, sel3c * g.z);
