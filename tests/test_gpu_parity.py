@@ -323,6 +323,21 @@ def test_matrix_core_shapes(tmd, ctx, torch, K, radial):
     _check_ef(E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, s, spec, 0)
 
 
+@pytest.mark.parametrize("S", [1, 3, 4])
+def test_matrix_core_species(tmd, ctx, torch, S):
+    """The 4x4x1 matrix-core descriptor and adjoint with one, three and four
+    species (one P tile, list row and dE/dG slice per neighbour species), K = 12
+    on 6 x 6 x 6 bcc cells with species drawn at random; E, F and virial
+    against the oracle."""
+    s = inputs.make_system("bcc", 3.16, (6, 6, 6), 0.1, S, seed=80 + S)
+    spec = inputs.make_model(S, 12, 3, [64, 64], 6.0, seed=81)
+    _note(f"matrix-core adjoint, {S} species, K=12 M=3 n={s.n}")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx)
+    E, Ea, F, W = ev.energy_forces(pos, sp, s.box)
+    _check_ef(E, Ea.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), W, s, spec, 0)
+
+
 @pytest.mark.parametrize("K", [24, 32, 64, 128])
 @pytest.mark.parametrize("radial", ["uniform_wide", "uniform", "jittered_mu", "table"])
 def test_matrix_core_large_k(tmd, ctx, torch, K, radial):
