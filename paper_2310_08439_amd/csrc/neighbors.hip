@@ -68,7 +68,21 @@ __global__ void k_bin(int64_t n, const double* __restrict__ pos, const int32_t* 
     if (s < 0 || s >= S) atomicOr(&flags[0], kErrSpecies);
     int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
     cell_of[i] = cell;
-    cell_rank[i] = atomicAdd(&cellcount[cell], 1);  // arrival order in the cell (k_sort_gather fixes the order)
+    // Arrival order in the cell (k_sort_gather fixes the order).  Consecutive
+    // lanes in one cell (atoms in lattice or trajectory order) form a run that
+    // takes one atomic: its first lane adds the run length, and the run's lanes
+    // take consecutive ranks.  The active lanes are a prefix of the wave.
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(cell, 1);
+    const bool head = lane == 0 || prev != cell;
+    const unsigned long long heads = __ballot(head), active = __ballot(true);
+    const int h = 63 - __builtin_clzll(heads & ((2ull << lane) - 1));  // this lane's run head
+    const unsigned long long after = heads & ~((2ull << h) - 1);       // heads past it
+    const int end = after ? __builtin_ctzll(after) : 64 - __builtin_clzll(active);
+    int base = 0;
+    if (head) base = atomicAdd(&cellcount[cell], end - h);
+    base = __shfl(base, h);
+    cell_rank[i] = base + (lane - h);
 }
 
 // Exclusive scan by one block of 1024 threads over tiles of 1024 consecutive
@@ -167,10 +181,12 @@ __global__ void k_place(int64_t n, const int32_t* __restrict__ cell_of, const in
     order[start[cell_of[i]] + cell_rank[i]] = (int32_t)i;
 }
 
-// One wave per cell: the cell's atoms (in the arbitrary order the atomic
-// placement left) are ranked by original index, which fixes a deterministic
-// order, and each atom's wrapped position, image shift, species and cell are
-// gathered straight to its sorted slot start[cell] + rank.
+// Sixteen lanes per cell (cells hold about 14 atoms at the list cutoff): the
+// cell's atoms (in the arbitrary order the atomic placement left) are ranked by
+// original index, which fixes a deterministic order, and each atom's wrapped
+// position, image shift, species and cell are gathered straight to its sorted
+// slot start[cell] + rank.  Fuller cells take several rounds of 16.
+constexpr int kSortLanes = 16;
 __global__ void __launch_bounds__(256) k_sort_gather(int64_t ncells, const int32_t* __restrict__ start,
                                                      const int32_t* __restrict__ order, const double* __restrict__ wpos,
                                                      const double* __restrict__ pos,
@@ -178,18 +194,18 @@ __global__ void __launch_bounds__(256) k_sort_gather(int64_t ncells, const int32
                                                      int32_t* __restrict__ perm, int32_t* __restrict__ shift,
                                                      double4* __restrict__ xs, int32_t* __restrict__ sp,
                                                      int32_t* __restrict__ cell_sorted) {
-    const int lane = threadIdx.x & 63;
-    const int64_t cell = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (cell >= ncells) return;  // whole wave
+    const int lane = threadIdx.x % kSortLanes;
+    const int64_t cell = (int64_t)blockIdx.x * (kBlock / kSortLanes) + threadIdx.x / kSortLanes;
+    if (cell >= ncells) return;  // whole group
     const int lo = start[cell], m = start[cell + 1] - lo;
-    for (int k0 = 0; k0 < m; k0 += 64) {
+    for (int k0 = 0; k0 < m; k0 += kSortLanes) {
         const int k = k0 + lane;
         const int32_t v = k < m ? order[lo + k] : INT32_MAX;
         int r = 0;  // entries of the cell with a smaller original index
-        for (int j0 = 0; j0 < m; j0 += 64) {
+        for (int j0 = 0; j0 < m; j0 += kSortLanes) {
             const int32_t vj = j0 + lane < m ? order[lo + j0 + lane] : INT32_MAX;
-            const int nj = min(64, m - j0);
-            for (int t = 0; t < nj; ++t) r += __shfl(vj, t) < v ? 1 : 0;
+            const int nj = min(kSortLanes, m - j0);
+            for (int t = 0; t < nj; ++t) r += __shfl(vj, t, kSortLanes) < v ? 1 : 0;
         }
         if (k < m) {
             const int64_t p = lo + r;
@@ -835,7 +851,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     }
     {
         ProfScope ps_(ctx, "nb_sort");
-        k_sort_gather<<<(unsigned)((ncells + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
+        k_sort_gather<<<(unsigned)((ncells + kBlock / kSortLanes - 1) / (kBlock / kSortLanes)), kBlock, 0, st>>>(
             ncells, cellstart, order, wpos, sys->pos, sys->species, g, nl->perm, nl->shift, nl->xs, nl->sp,
             cell_sorted);
     }
