@@ -308,8 +308,11 @@ tmd_status run_energy_forces_in(tmd_context* ctx, const tmd_model* m, const tmd_
         pruned.cnt = nl->pcnt;
         use = &pruned;
     }
-    if ((st = launch_descriptors(ctx, m, use, b.G, b.P)) != TMD_OK) return st;
-    if ((st = launch_mlp(ctx, m, species_groups(nl), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
+    // a BF16 MLP takes its operand as BF16 descriptors, stored in the first
+    // half of the FP32 descriptor buffer
+    uint16_t* Gb = m->prec == TMD_BF16_MLP ? reinterpret_cast<uint16_t*>(b.G) : nullptr;
+    if ((st = launch_descriptors(ctx, m, use, b.G, b.P, Gb)) != TMD_OK) return st;
+    if ((st = launch_mlp(ctx, m, species_groups(nl), m->prec, b.G, Gb, b.Ei, b.dG)) != TMD_OK) return st;
     int nvir = 0;
     if ((st = launch_adjoint(ctx, m, use, b.dG, b.P, b.Fq, b.vir, &nvir)) != TMD_OK) return st;
     return launch_finalize(ctx, nl, b.Ei, b.Fq, b.vir, nvir, atom_energy, forces, totals7_dev ? totals7_dev : b.totals,
@@ -824,8 +827,9 @@ tmd_status tmd_energy_forces_batch(tmd_context* ctx, const tmd_model* m, int32_t
     TMD_HIP(ctx, hipMemcpyAsync(dsegs, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice,
                                 ctx->stream));
     if ((st = launch_batch_merge(ctx, dsegs, n_systems, &v, boxes)) != TMD_OK) return st;
-    if ((st = launch_descriptors(ctx, m, &v, b.G, b.P)) != TMD_OK) return st;
-    if ((st = launch_mlp(ctx, m, species_groups(&v), m->prec, b.G, b.Ei, b.dG)) != TMD_OK) return st;
+    uint16_t* Gb = m->prec == TMD_BF16_MLP ? reinterpret_cast<uint16_t*>(b.G) : nullptr;
+    if ((st = launch_descriptors(ctx, m, &v, b.G, b.P, Gb)) != TMD_OK) return st;
+    if ((st = launch_mlp(ctx, m, species_groups(&v), m->prec, b.G, Gb, b.Ei, b.dG)) != TMD_OK) return st;
     int nvir = 0;
     if ((st = launch_adjoint(ctx, m, &v, b.dG, b.P, b.Fq, b.vir, &nvir)) != TMD_OK) return st;
     return launch_batch_finalize(ctx, dsegs, n_systems, N, b.Fq, b.Ei, b.vir, kBlock / nch, totals7);

@@ -60,8 +60,10 @@ struct PathArgs {
     const int32_t* wperm;
     const float* mu;
     const float* eta;
-    // forward output / backward input
+    // forward output / backward input; with Gb non-null the forward output is
+    // stored there as the bits of (__bf16)G instead (the BF16 MLP's operand)
     float* G;
+    uint16_t* Gb;
     const float* dG;
     // P written by the forward pass (if non-null) and read back by the
     // adjoint: [S][K][DR][n] by work slot (VALU kernels), or, for the
@@ -439,7 +441,14 @@ __global__ void __launch_bounds__(256, KC <= 4 ? 3 : 2) k_descriptor(PathArgs a,
         // store: feature e of atom al is staged at al * RWp + e
         int al = lane / RW, e = lane - al * RW;
         for (int it = 0; it < nsp * GW; ++it) {
-            if (wave_w0 + al < a.n) a.G[(int64_t)sp_row[wv][al] * a.F + b0 * KM + e] = sg[wv][al * RWp + e];
+            if (wave_w0 + al < a.n) {
+                const int64_t gi = (int64_t)sp_row[wv][al] * a.F + b0 * KM + e;
+                const float gx = sg[wv][al * RWp + e];
+                if (a.Gb)
+                    a.Gb[gi] = __builtin_bit_cast(uint16_t, (__bf16)gx);
+                else
+                    a.G[gi] = gx;
+            }
             e += 64;
             while (e >= RW) {
                 e -= RW;
@@ -985,6 +994,7 @@ __global__ void __launch_bounds__(256) k_adjoint_blocked(PathArgs a, BlockGeom b
 // basis stays inside the lane, and a lane computes its P' entries from its
 // own four P components and dE/dG alone.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 
 // Image word of the centre atom's own cell (stencil offset 0, 0, 0).
 constexpr int32_t kCentreWord = (int32_t)(0x15u << 24);
@@ -1474,7 +1484,13 @@ __global__ void __launch_bounds__(256, 2) k_descriptor_mfma(PathArgs a, BlockGeo
                         gv[m] = sm;
                     }
                     gv[0] = fabsf(P[0][0]);  // sqrt(S) of the single order-0 component
-                    *reinterpret_cast<float4*>(a.G + p * a.F + b * KM + 4 * k) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+                    const int64_t gi = p * a.F + b * KM + 4 * k;
+                    if (a.Gb) {
+                        const bf16x4v h = {(__bf16)gv[0], (__bf16)gv[1], (__bf16)gv[2], (__bf16)gv[3]};
+                        *reinterpret_cast<uint2*>(a.Gb + gi) = __builtin_bit_cast(uint2, h);
+                    } else {
+                        *reinterpret_cast<float4*>(a.G + gi) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+                    }
                 }
             }
         }
@@ -1840,7 +1856,7 @@ __global__ void __launch_bounds__(1024) k_wo_scan(int64_t nblocks, const int32_t
 // too.  Atoms of equal length land in arbitrary order.
 __global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, int cap, const int32_t* __restrict__ base,
                                                   int32_t* __restrict__ wperm, uint8_t* __restrict__ wcell) {
-    extern __shared__ int32_t hist[];  // [cap + 2]: counts, then first slot per length
+    extern __shared__ int32_t hist[];  // [cap + 2]: counts, then first slot per length; per-wave counts
     __shared__ int32_t i_base[257], i_first[kMaxBlockCells], wtmp[kBlock / 64];
     const int t = threadIdx.x;
     const int64_t blk = blockIdx.x;
@@ -1853,7 +1869,7 @@ __global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, int cap, const int
         i_first[t] = gc >= 0 ? g.cellstart[gc] : 0;
         icount = gc >= 0 ? g.cellstart[gc + 1] - i_first[t] : 0;
     }
-    for (int k = t; k <= cap + 1; k += kBlock) hist[k] = 0;
+    for (int k = t; k < (cap + 2) + (kBlock / 64) * (cap + 1); k += kBlock) hist[k] = 0;
     scan256(icount, i_base, wtmp);  // ends with a barrier
     const int m = i_base[nI];
     for (int la = t; la < m; la += kBlock) {
@@ -1872,15 +1888,50 @@ __global__ void __launch_bounds__(256) k_wo_order(WorkGeom g, int cap, const int
         }
     }
     __syncthreads();
+    // Slots in a fixed order: atoms of equal length keep their cell order.
+    // Rounds of kBlock atoms; an atom's slot is its length's running first
+    // slot plus the number of earlier atoms of the round with that length:
+    // the lanes before it in its wave (ballots) and the earlier waves' counts
+    // of that length (LDS histograms per wave, whose totals do not depend on
+    // the order of the atomics).
+    const int lane = t & 63, wvi = t >> 6;
+    int32_t* whist = hist + cap + 2;  // [kBlock / 64][cap + 1]
     const int64_t w0 = base[blk];
-    for (int la = t; la < m; la += kBlock) {
-        int ic = 0;
-        while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
-        const int64_t p = i_first[ic] + (la - i_base[ic]);
-        const int len = min(g.cnt[p], cap);
-        const int r = atomicAdd(&hist[len], 1);
-        wperm[w0 + r] = (int32_t)p;
-        wcell[w0 + r] = (uint8_t)ic;
+    for (int r0 = 0; r0 < m; r0 += kBlock) {
+        const int la = r0 + t;
+        int ic = 0, len = -1;
+        int64_t p = 0;
+        if (la < m) {
+            while (ic + 1 < nI && i_base[ic + 1] <= la) ++ic;
+            p = i_first[ic] + (la - i_base[ic]);
+            len = min(g.cnt[p], cap);
+        }
+        int before = 0;
+        unsigned long long todo = __ballot(len >= 0);
+        while (todo) {  // the same in every lane: one pass per distinct length
+            const int lv = __shfl(len, __builtin_ctzll(todo));
+            const unsigned long long grp = __ballot(len == lv);
+            if (len == lv) before = __popcll(grp & ((1ull << lane) - 1));
+            todo &= ~grp;
+        }
+        if (len >= 0) atomicAdd(&whist[wvi * (cap + 1) + len], 1);
+        __syncthreads();
+        if (len >= 0) {
+            for (int u = 0; u < wvi; ++u) before += whist[u * (cap + 1) + len];
+            const int slot = hist[len] + before;
+            wperm[w0 + slot] = (int32_t)p;
+            wcell[w0 + slot] = (uint8_t)ic;
+        }
+        __syncthreads();  // every lane has its slot
+        for (int L = t; L <= cap; L += kBlock) {
+            int c = 0;
+            for (int u = 0; u < kBlock / 64; ++u) {
+                c += whist[u * (cap + 1) + L];
+                whist[u * (cap + 1) + L] = 0;
+            }
+            hist[L] += c;
+        }
+        __syncthreads();  // hist and whist are reused by the next round
     }
 }
 
@@ -2134,6 +2185,8 @@ bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
 
 }  // namespace
 
+constexpr size_t kWoOrderMaxLds = 48 * 1024;
+
 tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl) {
     nl->wo_valid = false;
     BlockGeom bg{};
@@ -2157,8 +2210,11 @@ tmd_status launch_work_order(tmd_context* ctx, tmd_nlist* nl) {
     }
     g.cellstart = nl->cellstart;
     g.cnt = nl->cnt;
-    // length histogram in LDS: one counter per possible row length
-    const size_t lds = sizeof(int32_t) * ((size_t)nl->cap + 2);
+    // length histograms in LDS: one counter per possible row length, for the
+    // block and for each of its waves (rows longer than ~2,400 entries would
+    // need more than 48 KB: no work order, the atomic adjoint instead)
+    const size_t lds = sizeof(int32_t) * (((size_t)nl->cap + 2) + (kBlock / 64) * ((size_t)nl->cap + 1));
+    if (lds > kWoOrderMaxLds) return TMD_OK;
     {
         ProfScope ps_(ctx, "work_order");
         k_wo_count<<<(unsigned)((nblocks + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, ctx->stream>>>(g, nblocks,
@@ -2189,9 +2245,11 @@ int64_t adjoint_max_partials(const tmd_model* m, const tmd_nlist* nl) {
     return std::max<int64_t>((int64_t)path_grid(m, nl), nl->ncells);
 }
 
-tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf) {
+tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf,
+                              uint16_t* Gb) {
     PathArgs a = make_args(m, nl);
     a.G = G;
+    a.Gb = Gb;
     a.Pbuf = Pbuf;
     if (nl->wo_valid && mfma_adjoint(m)) {
         const BlockGeom bg = wo_geom(nl);

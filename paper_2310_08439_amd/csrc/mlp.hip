@@ -35,7 +35,8 @@ struct MlpArgs {
     int64_t sp_off[kMaxSpecies + 1];
     int64_t tile_off[kMaxSpecies + 1];
     const int32_t* sp_idx;
-    const float* G;
+    const float* G;      // FP32 descriptors (FP32 kernels)
+    const uint16_t* Gb;  // BF16 descriptors, the bits of (__bf16)G (BF16 kernels)
     float* Ei;
     float* dG;
     const float* w32;
@@ -135,6 +136,20 @@ __device__ __forceinline__ f32x4 load_g4(const float* G, int64_t atom, int F, in
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         if (g0 + r < F) v[r] = row[g0 + r];
+    return v;
+}
+
+// The same four features stored as BF16 (rounded by the producer exactly as
+// to_bf4 rounds: nearest-even), so the operand bits are those of
+// to_bf4(load_g4(...)) on the FP32 row.
+__device__ __forceinline__ bf16x4 load_gb4(const uint16_t* Gb, int64_t atom, int F, int g0, bool valid) {
+    if (!valid || g0 >= F) return bf16x4{0, 0, 0, 0};
+    const uint16_t* row = Gb + atom * F;
+    if ((F & 3) == 0) return __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2*>(row + g0));
+    bf16x4 v = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (g0 + r < F) v[r] = __builtin_bit_cast(__bf16, row[g0 + r]);
     return v;
 }
 
@@ -278,8 +293,8 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs a) {
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
                         const int g0 = c0 + k0 + 4 * grp;
-                        bop[cb] = cat8(to_bf4(load_g4(a.G, atom[cb], a.F, g0, valid[cb])),
-                                       to_bf4(load_g4(a.G, atom[cb], a.F, g0 + 16, valid[cb])));
+                        bop[cb] = cat8(load_gb4(a.Gb, atom[cb], a.F, g0, valid[cb]),
+                                       load_gb4(a.Gb, atom[cb], a.F, g0 + 16, valid[cb]));
                     }
 #pragma unroll
                     for (int ob = 0; ob < NB; ++ob) {
@@ -494,8 +509,7 @@ __global__ void __launch_bounds__(1024) k_mlp_resident(MlpArgs a) {
             set_bias(bias);
             for (int k0 = 0; k0 < a.Fpad; k0 += 32) {
                 const int g0 = k0 + 4 * grp;
-                const bf16x8 bop = cat8(to_bf4(load_g4(a.G, atom, a.F, g0, valid)),
-                                        to_bf4(load_g4(a.G, atom, a.F, g0 + 16, valid)));
+                const bf16x8 bop = cat8(load_gb4(a.Gb, atom, a.F, g0, valid), load_gb4(a.Gb, atom, a.F, g0 + 16, valid));
 #pragma unroll
                 for (int ob = 0; ob < NB; ++ob) {
                     const T* wr = W1 + (16 * ob + col) * s1 + k0 + 4 * grp;
@@ -625,7 +639,9 @@ SpeciesGroups species_groups(const tmd_nlist* nl) {
 }
 
 tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups& g, tmd_precision prec,
-                      const float* G, float* Ei, float* dG) {
+                      const float* G, const uint16_t* Gb, float* Ei, float* dG) {
+    if ((prec == TMD_BF16_MLP) != (Gb != nullptr))
+        return fail(ctx, TMD_ERR_INVALID_ARGUMENT, "BF16 MLP without BF16 descriptors, or the reverse");
     MlpArgs a{};
     a.S = m->S;
     a.F = m->F;
@@ -645,6 +661,7 @@ tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups&
     a.tile_off[m->S] = tiles;
     a.sp_idx = g.idx;
     a.G = G;
+    a.Gb = Gb;
     a.Ei = Ei;
     a.dG = dG;
     a.w32 = m->w32;

@@ -318,8 +318,11 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
 tmd_status launch_refresh_positions(tmd_context* ctx, const tmd_system_view* sys, const tmd_nlist* nl);
 // Descriptors G [n][F] (sorted order); when Pbuf is non-null the per-atom P
 // tensors (kept components) are kept there for the adjoint: p_slots(m, nl)
-// x S x K x Dr floats.
-tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf);
+// x S x K x Dr floats.  When Gb is non-null G is stored there instead, as the
+// bits of (__bf16)G (nearest-even): the operand a BF16 MLP takes, at half the
+// bytes.
+tmd_status launch_descriptors(tmd_context* ctx, const tmd_model* m, const tmd_nlist* nl, float* G, float* Pbuf,
+                              uint16_t* Gb = nullptr);
 // Atom slots of the P buffer for this model and list (the matrix-core
 // kernels pad each work-order block to whole 16-atom groups), and a bound for
 // reserving workspace before any list exists (blocks of 128 atoms or more on
@@ -335,9 +338,11 @@ struct SpeciesGroups {
     const int32_t* idx = nullptr;
 };
 SpeciesGroups species_groups(const tmd_nlist* nl);
-// Per-element MLP: E_i and dE/dG for every grouped atom, in precision prec.
+// Per-element MLP: E_i and dE/dG for every grouped atom, in precision prec:
+// TMD_FP32 reads the FP32 descriptors G, TMD_BF16_MLP the BF16 ones Gb (the
+// other pointer may be null).
 tmd_status launch_mlp(tmd_context* ctx, const tmd_model* m, const SpeciesGroups& g, tmd_precision prec,
-                      const float* G, float* Ei, float* dG);
+                      const float* G, const uint16_t* Gb, float* Ei, float* dG);
 // Forces are accumulated as 64-bit fixed-point integers with 32 fractional
 // bits (F = q 2^-32, |F| < 2^31 eV/A): integer additions are associative, so
 // the sums do not depend on the order of the scatter's atomic adds and the

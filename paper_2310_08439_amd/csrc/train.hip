@@ -1217,7 +1217,7 @@ tmd_status tmd_train_step(tmd_context* ctx, tmd_model* m, const tmd_batch* bc, c
     tmd_status st;
     const int64_t N = b->N;
     // 1. energies and input gradients (FP32)
-    if ((st = launch_mlp(ctx, m, b->groups, TMD_FP32, b->G, b->Ei, b->dG)) != TMD_OK) return st;
+    if ((st = launch_mlp(ctx, m, b->groups, TMD_FP32, b->G, nullptr, b->Ei, b->dG)) != TMD_OK) return st;
     PtArgs a = pt_args(b);
     a.mu = m->mu;
     a.eta = m->eta;

@@ -499,6 +499,28 @@ def test_repeat_runs(tmd, ctx, torch):
     assert torch.equal(F1, F2)  # fixed-point force sums: independent of the atomics' order
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rebuild_bitwise_reproducible_bcc1m(tmd, ctx, torch, prec):
+    """Every output bit for bit across list rebuilds at 1,024,000 atoms.  The
+    rebuild also remakes the work order; its slots within one row length used
+    to be handed out by LDS atomics, and the atoms grouped with one another
+    then changed from build to build, which moved ~800 atoms' FP32 energies
+    and ~28,000 atoms' forces at rounding level."""
+    s, spec, _ = inputs.workload("bcc1m")
+    _note(f"bcc1m rebuild reproducibility prec={prec}")
+    pos, sp = _dev(torch, s)
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx, precision=tmd.FP32 if prec == 0 else tmd.BF16_MLP)
+    runs = [ev.energy_forces(pos, sp, s.box, rebuild=True) for _ in range(3)]
+    E0, Ea0, F0, W0 = runs[0]
+    for E, Ea, F, W in runs[1:]:
+        assert E == E0
+        assert torch.equal(Ea, Ea0)
+        assert torch.equal(F, F0)
+        assert np.array_equal(np.asarray(W), np.asarray(W0))
+    ev.model.close()
+    ev.nl.close()
+
+
 @pytest.mark.parametrize("hidden", [[64, 64], [64, 64, 64], [128]])
 def test_bf16_resident_weight_mlp(tmd, ctx, torch, hidden):
     """Systems of 64k+ atoms run the BF16 network with every weight resident in
