@@ -1003,6 +1003,7 @@ constexpr int32_t kCentreWord = (int32_t)(0x15u << 24);
 template <int KQ, int RAD>
 __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom bg) {
     constexpr int K = 4 * KQ, DR = Moments<3>::DR;
+    constexpr bool KA = RAD == kRadRec && KQ <= 3;  // k P' as the second product's A operand
     extern __shared__ __attribute__((aligned(8))) unsigned char lds_dyn[];
     __shared__ int32_t h_base[257], h_first[kMaxHaloCells], hoff[kMaxHaloCells];
     __shared__ int32_t wtmp[kBlock / 64];
@@ -1089,6 +1090,16 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
                 Ap[k][2] = fmaf(c2c * gbc, pc, -pd);
                 Ap[k][3] = c2f * gf * pf;
             }
+            // On a uniform grid B2 = k B1: for K <= 12 the factor k goes on the
+            // atom's slices once (k P') instead of on every pair's B (12 fewer
+            // multiplies per batch; at K = 16 the extra slices would spill)
+            float Ak[KA ? K : 1][4];
+            if constexpr (KA) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) Ak[k][q] = (float)k * Ap[k][q];
+            }
             const int nb = aval ? a.cnt[(int64_t)b * a.n + p] : 0;
             int nbmax = nb;
             for (int off = 4; off < 64; off <<= 1) nbmax = max(nbmax, __shfl_xor(nbmax, off));
@@ -1153,7 +1164,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         B1[k] = ek;
-                        B2[k] = (float)k * ek;
+                        if constexpr (!KA) B2[k] = (float)k * ek;
                         ek *= rk;
                         rk *= a.rec_c;
                     }
@@ -1185,7 +1196,10 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_mfma(PathArgs a, BlockGeom b
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         acc1[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ap[k][q], B1[k], acc1[q], 0, 0, 0);
-                        acc2[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ap[k][q], B2[k], acc2[q], 0, 0, 0);
+                        if constexpr (KA)
+                            acc2[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ak[k][q], B1[k], acc2[q], 0, 0, 0);
+                        else
+                            acc2[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ap[k][q], B2[k], acc2[q], 0, 0, 0);
                     }
                 }
                 float V1[DR], V2[DR];
