@@ -75,6 +75,9 @@ __global__ void __launch_bounds__(256) k_partials(int64_t n, const float* __rest
     for (int j = 0; j < 7; ++j) acc[j] = Comp{0.0, 0.0};
     const int64_t per = (n + kPartBlocks - 1) / kPartBlocks;
     const int64_t lo = blockIdx.x * per, hi = min<int64_t>(n, lo + per);
+    // unrolled so that a chunk's loads are in flight together (the sums keep
+    // their order: each thread adds its values in index order)
+#pragma unroll 8
     for (int64_t p = lo + threadIdx.x; p < hi; p += 256) comp_add(acc[0], (double)Ei[p]);
     const int64_t pv = (nvir + kPartBlocks - 1) / kPartBlocks;
     const int64_t vlo = blockIdx.x * pv, vhi = min<int64_t>(nvir, vlo + pv);
