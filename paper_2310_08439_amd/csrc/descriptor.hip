@@ -2168,19 +2168,24 @@ BlockGeom wo_geom(const tmd_nlist* nl) {
 bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
     // 4x2x2 cells per workgroup: enough workgroups (about 5,000 at 1 M atoms)
     // for several rounds of them per CU; measured fastest of 4x4x4 .. 2x2x2.
-    // The preferred shape's largest halo is counted exactly during the build;
-    // the fallbacks use (halo cells) x (densest cell).
-    static const int shapes[][3] = {{kBlockShape[0], kBlockShape[1], kBlockShape[2]}, {2, 2, 2}, {2, 2, 1},
-                                    {2, 1, 1}, {1, 1, 1}};
+    // The largest halos of the preferred shape and of kBlockShape2 (3x2x2, for
+    // cells too large for 4x2x2 halos in the LDS budget) are counted exactly
+    // during the build; the other fallbacks use (halo cells) x (densest cell).
+    static const int shapes[][3] = {{kBlockShape[0], kBlockShape[1], kBlockShape[2]},
+                                    {kBlockShape2[0], kBlockShape2[1], kBlockShape2[2]},
+                                    {2, 2, 2},
+                                    {2, 2, 1},
+                                    {2, 1, 1},
+                                    {1, 1, 1}};
     for (const auto& sh : shapes) {
         int B[3], H = 1;
         for (int d = 0; d < 3; ++d) {
             B[d] = std::min(sh[d], nl->nc[d]);
             H *= B[d] + 2;
         }
-        const bool pref = &sh == &shapes[0], last = &sh == &shapes[4];
-        const int64_t hmax = (pref && nl->halo_max >= 0) ? (int64_t)std::max(1, nl->halo_max)
-                                                          : (int64_t)H * std::max(1, nl->max_occ);
+        const bool last = &sh == &shapes[5];
+        const int counted = &sh == &shapes[0] ? nl->halo_max : &sh == &shapes[1] ? nl->halo_max2 : -1;
+        const int64_t hmax = counted >= 0 ? (int64_t)std::max(1, counted) : (int64_t)H * std::max(1, nl->max_occ);
         // small systems: smaller blocks until every CU gets two workgroups
         int64_t nblocks = 1;
         for (int d = 0; d < 3; ++d) nblocks *= (nl->nc[d] + B[d] - 1) / B[d];

@@ -387,35 +387,44 @@ __device__ inline int floor_div(int a, int b) {
 // periodic halo into *out: waves stride over the blocks (lanes over a block's
 // halo cells); one atomic per workgroup.
 constexpr int kHaloMaxGroups = 256;
-__global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int B0, int B1, int B2, int64_t nblocks,
-                                                  const int32_t* __restrict__ start, int32_t* __restrict__ out) {
-    __shared__ int32_t wmax[kBlock / 64];
+__global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int3 A, int64_t nbA, int3 B, int64_t nbB,
+                                                  const int32_t* __restrict__ start, int32_t* __restrict__ outA,
+                                                  int32_t* __restrict__ outB) {
+    __shared__ int32_t wmax[2][kBlock / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nb0 = (g.nc[0] + B0 - 1) / B0, nb1 = (g.nc[1] + B1 - 1) / B1;
-    const int HX = B0 + 2, HY = B1 + 2, nh = HX * HY * (B2 + 2);
-    int best = 0;
-    for (int64_t blk = (int64_t)blockIdx.x * (kBlock / 64) + wv; blk < nblocks;
-         blk += (int64_t)gridDim.x * (kBlock / 64)) {
-        const int x0 = (int)(blk % nb0) * B0, y0 = (int)((blk / nb0) % nb1) * B1,
-                  z0 = (int)(blk / ((int64_t)nb0 * nb1)) * B2;
-        int c = 0;
-        for (int h = lane; h < nh; h += 64) {
-            const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
-            const int wx = x - floor_div(x, g.nc[0]) * g.nc[0];
-            const int wy = y - floor_div(y, g.nc[1]) * g.nc[1];
-            const int wz = z - floor_div(z, g.nc[2]) * g.nc[2];
-            const int cell = (wz * g.nc[1] + wy) * g.nc[0] + wx;
-            c += start[cell + 1] - start[cell];
+    // largest atom count of one block of shape S plus its one-cell halo
+    auto largest = [&](int3 S, int64_t nblocks) {
+        const int nb0 = (g.nc[0] + S.x - 1) / S.x, nb1 = (g.nc[1] + S.y - 1) / S.y;
+        const int HX = S.x + 2, HY = S.y + 2, nh = HX * HY * (S.z + 2);
+        int best = 0;
+        for (int64_t blk = (int64_t)blockIdx.x * (kBlock / 64) + wv; blk < nblocks;
+             blk += (int64_t)gridDim.x * (kBlock / 64)) {
+            const int x0 = (int)(blk % nb0) * S.x, y0 = (int)((blk / nb0) % nb1) * S.y,
+                      z0 = (int)(blk / ((int64_t)nb0 * nb1)) * S.z;
+            int c = 0;
+            for (int h = lane; h < nh; h += 64) {
+                const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+                const int wx = x - floor_div(x, g.nc[0]) * g.nc[0];
+                const int wy = y - floor_div(y, g.nc[1]) * g.nc[1];
+                const int wz = z - floor_div(z, g.nc[2]) * g.nc[2];
+                const int cell = (wz * g.nc[1] + wy) * g.nc[0] + wx;
+                c += start[cell + 1] - start[cell];
+            }
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+            best = max(best, c);
         }
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-        best = max(best, c);
+        return best;
+    };
+    const int bestA = largest(A, nbA), bestB = largest(B, nbB);
+    if (lane == 0) {
+        wmax[0][wv] = bestA;
+        wmax[1][wv] = bestB;
     }
-    if (lane == 0) wmax[wv] = best;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int m = wmax[0];
-        for (int w = 1; w < kBlock / 64; ++w) m = max(m, wmax[w]);
-        atomicMax(out, m);
+    if (threadIdx.x < 2) {
+        int m = wmax[threadIdx.x][0];
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, wmax[threadIdx.x][w]);
+        atomicMax(threadIdx.x == 0 ? outA : outB, m);
     }
 }
 
@@ -836,14 +845,20 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         k_scan_tile_sums<<<1, 1024, 0, st>>>(ntiles, tiles);
         k_scan_add<<<grid_for(ncells + 1), kBlock, 0, st>>>(ncells, tiles, cellstart);
     }
-    int hb[3] = {1, 1, 1};
     if (narrow) {
-        for (int d = 0; d < 3; ++d) hb[d] = std::min(kBlockShape[d], g.nc[d]);
-        const int64_t nbk = (int64_t)((g.nc[0] + hb[0] - 1) / hb[0]) * ((g.nc[1] + hb[1] - 1) / hb[1]) *
-                            ((g.nc[2] + hb[2] - 1) / hb[2]);
+        // the two block shapes the work order may take, clamped to the grid
+        auto shape = [&](const int* B) {
+            return make_int3(std::min(B[0], g.nc[0]), std::min(B[1], g.nc[1]), std::min(B[2], g.nc[2]));
+        };
+        auto count = [&](int3 S) {
+            return (int64_t)((g.nc[0] + S.x - 1) / S.x) * ((g.nc[1] + S.y - 1) / S.y) * ((g.nc[2] + S.z - 1) / S.z);
+        };
+        const int3 A = shape(kBlockShape), B = shape(kBlockShape2);
+        const int64_t nbA = count(A), nbB = count(B);
         ProfScope ps_(ctx, "nb_halo_max");
-        const int64_t groups = std::min<int64_t>(kHaloMaxGroups, (nbk + kBlock / 64 - 1) / (kBlock / 64));
-        k_halo_max<<<(unsigned)groups, kBlock, 0, st>>>(g, hb[0], hb[1], hb[2], nbk, cellstart, flags + 5);
+        const int64_t groups =
+            std::min<int64_t>(kHaloMaxGroups, (std::max(nbA, nbB) + kBlock / 64 - 1) / (kBlock / 64));
+        k_halo_max<<<(unsigned)groups, kBlock, 0, st>>>(g, A, nbA, B, nbB, cellstart, flags + 5, flags + 6);
     }
     {
         ProfScope ps_(ctx, "nb_place");
@@ -939,6 +954,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     nl->ncells = ncells;
     nl->max_occ = ctx->h_flags[4];
     nl->halo_max = narrow ? ctx->h_flags[5] : -1;
+    nl->halo_max2 = narrow ? ctx->h_flags[6] : -1;
     nl->narrow = narrow;
     for (int a = 0; a < 3; ++a) {
         nl->box[a] = sys->box[a];
