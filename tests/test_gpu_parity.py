@@ -499,6 +499,31 @@ def test_repeat_runs(tmd, ctx, torch):
     assert torch.equal(F1, F2)  # fixed-point force sums: independent of the atomics' order
 
 
+def test_bcc1m_skin_list_sampled_parity(tmd, ctx, torch):
+    """The 1,024,000-atom alloy on a list with a 1 A skin: 7 A cells, whose
+    4x2x2-cell blocks have halos beyond the LDS budget, so the work order takes
+    3x2x2 blocks.  FP32, 2,000 sampled atoms against the oracle, and every
+    atom's energy against the evaluation on the skin-free list (6 A cells,
+    4x2x2 blocks) within the FP32 rounding of the LDS position offsets."""
+    s, spec, _ = inputs.workload("bcc1m")
+    _note(f"bcc1m n={s.n} fp32, 1 A skin list, sampled atoms vs oracle")
+    pos, sp = _dev(torch, s)
+    ev0 = tmd.Evaluator(spec, s.n, s.box, ctx=ctx, precision=tmd.FP32)
+    E0, Ea0, _, _ = ev0.energy_forces(pos, sp, s.box)
+    ev0.model.close()
+    ev0.nl.close()
+    ev = tmd.Evaluator(spec, s.n, s.box, ctx=ctx, skin=1.0, precision=tmd.FP32)
+    E, Ea, F, _ = ev.energy_forces(pos, sp, s.box)
+    Ea = Ea.cpu().numpy().astype(np.float64)
+    F = F.cpu().numpy().astype(np.float64)
+    parity.check_sampled(Ea, F, s, spec, False, seeds=(82,))
+    dEa = np.abs(Ea - Ea0.cpu().numpy().astype(np.float64))
+    print(f"  skin 1 vs skin 0: |dE|/N={abs(E - E0) / s.n:.3e}  max|dE_i|={dEa.max():.3e}", flush=True)
+    assert abs(E - E0) / s.n <= 1e-6 and dEa.max() <= 1e-5
+    ev.model.close()
+    ev.nl.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rebuild_bitwise_reproducible_bcc1m(tmd, ctx, torch, prec):
     """Every output bit for bit across list rebuilds at 1,024,000 atoms.  The
