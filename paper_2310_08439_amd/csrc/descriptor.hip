@@ -2166,13 +2166,14 @@ BlockGeom wo_geom(const tmd_nlist* nl) {
 
 // Largest block shape whose halo accumulators fit in LDS for the densest cell.
 bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
-    // 4x2x2 cells per workgroup: enough workgroups (about 5,000 at 1 M atoms)
-    // for several rounds of them per CU; measured fastest of 4x4x4 .. 2x2x2.
-    // The largest halos of the preferred shape and of kBlockShape2 (3x2x2, for
-    // cells too large for 4x2x2 halos in the LDS budget) are counted exactly
-    // during the build; the other fallbacks use (halo cells) x (densest cell).
+    // 4x4x2 cells per workgroup (about 2,500 workgroups at 1 M atoms, several
+    // rounds per CU; its halo of 4.5 cells per interior cell fits the LDS
+    // budget at r_c = 6 A), then 4x2x2 and 3x2x2 for denser or larger cells.
+    // The largest halos of these three are counted exactly during the build;
+    // the other fallbacks use (halo cells) x (densest cell).
     static const int shapes[][3] = {{kBlockShape[0], kBlockShape[1], kBlockShape[2]},
                                     {kBlockShape2[0], kBlockShape2[1], kBlockShape2[2]},
+                                    {kBlockShape3[0], kBlockShape3[1], kBlockShape3[2]},
                                     {2, 2, 2},
                                     {2, 2, 1},
                                     {2, 1, 1},
@@ -2183,8 +2184,11 @@ bool choose_blocks(const tmd_nlist* nl, BlockGeom* bg) {
             B[d] = std::min(sh[d], nl->nc[d]);
             H *= B[d] + 2;
         }
-        const bool last = &sh == &shapes[5];
-        const int counted = &sh == &shapes[0] ? nl->halo_max : &sh == &shapes[1] ? nl->halo_max2 : -1;
+        const bool last = &sh == &shapes[6];
+        const int counted = &sh == &shapes[0]   ? nl->halo_max
+                            : &sh == &shapes[1] ? nl->halo_max2
+                            : &sh == &shapes[2] ? nl->halo_max3
+                                                : -1;
         const int64_t hmax = counted >= 0 ? (int64_t)std::max(1, counted) : (int64_t)H * std::max(1, nl->max_occ);
         // small systems: smaller blocks until every CU gets two workgroups
         int64_t nblocks = 1;

@@ -387,10 +387,10 @@ __device__ inline int floor_div(int a, int b) {
 // periodic halo into *out: waves stride over the blocks (lanes over a block's
 // halo cells); one atomic per workgroup.
 constexpr int kHaloMaxGroups = 256;
-__global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int3 A, int64_t nbA, int3 B, int64_t nbB,
-                                                  const int32_t* __restrict__ start, int32_t* __restrict__ outA,
-                                                  int32_t* __restrict__ outB) {
-    __shared__ int32_t wmax[2][kBlock / 64];
+__global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int3 A, int64_t nbA, int3 B, int64_t nbB, int3 C,
+                                                  int64_t nbC, const int32_t* __restrict__ start,
+                                                  int32_t* __restrict__ out) {
+    __shared__ int32_t wmax[3][kBlock / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // largest atom count of one block of shape S plus its one-cell halo
     auto largest = [&](int3 S, int64_t nblocks) {
@@ -415,16 +415,17 @@ __global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int3 A, int64_t nb
         }
         return best;
     };
-    const int bestA = largest(A, nbA), bestB = largest(B, nbB);
+    const int bestA = largest(A, nbA), bestB = largest(B, nbB), bestC = largest(C, nbC);
     if (lane == 0) {
         wmax[0][wv] = bestA;
         wmax[1][wv] = bestB;
+        wmax[2][wv] = bestC;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
+    if (threadIdx.x < 3) {  // out[0 .. 2]: shapes A, B, C
         int m = wmax[threadIdx.x][0];
         for (int w = 1; w < kBlock / 64; ++w) m = max(m, wmax[threadIdx.x][w]);
-        atomicMax(threadIdx.x == 0 ? outA : outB, m);
+        atomicMax(out + threadIdx.x, m);
     }
 }
 
@@ -846,19 +847,19 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         k_scan_add<<<grid_for(ncells + 1), kBlock, 0, st>>>(ncells, tiles, cellstart);
     }
     if (narrow) {
-        // the two block shapes the work order may take, clamped to the grid
+        // the block shapes the work order prefers, clamped to the grid
         auto shape = [&](const int* B) {
             return make_int3(std::min(B[0], g.nc[0]), std::min(B[1], g.nc[1]), std::min(B[2], g.nc[2]));
         };
         auto count = [&](int3 S) {
             return (int64_t)((g.nc[0] + S.x - 1) / S.x) * ((g.nc[1] + S.y - 1) / S.y) * ((g.nc[2] + S.z - 1) / S.z);
         };
-        const int3 A = shape(kBlockShape), B = shape(kBlockShape2);
-        const int64_t nbA = count(A), nbB = count(B);
+        const int3 A = shape(kBlockShape), B = shape(kBlockShape2), C = shape(kBlockShape3);
+        const int64_t nbA = count(A), nbB = count(B), nbC = count(C);
         ProfScope ps_(ctx, "nb_halo_max");
         const int64_t groups =
-            std::min<int64_t>(kHaloMaxGroups, (std::max(nbA, nbB) + kBlock / 64 - 1) / (kBlock / 64));
-        k_halo_max<<<(unsigned)groups, kBlock, 0, st>>>(g, A, nbA, B, nbB, cellstart, flags + 5, flags + 6);
+            std::min<int64_t>(kHaloMaxGroups, (std::max({nbA, nbB, nbC}) + kBlock / 64 - 1) / (kBlock / 64));
+        k_halo_max<<<(unsigned)groups, kBlock, 0, st>>>(g, A, nbA, B, nbB, C, nbC, cellstart, flags + 5);
     }
     {
         ProfScope ps_(ctx, "nb_place");
@@ -955,6 +956,7 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
     nl->max_occ = ctx->h_flags[4];
     nl->halo_max = narrow ? ctx->h_flags[5] : -1;
     nl->halo_max2 = narrow ? ctx->h_flags[6] : -1;
+    nl->halo_max3 = narrow ? ctx->h_flags[7] : -1;
     nl->narrow = narrow;
     for (int a = 0; a < 3; ++a) {
         nl->box[a] = sys->box[a];

@@ -16,11 +16,12 @@ namespace tmd {
 
 constexpr int kMaxSpecies = 8;
 // Preferred cell block of the blocked adjoint (cells per axis, clamped to the grid).
-constexpr int kBlockShape[3] = {4, 2, 2};
-// Second block shape whose largest halo the build counts exactly: taken when
-// the first one's halo does not fit the LDS budget (large cells, e.g. lists
-// with a skin).
-constexpr int kBlockShape2[3] = {3, 2, 2};
+constexpr int kBlockShape[3] = {4, 4, 2};
+// Further block shapes whose largest halos the build counts exactly, taken in
+// turn when the previous one's halo does not fit the LDS budget (dense
+// systems, large cells such as lists with a skin).
+constexpr int kBlockShape2[3] = {4, 2, 2};
+constexpr int kBlockShape3[3] = {3, 2, 2};
 constexpr int kBlock = 256;
 
 // Workgroups are dispatched to the eight XCDs round-robin (workgroup b runs on
@@ -254,6 +255,7 @@ struct tmd_nlist {
     int max_occ = 0;               // most atoms in one cell
     int halo_max = -1;             // most atoms in one kBlockShape block plus halo (-1: not counted)
     int halo_max2 = -1;            // the same for kBlockShape2
+    int halo_max3 = -1;            // and for kBlockShape3
     bool narrow = false;           // 3x3x3 stencil (every reach is 1)
     // Work order of the descriptor and adjoint kernels, set by every build
     // when the adjoint runs over cell blocks (wo_valid): blocks of wo_B cells
