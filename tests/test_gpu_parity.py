@@ -501,10 +501,10 @@ def test_repeat_runs(tmd, ctx, torch):
 
 def test_bcc1m_skin_list_sampled_parity(tmd, ctx, torch):
     """The 1,024,000-atom alloy on a list with a 1 A skin: 7 A cells, whose
-    4x2x2-cell blocks have halos beyond the LDS budget, so the work order takes
-    3x2x2 blocks.  FP32, 2,000 sampled atoms against the oracle, and every
-    atom's energy against the evaluation on the skin-free list (6 A cells,
-    4x2x2 blocks) within the FP32 rounding of the LDS position offsets."""
+    4x4x2- and 4x2x2-cell blocks have halos beyond the LDS budget, so the work
+    order takes 3x2x2 blocks.  FP32, 2,000 sampled atoms against the oracle,
+    and every atom's energy against the evaluation on the skin-free list (6 A
+    cells, 4x4x2 blocks) within the FP32 rounding of the LDS position offsets."""
     s, spec, _ = inputs.workload("bcc1m")
     _note(f"bcc1m n={s.n} fp32, 1 A skin list, sampled atoms vs oracle")
     pos, sp = _dev(torch, s)
