@@ -27,6 +27,10 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3     # published MI355X FP32 vector peak
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# device memory the serving leg's server may hold: every resident system's
+# neighbour list (about 30 GB for the pool of 256) plus the slots' workspaces,
+# well within the 288 GB of one MI355X
+SERVE_HBM_BUDGET = 96 << 30
 
 
 def padded_k(K: int) -> int:
@@ -281,7 +285,7 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
     out = {"workload": f"Poisson {rate:g} req/s, {n_requests} requests after {n_warmup} warm-up, pool of {pool} "
                        f"resident fcc/bcc systems of {sizes.min()}..{sizes.max()} atoms (mean {sizes.mean():.0f}), "
                        f"50% E+F / 50% 10 VV steps, {slots} slots, BF16 MLP, E+F on systems of <= {batch_atoms} "
-                       f"atoms batched"}
+                       f"atoms batched, HBM budget {SERVE_HBM_BUDGET >> 30} GiB"}
     out.update(runs[batch_atoms])
     out["without_batching"] = runs[0]
     return out
@@ -290,7 +294,8 @@ def serve_leg(tmd, ctx, spec, n_requests: int, n_warmup: int, pool: int, rate: f
 def _serve_run(tmd, ctx, spec, systems, plan, burst, small_burst, n_warmup, slots, batch_atoms) -> dict:
     import numpy as np
     model = tmd.Model(ctx, spec, precision=tmd.BF16_MLP)
-    srv = tmd.Server(model, max_slots=slots, max_atoms=262144, skin=1.0, batch_atoms=batch_atoms)
+    srv = tmd.Server(model, max_slots=slots, max_atoms=262144, skin=1.0, batch_atoms=batch_atoms,
+                     hbm_budget_bytes=SERVE_HBM_BUDGET)
     ids = [srv.add_system(s.pos, s.species, s.box, masses) for (s, masses, _) in systems]
     tickets = []
     start = time.perf_counter()

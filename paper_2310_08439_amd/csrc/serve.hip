@@ -85,12 +85,23 @@ struct tmd_server {
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     std::vector<tmd_context*> ctxs;
+    std::vector<hipEvent_t> events;  // two per slot: the ends of an MD request's last two queued chunks
+    // lists evicted under the lock, destroyed by a worker after it releases the
+    // lock (destroying a list waits for the whole device)
+    std::vector<tmd_nlist*> retired;
     bool stop = false;
     std::string last_error;
 };
 
 namespace tmd {
 namespace {
+
+// An MD request queues its steps in chunks of at least this many atom-steps
+// and keeps at most two chunks on its stream: streams share the device's few
+// hardware queues, whose packets run in order, so a request submitted on
+// another slot waits behind at most two chunks of a long MD request rather
+// than behind all of its steps.
+constexpr int64_t kMdChunkAtomSteps = 65536;
 
 void account(tmd_server* sv, int64_t delta) {
     sv->mem_in_use += delta;
@@ -177,13 +188,18 @@ tmd_status kinetic(tmd_context* ctx, const System* sys, double* part, double* ou
 // step's largest displacement since the list build (maxd2[s]) gates the
 // reuse of pruned rows on the device, and a sticky device flag records
 // whether any step moved an atom beyond skin/2, which would have made the
-// list incomplete.  The caller reads the flag with the results.
+// list incomplete.  The caller reads the flag with the results.  The steps go
+// out in chunks of kMdChunkAtomSteps: after queueing chunk c the host waits
+// for the end of chunk c - 1 (ev[0], ev[1] alternate), which leaves chunk c
+// queued, so the device never idles for the wait.
 tmd_status md_steps_device_gated(tmd_server* sv, tmd_context* ctx, System* sys, const tmd_system_view& view,
-                                 const SlotBuffers& b, int nsteps, double dt) {
+                                 const SlotBuffers& b, int nsteps, double dt, hipEvent_t* ev) {
     const tmd_model* m = sv->model;
     const double half_skin2 = 0.25 * sv->opts.skin * sv->opts.skin;
     tmd_status st;
     if ((st = launch_zero_u64(ctx, b.maxd2, nsteps + 1)) != TMD_OK) return st;
+    int64_t queued = 0;  // atom-steps queued since the last chunk end
+    int chunk = 0;
     for (int s = 1; s <= nsteps; ++s) {
         if ((st = launch_kick_drift(ctx, sys->n, sys->x, sys->v, sys->F, sys->sp, sys->acc, dt, sys->xref,
                                     b.maxd2 + s)) != TMD_OK)
@@ -196,6 +212,13 @@ tmd_status md_steps_device_gated(tmd_server* sv, tmd_context* ctx, System* sys, 
             return st;
         if ((st = launch_kick(ctx, sys->n, sys->v, sys->F, sys->sp, sys->acc, dt)) != TMD_OK) return st;
         if ((st = kinetic(ctx, sys, b.part, b.ekin + 4 * s)) != TMD_OK) return st;
+        queued += sys->n;
+        if (queued >= kMdChunkAtomSteps && s < nsteps) {
+            TMD_HIP(ctx, hipEventRecord(ev[chunk & 1], ctx->stream));
+            if (chunk > 0) TMD_HIP(ctx, hipEventSynchronize(ev[(chunk - 1) & 1]));
+            ++chunk;
+            queued = 0;
+        }
     }
     return TMD_OK;
 }
@@ -242,7 +265,8 @@ tmd_status md_steps_host_checked(tmd_server* sv, tmd_context* ctx, System* sys, 
 // (md_steps_device_gated); if the device flag shows that some step moved an
 // atom beyond skin/2 (so that a list rebuild was due), the request restarts
 // from its saved positions and velocities and runs with a check per step.
-tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pending& p, Finished* out) {
+tmd_status run_request(tmd_server* sv, tmd_context* ctx, hipEvent_t* ev, System* sys, const Pending& p,
+                       Finished* out) {
     const tmd_model* m = sv->model;
     tmd_result& r = out->res;
     tmd_status st;
@@ -271,7 +295,7 @@ tmd_status run_request(tmd_server* sv, tmd_context* ctx, System* sys, const Pend
         const double dt = p.req.dt_fs;
         bool done = false;
         if (fast) {
-            if ((st = md_steps_device_gated(sv, ctx, sys, view, b, nsteps, dt)) != TMD_OK) return st;
+            if ((st = md_steps_device_gated(sv, ctx, sys, view, b, nsteps, dt, ev)) != TMD_OK) return st;
             TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, b.flag, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                         ctx->stream));
             TMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -419,7 +443,7 @@ bool pick(tmd_server* sv, Pending* out, System** sys_out, bool* rejected, Finish
             std::sort(idle.begin(), idle.end(), [](System* a, System* b) { return a->last_use < b->last_use; });
             for (System* s : idle) {
                 if (sv->mem_in_use + need <= budget) break;
-                tmd_nlist_destroy(s->nl);
+                sv->retired.push_back(s->nl);
                 s->nl = nullptr;
                 s->nl_valid = false;
                 account(sv, -(int64_t)s->nl_bytes);
@@ -486,6 +510,11 @@ void serve_batch(tmd_server* sv, tmd_context* ctx, std::vector<Pending>& reqs, s
     sv->cv_work.notify_all();
 }
 
+void destroy_lists(std::vector<tmd_nlist*>& lists) {
+    for (tmd_nlist* nl : lists) tmd_nlist_destroy(nl);
+    lists.clear();
+}
+
 void worker_main(tmd_server* sv, int slot) {
     (void)hipSetDevice(sv->opts.device);
     tmd_context* ctx = sv->ctxs[slot];
@@ -494,13 +523,17 @@ void worker_main(tmd_server* sv, int slot) {
         System* sys = nullptr;
         bool rejected = false;
         Finished fin;
+        std::vector<tmd_nlist*> dead;  // lists that pick() evicted, freed once the lock is released
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_work.wait(lk, [&] { return sv->stop || pick(sv, &p, &sys, &rejected, &fin); });
             if (sv->stop) break;
+            dead.swap(sv->retired);
             if (rejected) {
                 sv->done[p.ticket] = std::move(fin);
                 sv->cv_done.notify_all();
+                lk.unlock();
+                destroy_lists(dead);
                 continue;
             }
             sv->running.insert(p.ticket);
@@ -513,12 +546,14 @@ void worker_main(tmd_server* sv, int slot) {
                 pick_batch(sv, sys, reqs, systems);
                 if (systems.size() > 1) {
                     lk.unlock();
+                    destroy_lists(dead);
                     serve_batch(sv, ctx, reqs, systems);
                     continue;
                 }
                 p = std::move(reqs[0]);
             }
         }
+        destroy_lists(dead);
         Finished f;
         f.res.kind = p.req.kind;
         f.res.system_id = sys->id;
@@ -537,7 +572,7 @@ void worker_main(tmd_server* sv, int slot) {
                 sys->nl_valid = false;
             }
         }
-        if (st == TMD_OK) st = run_request(sv, ctx, sys, p, &f);
+        if (st == TMD_OK) st = run_request(sv, ctx, sv->events.data() + 2 * slot, sys, p, &f);
         f.res.status = st;
         f.res.t_done = now_s(sv->t0);
         {
@@ -562,8 +597,11 @@ void release_slots(tmd_server* sv) {
         if (c) tmd_context_destroy(c);
     for (hipStream_t st : sv->streams)
         if (st) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : sv->events)
+        if (e) (void)hipEventDestroy(e);
     sv->ctxs.clear();
     sv->streams.clear();
+    sv->events.clear();
 }
 
 tmd_status sfail(tmd_server* sv, tmd_status st, const char* msg) {
@@ -619,6 +657,15 @@ tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, 
             break;
         }
         sv->streams.push_back(stream);
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                st = TMD_ERR_DEVICE;
+                break;
+            }
+            sv->events.push_back(e);
+        }
+        if (st != TMD_OK) break;
         st = tmd_context_create(o.device, stream, &ctx);
         if (st != TMD_OK) break;
         sv->ctxs.push_back(ctx);
@@ -845,6 +892,7 @@ void tmd_serve_destroy(tmd_server* sv) {
     for (auto& t : sv->workers) t.join();
     (void)hipSetDevice(sv->opts.device);
     (void)hipDeviceSynchronize();
+    destroy_lists(sv->retired);
     release_slots(sv);
     for (auto& kv : sv->systems) {
         System* s = kv.second.get();
