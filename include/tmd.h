@@ -481,8 +481,12 @@ typedef struct {
  * change while requests run) and uses its precision setting. */
 tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, tmd_server** out);
 /* Register a system: host FP64 positions [n][3], host int32 species [n], box,
- * host FP64 masses per species [S] (amu).  Velocities start at zero.
- * TMD_ERR_REJECTED when it is larger than max_atoms or its state cannot fit. */
+ * host FP64 masses per species [S] (amu).  Velocities start at zero.  When
+ * hbm_budget_bytes has room, the system's neighbour list is also allocated and
+ * built here (blocking the caller), so that requests on it start with a
+ * resident list; otherwise, or if that build fails, its first request builds
+ * it.  TMD_ERR_REJECTED when it is larger than max_atoms or its state cannot
+ * fit. */
 tmd_status tmd_serve_add_system(tmd_server* server, int64_t n_atoms, const double* pos, const int32_t* species,
                                 const double box[3], const double* masses, int64_t* system_id);
 /* Queue a request; *ticket identifies it.  Thread-safe. */
@@ -504,6 +508,11 @@ tmd_status tmd_serve_read_system(tmd_server* server, int64_t system_id, double* 
 /* Device memory the server holds (system state, lists, slot workspaces) and
  * its high-water mark, in bytes. */
 tmd_status tmd_serve_memory(tmd_server* server, int64_t* in_use, int64_t* peak);
+/* The part of it that one system holds: its state (positions, velocities,
+ * forces, species; bytes) and its neighbour list (0 while it has none resident:
+ * evicted, or left to its first request).  Either pointer may be NULL;
+ * TMD_ERR_INVALID_ARGUMENT for an unknown system. */
+tmd_status tmd_serve_system_memory(tmd_server* server, int64_t system_id, int64_t* state_bytes, int64_t* list_bytes);
 const char* tmd_serve_last_error(tmd_server* server);
 /* Finish the running requests, drop queued ones, free everything. */
 void tmd_serve_destroy(tmd_server* server);

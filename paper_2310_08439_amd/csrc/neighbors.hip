@@ -1003,6 +1003,8 @@ tmd_status prune_rows(tmd_context* ctx, tmd_nlist* nl, double r, const int32_t* 
 
 }  // namespace
 
+tmd_status reserve_pruned_rows(tmd_context* ctx, tmd_nlist* nl) { return reserve_pruned(ctx, nl); }
+
 tmd_status launch_prune(tmd_context* ctx, tmd_nlist* nl, double rcut) {
     tmd_status st = reserve_pruned(ctx, nl);
     if (st != TMD_OK) return st;

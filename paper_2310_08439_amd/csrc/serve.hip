@@ -89,6 +89,11 @@ struct tmd_server {
     // lists evicted under the lock, destroyed by a worker after it releases the
     // lock (destroying a list waits for the whole device)
     std::vector<tmd_nlist*> retired;
+    // builds the lists of newly registered systems (under admin_mu), so that
+    // requests on them neither allocate nor build a first list
+    tmd_context* admin = nullptr;
+    hipStream_t admin_stream = nullptr;
+    std::mutex admin_mu;
     bool stop = false;
     std::string last_error;
 };
@@ -155,6 +160,43 @@ tmd_status build_list(tmd_server* sv, tmd_context* ctx, System* sys, int* rebuil
         sys->cap = nl->cap;
     }
     return fail(ctx, TMD_ERR_CAPACITY, "neighbour list kept overflowing");
+}
+
+// At registration, when the budget has room: allocate the new system's list
+// (with its pruned rows) and build it on the admission context, so that the
+// first request on the system neither allocates (an allocation can wait for
+// the whole device, i.e. for every other slot's work) nor builds.  On any
+// failure the list is left to the first request, as for an evicted one.
+void admit_list(tmd_server* sv, System* sys) {
+    const int S = sv->model->S;
+    const bool skin = sv->opts.skin > 0.0;
+    const size_t lb = nlist_bytes(sys->n, S, sys->cap, skin);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->mem_in_use + (int64_t)lb > sv->opts.hbm_budget_bytes) return;
+        account(sv, (int64_t)lb);
+    }
+    std::lock_guard<std::mutex> ak(sv->admin_mu);
+    tmd_context* ctx = sv->admin;
+    tmd_nlist* nl = nullptr;
+    tmd_status st = tmd_nlist_create(ctx, sys->n, S, sys->cap, &nl);
+    int rebuilds = 0;
+    if (st == TMD_OK) {
+        sys->nl = nl;
+        sys->nl_bytes = lb;
+        sys->nl_valid = false;
+        st = build_list(sv, ctx, sys, &rebuilds);  // may grow the list (and its accounted bytes)
+    }
+    if (st == TMD_OK && skin) st = reserve_pruned_rows(ctx, sys->nl);
+    if (st == TMD_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = TMD_ERR_DEVICE;
+    if (st == TMD_OK) return;
+    const size_t held = sys->nl ? sys->nl_bytes : lb;
+    if (sys->nl) tmd_nlist_destroy(sys->nl);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    account(sv, -(int64_t)held);
+    sys->nl = nullptr;
+    sys->nl_bytes = 0;
+    sys->nl_valid = false;
 }
 
 struct SlotBuffers {
@@ -599,9 +641,13 @@ void release_slots(tmd_server* sv) {
         if (st) (void)hipStreamDestroy(st);
     for (hipEvent_t e : sv->events)
         if (e) (void)hipEventDestroy(e);
+    if (sv->admin) tmd_context_destroy(sv->admin);
+    if (sv->admin_stream) (void)hipStreamDestroy(sv->admin_stream);
     sv->ctxs.clear();
     sv->streams.clear();
     sv->events.clear();
+    sv->admin = nullptr;
+    sv->admin_stream = nullptr;
 }
 
 tmd_status sfail(tmd_server* sv, tmd_status st, const char* msg) {
@@ -639,7 +685,8 @@ tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, 
         return TMD_ERR_DEVICE;
     }
     account(sv, (int64_t)o.max_slots *
-                    (int64_t)(eval_workspace_bytes(model, o.max_atoms) + nlist_workspace_bytes(o.max_atoms)));
+                        (int64_t)(eval_workspace_bytes(model, o.max_atoms) + nlist_workspace_bytes(o.max_atoms)) +
+                    (int64_t)nlist_workspace_bytes(o.max_atoms));  // + the admission context's
     // merged lists of batched requests (rows estimated at 64 entries per species)
     if (o.batch_atoms > 0)
         account(sv, (int64_t)o.max_slots * std::min<int64_t>(o.max_atoms, kServeBatchAtoms) *
@@ -672,6 +719,11 @@ tmd_status tmd_serve_create(const tmd_model* model, const tmd_serve_opts* opts, 
         if ((st = reserve_eval_workspace(ctx, model, o.max_atoms)) != TMD_OK) break;
         st = reserve_nlist_workspace(ctx, o.max_atoms, model->S);
     }
+    if (st == TMD_OK) {
+        if (hipStreamCreateWithFlags(&sv->admin_stream, hipStreamNonBlocking) != hipSuccess) st = TMD_ERR_DEVICE;
+        if (st == TMD_OK) st = tmd_context_create(o.device, sv->admin_stream, &sv->admin);
+        if (st == TMD_OK) st = reserve_nlist_workspace(sv->admin, o.max_atoms, model->S);
+    }
     if (st != TMD_OK) {
         release_slots(sv);
         delete sv;
@@ -702,8 +754,12 @@ tmd_status tmd_serve_add_system(tmd_server* sv, int64_t n, const double* pos, co
     sys->state_bytes = (size_t)n * (24 * 3 + 12 + 4) + 16 * (size_t)S;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
+        // the resident lists can all be evicted to make room for this one
+        int64_t lists = 0;
+        for (auto& kv : sv->systems)
+            if (kv.second->nl) lists += (int64_t)kv.second->nl_bytes;
         const int64_t need = (int64_t)sys->state_bytes + (int64_t)nlist_bytes(n, S, sys->cap, sv->opts.skin > 0.0);
-        if (sv->mem_in_use + need > sv->opts.hbm_budget_bytes) {
+        if (sv->mem_in_use - lists + need > sv->opts.hbm_budget_bytes) {
             sv->last_error = "system state does not fit in the memory budget";
             return TMD_ERR_REJECTED;
         }
@@ -737,6 +793,7 @@ tmd_status tmd_serve_add_system(tmd_server* sv, int64_t n, const double* pos, co
         sv->last_error = std::string("system upload: ") + hipGetErrorString(e);
         return e == hipErrorOutOfMemory ? TMD_ERR_OUT_OF_MEMORY : TMD_ERR_DEVICE;
     }
+    admit_list(sv, sys.get());
     std::lock_guard<std::mutex> lk(sv->mu);
     sys->id = sv->next_system++;
     *system_id = sys->id;
@@ -872,6 +929,19 @@ tmd_status tmd_serve_memory(tmd_server* sv, int64_t* in_use, int64_t* peak) {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (in_use) *in_use = sv->mem_in_use;
     if (peak) *peak = sv->mem_peak;
+    return TMD_OK;
+}
+
+tmd_status tmd_serve_system_memory(tmd_server* sv, int64_t system_id, int64_t* state_bytes, int64_t* list_bytes) {
+    if (!sv) return TMD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->systems.find(system_id);
+    if (it == sv->systems.end()) {
+        sv->last_error = "unknown system id";
+        return TMD_ERR_INVALID_ARGUMENT;
+    }
+    if (state_bytes) *state_bytes = (int64_t)it->second->state_bytes;
+    if (list_bytes) *list_bytes = it->second->nl ? (int64_t)it->second->nl_bytes : 0;
     return TMD_OK;
 }
 

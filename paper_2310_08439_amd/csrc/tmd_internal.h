@@ -387,6 +387,9 @@ tmd_status reserve_eval_workspace(tmd_context* ctx, const tmd_model* m, int64_t 
 size_t eval_workspace_bytes(const tmd_model* m, int64_t n);
 tmd_status reserve_nlist_workspace(tmd_context* ctx, int64_t n, int S);
 size_t nlist_workspace_bytes(int64_t n);
+// Allocate a list's rows pruned to the cutoff now rather than at its first
+// evaluation (a no-op once they exist).
+tmd_status reserve_pruned_rows(tmd_context* ctx, tmd_nlist* nl);
 
 // Velocity Verlet pieces (md.hip).  acc[S] = 9.648533e-3 / m_s; maxd2
 // (nullable) receives the largest squared displacement from xref as ordered

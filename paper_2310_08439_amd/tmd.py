@@ -39,7 +39,8 @@ EXPORTS = (
     "tmd_profile_enable", "tmd_profile_reset", "tmd_profile_read",
     "tmd_model_get_params", "tmd_batch_create", "tmd_batch_destroy", "tmd_train_step", "tmd_batch_read",
     "tmd_serve_create", "tmd_serve_add_system", "tmd_serve_submit", "tmd_serve_poll", "tmd_serve_wait",
-    "tmd_serve_fetch", "tmd_serve_release", "tmd_serve_read_system", "tmd_serve_memory", "tmd_serve_last_error",
+    "tmd_serve_fetch", "tmd_serve_release", "tmd_serve_read_system", "tmd_serve_memory", "tmd_serve_system_memory",
+    "tmd_serve_last_error",
     "tmd_serve_destroy",
     "tmd_md_create", "tmd_md_run", "tmd_md_read", "tmd_md_thermostat_state", "tmd_md_destroy",
     "tmd_model_tabulate", "tmd_model_tab_spacing",
@@ -195,6 +196,7 @@ def load_library(path: str = LIB_PATH):
     L.tmd_serve_release.argtypes = [vp, ctypes.c_uint64]
     L.tmd_serve_read_system.argtypes = [vp, i64, vp, vp]
     L.tmd_serve_memory.argtypes = [vp, P(i64), P(i64)]
+    L.tmd_serve_system_memory.argtypes = [vp, i64, P(i64), P(i64)]
     L.tmd_serve_last_error.argtypes = [vp]
     L.tmd_serve_last_error.restype = ctypes.c_char_p
     L.tmd_serve_destroy.argtypes = [vp]
@@ -724,6 +726,14 @@ class Server:
         a = ctypes.c_int64(0)
         b = ctypes.c_int64(0)
         self._check(self.lib.tmd_serve_memory(self.h, ctypes.byref(a), ctypes.byref(b)), "tmd_serve_memory")
+        return int(a.value), int(b.value)
+
+    def system_memory(self, system_id: int) -> Tuple[int, int]:
+        """(state bytes, resident list bytes) of one system."""
+        a = ctypes.c_int64(0)
+        b = ctypes.c_int64(0)
+        self._check(self.lib.tmd_serve_system_memory(self.h, system_id, ctypes.byref(a), ctypes.byref(b)),
+                    "tmd_serve_system_memory")
         return int(a.value), int(b.value)
 
     def close(self):

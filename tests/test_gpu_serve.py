@@ -224,21 +224,24 @@ def test_serve_admission_by_memory_budget(tmd, ctx):
     _, spec, _ = inputs.workload("oracle32")
     model = tmd.Model(ctx, spec)
     systems = [inputs.make_system("fcc", 3.61, (c, c, c), 0.05, 1, seed=90 + c, masses=[CU_MASS]) for c in (5, 6, 7)]
-    # measure the fixed part and the largest list with an unconstrained server
+    # measure the fixed part and the largest list with an unconstrained server,
+    # which builds every system's list at registration
     srv = tmd.Server(model, max_slots=2, max_atoms=2048, skin=1.0)
     ids = [srv.add_system(s.pos, s.species, s.box, s.masses) for s in systems]
-    base, _ = srv.memory()
-    lists = []
-    for i in ids:
-        before, _ = srv.memory()
-        r = srv.wait(srv.submit(i), 60.0)
-        assert r["status"] == 0
-        lists.append(srv.memory()[0] - before)
-    srv.close()
+    total, _ = srv.memory()
+    lists = [srv.system_memory(i)[1] for i in ids]
     assert min(lists) > 0
-    budget = base + max(lists) + 1024  # room for one list at a time
+    for i in ids:
+        r = srv.wait(srv.submit(i), 60.0)
+        assert r["status"] == 0 and r["rebuilds"] == 0  # the list was resident
+    assert srv.memory()[0] == total
+    srv.close()
+    base = total - sum(lists)  # workspaces and system states
+    budget = base + max(lists) + 1024  # room for about one list at a time
     srv = tmd.Server(model, max_slots=2, max_atoms=2048, skin=1.0, hbm_budget_bytes=budget)
     ids = [srv.add_system(s.pos, s.species, s.box, s.masses) for s in systems]
+    resident = [srv.system_memory(i)[1] > 0 for i in ids]
+    assert resident[0] and not all(resident)  # the others wait for their first request
     tickets = [srv.submit(i) for i in ids for _ in range(2)]
     for t, s in zip(tickets, [s for s in systems for _ in range(2)]):
         r = srv.wait(t, 60.0)
