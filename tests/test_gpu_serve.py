@@ -101,6 +101,35 @@ def test_serve_md_matches_oracle_velocity_verlet(tmd, ctx):
     srv.close()
 
 
+def test_serve_md_in_queued_chunks_matches_oracle(tmd, ctx):
+    """40 NVE steps of 4,000 atoms (160,000 atom-steps): the server queues them
+    in chunks of at least 65,536 atom-steps (17 steps here) and waits for the
+    end of the first chunk once the third is queued; the trajectory still
+    follows the FP64 oracle's velocity Verlet.  With a 1 A skin no atom moves
+    beyond skin/2, so no step rebuilds the list that registration built.
+    Bars: a force error of 5e-6 eV/A (the FP32 path's largest) acting for the
+    whole 40 fs moves an atom by 0.5 * 9.65e-3 * 5e-6 / 63.5 * 40^2 = 6e-7 A
+    and changes its velocity by 3e-8 A/fs; the bars allow three times that."""
+    _note("serve MD in chunks vs oracle NVE")
+    _, spec, _ = inputs.workload("oracle32")
+    model = tmd.Model(ctx, spec)
+    srv = tmd.Server(model, max_slots=2, max_atoms=4096, skin=1.0)
+    s = inputs.make_system("fcc", 3.61, (10, 10, 10), 0.05, 1, seed=74, masses=[CU_MASS])
+    v0 = inputs.maxwell_boltzmann(np.full(s.n, CU_MASS), 300.0, seed=75)
+    sid = srv.add_system(s.pos, s.species, s.box, s.masses)
+    t = srv.submit(sid, tmd.REQ_MD, n_steps=40, dt_fs=1.0, velocities=v0)
+    r = srv.wait(t, 60.0)
+    assert r["status"] == 0 and r["rebuilds"] == 0
+    out = srv.fetch(t, r)
+    x, v, epot, ekin = oracle.nve(spec, s.pos, v0, s.species, s.masses, s.box, 1.0, 40)
+    print(f"  max |dx|={np.abs(out['pos'] - x).max():.3e}  max |dv|={np.abs(out['vel'] - v).max():.3e}", flush=True)
+    np.testing.assert_allclose(out["pos"], x, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(out["vel"], v, rtol=0, atol=1e-7)
+    assert np.abs(out["epot"] - epot).max() / s.n <= 1e-5
+    np.testing.assert_allclose(out["ekin"], ekin, rtol=1e-5, atol=1e-8)
+    srv.close()
+
+
 def test_serve_nve_conserves_energy_across_list_rebuilds(tmd, ctx):
     _note("serve NVE 400 steps")
     _, spec, _ = inputs.workload("oracle32")
