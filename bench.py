@@ -296,7 +296,9 @@ def _serve_run(tmd, ctx, spec, systems, plan, burst, small_burst, n_warmup, slot
     model = tmd.Model(ctx, spec, precision=tmd.BF16_MLP)
     srv = tmd.Server(model, max_slots=slots, max_atoms=262144, skin=1.0, batch_atoms=batch_atoms,
                      hbm_budget_bytes=SERVE_HBM_BUDGET)
+    t_reg = time.perf_counter()
     ids = [srv.add_system(s.pos, s.species, s.box, masses) for (s, masses, _) in systems]
+    t_reg = time.perf_counter() - t_reg  # uploads and first list builds of the pool
     tickets = []
     start = time.perf_counter()
     for (ta, q, md, vel) in plan:
@@ -376,6 +378,7 @@ def _serve_run(tmd, ctx, spec, systems, plan, burst, small_burst, n_warmup, slot
             "small_system_ef_burst": small_systems,
             "latency_by_size": buckets,
             "requests_batched": round(float((bsz > 1).mean()), 3),
+            "registration_s": round(t_reg, 3),
             "mean_batch_size_of_batched": round(float(bsz[bsz > 1].mean()), 2) if (bsz > 1).any() else None,
             "device_bytes_peak": int(peak)}
 
