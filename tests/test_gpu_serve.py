@@ -297,6 +297,11 @@ def test_serve_input_errors(tmd, ctx):
         srv.submit(sid + 100)
     assert ei.value.status == 1
     with pytest.raises(tmd.TMDError) as ei:
+        srv.system_memory(sid + 100)
+    assert ei.value.status == 1
+    state, lst = srv.system_memory(sid)
+    assert state > 0 and lst > 0  # registration built the list
+    with pytest.raises(tmd.TMDError) as ei:
         srv.submit(sid, tmd.REQ_MD, 10, 0.0)
     assert ei.value.status == 1
     with pytest.raises(tmd.TMDError) as ei:
