@@ -430,14 +430,33 @@ __global__ void __launch_bounds__(256) k_halo_max(GridArgs g, int3 A, int64_t nb
 }
 
 
+// Systems of at most this many atoms have every workgroup of k_fill stage all
+// positions in LDS (32 KB): their cells are few and crowded, so each thread
+// walks hundreds of candidates, which the lanes of one cell then read from
+// LDS at one address instead of from L2.  The per-thread FP64 tests still
+// bound such a launch: a few workgroups run the whole list serially.
+constexpr int kFillLdsAtoms = 1024;
+
 // One thread per atom (cell-major order): scan the stencil of cells within
 // `reach` (periodic images folded in), append accepted neighbours to the
 // list of their species.
+template <bool kLds>
 __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
+    __shared__ double4 xs_lds[kLds ? kFillLdsAtoms : 1];
+    if constexpr (kLds) {
+        for (int64_t i = threadIdx.x; i < a.n; i += blockDim.x) xs_lds[i] = a.xs[i];
+        __syncthreads();
+    }
+    auto pos = [&](int64_t i) -> double4 {
+        if constexpr (kLds)
+            return xs_lds[i];
+        else
+            return a.xs[i];
+    };
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
     const GridArgs& g = a.g;
-    const double4 xi = a.xs[p];
+    const double4 xi = pos(p);
     const int cell = a.cell_sorted[p];
     const int cx = cell % g.nc[0];
     const int cy = (cell / g.nc[0]) % g.nc[1];
@@ -472,7 +491,7 @@ __global__ void __launch_bounds__(256) k_fill(FillArgs a) {
                 for (int q0 = lo; q0 < hi; q0 += 4) {
                     double4 xj[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) xj[j] = a.xs[min(q0 + j, hi - 1)];
+                    for (int j = 0; j < 4; ++j) xj[j] = pos(min(q0 + j, hi - 1));
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int q = q0 + j;
@@ -916,7 +935,10 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         fn<<<grid, kBlock, 0, st>>>(fa, ncells);
     } else {
         ProfScope ps_(ctx, "nb_fill");
-        k_fill<<<grid_for(n), kBlock, 0, st>>>(fa);
+        if (n <= kFillLdsAtoms)
+            k_fill<true><<<grid_for(n), kBlock, 0, st>>>(fa);
+        else
+            k_fill<false><<<grid_for(n), kBlock, 0, st>>>(fa);
     }
     TMD_HIP(ctx, hipGetLastError());
     TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, flags, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, st));
@@ -925,7 +947,10 @@ tmd_status launch_build_neighbors(tmd_context* ctx, const tmd_system_view* sys, 
         // a cell holds more atoms than one wave can track: per-atom fill instead
         {
             ProfScope ps_(ctx, "nb_fill");
-            k_fill<<<grid_for(n), kBlock, 0, st>>>(fa);
+            if (n <= kFillLdsAtoms)
+                k_fill<true><<<grid_for(n), kBlock, 0, st>>>(fa);
+            else
+                k_fill<false><<<grid_for(n), kBlock, 0, st>>>(fa);
         }
         TMD_HIP(ctx, hipGetLastError());
         TMD_HIP(ctx, hipMemcpyAsync(ctx->h_flags, flags, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, st));

@@ -108,6 +108,8 @@ NB_CASES = {
     # cells of ~107 atoms: more than one wave tracks, so the build falls back
     # to the per-atom fill
     "fcc2916_rc10_crowded_cells": lambda: (inputs.make_system("fcc", 3.61, (9, 9, 9), 0.05, 2, seed=33), 10.0, 0.0),
+    # one cell of 108 atoms: the per-atom fill with the positions staged in LDS
+    "fcc108_one_crowded_cell_rc6": lambda: (inputs.make_system("fcc", 3.61, (3, 3, 3), 0.05, 2, seed=34), 6.0, 0.0),
 }
 
 
